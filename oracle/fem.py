@@ -154,14 +154,23 @@ def solve(K, f, fixed_flat):
     return u
 
 
-def element_energy(mesh: Mesh, u, K0, cells=None):
-    """w_e = sum_r u_{r,e}^T K0_e u_{r,e} (unit modulus)."""
+def element_energy(mesh: Mesh, u, nu: float, paper_mode: bool = False, cells=None):
+    """w_e = sum_r u_{r,e}^T K0_e u_{r,e} (unit modulus).
+
+    Evaluated from the strain, w_e = |T_e| eps_e^T D eps_e with
+    eps_e = B_e u_e: the energy density is a function of the strain
+    (Section 2, eq. str_energy), and forming the strain first avoids the
+    cancellation of the quadratic form u^T K0 u when u_e is close to a
+    rigid motion."""
     dofs = element_dofs(mesh, cells)
+    vol, g = geometry(mesh, cells)
+    B = B_matrices(g)
+    D = material_D(mesh.dim, nu, paper_mode)
     u = np.atleast_2d(u)
     w = np.zeros(dofs.shape[0], dtype=u.dtype)
     for r in range(u.shape[0]):
-        ue = u[r][dofs]
-        w = w + np.einsum("ei,eij,ej->e", ue, K0, ue)
+        eps = np.einsum("eki,ei->ek", B, u[r][dofs])
+        w = w + vol * np.einsum("ek,kl,el->e", eps, D, eps)
     return w
 
 

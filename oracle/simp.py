@@ -56,7 +56,7 @@ def solve_state(S: Setup, rho):
     K = fem.assemble(S.mesh, E, p.nu, p.paper_mode, S.K0)
     u = fem.solve(K, S.f, S.fixed_flat)
     c = fem.compliance(S.f, u)
-    w = fem.element_energy(S.mesh, u, S.K0)
+    w = fem.element_energy(S.mesh, u, p.nu, p.paper_mode)
     s = fem.sensitivity(rho, w, p.E0, p.Emin, p.penal, p.paper_mode)
     if p.paper_mode:
         s = s * fem.paper_sensitivity_scale(S.mesh)

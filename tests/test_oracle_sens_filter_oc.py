@@ -41,7 +41,7 @@ def test_sensitivity_complex_step(dim):
     f = p.loads.reshape(p.nrhs, -1)
     rho = synth.rho_random(11, m.n_cells, 0.2, 1.0)
     c, u = _compliance_of(m, K0, rho, f, fixed, p)
-    w = fem.element_energy(m, u, K0)
+    w = fem.element_energy(m, u, p.nu)
     s = fem.sensitivity(rho, w, p.E0, p.Emin, p.penal)
     h = 1e-30
     for e in range(0, m.n_cells, max(1, m.n_cells // 8)):
