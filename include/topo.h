@@ -1,0 +1,206 @@
+/*
+ * topo.h -- C ABI of the MI355X (gfx950) SIMP topology-optimisation library.
+ *
+ * The library runs one iteration of the SIMP method of arXiv 2012.08208
+ * ("A 55-line code for large-scale parallel topology optimization in 2D
+ * and 3D") on one GPU, on structured P1 simplex grids:
+ *
+ *   solve        K(rho) u = f                 (Sec. 3.1, eq. fe_form; Sec. 2, eq. simp)
+ *   sensitivity  c = f^T u and dc/drho_e      (Sec. 3.2, sensitivity of f)
+ *   filter       s~ = W (rho s) / (rho R)     (Sec. 3.2.2, eq. filter, eq. filter_cond;
+ *                                             Sec. 4.4, eq. filter_mat)
+ *   oc_update    rho_new by the OC rule       (Sec. 3.2, eq. kkt, eq. update; Sec. 3.2.1)
+ *   iterate      the loop of all four         (Sec. 4.3 and the Appendix code)
+ *
+ * Conventions (shared by every entry point)
+ * -----------------------------------------
+ * Grid: nel = (nx, ny[, nz]) unit cells.  Nodes are numbered x-fastest,
+ *   n = j*(nx+1) + i (2D), n = (k*(ny+1) + j)*(nx+1) + i (3D).
+ * Cells: 2D unit squares are cut into two triangles, e = 2*(j*nx + i) + t.
+ *   Diagonal A joins (0,0)-(1,1): t=0 is (0,0),(1,0),(1,1), t=1 is
+ *   (0,0),(1,1),(0,1).  Diagonal B joins (1,0)-(0,1): t=0 is (0,0),(1,0),(0,1),
+ *   t=1 is (1,0),(1,1),(0,1).  TOPO_SPLIT_ALT_ROWS uses A on even rows and
+ *   B on odd rows; TOPO_SPLIT_UNIFORM uses A everywhere.
+ *   3D unit cubes are cut into the six Kuhn tetrahedra, e = 6*h + t with
+ *   h = (k*ny + j)*nx + i; tetrahedron t follows the t-th permutation pi of
+ *   (x,y,z) in lexicographic order and has vertices v0 = corner,
+ *   v1 = v0 + e_pi1, v2 = v1 + e_pi2, v3 = corner + (1,1,1).
+ * Nodal vectors (loads f, displacements u) are float64 structure-of-arrays
+ *   [nrhs][dim][N_n]: load case, component, node.  Densities and
+ *   sensitivities are float64 [N_c].
+ * Material: unit-modulus isotropic law with Poisson ratio nu (plane stress
+ *   in 2D); SIMP modulus E_e = Emin + rho_e^p (E0 - Emin).  paper_mode
+ *   switches to the listing's law: E_e = rho_e^p, Lame mu = 0.4,
+ *   lambda = 0.6, and the per-cell sensitivity -p rho^(p-1) psi_e
+ *   (= dc/drho_e / (2|T_e|)).
+ * Dirichlet conditions: a host mask fixed[dim][N_n] (uint8, nonzero = fixed)
+ *   given at creation.  The operator is Z K Z with Z zeroing fixed DOFs.
+ *
+ * Memory, streams, errors
+ * -----------------------
+ * Every pointer argument is a DEVICE pointer unless marked "host".  The
+ * caller owns all buffers, including the workspace given to topo_create;
+ * the library allocates no device memory and keeps no caller pointer
+ * after a call returns.  All compute calls are asynchronous on the
+ * context's stream (a hipStream_t passed as void*; NULL = default stream).
+ * Scalars are written to device memory; topo_sync waits for the stream and
+ * returns the sticky device status.  A context is not thread-safe.
+ *
+ * Return values: 0 = OK; negative = host-detected error (TOPO_E_*), in
+ * which case nothing was enqueued.  Device-detected outcomes (not converged,
+ * non-finite values, OC infeasible) go to the sticky status read by
+ * topo_sync.
+ */
+#ifndef TOPO_H
+#define TOPO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct topo_ctx topo_ctx;
+
+enum {
+  TOPO_OK = 0,
+  TOPO_E_INVALID = -1,   /* invalid argument or parameter */
+  TOPO_E_SHAPE = -2,     /* sizes / alignment do not match the problem */
+  TOPO_E_STATE = -3,     /* call out of order (e.g. solve before set_loads) */
+  TOPO_E_HIP = -4,       /* a HIP runtime call failed */
+  TOPO_E_WORKSPACE = -7, /* workspace smaller than topo_workspace_size */
+  /* sticky device status (topo_sync) */
+  TOPO_S_NOT_CONVERGED = 1, /* a solve stopped at maxit; outputs inexact */
+  TOPO_S_NUMERIC = -5,      /* NaN/Inf or CG breakdown (p^T K p <= 0) */
+  TOPO_S_OC_INFEASIBLE = -6 /* volfrac*N outside [sum lo, sum hi] */
+};
+
+enum { TOPO_SPLIT_ALT_ROWS = 0, TOPO_SPLIT_UNIFORM = 1 };
+enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1 };
+enum { TOPO_PC_JACOBI = 0, TOPO_PC_GMG = 1 };
+
+/* Problem description (host struct, copied by topo_create). */
+typedef struct topo_problem {
+  int32_t dim;        /* 2 or 3 */
+  int32_t nel[3];     /* cells per axis, each >= 1; nel[2] ignored in 2D */
+  int32_t split2d;    /* TOPO_SPLIT_*; ignored in 3D */
+  int32_t nrhs;       /* number of load cases, 1..4 (Sec. 5.3: summed) */
+  double E0, Emin, nu;        /* 1, 1e-9, 0.3 */
+  double penal;               /* p, e.g. 3 */
+  double volfrac;             /* k in (0, 1] */
+  double rmin;                /* filter radius in cell widths, > 0 */
+  double move, eta, rho_min;  /* OC move limit m, damping eta, lower bound */
+  int32_t precision;  /* TOPO_FP64 | TOPO_MIXED_FP32 (FP32 operator inside
+                         FP64 iterative refinement) */
+  int32_t precond;    /* TOPO_PC_JACOBI | TOPO_PC_GMG */
+  double rtol;        /* stop when ||f_r - K u_r|| <= rtol ||f_r|| for each r */
+  int32_t maxit;      /* cap on preconditioned CG iterations per solve */
+  int32_t paper_mode; /* 0: E = Emin + rho^p (E0-Emin), exact dc/drho;
+                         1: the listing's law, see above */
+  int32_t warm_start; /* 1: topo_solve starts from the u it is given */
+  int32_t gmg_levels; /* 0 = automatic; otherwise the number of levels */
+} topo_problem;
+
+/* Length of the per-solve info record written by topo_solve (doubles):
+   [0] PCG iterations, [1] converged (1/0), [2..5] final relative residual
+   of load cases 0..3 (0 for absent cases). */
+#define TOPO_SOLVE_INFO_LEN 6
+/* Length of one per-iteration log record written by topo_iterate (doubles):
+   [0] compliance c = sum_r f_r^T u_r, [1] the listing's objective
+   sum_e rho^p psi_e, [2] volume fraction of the new design, [3] change
+   max|rho_new - rho|, [4] Lagrange multiplier, [5] PCG iterations,
+   [6] max relative residual over load cases, [7] converged (1/0). */
+#define TOPO_LOG_LEN 8
+
+/* Bytes of device workspace topo_create needs for this problem.
+   Returns TOPO_E_INVALID for an invalid problem. */
+int topo_workspace_size(const topo_problem* prob, size_t* bytes /* host */);
+
+/* Creates a context.  fixed_mask (host, [dim][N_n] uint8) marks Dirichlet
+   DOFs.  workspace must be device memory of at least
+   topo_workspace_size bytes, 256-byte aligned, owned by the caller and kept
+   alive (and otherwise unused) until topo_destroy.  stream is a hipStream_t
+   (NULL = default).  Precomputes the filter row sums R_a = sum_b W_ab.
+   Synchronises the stream before returning. */
+int topo_create(const topo_problem* prob, const uint8_t* fixed_mask /* host */,
+                void* workspace, size_t ws_bytes, void* stream, topo_ctx** out /* host */);
+
+/* Releases the host-side context.  The workspace stays the caller's. */
+int topo_destroy(topo_ctx* ctx);
+
+/* Copies the loads f [nrhs][dim][N_n] into the workspace (stream-ordered).
+   Values on fixed DOFs are ignored.  nrhs must equal the problem's. */
+int topo_set_loads(topo_ctx* ctx, const double* f, int nrhs);
+
+/* Solves K(rho) u_r = f_r for every load case by preconditioned CG (Jacobi
+   or geometric multigrid) to the problem's rtol, matrix-free.  rho [N_c]
+   in [rho_min, 1]; u [nrhs][dim][N_n] output (also the start vector when
+   warm_start is set); info (device, may be NULL) receives
+   TOPO_SOLVE_INFO_LEN doubles.  The loop checks convergence on the
+   device; the host polls a pinned flag every few iterations. */
+int topo_solve(topo_ctx* ctx, const double* rho, double* u, double* info);
+
+/* Compliance c = sum_r f_r^T u_r (written to *compliance, device scalar)
+   and the sensitivity dc [N_c]:
+   dc_e = -p rho_e^(p-1) (E0 - Emin) sum_r u_{r,e}^T K0_e u_{r,e}
+   (paper_mode: the listing's -p rho^(p-1) psi_e).  compliance may be NULL. */
+int topo_sensitivity(topo_ctx* ctx, const double* rho, const double* u, double* dc,
+                     double* compliance);
+
+/* Filtered sensitivity dcf_a = sum_b W_ab rho_b dc_b / (rho_a R_a), with
+   W_ab = max(0, rmin - |x_a - x_b|) between cell centroids; cells near
+   the boundary use only the cells that exist.  dcf must not alias dc. */
+int topo_filter(topo_ctx* ctx, const double* rho, const double* dc, double* dcf);
+
+/* OC update: rho_new_e = clamp(rho_e (-dcf_e / lambda)^eta,
+   max(rho_min, rho_e - move), min(1, rho_e + move)) with lambda chosen so
+   that sum_e rho_new_e = volfrac * N_c (to rounding).  scalars (device,
+   may be NULL) receives [lambda, sum_e rho_new_e, max_e |rho_new_e - rho_e|].
+   rho_new must not alias rho. */
+int topo_oc_update(topo_ctx* ctx, const double* rho, const double* dcf, double* rho_new,
+                   double* scalars);
+
+/* Runs up to max_iter SIMP iterations in place on rho [N_c] (solve ->
+   sensitivity -> filter -> OC).  change_tol <= 0: exactly max_iter
+   iterations; otherwise stop after the first iteration whose change is
+   below change_tol (this polls the device once per iteration).  u
+   [nrhs][dim][N_n] is the displacement work/output buffer (warm-started
+   across iterations).  log (device, may be NULL) receives max_iter records
+   of TOPO_LOG_LEN doubles; *n_done (host, may be NULL) the iterations
+   run. */
+int topo_iterate(topo_ctx* ctx, double* rho, double* u, int max_iter, double change_tol,
+                 double* log, int* n_done /* host */);
+
+/* Operator apply y = Z K(rho) Z x for all nrhs load cases (x, y
+   [nrhs][dim][N_n]); the hot kernel of every solve, exported for checks
+   and measurement. */
+int topo_apply(topo_ctx* ctx, const double* rho, const double* x, double* y);
+
+/* Jacobi diagonal d = diag(K(rho)) on free DOFs and 1 on fixed DOFs,
+   d [dim][N_n]. */
+int topo_diagonal(topo_ctx* ctx, const double* rho, double* d);
+
+/* Filter row sums R [N_c] computed at creation. */
+int topo_filter_rowsums(topo_ctx* ctx, double* R);
+
+/* Kernel timing (host outputs).  When enabled, every launch of the
+   operator-apply kernel inside topo_solve/topo_apply is bracketed by HIP
+   events on the context stream; topo_timing_read returns the number of
+   launches and their summed duration in milliseconds since the last
+   reset, and resets.  Reading synchronises the stream. */
+int topo_timing_enable(topo_ctx* ctx, int enable);
+int topo_timing_read(topo_ctx* ctx, int64_t* launches /* host */, double* total_ms /* host */);
+
+/* Waits for the context stream; *device_status (host, may be NULL) gets the
+   sticky device status (TOPO_OK or a TOPO_S_* value), which is then
+   cleared. */
+int topo_sync(topo_ctx* ctx, int* device_status /* host */);
+
+/* Static description of a status or error code. */
+const char* topo_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOPO_H */

@@ -1,0 +1,276 @@
+"""ctypes binding of the gfx950 SIMP library (argument marshalling only).
+
+Every compute step runs in the HIP kernels of ``libtopo.so``; this module
+only checks tensor shapes/dtypes/devices, passes raw device pointers and
+the current torch stream, and owns the workspace tensor.  There is no CPU
+path: if the library is missing the import of a context fails loudly.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtopo.so")
+
+TOPO_SPLIT_ALT_ROWS = 0
+TOPO_SPLIT_UNIFORM = 1
+TOPO_FP64 = 0
+TOPO_MIXED_FP32 = 1
+TOPO_PC_JACOBI = 0
+TOPO_PC_GMG = 1
+SOLVE_INFO_LEN = 6
+LOG_LEN = 8
+
+EXPORTED = [
+    "topo_workspace_size", "topo_create", "topo_destroy", "topo_set_loads", "topo_solve",
+    "topo_sensitivity", "topo_filter", "topo_oc_update", "topo_iterate", "topo_apply",
+    "topo_diagonal", "topo_filter_rowsums", "topo_timing_enable", "topo_timing_read",
+    "topo_sync", "topo_status_string",
+]
+
+
+class TopoError(RuntimeError):
+    pass
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("nel", ctypes.c_int32 * 3), ("split2d", ctypes.c_int32),
+        ("nrhs", ctypes.c_int32), ("E0", ctypes.c_double), ("Emin", ctypes.c_double),
+        ("nu", ctypes.c_double), ("penal", ctypes.c_double), ("volfrac", ctypes.c_double),
+        ("rmin", ctypes.c_double), ("move", ctypes.c_double), ("eta", ctypes.c_double),
+        ("rho_min", ctypes.c_double), ("precision", ctypes.c_int32), ("precond", ctypes.c_int32),
+        ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("paper_mode", ctypes.c_int32),
+        ("warm_start", ctypes.c_int32), ("gmg_levels", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libtopo.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise TopoError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    P = ctypes.POINTER
+    lib.topo_workspace_size.argtypes = [P(CProblem), P(ctypes.c_size_t)]
+    lib.topo_create.argtypes = [P(CProblem), vp, vp, ctypes.c_size_t, vp, P(vp)]
+    lib.topo_destroy.argtypes = [vp]
+    lib.topo_set_loads.argtypes = [vp, vp, i32]
+    lib.topo_solve.argtypes = [vp, vp, vp, vp]
+    lib.topo_sensitivity.argtypes = [vp, vp, vp, vp, vp]
+    lib.topo_filter.argtypes = [vp, vp, vp, vp]
+    lib.topo_oc_update.argtypes = [vp, vp, vp, vp, vp]
+    lib.topo_iterate.argtypes = [vp, vp, vp, i32, dbl, vp, P(i32)]
+    lib.topo_apply.argtypes = [vp, vp, vp, vp]
+    lib.topo_diagonal.argtypes = [vp, vp, vp]
+    lib.topo_filter_rowsums.argtypes = [vp, vp]
+    lib.topo_timing_enable.argtypes = [vp, i32]
+    lib.topo_timing_read.argtypes = [vp, P(ctypes.c_int64), P(dbl)]
+    lib.topo_sync.argtypes = [vp, P(i32)]
+    lib.topo_status_string.argtypes = [i32]
+    lib.topo_status_string.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name != "topo_status_string":
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        msg = load_library().topo_status_string(rc).decode()
+        raise TopoError(f"{what} failed: {rc} ({msg})")
+
+
+def make_problem(dim: int, nel: Sequence[int], nrhs: int = 1, split: int = TOPO_SPLIT_ALT_ROWS,
+                 E0: float = 1.0, Emin: float = 1e-9, nu: float = 0.3, penal: float = 3.0,
+                 volfrac: float = 0.5, rmin: float = 1.5, move: float = 0.2, eta: float = 0.5,
+                 rho_min: float = 1e-3, precision: int = TOPO_FP64, precond: int = TOPO_PC_JACOBI,
+                 rtol: float = 1e-10, maxit: int = 20000, paper_mode: bool = False,
+                 warm_start: bool = False, gmg_levels: int = 0) -> CProblem:
+    p = CProblem()
+    p.dim = int(dim)
+    nel3 = list(nel) + [0] * (3 - len(nel))
+    for a in range(3):
+        p.nel[a] = int(nel3[a])
+    p.split2d = int(split)
+    p.nrhs = int(nrhs)
+    p.E0, p.Emin, p.nu, p.penal = float(E0), float(Emin), float(nu), float(penal)
+    p.volfrac, p.rmin, p.move, p.eta, p.rho_min = (float(volfrac), float(rmin), float(move),
+                                                   float(eta), float(rho_min))
+    p.precision, p.precond = int(precision), int(precond)
+    p.rtol, p.maxit = float(rtol), int(maxit)
+    p.paper_mode, p.warm_start, p.gmg_levels = int(bool(paper_mode)), int(bool(warm_start)), int(gmg_levels)
+    return p
+
+
+class Topo:
+    """One library context on the current CUDA(HIP) device and stream."""
+
+    def __init__(self, cprob: CProblem, fixed_mask: np.ndarray, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.prob = cprob
+        self.dim = cprob.dim
+        nel = [cprob.nel[a] for a in range(cprob.dim)]
+        self.nel = tuple(nel)
+        self.n_nodes = int(np.prod([n + 1 for n in nel]))
+        self.n_cells = int(np.prod(nel)) * (2 if cprob.dim == 2 else 6)
+        self.nrhs = cprob.nrhs
+        self.device = torch.device(device)
+        mask = np.ascontiguousarray(fixed_mask, dtype=np.uint8).reshape(-1)
+        if mask.size != self.dim * self.n_nodes:
+            raise TopoError("fixed mask must have dim * n_nodes entries")
+        self._mask = mask
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib.topo_workspace_size(ctypes.byref(cprob), ctypes.byref(nbytes)),
+               "topo_workspace_size")
+        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = base + off
+        self._ws_bytes = int(nbytes.value)
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        _check(self.lib.topo_create(ctypes.byref(cprob), mask.ctypes.data, ctypes.c_void_p(self._ws_ptr),
+                                    self._ws_bytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(ctx)), "topo_create")
+        self.ctx = ctx
+
+    @classmethod
+    def from_problem(cls, p, precision=TOPO_FP64, precond=TOPO_PC_JACOBI, rtol=None, maxit=20000,
+                     warm_start=False, device="cuda"):
+        """Builds a context from any object with the problem attributes
+        (dim, nel, split, loads, fixed, E0, Emin, nu, penal, volfrac, rmin,
+        move, eta, rho_min, paper_mode, rtol)."""
+        cp = make_problem(p.dim, p.nel, p.loads.shape[0], p.split, p.E0, p.Emin, p.nu, p.penal,
+                          p.volfrac, p.rmin, p.move, p.eta, p.rho_min, precision, precond,
+                          p.rtol if rtol is None else rtol, maxit, p.paper_mode, warm_start)
+        t = cls(cp, p.fixed, device)
+        import torch
+        t.set_loads(torch.as_tensor(np.ascontiguousarray(p.loads), dtype=torch.float64,
+                                    device=t.device))
+        return t
+
+    # ---------------------------------------------------------------- utils
+    def _ptr(self, t, numel: int, name: str, dtype=None):
+        torch = self.torch
+        if t is None:
+            return None
+        if dtype is None:
+            dtype = torch.float64
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TopoError(f"{name} must be a CUDA tensor")
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+            raise TopoError(f"{name} must be contiguous {dtype} with {numel} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    @property
+    def n_dofs(self):
+        return self.dim * self.n_nodes
+
+    def vec_numel(self):
+        return self.nrhs * self.n_dofs
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.topo_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- API
+    def set_loads(self, f):
+        _check(self.lib.topo_set_loads(self.ctx, self._ptr(f, self.vec_numel(), "f"), self.nrhs),
+               "topo_set_loads")
+
+    def solve(self, rho, u, info=None):
+        _check(self.lib.topo_solve(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                   self._ptr(u, self.vec_numel(), "u"),
+                                   self._ptr(info, SOLVE_INFO_LEN, "info")), "topo_solve")
+
+    def sensitivity(self, rho, u, dc, compliance=None):
+        _check(self.lib.topo_sensitivity(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                         self._ptr(u, self.vec_numel(), "u"),
+                                         self._ptr(dc, self.n_cells, "dc"),
+                                         self._ptr(compliance, 1, "compliance")), "topo_sensitivity")
+
+    def filter(self, rho, dc, dcf):
+        _check(self.lib.topo_filter(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                    self._ptr(dc, self.n_cells, "dc"),
+                                    self._ptr(dcf, self.n_cells, "dcf")), "topo_filter")
+
+    def oc_update(self, rho, dcf, rho_new, scalars=None):
+        _check(self.lib.topo_oc_update(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                       self._ptr(dcf, self.n_cells, "dcf"),
+                                       self._ptr(rho_new, self.n_cells, "rho_new"),
+                                       self._ptr(scalars, 3, "scalars")), "topo_oc_update")
+
+    def iterate(self, rho, u, max_iter: int, change_tol: float = 0.0, log=None) -> int:
+        n = ctypes.c_int(0)
+        _check(self.lib.topo_iterate(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                     self._ptr(u, self.vec_numel(), "u"), int(max_iter),
+                                     float(change_tol),
+                                     self._ptr(log, int(max_iter) * LOG_LEN, "log"),
+                                     ctypes.byref(n)), "topo_iterate")
+        return int(n.value)
+
+    def apply(self, rho, x, y):
+        _check(self.lib.topo_apply(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                   self._ptr(x, self.vec_numel(), "x"),
+                                   self._ptr(y, self.vec_numel(), "y")), "topo_apply")
+
+    def diagonal(self, rho, d):
+        _check(self.lib.topo_diagonal(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                      self._ptr(d, self.n_dofs, "d")), "topo_diagonal")
+
+    def filter_rowsums(self, R):
+        _check(self.lib.topo_filter_rowsums(self.ctx, self._ptr(R, self.n_cells, "R")),
+               "topo_filter_rowsums")
+
+    def timing_enable(self, on: bool = True):
+        _check(self.lib.topo_timing_enable(self.ctx, int(bool(on))), "topo_timing_enable")
+
+    def timing_read(self):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check(self.lib.topo_timing_read(self.ctx, ctypes.byref(n), ctypes.byref(ms)),
+               "topo_timing_read")
+        return int(n.value), float(ms.value)
+
+    def sync(self) -> int:
+        st = ctypes.c_int(0)
+        _check(self.lib.topo_sync(self.ctx, ctypes.byref(st)), "topo_sync")
+        return int(st.value)
+
+
+def status_string(code: int) -> str:
+    return load_library().topo_status_string(int(code)).decode()
+
+
+def check_exports(path: Optional[str] = None):
+    """Returns the list of declared entry points missing from the library."""
+    lib = ctypes.CDLL(path or LIB_PATH)
+    missing = []
+    for name in EXPORTED:
+        try:
+            getattr(lib, name)
+        except AttributeError:
+            missing.append(name)
+    return missing

@@ -1,0 +1,409 @@
+// C ABI entry points: argument checks, workspace carving and the host-side
+// drivers of the SIMP loop (Sec. 4.3 and the Appendix code: solve ->
+// sensitivity -> filter -> OC -> change).
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.h"
+#include "topo_internal.h"
+
+using namespace topo;
+
+namespace topo {
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool valid_problem(const topo_problem* p) {
+  if (!p) return false;
+  if (p->dim != 2 && p->dim != 3) return false;
+  for (int a = 0; a < p->dim; ++a)
+    if (p->nel[a] < 1 || p->nel[a] > (1 << 20)) return false;
+  if (p->nrhs < 1 || p->nrhs > kMaxRhs) return false;
+  if (!(p->volfrac > 0.0 && p->volfrac <= 1.0)) return false;
+  if (!(p->rmin > 0.0 && p->rmin <= 16.0)) return false;
+  if (!(p->penal >= 1.0 && p->penal <= 10.0)) return false;
+  if (!(p->nu > -1.0 && p->nu < 0.5)) return false;
+  if (!(p->E0 > 0.0) || !(p->Emin >= 0.0) || !(p->Emin < p->E0)) return false;
+  if (!(p->move > 0.0) || !(p->eta > 0.0) || !(p->rho_min > 0.0 && p->rho_min < 1.0)) return false;
+  if (!(p->rtol > 0.0) || p->maxit < 1) return false;
+  if (p->precision != TOPO_FP64 && p->precision != TOPO_MIXED_FP32) return false;
+  if (p->precond != TOPO_PC_JACOBI && p->precond != TOPO_PC_GMG) return false;
+  if (p->dim == 2 && p->split2d != TOPO_SPLIT_ALT_ROWS && p->split2d != TOPO_SPLIT_UNIFORM)
+    return false;
+  return true;
+}
+
+static Grid make_grid(const topo_problem* p) {
+  Grid g;
+  g.dim = p->dim;
+  g.nx = p->nel[0];
+  g.ny = p->nel[1];
+  g.nz = p->dim == 3 ? p->nel[2] : 1;
+  g.nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (p->dim == 3 ? (g.nz + 1) : 1);
+  g.nc = (int64_t)g.nx * g.ny * (p->dim == 3 ? g.nz : 1) * (p->dim == 3 ? 6 : 2);
+  g.nd = g.nn * g.dim;
+  g.split = p->dim == 2 ? p->split2d : TOPO_SPLIT_UNIFORM;
+  return g;
+}
+
+static int pick_kz(const Grid& g) {
+  const char* env = getenv("TOPO_APPLY_KZ");
+  if (env) {
+    int v = atoi(env);
+    if (v >= 1 && v <= 1024) return v;
+  }
+  if (g.dim == 2) return 1;
+  const long cols = (long)((g.nx + 15) / 15) * ((g.ny + 15) / 15);
+  long kz = (long)(g.nz + 1) * cols / 1024;
+  if (kz < 4) kz = 4;
+  if (kz > 16) kz = 16;
+  return (int)kz;
+}
+
+static long apply_blocks(const Grid& g, int kz) {
+  long b = (long)((g.nx + 15) / 15) * ((g.ny + 15) / 15);
+  if (g.dim == 3) b *= (g.nz + 1 + kz - 1) / kz;
+  return b;
+}
+
+static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
+  WsLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t nr = (size_t)p->nrhs;
+  const bool mixed = p->precision == TOPO_MIXED_FP32;
+  long nblk = apply_blocks(g, kz);
+  if (nblk < kRedBlocks) nblk = kRedBlocks;
+  L.mask = take((size_t)g.nn);
+  L.f = take(nr * g.nd * 8);
+  L.E = take((size_t)g.nc * 8);
+  L.E32 = mixed ? take((size_t)g.nc * 4) : 0;
+  L.invd = take((size_t)g.nd * 8);
+  L.invd32 = mixed ? take((size_t)g.nd * 4) : 0;
+  L.r = take(nr * g.nd * 8);
+  L.p = take(nr * g.nd * 8);
+  L.q = take(nr * g.nd * 8);
+  L.z = 0;
+  L.wv = 0;
+  L.partials = take((size_t)nblk * 16 * 8);
+  L.scal = take(sizeof(DevScalars));
+  L.R = take((size_t)g.nc * 8);
+  L.taps = take((size_t)8 * kMaxFilterTaps * sizeof(FilterTap) + 64);
+  L.qsoa = take((size_t)g.nc * 8);
+  L.dc = take((size_t)g.nc * 8);
+  L.dcf = take((size_t)g.nc * 8);
+  L.rho_new = take((size_t)g.nc * 8);
+  L.rho_tmp = take((size_t)g.nc * 8);
+  L.ir_x = L.ir_r32 = L.ir_p32 = L.ir_q32 = L.ir_z32 = L.ir_u32 = 0;
+  L.total = o;
+  return L;
+}
+
+int timing_begin(Ctx* c, hipEvent_t*) {
+  if (c->tev_used >= c->tev.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) return -1;
+    c->tev.push_back({a, b});
+  }
+  const int slot = (int)c->tev_used++;
+  (void)hipEventRecord(c->tev[slot].first, c->stream);
+  return slot;
+}
+
+void timing_end(Ctx* c, int slot) { (void)hipEventRecord(c->tev[slot].second, c->stream); }
+
+__global__ void log_record_kernel(const DevScalars* sc, double* rec, long nc, int nr) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mx = 0.0;
+  for (int k = 0; k < nr; ++k)
+    if (sc->pcg.ff[k] > 0.0) mx = fmax(mx, sqrt(sc->pcg.rr[k] / sc->pcg.ff[k]));
+  rec[0] = sc->compliance;
+  rec[1] = sc->c_paper;
+  rec[2] = sc->oc.vol / (double)nc;
+  rec[3] = sc->oc.change;
+  rec[4] = sc->oc.lam;
+  rec[5] = sc->pcg.iters;
+  rec[6] = mx;
+  rec[7] = (sc->pcg.done && !sc->pcg.breakdown) ? 1.0 : 0.0;
+}
+
+}  // namespace topo
+
+struct topo_ctx : public Ctx {};
+
+extern "C" {
+
+int topo_workspace_size(const topo_problem* prob, size_t* bytes) {
+  if (!valid_problem(prob) || !bytes) return TOPO_E_INVALID;
+  Grid g = make_grid(prob);
+  *bytes = make_layout(prob, g, pick_kz(g)).total;
+  return TOPO_OK;
+}
+
+int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* workspace,
+                size_t ws_bytes, void* stream, topo_ctx** out) {
+  if (!out) return TOPO_E_INVALID;
+  *out = nullptr;
+  if (!valid_problem(prob) || !fixed_mask || !workspace) return TOPO_E_INVALID;
+  if (((uintptr_t)workspace & 255) != 0) return TOPO_E_SHAPE;
+  topo_ctx* c = new (std::nothrow) topo_ctx();
+  if (!c) return TOPO_E_INVALID;
+  c->prob = *prob;
+  c->g = make_grid(prob);
+  c->apply_kz = pick_kz(c->g);
+  c->L = make_layout(prob, c->g, c->apply_kz);
+  if (ws_bytes < c->L.total) {
+    delete c;
+    return TOPO_E_WORKSPACE;
+  }
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)workspace;
+  c->ws_bytes = ws_bytes;
+  const WsLayout& L = c->L;
+  char* w = c->ws;
+  c->mask = (uint8_t*)(w + L.mask);
+  c->f = (double*)(w + L.f);
+  c->E = (double*)(w + L.E);
+  c->E32 = L.E32 ? (float*)(w + L.E32) : nullptr;
+  c->invd = (double*)(w + L.invd);
+  c->invd32 = L.invd32 ? (float*)(w + L.invd32) : nullptr;
+  c->r = (double*)(w + L.r);
+  c->p = (double*)(w + L.p);
+  c->q = (double*)(w + L.q);
+  c->z = nullptr;
+  c->wv = nullptr;
+  c->partials = (double*)(w + L.partials);
+  c->scal = (DevScalars*)(w + L.scal);
+  c->R = (double*)(w + L.R);
+  c->taps = (FilterTap*)(w + L.taps);
+  c->qsoa = (double*)(w + L.qsoa);
+  c->dc = (double*)(w + L.dc);
+  c->dcf = (double*)(w + L.dcf);
+  c->rho_new = (double*)(w + L.rho_new);
+  c->rho_tmp = (double*)(w + L.rho_tmp);
+  // material of the unit-modulus element law
+  Material& m = c->m;
+  const double nu = prob->nu;
+  if (prob->paper_mode) {
+    m.lam0 = 0.6;
+    m.mu0 = 0.4;
+  } else if (prob->dim == 2) {
+    m.lam0 = nu / (1.0 - nu * nu);  // plane stress
+    m.mu0 = 1.0 / (2.0 * (1.0 + nu));
+  } else {
+    m.lam0 = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    m.mu0 = 1.0 / (2.0 * (1.0 + nu));
+  }
+  m.vol = prob->dim == 2 ? 0.5 : 1.0 / 6.0;
+  m.E0 = prob->E0;
+  m.Emin = prob->Emin;
+  m.penal = prob->penal;
+  m.paper = prob->paper_mode ? 1 : 0;
+  // node mask: bit c set when component c is fixed
+  std::vector<uint8_t> bits((size_t)c->g.nn, 0);
+  for (int comp = 0; comp < prob->dim; ++comp)
+    for (int64_t n = 0; n < c->g.nn; ++n)
+      if (fixed_mask[(size_t)comp * c->g.nn + n]) bits[n] |= (uint8_t)(1u << comp);
+  void* pin = nullptr;
+  if (hipHostMalloc(&pin, 64, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return TOPO_E_HIP;
+  }
+  c->pinned = (volatile int*)pin;
+  memset(pin, 0, 64);
+  if (hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipHostFree(pin);
+    delete c;
+    return TOPO_E_HIP;
+  }
+  bool ok = hipMemcpy(c->mask, bits.data(), bits.size(), hipMemcpyHostToDevice) == hipSuccess;
+  DevScalars zero;
+  memset(&zero, 0, sizeof(zero));
+  ok = ok && hipMemcpy(c->scal, &zero, sizeof(zero), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok) {
+    build_filter_taps(c);
+    launch_filter_rowsums(c);
+    ok = hipStreamSynchronize(c->stream) == hipSuccess && hipGetLastError() == hipSuccess;
+  }
+  if (!ok) {
+    (void)hipEventDestroy(c->ev_poll[0]);
+    (void)hipEventDestroy(c->ev_poll[1]);
+    (void)hipHostFree(pin);
+    delete c;
+    return TOPO_E_HIP;
+  }
+  c->loads_set = false;
+  c->timing = false;
+  c->tev_used = 0;
+  c->t_launches = 0;
+  c->t_ms = 0.0;
+  *out = c;
+  return TOPO_OK;
+}
+
+int topo_destroy(topo_ctx* c) {
+  if (!c) return TOPO_E_INVALID;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->tev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  (void)hipEventDestroy(c->ev_poll[0]);
+  (void)hipEventDestroy(c->ev_poll[1]);
+  (void)hipHostFree((void*)c->pinned);
+  delete c;
+  return TOPO_OK;
+}
+
+int topo_set_loads(topo_ctx* c, const double* f, int nrhs) {
+  if (!c || !f) return TOPO_E_INVALID;
+  if (nrhs != c->prob.nrhs) return TOPO_E_SHAPE;
+  TOPO_HIP(hipMemcpyAsync(c->f, f, (size_t)nrhs * c->g.nd * 8, hipMemcpyDeviceToDevice, c->stream));
+  c->loads_set = true;
+  return TOPO_OK;
+}
+
+static int solve_impl(topo_ctx* c, const double* rho, double* u, double* info, bool warm) {
+  launch_simp_modulus(c, rho);
+  launch_diagonal(c, c->invd, true);
+  topo_problem saved = c->prob;
+  c->prob.warm_start = warm ? 1 : 0;
+  pcg_solve(c, u, info);
+  c->prob = saved;
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_solve(topo_ctx* c, const double* rho, double* u, double* info) {
+  if (!c || !rho || !u) return TOPO_E_INVALID;
+  if (!c->loads_set) return TOPO_E_STATE;
+  return solve_impl(c, rho, u, info, c->prob.warm_start != 0);
+}
+
+int topo_sensitivity(topo_ctx* c, const double* rho, const double* u, double* dc,
+                     double* compliance) {
+  if (!c || !rho || !u || !dc) return TOPO_E_INVALID;
+  if (!c->loads_set) return TOPO_E_STATE;
+  launch_sensitivity(c, rho, u, dc, compliance);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_filter(topo_ctx* c, const double* rho, const double* dc, double* dcf) {
+  if (!c || !rho || !dc || !dcf || dc == dcf) return TOPO_E_INVALID;
+  launch_filter(c, rho, dc, dcf);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_oc_update(topo_ctx* c, const double* rho, const double* dcf, double* rho_new,
+                   double* scalars) {
+  if (!c || !rho || !dcf || !rho_new || rho == rho_new) return TOPO_E_INVALID;
+  oc_update(c, rho, dcf, rho_new, scalars);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_iterate(topo_ctx* c, double* rho, double* u, int max_iter, double change_tol,
+                 double* log, int* n_done) {
+  if (!c || !rho || !u || max_iter < 0) return TOPO_E_INVALID;
+  if (!c->loads_set) return TOPO_E_STATE;
+  int done = 0;
+  for (int it = 0; it < max_iter; ++it) {
+    const bool warm = it > 0 || c->prob.warm_start != 0;
+    int rc = solve_impl(c, rho, u, nullptr, warm);
+    if (rc != TOPO_OK) return rc;
+    launch_sensitivity(c, rho, u, c->dc, nullptr);
+    launch_filter(c, rho, c->dc, c->dcf);
+    oc_update(c, rho, c->dcf, c->rho_new, nullptr);
+    if (log) log_record_kernel<<<1, 64, 0, c->stream>>>(c->scal, log + (size_t)it * TOPO_LOG_LEN,
+                                                        c->g.nc, c->prob.nrhs);
+    TOPO_HIP(hipMemcpyAsync(rho, c->rho_new, (size_t)c->g.nc * 8, hipMemcpyDeviceToDevice,
+                            c->stream));
+    ++done;
+    if (change_tol > 0.0) {
+      double ch = 0.0;
+      TOPO_HIP(hipMemcpyAsync((void*)&c->pinned[4], &c->scal->oc.change, sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+      TOPO_HIP(hipStreamSynchronize(c->stream));
+      memcpy(&ch, (const void*)&c->pinned[4], sizeof(double));
+      if (ch < change_tol) break;
+    }
+  }
+  if (n_done) *n_done = done;
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_apply(topo_ctx* c, const double* rho, const double* x, double* y) {
+  if (!c || !rho || !x || !y || x == y) return TOPO_E_INVALID;
+  launch_simp_modulus(c, rho);
+  launch_apply(c, x, y, c->prob.nrhs, false);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_diagonal(topo_ctx* c, const double* rho, double* d) {
+  if (!c || !rho || !d) return TOPO_E_INVALID;
+  launch_simp_modulus(c, rho);
+  launch_diagonal(c, d, false);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_filter_rowsums(topo_ctx* c, double* R) {
+  if (!c || !R) return TOPO_E_INVALID;
+  TOPO_HIP(hipMemcpyAsync(R, c->R, (size_t)c->g.nc * 8, hipMemcpyDeviceToDevice, c->stream));
+  return TOPO_OK;
+}
+
+int topo_timing_enable(topo_ctx* c, int enable) {
+  if (!c) return TOPO_E_INVALID;
+  c->timing = enable != 0;
+  return TOPO_OK;
+}
+
+int topo_timing_read(topo_ctx* c, int64_t* launches, double* total_ms) {
+  if (!c) return TOPO_E_INVALID;
+  TOPO_HIP(hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i < c->tev_used; ++i) {
+    float ms = 0.f;
+    TOPO_HIP(hipEventElapsedTime(&ms, c->tev[i].first, c->tev[i].second));
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)c->tev_used;
+  if (total_ms) *total_ms = tot;
+  c->tev_used = 0;
+  return TOPO_OK;
+}
+
+int topo_sync(topo_ctx* c, int* device_status) {
+  if (!c) return TOPO_E_INVALID;
+  TOPO_HIP(hipStreamSynchronize(c->stream));
+  int st = 0;
+  TOPO_HIP(hipMemcpy(&st, &c->scal->status, sizeof(int), hipMemcpyDeviceToHost));
+  int zero = 0;
+  TOPO_HIP(hipMemcpy(&c->scal->status, &zero, sizeof(int), hipMemcpyHostToDevice));
+  if (device_status) *device_status = st;
+  return TOPO_OK;
+}
+
+const char* topo_status_string(int code) {
+  switch (code) {
+    case TOPO_OK: return "ok";
+    case TOPO_E_INVALID: return "invalid argument";
+    case TOPO_E_SHAPE: return "shape or alignment mismatch";
+    case TOPO_E_STATE: return "call out of order (loads not set?)";
+    case TOPO_E_HIP: return "HIP runtime error";
+    case TOPO_E_WORKSPACE: return "workspace too small";
+    case TOPO_S_NOT_CONVERGED: return "solve not converged within maxit";
+    case TOPO_S_NUMERIC: return "non-finite value or CG breakdown";
+    case TOPO_S_OC_INFEASIBLE: return "OC volume target infeasible";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

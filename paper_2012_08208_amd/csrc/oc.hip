@@ -1,0 +1,180 @@
+// Optimality-criteria update (Sec. 3.2, eq. kkt and eq. update; Sec. 3.2.1):
+//   rho_new_e(lambda) = clamp(rho_e (-dcf_e / lambda)^eta, lo_e, hi_e),
+//   lo_e = max(rho_min, rho_e - m),  hi_e = min(1, rho_e + m),
+// with lambda such that sum_e rho_new_e = volfrac * N.
+//
+// The paper finds lambda by bisection.  Writing mu = lambda^(-eta) and
+// a_e = rho_e (-dcf_e)^eta, every cell is clamp(a_e mu, lo_e, hi_e), so the
+// volume V(mu) is piecewise linear and non-decreasing in mu, and its root
+// gives the same (unique) design.  This kernel set finds that root with
+// Newton steps on V(mu) - target safeguarded by a bisection bracket: a pass
+// reduces V and its slope S = sum over unclamped cells of a_e; once the
+// clamped set is right, one Newton step lands on the root to rounding.
+// Each pass is one kernel with a fused single-pass reduction; the host
+// polls the done flag between batches of passes.
+#include <math.h>
+
+#include "common.h"
+#include "topo_internal.h"
+
+namespace topo {
+
+__device__ __forceinline__ double oc_a(double rho, double s, double eta) {
+  const double ns = s < 0.0 ? -s : 0.0;
+  return rho * (eta == 0.5 ? sqrt(ns) : pow(ns, eta));
+}
+
+__global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__ rho,
+                                                      const double* __restrict__ dcf, double* a_out,
+                                                      long nc, double move, double eta,
+                                                      double rho_min, double volfrac,
+                                                      double* partials, unsigned* counter,
+                                                      OcState* st, int* status) {
+  double acc[3] = {0.0, 0.0, 0.0};
+  double mx[1] = {0.0};
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += (long)gridDim.x * blockDim.x) {
+    const double r = rho[e];
+    const double a = oc_a(r, dcf[e], eta);
+    a_out[e] = a;
+    const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
+    acc[0] += lo;
+    acc[1] += (a > 0.0) ? hi : lo;  // volume once mu is large
+    acc[2] += a;
+    if (a > 0.0) mx[0] = fmax(mx[0], hi / a);
+  }
+  __shared__ double tot[4];
+  if (grid_reduce<3, 1>(acc, mx, partials, counter, tot)) {
+    if (threadIdx.x == 0) {
+      const double target = volfrac * (double)nc;
+      st->target = target;
+      st->sum_lo = tot[0];
+      st->sum_hi = tot[1];
+      st->sum_a = tot[2];
+      st->passes = 0;
+      st->infeasible = 0;
+      st->mu_lo = 0.0;
+      st->mu_hi = tot[3];
+      const double tol = 1e-13 * (double)nc;
+      if (target < tot[0] - tol || target > tot[1] + tol || !(tot[2] > 0.0)) {
+        st->infeasible = 1;
+        st->mu = (target < tot[0]) ? 0.0 : tot[3];
+        st->done = 1;
+        *status = TOPO_S_OC_INFEASIBLE;
+      } else {
+        double mu = target / tot[2];
+        if (!(mu < st->mu_hi)) mu = 0.5 * st->mu_hi;
+        st->mu = mu;
+        st->done = 0;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__ rho,
+                                                      const double* __restrict__ a_in, long nc,
+                                                      double move, double rho_min,
+                                                      double* partials, unsigned* counter,
+                                                      OcState* st) {
+  if (st->done) return;
+  const double mu = st->mu;
+  double acc[2] = {0.0, 0.0};
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += (long)gridDim.x * blockDim.x) {
+    const double r = rho[e];
+    const double a = a_in[e];
+    const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
+    const double v = a * mu;
+    acc[0] += fmax(lo, fmin(hi, v));
+    acc[1] += (v > lo && v < hi) ? a : 0.0;
+  }
+  double dummy[1] = {0.0};
+  __shared__ double tot[2];
+  if (grid_reduce<2, 0>(acc, dummy, partials, counter, tot)) {
+    if (threadIdx.x == 0) {
+      const double V = tot[0], S = tot[1], T = st->target;
+      st->V = V;
+      st->S = S;
+      st->passes += 1;
+      const double err = V - T;
+      const double tol = 1e-14 * (double)nc;
+      if (fabs(err) <= tol || st->passes >= 200) {
+        st->done = 1;
+        return;
+      }
+      if (err < 0.0) st->mu_lo = mu; else st->mu_hi = mu;
+      double next = 0.5 * (st->mu_lo + st->mu_hi);
+      if (S > 0.0) {
+        const double nw = mu - err / S;
+        if (nw > st->mu_lo && nw < st->mu_hi) next = nw;
+      }
+      if (!(next > st->mu_lo && next < st->mu_hi)) {
+        // the bracket cannot be split further in FP64: keep the last point
+        st->done = 1;
+        return;
+      }
+      st->mu = next;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict__ rho,
+                                                       const double* __restrict__ a_in,
+                                                       double* rho_new, long nc, double move,
+                                                       double rho_min, double eta,
+                                                       double* partials, unsigned* counter,
+                                                       OcState* st, double* scalars) {
+  const double mu = st->mu;
+  double acc[1] = {0.0};
+  double mx[1] = {0.0};
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += (long)gridDim.x * blockDim.x) {
+    const double r = rho[e];
+    const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
+    const double v = fmax(lo, fmin(hi, a_in[e] * mu));
+    rho_new[e] = v;
+    acc[0] += v;
+    mx[0] = fmax(mx[0], fabs(v - r));
+  }
+  __shared__ double tot[2];
+  if (grid_reduce<1, 1>(acc, mx, partials, counter, tot)) {
+    if (threadIdx.x == 0) {
+      st->vol = tot[0];
+      st->change = tot[1];
+      st->lam = (mu > 0.0) ? pow(mu, -1.0 / eta) : INFINITY;
+      if (scalars) {
+        scalars[0] = st->lam;
+        scalars[1] = tot[0];
+        scalars[2] = tot[1];
+      }
+    }
+  }
+}
+
+void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars) {
+  const long nc = c->g.nc;
+  long nb = (nc + 255) / 256;
+  if (nb > kRedBlocks) nb = kRedBlocks;
+  if (nb < 1) nb = 1;
+  const topo_problem& p = c->prob;
+  OcState* st = &c->scal->oc;
+  double* a = c->qsoa;
+  oc_init_kernel<<<(unsigned)nb, 256, 0, c->stream>>>(rho, dcf, a, nc, p.move, p.eta, p.rho_min,
+                                                      p.volfrac, c->partials,
+                                                      &c->scal->counters[CNT_OC_INIT], st,
+                                                      &c->scal->status);
+  const int batch = 6;
+  for (int b = 0; b < 40; ++b) {
+    for (int k = 0; k < batch; ++k)
+      oc_pass_kernel<<<(unsigned)nb, 256, 0, c->stream>>>(rho, a, nc, p.move, p.rho_min,
+                                                          c->partials,
+                                                          &c->scal->counters[CNT_OC_PASS], st);
+    (void)hipMemcpyAsync((void*)&c->pinned[2], &st->done, sizeof(int), hipMemcpyDeviceToHost,
+                         c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->pinned[2]) break;
+  }
+  oc_final_kernel<<<(unsigned)nb, 256, 0, c->stream>>>(rho, a, rho_new, nc, p.move, p.rho_min,
+                                                       p.eta, c->partials,
+                                                       &c->scal->counters[CNT_OC_FINAL], st,
+                                                       scalars);
+}
+
+}  // namespace topo

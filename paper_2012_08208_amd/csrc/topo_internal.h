@@ -1,0 +1,166 @@
+// Internal definitions of the gfx950 SIMP library: device state, workspace
+// layout and kernel launchers.  Element-level arithmetic follows the P1
+// Galerkin form of Sec. 3.1 (eq. fe_form) with the isotropic law of Sec. 2
+// (eq. str_energy) and the SIMP modulus of eq. simp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "topo.h"
+
+namespace topo {
+
+constexpr int kMaxRhs = 4;
+constexpr int kRedBlocks = 1024;   // fixed block count of grid-stride reductions
+constexpr int kMaxFilterTaps = 2048;
+constexpr int kMaxFilterClasses = 6;
+
+// Scalars that live in device memory (part of the workspace).
+struct PcgState {
+  double rz[kMaxRhs];
+  double rz_old[kMaxRhs];
+  double pq[kMaxRhs];
+  double alpha[kMaxRhs];
+  double beta[kMaxRhs];
+  double rr[kMaxRhs];
+  double ff[kMaxRhs];
+  double tol2[kMaxRhs];
+  int active[kMaxRhs];
+  int done;
+  int iters;
+  int breakdown;
+  int pad;
+};
+
+struct OcState {
+  double target;
+  double mu, mu_lo, mu_hi;
+  double V, S;
+  double sum_lo, sum_hi, sum_a;
+  double lam;
+  double vol;
+  double change;
+  int done;
+  int passes;
+  int infeasible;
+  int pad;
+};
+
+struct DevScalars {
+  PcgState pcg;
+  OcState oc;
+  double compliance;
+  double c_energy;
+  double c_paper;
+  double scratch[8];
+  int status;       // sticky device status
+  int pad;
+  unsigned counters[16];  // last-block-done counters, one per reduction site
+};
+
+enum CounterId {
+  CNT_APPLY_DOT = 0,
+  CNT_PCG_INIT = 1,
+  CNT_PCG_UPDATE = 2,
+  CNT_DOT = 3,
+  CNT_SENS = 4,
+  CNT_OC_INIT = 5,
+  CNT_OC_PASS = 6,
+  CNT_OC_FINAL = 7,
+  CNT_IR = 8,
+};
+
+// Filter stencil entry: neighbour cell offset (di, dj, dk) in unit cells,
+// neighbour class tb, weight w = rmin - |x_a - x_b| > 0.
+struct FilterTap {
+  int32_t di, dj, dk, tb;
+  double w;
+};
+
+struct Grid {
+  int dim;
+  int nx, ny, nz;      // cells per axis (nz = 1 in 2D for sizing convenience)
+  int64_t nn;          // nodes
+  int64_t nc;          // cells
+  int64_t nd;          // dofs per load case = dim * nn
+  int split;           // 2D split rule
+};
+
+struct Material {
+  double lam0, mu0;    // unit-modulus Lame constants of the element law
+  double vol;          // cell measure |T| (1/2 or 1/6)
+  double E0, Emin, penal;
+  int paper;
+};
+
+struct WsLayout {
+  size_t mask, f, E, E32, invd, invd32, r, p, q, z, wv, partials, scal, R, taps,
+      qsoa, dc, dcf, rho_new, rho_tmp, ir_x, ir_r32, ir_p32, ir_q32, ir_z32, ir_u32, total;
+};
+
+struct Ctx {
+  topo_problem prob;
+  Grid g;
+  Material m;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  WsLayout L;
+  // typed views into the workspace
+  uint8_t* mask;      // [nn] bit c set if component c fixed
+  double* f;          // [nrhs][dim][nn]
+  double* E;          // [nc]
+  float* E32;         // [nc] (mixed precision)
+  double* invd;       // [dim][nn]
+  float* invd32;      // [dim][nn]
+  double *r, *p, *q, *z, *wv;  // [nrhs][dim][nn]
+  double* partials;   // [kRedBlocks * 16]
+  DevScalars* scal;
+  double* R;          // [nc] filter row sums
+  FilterTap* taps;    // [classes][kMaxFilterTaps]
+  int ntaps[8];
+  int nclasses;
+  double* qsoa;       // [nc] filter input in class-major order
+  double *dc, *dcf, *rho_new, *rho_tmp;  // [nc]
+  // mixed-precision inner solve buffers
+  double* ir_x;       // [nrhs][dim][nn] fp64 correction accumulator
+  float *r32, *p32, *q32, *z32, *u32;
+  bool loads_set;
+  // host side
+  volatile int* pinned;   // pinned host flags
+  hipEvent_t ev_poll[2];
+  bool timing;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
+  size_t tev_used;
+  int64_t t_launches;
+  double t_ms;
+  int apply_kz;       // z-chunk (node planes) of the 3D apply
+};
+
+// ---- launchers (defined in the .hip files) ----
+void launch_simp_modulus(Ctx* c, const double* rho);
+void launch_apply(Ctx* c, const double* x, double* y, int nrhs, bool fuse_dot);
+void launch_apply_f32(Ctx* c, const float* x, float* y, int nrhs, bool fuse_dot);
+void launch_diagonal(Ctx* c, double* d, bool inverse);
+void launch_mask_copy(Ctx* c, const double* src, double* dst, int nrhs);
+void launch_fill(Ctx* c, double* dst, double v, int64_t n);
+void pcg_solve(Ctx* c, double* u, double* info);
+void launch_sensitivity(Ctx* c, const double* rho, const double* u, double* dc, double* compliance);
+void launch_filter(Ctx* c, const double* rho, const double* dc, double* dcf);
+void launch_filter_rowsums(Ctx* c);
+void build_filter_taps(Ctx* c);
+void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars);
+void launch_log_record(Ctx* c, double* rec, const double* info);
+int timing_begin(Ctx* c, hipEvent_t* e1);
+void timing_end(Ctx* c, int slot);
+
+}  // namespace topo
+
+#define TOPO_HIP(call)                                 \
+  do {                                                 \
+    hipError_t _e = (call);                            \
+    if (_e != hipSuccess) return TOPO_E_HIP;           \
+  } while (0)

@@ -1,0 +1,57 @@
+"""Host-only checks of the C ABI: the library loads, exports every entry point
+that include/topo.h declares, and sizes workspaces without touching a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "topo.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(topo_[a-z_]+)\s*\(", txt)))
+
+
+def _lib():
+    from paper_2012_08208_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libtopo.so not built (run __graft_entry__.build())")
+    return binding
+
+
+def test_header_declares_the_seven_path_calls():
+    names = _declared()
+    for n in ["topo_create", "topo_set_loads", "topo_solve", "topo_sensitivity", "topo_filter",
+              "topo_oc_update", "topo_iterate"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    b = _lib()
+    lib = ctypes.CDLL(b.LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(_declared()) <= set(b.EXPORTED)
+
+
+def test_workspace_size_and_validation():
+    b = _lib()
+    lib = b.load_library()
+    p = b.make_problem(3, (192, 96, 96), nrhs=4, volfrac=0.3, rmin=2.5)
+    n = ctypes.c_size_t(0)
+    assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    nd = 3 * 193 * 97 * 97
+    assert n.value > 4 * nd * 8 * 4          # loads + three CG vectors
+    assert n.value < 8 * 1024 ** 3          # modest on a 288 GB device
+    bad = b.make_problem(4, (2, 2, 2))
+    assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == -1
+    bad = b.make_problem(2, (8, 4), nrhs=5)
+    assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == -1
+    bad = b.make_problem(2, (8, 4), volfrac=0.0)
+    assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == -1
+    assert lib.topo_status_string(-7) == b"workspace too small"
