@@ -49,24 +49,47 @@ static Grid make_grid(const topo_problem* p) {
   return g;
 }
 
-static int pick_kz(const Grid& g) {
+int pick_kz(int dim, int nx, int ny, int nz) {
   const char* env = getenv("TOPO_APPLY_KZ");
   if (env) {
     int v = atoi(env);
     if (v >= 1 && v <= 1024) return v;
   }
-  if (g.dim == 2) return 1;
-  const long cols = (long)((g.nx + 15) / 15) * ((g.ny + 15) / 15);
-  long kz = (long)(g.nz + 1) * cols / 1024;
+  if (dim == 2) return 1;
+  const long cols = (long)((nx + 15) / 15) * ((ny + 15) / 15);
+  long kz = (long)(nz + 1) * cols / 1024;
   if (kz < 4) kz = 4;
   if (kz > 16) kz = 16;
   return (int)kz;
 }
 
-static long apply_blocks(const Grid& g, int kz) {
-  long b = (long)((g.nx + 15) / 15) * ((g.ny + 15) / 15);
-  if (g.dim == 3) b *= (g.nz + 1 + kz - 1) / kz;
-  return b;
+static int pick_kz(const Grid& g) { return pick_kz(g.dim, g.nx, g.ny, g.nz); }
+
+// Multigrid levels: halve (rounding up) every axis until the level has at
+// most 128 DOFs, the size the dense coarsest solve handles.
+struct LevelDims {
+  int nx, ny, nz;
+};
+
+static std::vector<LevelDims> gmg_plan(const Grid& g) {
+  std::vector<LevelDims> out;
+  LevelDims d{g.nx, g.ny, g.dim == 3 ? g.nz : 1};
+  out.push_back(d);
+  for (int l = 0; l < 24; ++l) {
+    const long nn = (long)(d.nx + 1) * (d.ny + 1) * (g.dim == 3 ? (d.nz + 1) : 1);
+    if (nn * g.dim <= 128) break;
+    LevelDims e{(d.nx + 1) / 2, (d.ny + 1) / 2, g.dim == 3 ? (d.nz + 1) / 2 : 1};
+    if (e.nx == d.nx && e.ny == d.ny && e.nz == d.nz) break;
+    d = e;
+    out.push_back(d);
+  }
+  return out;
+}
+
+static long apply_blocks(const Grid& g, int kz, int nrhs) {
+  long tiles = (long)((g.nx + 15) / 15) * ((g.ny + 15) / 15);
+  if (g.dim == 3) tiles *= (g.nz + 1 + kz - 1) / kz;
+  return 8L * ((tiles + 7) / 8) * nrhs;
 }
 
 static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
@@ -79,7 +102,7 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   };
   const size_t nr = (size_t)p->nrhs;
   const bool mixed = p->precision == TOPO_MIXED_FP32;
-  long nblk = apply_blocks(g, kz);
+  long nblk = apply_blocks(g, kz, p->nrhs);
   if (nblk < kRedBlocks) nblk = kRedBlocks;
   L.mask = take((size_t)g.nn);
   L.f = take(nr * g.nd * 8);
@@ -102,6 +125,39 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.rho_new = take((size_t)g.nc * 8);
   L.rho_tmp = take((size_t)g.nc * 8);
   L.ir_x = L.ir_r32 = L.ir_p32 = L.ir_q32 = L.ir_z32 = L.ir_u32 = 0;
+  L.gmg_scal = 0;
+  L.levels.clear();
+  if (p->precond == TOPO_PC_GMG) {
+    L.z = take(nr * g.nd * 8);
+    const std::vector<LevelDims> plan = gmg_plan(g);
+    L.gmg_scal = take(8 * 2 * (plan.size() + 1));
+    for (size_t l = 0; l < plan.size(); ++l) {
+      GmgLevel lv;
+      memset(&lv, 0, sizeof(lv));
+      const LevelDims& d = plan[l];
+      const long nn = (long)(d.nx + 1) * (d.ny + 1) * (g.dim == 3 ? (d.nz + 1) : 1);
+      const long nc = (long)d.nx * d.ny * (g.dim == 3 ? d.nz * 6 : 2);
+      const long nd = nn * g.dim;
+      const bool last = l + 1 == plan.size();
+      if (l > 0) {
+        lv.off_E = take((size_t)nc * 8);
+        lv.off_invd = take((size_t)nd * 8);
+        lv.off_b = take(nr * nd * 8);
+        lv.off_x = take(nr * nd * 8);
+        lv.off_mask = take((size_t)nn);
+      }
+      if (!last) {
+        lv.off_r = take(nr * nd * 8);
+        lv.off_d = take(nr * nd * 8);
+        lv.off_q = take(nr * nd * 8);
+        lv.off_pv = take((size_t)nd * 8);
+        lv.off_pw = take((size_t)nd * 8);
+      } else {
+        lv.off_A = take((size_t)nd * nd * 8);
+      }
+      L.levels.push_back(lv);
+    }
+  }
   L.total = o;
   return L;
 }
@@ -178,7 +234,6 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->r = (double*)(w + L.r);
   c->p = (double*)(w + L.p);
   c->q = (double*)(w + L.q);
-  c->z = nullptr;
   c->wv = nullptr;
   c->partials = (double*)(w + L.partials);
   c->scal = (DevScalars*)(w + L.scal);
@@ -189,6 +244,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->dcf = (double*)(w + L.dcf);
   c->rho_new = (double*)(w + L.rho_new);
   c->rho_tmp = (double*)(w + L.rho_tmp);
+  c->z = L.z ? (double*)(w + L.z) : nullptr;
   // material of the unit-modulus element law
   Material& m = c->m;
   const double nu = prob->nu;
@@ -212,8 +268,75 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   for (int comp = 0; comp < prob->dim; ++comp)
     for (int64_t n = 0; n < c->g.nn; ++n)
       if (fixed_mask[(size_t)comp * c->g.nn + n]) bits[n] |= (uint8_t)(1u << comp);
+  bool mask_ok = true;
+  std::vector<std::vector<uint8_t>> lmasks;
+  if (prob->precond == TOPO_PC_GMG) {
+    const std::vector<LevelDims> plan = gmg_plan(c->g);
+    lmasks.push_back(bits);
+    for (size_t l = 0; l < plan.size(); ++l) {
+      GmgLevel lv = L.levels[l];
+      const LevelDims& d = plan[l];
+      lv.op.dim = c->g.dim;
+      lv.op.nx = d.nx;
+      lv.op.ny = d.ny;
+      lv.op.nz = d.nz;
+      lv.op.nn = (int64_t)(d.nx + 1) * (d.ny + 1) * (c->g.dim == 3 ? (d.nz + 1) : 1);
+      lv.op.split_uniform = l == 0 ? (c->g.split == TOPO_SPLIT_UNIFORM) : 1;
+      lv.op.kz = l == 0 ? c->apply_kz : pick_kz(c->g.dim, d.nx, d.ny, d.nz);
+      lv.nc = (int64_t)d.nx * d.ny * (c->g.dim == 3 ? d.nz * 6 : 2);
+      double* gs = (double*)(w + L.gmg_scal);
+      lv.lmax = gs + 2 * l;
+      lv.pscale = gs + 2 * l + 1;
+      if (l == 0) {
+        lv.E = c->E;
+        lv.invd = c->invd;
+        lv.mask = c->mask;
+        lv.b = lv.x = nullptr;
+      } else {
+        lv.E = (double*)(w + lv.off_E);
+        lv.invd = (double*)(w + lv.off_invd);
+        lv.b = (double*)(w + lv.off_b);
+        lv.x = (double*)(w + lv.off_x);
+        lv.mask = (uint8_t*)(w + lv.off_mask);
+        // coarse mask: fixed when any fine node of the basis support is fixed
+        const LevelDims& f = plan[l - 1];
+        const std::vector<uint8_t>& fm = lmasks[l - 1];
+        std::vector<uint8_t> cm((size_t)lv.op.nn, 0);
+        const int dim = c->g.dim;
+        const int nzf = dim == 3 ? f.nz : 0, nzc = dim == 3 ? d.nz : 0;
+        for (int K = 0; K <= nzc; ++K)
+          for (int J = 0; J <= d.ny; ++J)
+            for (int I = 0; I <= d.nx; ++I) {
+              uint8_t m = 0;
+              for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                  for (int dx = -1; dx <= 1; ++dx) {
+                    if (dim == 2 && dz != 0) continue;
+                    // only the 2C +- d offsets with d in {0,1}^dim
+                    const bool pos = dx >= 0 && dy >= 0 && dz >= 0;
+                    const bool neg = dx <= 0 && dy <= 0 && dz <= 0;
+                    if (!pos && !neg) continue;
+                    const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
+                    if (fi < 0 || fj < 0 || fk < 0 || fi > f.nx || fj > f.ny || fk > nzf) continue;
+                    m |= fm[((size_t)fk * (f.ny + 1) + fj) * (f.nx + 1) + fi];
+                  }
+              cm[((size_t)K * (d.ny + 1) + J) * (d.nx + 1) + I] = m;
+            }
+        lmasks.push_back(cm);
+        mask_ok = mask_ok && hipMemcpy(lv.mask, cm.data(), cm.size(), hipMemcpyHostToDevice) == hipSuccess;
+      }
+      lv.op.mask = lv.mask;
+      lv.r = lv.off_r ? (double*)(w + lv.off_r) : nullptr;
+      lv.d = lv.off_d ? (double*)(w + lv.off_d) : nullptr;
+      lv.q = lv.off_q ? (double*)(w + lv.off_q) : nullptr;
+      lv.pv = lv.off_pv ? (double*)(w + lv.off_pv) : nullptr;
+      lv.pw = lv.off_pw ? (double*)(w + lv.off_pw) : nullptr;
+      lv.Ainv = lv.off_A ? (double*)(w + lv.off_A) : nullptr;
+      c->lv.push_back(lv);
+    }
+  }
   void* pin = nullptr;
-  if (hipHostMalloc(&pin, 64, hipHostMallocDefault) != hipSuccess) {
+  if (!mask_ok || hipHostMalloc(&pin, 64, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return TOPO_E_HIP;
   }

@@ -20,60 +20,101 @@ constexpr int TILE = 15;       // owned nodes per tile edge
 constexpr int PATCH = 17;      // staged node patch edge
 constexpr int PATCH2 = PATCH * PATCH;
 
+static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
 template <typename T>
 __device__ __forceinline__ T shift_down1(T v) {
   return __shfl_down(v, 1, 16);
 }
 
+// Block -> (tile, load case) map.  Work-groups are handed to the 8 XCDs
+// round-robin by linear id, so id % 8 selects the XCD.  Each XCD gets a
+// contiguous range of tiles (neighbouring tiles share halo nodes in the
+// same L2), and the nrhs blocks of one tile are consecutive on that XCD (they
+// read the same moduli while they are still in L2).
+struct TileMap {
+  int gx, gy, gz;     // tiles per axis
+  int per_xcd;        // tiles per XCD
+  int nrhs;
+};
+
+__device__ __forceinline__ bool map_block(const TileMap& tm, int& bx, int& by, int& bz, int& rhs) {
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int k = b >> 3;
+  rhs = k % tm.nrhs;
+  const int tl = k / tm.nrhs;
+  if (tl >= tm.per_xcd) return false;
+  const int tile = xcd * tm.per_xcd + tl;
+  const int ntiles = tm.gx * tm.gy * tm.gz;
+  if (tile >= ntiles) return false;
+  bx = tile % tm.gx;
+  by = (tile / tm.gx) % tm.gy;
+  bz = tile / (tm.gx * tm.gy);
+  return true;
+}
+
+__device__ __forceinline__ void dot_partials(double dot, int rhs, double* partials) {
+  double acc[kMaxRhs];
+#pragma unroll
+  for (int r = 0; r < kMaxRhs; ++r) acc[r] = (r == rhs) ? dot : 0.0;
+  const double none[1] = {0.0};
+  block_partials<kMaxRhs, 0>(acc, none, partials);
+}
+
 // -------------------------------------------------------------- 2D apply
-template <typename T, typename TE, int NR>
+template <typename T, typename TE>
 __global__ __launch_bounds__(256) void apply2d_kernel(const T* __restrict__ x, T* __restrict__ y,
-                                                      const TE* __restrict__ E,
-                                                      const uint8_t* __restrict__ mask, int nx,
-                                                      int ny, long nn, int split_uniform, T lam0,
-                                                      T mu0, double* partials, unsigned* counter,
-                                                      PcgState* st) {
-  __shared__ T xs[NR][2][PATCH2];
+                                                      const TE* __restrict__ E, OpDesc d,
+                                                      TileMap tm, T lam0, T mu0, double* partials,
+                                                      const int* stop) {
+  __shared__ T xs[2][PATCH2];
   __shared__ T ex[2][256];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  const int i0 = blockIdx.x * TILE, j0 = blockIdx.y * TILE;
-  if (st && st->done) return;
-  for (int idx = tid; idx < PATCH2; idx += 256) {
-    const int a = idx % PATCH, b = idx / PATCH;
-    const int gi = i0 - 1 + a, gj = j0 - 1 + b;
-    const bool ok = gi >= 0 && gi <= nx && gj >= 0 && gj <= ny;
-    const long n = (long)gj * (nx + 1) + gi;
-    const int m = ok ? mask[n] : 3;
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-        xs[r][c][idx] = ((m >> c) & 1) ? T(0) : x[((long)r * 2 + c) * nn + n];
+  if (stop && *stop) return;
+  int bx, by, bz, rhs;
+  const bool live = map_block(tm, bx, by, bz, rhs);
+  if (!live && !partials) return;
+  const int nx = d.nx, ny = d.ny;
+  const long nn = d.nn;
+  const int i0 = bx * TILE, j0 = by * TILE;
+  const T* xr = x + (long)rhs * 2 * nn;
+  double dot = 0.0;
+  if (live) {
+    for (int idx = tid; idx < PATCH2; idx += 256) {
+      const int a = idx % PATCH, b = idx / PATCH;
+      const int gi = i0 - 1 + a, gj = j0 - 1 + b;
+      const bool ok = gi >= 0 && gi <= nx && gj >= 0 && gj <= ny;
+      const long n = (long)gj * (nx + 1) + gi;
+      const int m = ok ? d.mask[n] : 3;
+      const T v0 = ok ? xr[n] : T(0);
+      const T v1 = ok ? xr[nn + n] : T(0);
+      xs[0][idx] = (m & 1) ? T(0) : v0;
+      xs[1][idx] = (m & 2) ? T(0) : v1;
+    }
   }
-  __syncthreads();
   const int hi = i0 - 1 + tx, hj = j0 - 1 + ty;
-  const bool cell_ok = hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+  const bool cell_ok = live && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
   T l0 = 0, m0 = 0, l1 = 0, m1 = 0;
   if (cell_ok) {
     const long e = 2 * ((long)hj * nx + hi);
     const T e0 = T(E[e]), e1 = T(E[e + 1]);
     l0 = lam0 * e0; m0 = mu0 * e0; l1 = lam0 * e1; m1 = mu0 * e1;
   }
-  const bool diag_a = split_uniform || ((hj & 1) == 0);
-  const int oi = i0 + tx, oj = j0 + ty;
-  const bool owner = tx < TILE && ty < TILE && oi <= nx && oj <= ny;
-  const long on = (long)oj * (nx + 1) + oi;
-  const int om = owner ? mask[on] : 3;
-  double dot[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
+  __syncthreads();
+  if (live) {
+    const bool diag_a = d.split_uniform || ((hj & 1) == 0);
+    const int oi = i0 + tx, oj = j0 + ty;
+    const bool owner = tx < TILE && ty < TILE && oi <= nx && oj <= ny;
+    const long on = (long)oj * (nx + 1) + oi;
+    const int om = owner ? d.mask[on] : 3;
     T u[4][2], f[4][2];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int li = (ty + (c >> 1)) * PATCH + tx + (c & 1);
-      u[c][0] = xs[r][0][li];
-      u[c][1] = xs[r][1][li];
+      u[c][0] = xs[0][li];
+      u[c][1] = xs[1][li];
       f[c][0] = 0; f[c][1] = 0;
     }
     square_force<T>(diag_a, u, l0, m0, l1, m1, f);
@@ -82,123 +123,117 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const T* __restrict__ x, T
     for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
       for (int c = 0; c < 2; ++c) X[cy][c] = f[1 + 2 * cy][c] + shift_down1(f[2 * cy][c]);
-    if (r > 0) __syncthreads();
     ex[0][tid] = X[0][0];
     ex[1][tid] = X[0][1];
     __syncthreads();
-    dot[r] = 0.0;
     if (owner) {
-      const int lc = (ty + 1) * PATCH + tx + 1;
+      T* yr = y + (long)rhs * 2 * nn;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         T v = X[1][c] + ex[c][tid + 16];
         if ((om >> c) & 1) v = 0;
-        y[((long)r * 2 + c) * nn + on] = v;
-        dot[r] += (double)v * (double)xs[r][c][lc];
+        yr[c * nn + on] = v;
+        dot += (double)v * (double)u[3][c];
       }
     }
   }
-  if (partials) {
-    double dummy[1] = {0.0};
-    __shared__ double tot[NR];
-    if (grid_reduce<NR, 0>(dot, dummy, partials, counter, tot)) {
-      if (tid == 0) {
-        for (int r = 0; r < NR; ++r) {
-          st->pq[r] = tot[r];
-          if (st->active[r]) {
-            if (!(tot[r] > 0.0)) { st->breakdown = 1; st->alpha[r] = 0.0; }
-            else st->alpha[r] = st->rz[r] / tot[r];
-          } else {
-            st->alpha[r] = 0.0;
-          }
-        }
-      }
-    }
-  }
+  if (partials) dot_partials(dot, live ? rhs : 0, partials);
 }
 
 // -------------------------------------------------------------- 3D apply
-template <typename T, typename TE, int NR>
+// One block: one tile of 15 x 15 node columns, one z-chunk, one load case.
+// Per cube layer: the next node plane is committed from registers to LDS,
+// the plane after it is fetched from memory while the layer is computed,
+// and the cube forces are combined into owned nodes (2 barriers per layer).
+template <typename T, typename TE>
 __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T* __restrict__ y,
-                                                      const TE* __restrict__ E,
-                                                      const uint8_t* __restrict__ mask, int nx,
-                                                      int ny, int nz, long nn, int kz, T lam0,
-                                                      T mu0, double* partials, unsigned* counter,
-                                                      PcgState* st) {
-  __shared__ T xs[2][NR][3][PATCH2];
-  __shared__ T ex[6][256];
+                                                      const TE* __restrict__ E, OpDesc d,
+                                                      TileMap tm, T lam0, T mu0, double* partials,
+                                                      const int* stop) {
+  __shared__ T xs[2][3][PATCH2];
+  __shared__ T ex[2][6][256];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  const int i0 = blockIdx.x * TILE, j0 = blockIdx.y * TILE;
-  if (st && st->done) return;
-  const int k0 = blockIdx.z * kz;
-  const int k1 = min(k0 + kz, nz + 1);
-  const long plane = (long)(nx + 1) * (ny + 1);
+  if (stop && *stop) return;
+  int bx, by, bz, rhs;
+  const bool live = map_block(tm, bx, by, bz, rhs);
+  if (!live && !partials) return;
+  double dot = 0.0;
+  if (live) {
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const long nn = d.nn;
+    const int i0 = bx * TILE, j0 = by * TILE;
+    const int k0 = bz * d.kz;
+    const int k1 = min(k0 + d.kz, nz + 1);
+    const long plane = (long)(nx + 1) * (ny + 1);
+    const T* xr = x + (long)rhs * 3 * nn;
+    T* yr = y + (long)rhs * 3 * nn;
 
-  auto load_plane = [&](int kk) {
-    const int s = kk & 1;
-    for (int idx = tid; idx < PATCH2; idx += 256) {
-      const int a = idx % PATCH, b = idx / PATCH;
-      const int gi = i0 - 1 + a, gj = j0 - 1 + b;
-      const bool ok = gi >= 0 && gi <= nx && gj >= 0 && gj <= ny && kk >= 0 && kk <= nz;
-      const long n = (long)kk * plane + (long)gj * (nx + 1) + gi;
-      const int m = ok ? mask[n] : 7;
+    // each thread stages node idx = tid and idx = tid + 256 (< 289) of a plane
+    T pf[2][3];
+    int pm[2];
+    auto fetch = [&](int kk) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
+      for (int q = 0; q < 2; ++q) {
+        const int idx = tid + 256 * q;
+        const int a = idx % PATCH, b = idx / PATCH;
+        const int gi = i0 - 1 + a, gj = j0 - 1 + b;
+        const bool ok = idx < PATCH2 && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny && kk >= 0 &&
+                        kk <= nz;
+        const long n = (long)kk * plane + (long)gj * (nx + 1) + gi;
+        pm[q] = ok ? d.mask[n] : 7;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          xs[s][r][c][idx] = ((m >> c) & 1) ? T(0) : x[((long)r * 3 + c) * nn + n];
-    }
-  };
-
-  const int hi = i0 - 1 + tx, hj = j0 - 1 + ty;
-  const bool col_ok = hi >= 0 && hi < nx && hj >= 0 && hj < ny;
-  const int oi = i0 + tx, oj = j0 + ty;
-  const bool owner = tx < TILE && ty < TILE && oi <= nx && oj <= ny;
-  T carry[NR][3];
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) carry[r][c] = 0;
-  double dot[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) dot[r] = 0.0;
-
-  load_plane(k0 - 1);
-  for (int kh = k0 - 1; kh < k1; ++kh) {
-    // the slot being refilled held plane kh - 1, read until the end of the
-    // previous step
-    if (kh > k0 - 1) __syncthreads();
-    load_plane(kh + 1);
-    __syncthreads();
-    const bool cell_ok = col_ok && kh >= 0 && kh < nz;
-    T lam[6], mu[6];
-    if (cell_ok) {
-      const long h = ((long)kh * ny + hj) * nx + hi;
-#pragma unroll
-      for (int t = 0; t < 6; ++t) {
-        const T e = T(E[6 * h + t]);
-        lam[t] = lam0 * e;
-        mu[t] = mu0 * e;
+        for (int c = 0; c < 3; ++c) pf[q][c] = ok ? xr[c * nn + n] : T(0);
       }
-    } else {
+    };
+    auto commit = [&](int kk) {
+      const int s = kk & 1;
 #pragma unroll
-      for (int t = 0; t < 6; ++t) { lam[t] = 0; mu[t] = 0; }
-    }
-    const int sb = kh & 1, st_ = (kh + 1) & 1;
-    const bool store = owner && kh >= k0 && kh <= nz;
-    const long on = (long)kh * plane + (long)oj * (nx + 1) + oi;
-    const int om = store ? mask[on] : 7;
+      for (int q = 0; q < 2; ++q) {
+        const int idx = tid + 256 * q;
+        if (idx < PATCH2) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
+          for (int c = 0; c < 3; ++c) xs[s][c][idx] = ((pm[q] >> c) & 1) ? T(0) : pf[q][c];
+        }
+      }
+    };
+
+    const int hi = i0 - 1 + tx, hj = j0 - 1 + ty;
+    const bool col_ok = hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+    const int oi = i0 + tx, oj = j0 + ty;
+    const bool owner = tx < TILE && ty < TILE && oi <= nx && oj <= ny;
+    T carry[3] = {0, 0, 0};
+
+    fetch(k0 - 1);
+    commit(k0 - 1);
+    fetch(k0);
+    for (int kh = k0 - 1; kh < k1; ++kh) {
+      // moduli of this cube layer (independent of LDS, issued early)
+      const bool cell_ok = col_ok && kh >= 0 && kh < nz;
+      T ev[6];
+      if (cell_ok) {
+        const long h = ((long)kh * ny + hj) * nx + hi;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) ev[t] = T(E[6 * h + t]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 6; ++t) ev[t] = T(0);
+      }
+      commit(kh + 1);
+      __syncthreads();
+      if (kh + 2 <= k1) fetch(kh + 2);
+      T lam[6], mu[6];
+#pragma unroll
+      for (int t = 0; t < 6; ++t) { lam[t] = lam0 * ev[t]; mu[t] = mu0 * ev[t]; }
+      const int sb = kh & 1, stp = (kh + 1) & 1;
       T u[8][3], f[8][3];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int li = (ty + ((c >> 1) & 1)) * PATCH + tx + (c & 1);
-        const int s = (c >> 2) ? st_ : sb;
+        const int s = (c >> 2) ? stp : sb;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          u[c][a] = xs[s][r][a][li];
+          u[c][a] = xs[s][a][li];
           f[c][a] = 0;
         }
       }
@@ -211,44 +246,30 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
 #pragma unroll
           for (int a = 0; a < 3; ++a)
             X[cy][cz][a] = f[1 + 2 * cy + 4 * cz][a] + shift_down1(f[2 * cy + 4 * cz][a]);
-      __syncthreads();
+      const int eb = kh & 1;
 #pragma unroll
       for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) ex[cz * 3 + a][tid] = X[0][cz][a];
+        for (int a = 0; a < 3; ++a) ex[eb][cz * 3 + a][tid] = X[0][cz][a];
       __syncthreads();
       if (owner) {
-        const int lc = (ty + 1) * PATCH + tx + 1;
+        const bool store = kh >= k0;
+        const long on = (long)kh * plane + (long)oj * (nx + 1) + oi;
+        const int om = store ? d.mask[on] : 7;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          T yb = carry[r][a] + X[1][0][a] + ex[a][tid + 16];
-          carry[r][a] = X[1][1][a] + ex[3 + a][tid + 16];
+          T yb = carry[a] + X[1][0][a] + ex[eb][a][tid + 16];
+          carry[a] = X[1][1][a] + ex[eb][3 + a][tid + 16];
           if (store) {
             if ((om >> a) & 1) yb = 0;
-            y[((long)r * 3 + a) * nn + on] = yb;
-            dot[r] += (double)yb * (double)xs[sb][r][a][lc];
+            yr[a * nn + on] = yb;
+            dot += (double)yb * (double)u[3][a];
           }
         }
       }
     }
   }
-  if (partials) {
-    double dummy[1] = {0.0};
-    __shared__ double tot[NR];
-    if (grid_reduce<NR, 0>(dot, dummy, partials, counter, tot)) {
-      if (tid == 0) {
-        for (int r = 0; r < NR; ++r) {
-          st->pq[r] = tot[r];
-          if (st->active[r]) {
-            if (!(tot[r] > 0.0)) { st->breakdown = 1; st->alpha[r] = 0.0; }
-            else st->alpha[r] = st->rz[r] / tot[r];
-          } else {
-            st->alpha[r] = 0.0;
-          }
-        }
-      }
-    }
-  }
+  if (partials) dot_partials(dot, live ? rhs : 0, partials);
 }
 
 // ------------------------------------------------------------- diagonal
@@ -261,9 +282,12 @@ __device__ __forceinline__ void diag_add(double (&d)[3], int dim, const int* g, 
   for (int c = 0; c < dim; ++c) d[c] += lam * g[c] * g[c] + mu * (g[c] * g[c] + gg);
 }
 
-__global__ void diag2d_kernel(double* d, const double* E, const uint8_t* mask, int nx, int ny,
-                              long nn, int split_uniform, double lam0, double mu0, double vol,
-                              int inverse) {
+__global__ void diag2d_kernel(double* d, const double* E, OpDesc od, double lam0, double mu0,
+                              double vol, int inverse) {
+  const int nx = od.nx, ny = od.ny;
+  const long nn = od.nn;
+  const int split_uniform = od.split_uniform;
+  const uint8_t* mask = od.mask;
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int i = (int)(n % (nx + 1)), j = (int)(n / (nx + 1));
@@ -296,8 +320,11 @@ __global__ void diag2d_kernel(double* d, const double* E, const uint8_t* mask, i
   }
 }
 
-__global__ void diag3d_kernel(double* d, const double* E, const uint8_t* mask, int nx, int ny,
-                              int nz, long nn, double lam0, double mu0, double vol, int inverse) {
+__global__ void diag3d_kernel(double* d, const double* E, OpDesc od, double lam0, double mu0,
+                              double vol, int inverse) {
+  const int nx = od.nx, ny = od.ny, nz = od.nz;
+  const long nn = od.nn;
+  const uint8_t* mask = od.mask;
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int i = (int)(n % (nx + 1));
@@ -362,7 +389,6 @@ __global__ void fill_kernel(double* dst, double v, long n) {
 }
 
 // ------------------------------------------------------------ launchers
-static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 void launch_simp_modulus(Ctx* c, const double* rho) {
   simp_modulus_kernel<<<cdiv(c->g.nc, 256), 256, 0, c->stream>>>(
@@ -370,49 +396,84 @@ void launch_simp_modulus(Ctx* c, const double* rho) {
       c->m.Emin, c->m.penal, c->m.paper);
 }
 
+static TileMap make_tilemap(const OpDesc& d, int nrhs) {
+  TileMap tm;
+  tm.gx = (int)cdiv(d.nx + 1, TILE);
+  tm.gy = (int)cdiv(d.ny + 1, TILE);
+  tm.gz = d.dim == 3 ? (int)cdiv(d.nz + 1, d.kz) : 1;
+  const long ntiles = (long)tm.gx * tm.gy * tm.gz;
+  tm.per_xcd = (int)((ntiles + 7) / 8);
+  tm.nrhs = nrhs;
+  return tm;
+}
+
+long apply_grid_blocks(const OpDesc& d, int nrhs) {
+  TileMap tm = make_tilemap(d, nrhs);
+  return 8L * tm.per_xcd * nrhs;
+}
+
+OpDesc fine_op(const Ctx* c) {
+  OpDesc d;
+  d.dim = c->g.dim;
+  d.nx = c->g.nx;
+  d.ny = c->g.ny;
+  d.nz = c->g.dim == 3 ? c->g.nz : 1;
+  d.nn = c->g.nn;
+  d.split_uniform = c->g.split == TOPO_SPLIT_UNIFORM;
+  d.mask = c->mask;
+  d.kz = c->apply_kz;
+  return d;
+}
+
 template <typename T, typename TE>
-static void apply_dispatch(Ctx* c, const T* x, T* y, const TE* E, int nrhs, bool fuse_dot) {
-  const Grid& g = c->g;
+static void apply_dispatch(Ctx* c, const OpDesc& d, const TE* E, const T* x, T* y, int nrhs,
+                           bool fuse_dot, const int* stop) {
   double* part = fuse_dot ? c->partials : nullptr;
-  unsigned* cnt = &c->scal->counters[CNT_APPLY_DOT];
-  PcgState* st = fuse_dot ? &c->scal->pcg : nullptr;
+  const int* st = stop;
   const T lam = T(c->m.lam0 * c->m.vol), mu = T(c->m.mu0 * c->m.vol);
-  if (g.dim == 2) {
-    dim3 grid(cdiv(g.nx + 1, TILE), cdiv(g.ny + 1, TILE));
-    const int su = g.split == TOPO_SPLIT_UNIFORM;
-#define A2(NR) apply2d_kernel<T, TE, NR><<<grid, 256, 0, c->stream>>>(x, y, E, c->mask, g.nx, g.ny, g.nn, su, lam, mu, part, cnt, st)
-    switch (nrhs) { case 1: A2(1); break; case 2: A2(2); break; case 3: A2(3); break; default: A2(4); }
-#undef A2
-  } else {
-    const int kz = c->apply_kz;
-    dim3 grid(cdiv(g.nx + 1, TILE), cdiv(g.ny + 1, TILE), cdiv(g.nz + 1, kz));
-#define A3(NR) apply3d_kernel<T, TE, NR><<<grid, 256, 0, c->stream>>>(x, y, E, c->mask, g.nx, g.ny, g.nz, g.nn, kz, lam, mu, part, cnt, st)
-    switch (nrhs) { case 1: A3(1); break; case 2: A3(2); break; case 3: A3(3); break; default: A3(4); }
-#undef A3
-  }
+  const TileMap tm = make_tilemap(d, nrhs);
+  const unsigned blocks = (unsigned)(8L * tm.per_xcd * nrhs);
+  if (d.dim == 2)
+    apply2d_kernel<T, TE><<<blocks, 256, 0, c->stream>>>(x, y, E, d, tm, lam, mu, part, st);
+  else
+    apply3d_kernel<T, TE><<<blocks, 256, 0, c->stream>>>(x, y, E, d, tm, lam, mu, part, st);
+}
+
+void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, double* y,
+                     int nrhs, bool fuse_dot, bool timed, const int* stop) {
+  int slot = (timed && c->timing) ? timing_begin(c, nullptr) : -1;
+  apply_dispatch<double, double>(c, d, E, x, y, nrhs, fuse_dot, stop);
+  if (slot >= 0) timing_end(c, slot);
+}
+
+void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
+                         int nrhs, bool timed, const int* stop) {
+  int slot = (timed && c->timing) ? timing_begin(c, nullptr) : -1;
+  apply_dispatch<float, float>(c, d, E, x, y, nrhs, false, stop);
+  if (slot >= 0) timing_end(c, slot);
 }
 
 void launch_apply(Ctx* c, const double* x, double* y, int nrhs, bool fuse_dot) {
-  int slot = c->timing ? timing_begin(c, nullptr) : -1;
-  apply_dispatch<double, double>(c, x, y, c->E, nrhs, fuse_dot);
-  if (slot >= 0) timing_end(c, slot);
+  launch_apply_op(c, fine_op(c), c->E, x, y, nrhs, fuse_dot, true,
+                  fuse_dot ? &c->scal->pcg.done : nullptr);
 }
 
 void launch_apply_f32(Ctx* c, const float* x, float* y, int nrhs, bool fuse_dot) {
-  int slot = c->timing ? timing_begin(c, nullptr) : -1;
-  apply_dispatch<float, float>(c, x, y, c->E32, nrhs, fuse_dot);
-  if (slot >= 0) timing_end(c, slot);
+  (void)fuse_dot;
+  launch_apply_op_f32(c, fine_op(c), c->E32, x, y, nrhs, true, nullptr);
+}
+
+void launch_diagonal_op(Ctx* c, const OpDesc& od, const double* E, double* d, bool inverse) {
+  if (od.dim == 2)
+    diag2d_kernel<<<cdiv(od.nn, 256), 256, 0, c->stream>>>(d, E, od, c->m.lam0, c->m.mu0, c->m.vol,
+                                                          inverse);
+  else
+    diag3d_kernel<<<cdiv(od.nn, 256), 256, 0, c->stream>>>(d, E, od, c->m.lam0, c->m.mu0, c->m.vol,
+                                                          inverse);
 }
 
 void launch_diagonal(Ctx* c, double* d, bool inverse) {
-  const Grid& g = c->g;
-  if (g.dim == 2)
-    diag2d_kernel<<<cdiv(g.nn, 256), 256, 0, c->stream>>>(
-        d, c->E, c->mask, g.nx, g.ny, g.nn, g.split == TOPO_SPLIT_UNIFORM, c->m.lam0, c->m.mu0,
-        c->m.vol, inverse);
-  else
-    diag3d_kernel<<<cdiv(g.nn, 256), 256, 0, c->stream>>>(
-        d, c->E, c->mask, g.nx, g.ny, g.nz, g.nn, c->m.lam0, c->m.mu0, c->m.vol, inverse);
+  launch_diagonal_op(c, fine_op(c), c->E, d, inverse);
 }
 
 void launch_mask_copy(Ctx* c, const double* src, double* dst, int nrhs) {

@@ -1,10 +1,18 @@
-// Device helpers shared by the kernels: deterministic block reductions and
-// the single-pass "last block finalises" grid reduction.
+// Device helpers shared by the kernels: deterministic two-stage reductions.
+//
+// Stage 1 (inside a wide kernel): every block reduces its values in a fixed
+// order and writes them to partials[linear block id * 16 + k].
+// Stage 2 (a one-block "finalise" kernel launched right after): the block
+// sums the partials in block order and applies the scalar update.  Kernel
+// boundaries make the partials visible across XCDs, so no device-scope
+// fence is needed inside the wide kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace topo {
+
+constexpr int kPartStride = 16;
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -18,97 +26,69 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// Sums NV values over the block in a fixed order; result valid in thread 0
-// (and returned via the shared array red_out to every thread after the
-// barrier).  blockDim.x must be a multiple of 64 and at most 1024.
-template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double (&red_out)[NV]) {
-  __shared__ double wsum[16][NV];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = wave_sum(v[k]);
-    if (lane == 0) wsum[wid][k] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += wsum[w][threadIdx.x];
-    red_out[threadIdx.x] = s;
-  }
-  __syncthreads();
+__device__ inline size_t linear_block_id() {
+  return blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
 }
 
-// Writes this block's NV partial sums (and NM partial maxima) to
-// partials[linear block id * 16 + k], then the last block to arrive sums all blocks in
-// block order and leaves the totals in tot[] (shared).  Returns true in the
-// last block only.  Deterministic: the summation order is fixed.
+// Stage 1: NV sums followed by NM maxima (maxima of non-negative values).
+// blockDim.x must be a multiple of 64 and at most 1024.
 template <int NV, int NM = 0>
-__device__ inline bool grid_reduce(double (&v)[NV], double (&vm)[NM > 0 ? NM : 1], double* partials,
-                                   unsigned* counter, double (&tot)[NV + (NM > 0 ? NM : 0)]) {
-  __shared__ double bsum[NV + (NM > 0 ? NM : 0)];
-  __shared__ double wtmp[16][NV + (NM > 0 ? NM : 0)];
-  __shared__ int am_last;
+__device__ inline void block_partials(const double (&v)[NV], const double (&vm)[NM > 0 ? NM : 1],
+                                      double* partials) {
+  constexpr int NT = NV + NM;
+  __shared__ double wtmp[16][NT];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  constexpr int NT = NV + (NM > 0 ? NM : 0);
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double s = wave_sum(v[k]);
+    const double s = wave_sum(v[k]);
     if (lane == 0) wtmp[wid][k] = s;
   }
 #pragma unroll
   for (int k = 0; k < NM; ++k) {
-    double s = wave_max(vm[k]);
+    const double s = wave_max(vm[k]);
     if (lane == 0) wtmp[wid][NV + k] = s;
   }
   __syncthreads();
   if (threadIdx.x < NT) {
     const int k = threadIdx.x;
-    double s = (k < NV) ? 0.0 : -1.0;
+    double s = 0.0;
     for (int w = 0; w < nw; ++w) s = (k < NV) ? s + wtmp[w][k] : fmax(s, wtmp[w][k]);
-    bsum[k] = s;
-    const size_t bid = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
-    partials[bid * 16 + k] = s;
+    partials[linear_block_id() * kPartStride + k] = s;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned nb = gridDim.x * gridDim.y * gridDim.z;
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (prev == nb - 1);
-  }
-  __syncthreads();
-  if (!am_last) return false;
-  __threadfence();
-  const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
-  // per-thread strided partial sums in block order, then fixed-tree combine
+}
+
+// Stage 2, called by every thread of a single block: totals of nb blocks'
+// partials in a fixed order (thread-strided over blocks, then a fixed tree).
+template <int NV, int NM = 0>
+__device__ inline void reduce_partials(const double* partials, long nb, double (&tot)[NV + NM]) {
+  constexpr int NT = NV + NM;
+  __shared__ double wtmp[16][NT];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
   double acc[NT];
 #pragma unroll
-  for (int k = 0; k < NT; ++k) acc[k] = (k < NV) ? 0.0 : -1.0;
-  for (unsigned b = threadIdx.x; b < nb; b += blockDim.x) {
+  for (int k = 0; k < NT; ++k) acc[k] = 0.0;
+  for (long b = threadIdx.x; b < nb; b += blockDim.x) {
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
-      double x = __builtin_nontemporal_load(&partials[(size_t)b * 16 + k]);
+      const double x = partials[b * kPartStride + k];
       acc[k] = (k < NV) ? acc[k] + x : fmax(acc[k], x);
     }
   }
 #pragma unroll
   for (int k = 0; k < NT; ++k) {
-    double s = (k < NV) ? wave_sum(acc[k]) : wave_max(acc[k]);
+    const double s = (k < NV) ? wave_sum(acc[k]) : wave_max(acc[k]);
     if (lane == 0) wtmp[wid][k] = s;
   }
   __syncthreads();
   if (threadIdx.x < NT) {
     const int k = threadIdx.x;
-    double s = (k < NV) ? 0.0 : -1.0;
+    double s = 0.0;
     for (int w = 0; w < nw; ++w) s = (k < NV) ? s + wtmp[w][k] : fmax(s, wtmp[w][k]);
     tot[k] = s;
   }
-  if (threadIdx.x == 0) *counter = 0u;
   __syncthreads();
-  return true;
 }
 
 }  // namespace topo

@@ -1,0 +1,476 @@
+// Geometric multigrid V-cycle used as the CG preconditioner.
+//
+// Hierarchy: level l+1 has ceil(n_l / 2) cells per axis and cell size 2^(l+1).
+// In 3D every Kuhn tetrahedron of a coarse cube is exactly the union of 8
+// Kuhn tetrahedra of the fine grid (Freudenthal refinement), and in 2D the
+// same holds for diagonal-A triangles.  The coarse P1 space is therefore
+// nested in the fine one, prolongation is linear interpolation on the coarse
+// simplices, fine(x) = coarse(x/2) at even nodes and the mean of
+// coarse(floor(x/2)) and coarse(ceil(x/2)) otherwise, restriction is its
+// transpose, and the Galerkin coarse operator P^T K P is the coarse P1
+// operator with each coarse modulus the mean of its 8 (2D: 4) children's
+// moduli -- fine cells outside an odd-sized grid count as void.  The coarse
+// levels re-use the fine-level apply kernels.  A coarse DOF is fixed when
+// any fine DOF of the same component in the support of its basis function
+// is fixed (this keeps every level non-singular).
+//
+// Smoother: Chebyshev polynomial of degree K in D^-1 K on
+// [0.09 lmax, lmax], lmax from a Rayleigh-quotient power iteration with a
+// safety factor; the same polynomial is used before and after the coarse
+// correction, so the V-cycle is a symmetric positive definite operator.
+// Coarsest level (<= 128 DOFs): dense matrix assembled per solve and
+// inverted by Gauss-Jordan elimination in one work-group.
+#include <math.h>
+
+#include "common.h"
+#include "element.h"
+#include "topo_internal.h"
+
+namespace topo {
+
+constexpr int kChebDegree = 2;
+constexpr int kPowerIters = 12;
+constexpr double kPowerSafety = 1.2;
+constexpr double kChebLowRatio = 0.09;
+
+static inline unsigned cdivu(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// ------------------------------------------------------ coarse moduli
+__global__ void restrict_E3_kernel(double* Ec, const double* __restrict__ Ef, int nxf, int nyf,
+                                   int nzf, int nxc, int nyc, int nzc) {
+  const long H = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nh = (long)nxc * nyc * nzc;
+  if (H >= nh) return;
+  const int I = (int)(H % nxc), J = (int)((H / nxc) % nyc), K = (int)(H / ((long)nxc * nyc));
+  const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
+        if (fi >= nxf || fj >= nyf || fk >= nzf) continue;
+        const long hf = ((long)fk * nyf + fj) * nxf + fi;
+        const int dlt[3] = {dx, dy, dz};
+        for (int s = 0; s < 6; ++s) {
+          // centroid of the fine tetrahedron in coarse-cube units of 1/8
+          int q[3];
+          q[perm[s][0]] = 3;
+          q[perm[s][1]] = 2;
+          q[perm[s][2]] = 1;
+          for (int a = 0; a < 3; ++a) q[a] += 4 * dlt[a];
+          int p0 = 0;
+          if (q[1] > q[p0]) p0 = 1;
+          if (q[2] > q[p0]) p0 = 2;
+          int p2 = 0;
+          if (q[1] < q[p2]) p2 = 1;
+          if (q[2] < q[p2]) p2 = 2;
+          const int p1 = 3 - p0 - p2;
+          const int t = 2 * p0 + (p1 > p2 ? 1 : 0);
+          acc[t] += Ef[6 * hf + s];
+        }
+      }
+  for (int t = 0; t < 6; ++t) Ec[6 * H + t] = acc[t] * 0.125;
+}
+
+__global__ void restrict_E2_kernel(double* Ec, const double* __restrict__ Ef, int nxf, int nyf,
+                                   int uniform_f, int nxc, int nyc) {
+  const long S = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (S >= (long)nxc * nyc) return;
+  const int I = (int)(S % nxc), J = (int)(S / nxc);
+  double acc[2] = {0, 0};
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      const int fi = 2 * I + dx, fj = 2 * J + dy;
+      if (fi >= nxf || fj >= nyf) continue;
+      const bool a = uniform_f || ((fj & 1) == 0);
+      // triangle centroids x3: A: (2,1), (1,2); B: (1,1), (2,2)
+      const int cx[2] = {a ? 2 : 1, a ? 1 : 2};
+      const int cy[2] = {a ? 1 : 1, a ? 2 : 2};
+      for (int t = 0; t < 2; ++t) {
+        const double e = Ef[2 * ((long)fj * nxf + fi) + t];
+        const int qx = 3 * dx + cx[t], qy = 3 * dy + cy[t];
+        if (qx > qy) acc[0] += e;
+        else if (qx < qy) acc[1] += e;
+        else { acc[0] += 0.5 * e; acc[1] += 0.5 * e; }
+      }
+    }
+  Ec[2 * S] = acc[0] * 0.25;
+  Ec[2 * S + 1] = acc[1] * 0.25;
+}
+
+// ----------------------------------------------- transfer operators
+// b_c = R (b_f - q_f): restriction of the fine residual
+__global__ void restrict_kernel(double* bc, const double* __restrict__ bf,
+                                const double* __restrict__ qf, OpDesc fo, OpDesc co, int nrhs,
+                                const int* stop) {
+  if (stop && *stop) return;
+  const long C = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (C >= co.nn) return;
+  const int dim = co.dim;
+  const int nxc1 = co.nx + 1, nyc1 = co.ny + 1;
+  const int I = (int)(C % nxc1), J = (int)((C / nxc1) % nyc1), K = dim == 3 ? (int)(C / ((long)nxc1 * nyc1)) : 0;
+  const int nxf1 = fo.nx + 1, nyf1 = fo.ny + 1;
+  const int nzf = dim == 3 ? fo.nz : 0;
+  const int cm = co.mask[C];
+  const int ndir = dim == 3 ? 7 : 3;
+  for (int r = 0; r < nrhs; ++r)
+    for (int c = 0; c < dim; ++c) {
+      const long off = ((long)r * dim + c) * fo.nn;
+      double acc = 0.0;
+      {
+        const int fi = 2 * I, fj = 2 * J, fk = 2 * K;
+        if (fi <= fo.nx && fj <= fo.ny && fk <= nzf) {
+          const long n = ((long)fk * nyf1 + fj) * nxf1 + fi;
+          acc += bf[off + n] - qf[off + n];
+        }
+      }
+      for (int dd = 1; dd <= ndir; ++dd) {
+        const int dx = dd & 1, dy = (dd >> 1) & 1, dz = (dd >> 2) & 1;
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+          const int fi = 2 * I + sgn * dx, fj = 2 * J + sgn * dy, fk = 2 * K + sgn * dz;
+          if (fi < 0 || fj < 0 || fk < 0 || fi > fo.nx || fj > fo.ny || fk > nzf) continue;
+          const long n = ((long)fk * nyf1 + fj) * nxf1 + fi;
+          acc += 0.5 * (bf[off + n] - qf[off + n]);
+        }
+      }
+      bc[((long)r * dim + c) * co.nn + C] = ((cm >> c) & 1) ? 0.0 : acc;
+    }
+}
+
+// x_f += P x_c (fixed fine DOFs untouched)
+__global__ void prolong_add_kernel(double* xf, const double* __restrict__ xc, OpDesc fo, OpDesc co,
+                                   int nrhs, const int* stop) {
+  if (stop && *stop) return;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= fo.nn) return;
+  const int dim = fo.dim;
+  const int nxf1 = fo.nx + 1, nyf1 = fo.ny + 1;
+  const int i = (int)(n % nxf1), j = (int)((n / nxf1) % nyf1), k = dim == 3 ? (int)(n / ((long)nxf1 * nyf1)) : 0;
+  const int nxc1 = co.nx + 1, nyc1 = co.ny + 1;
+  const long c0 = ((long)(k >> 1) * nyc1 + (j >> 1)) * nxc1 + (i >> 1);
+  const long c1 = ((long)((k + 1) >> 1) * nyc1 + ((j + 1) >> 1)) * nxc1 + ((i + 1) >> 1);
+  const bool even = ((i | j | k) & 1) == 0;
+  const int fm = fo.mask[n];
+  for (int r = 0; r < nrhs; ++r)
+    for (int c = 0; c < dim; ++c) {
+      if ((fm >> c) & 1) continue;
+      const double* xcr = xc + ((long)r * dim + c) * co.nn;
+      const double e = even ? xcr[c0] : 0.5 * (xcr[c0] + xcr[c1]);
+      xf[((long)r * dim + c) * fo.nn + n] += e;
+    }
+}
+
+// ------------------------------------------------------- smoother
+struct ChebCoef {
+  double r_cur, r_prev;  // rho_k, rho_(k-1) of the Chebyshev recurrence
+};
+
+__device__ __forceinline__ void cheb_interval(double lmax, double& theta, double& delta) {
+  const double hi = lmax, lo = kChebLowRatio * lmax;
+  theta = 0.5 * (hi + lo);
+  delta = 0.5 * (hi - lo);
+}
+
+// mode 0: x = 0 on entry (r = b);  mode 1: r = b - q with q = K x
+__global__ void cheb_first_kernel(double* x, double* r, double* d, const double* __restrict__ b,
+                                  const double* __restrict__ q, const double* __restrict__ invd,
+                                  const double* lmax, long nd, int nrhs, int mode,
+                                  const int* stop) {
+  if (stop && *stop) return;
+  double theta, delta;
+  cheb_interval(*lmax, theta, delta);
+  const double it = 1.0 / theta;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
+    const double id = invd[i];
+    for (int k = 0; k < nrhs; ++k) {
+      const long j = (long)k * nd + i;
+      const double rv = mode ? b[j] - q[j] : b[j];
+      const double dv = it * id * rv;
+      r[j] = rv;
+      d[j] = dv;
+      x[j] = mode ? x[j] + dv : dv;
+    }
+  }
+}
+
+__global__ void cheb_next_kernel(double* x, double* r, double* d, const double* __restrict__ q,
+                                 const double* __restrict__ invd, const double* lmax, long nd,
+                                 int nrhs, ChebCoef cf, const int* stop) {
+  if (stop && *stop) return;
+  double theta, delta;
+  cheb_interval(*lmax, theta, delta);
+  const double c1 = cf.r_cur * cf.r_prev, c2 = 2.0 * cf.r_cur / delta;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
+    const double id = invd[i];
+    for (int k = 0; k < nrhs; ++k) {
+      const long j = (long)k * nd + i;
+      const double rv = r[j] - q[j];
+      const double dv = c1 * d[j] + c2 * id * rv;
+      r[j] = rv;
+      d[j] = dv;
+      x[j] += dv;
+    }
+  }
+}
+
+// ------------------------------------------------- lmax estimation
+__global__ void power_init_kernel(double* v, const uint8_t* mask, long nn, int dim) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn * dim) return;
+  const long n = i % nn;
+  const int c = (int)(i / nn);
+  unsigned h = (unsigned)(i * 2654435761u) ^ 0x9e3779b9u;
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  const double v0 = (double)(h & 0xffffff) / 16777216.0 - 0.5;
+  v[i] = ((mask[n] >> c) & 1) ? 0.0 : v0;
+}
+
+// partial sums of v.(Kv) and v.(D v); then v <- scale * D^-1 (K v)
+__global__ __launch_bounds__(256) void power_step_kernel(double* v, const double* __restrict__ w,
+                                                         const double* __restrict__ invd, long nd,
+                                                         const double* scale, double* partials) {
+  const double sc = *scale;
+  double acc[2] = {0.0, 0.0};
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
+    const double id = invd[i];
+    const double vi = v[i], wi = w[i];
+    acc[0] += vi * wi;
+    acc[1] += vi * vi / id;
+    v[i] = sc * id * wi;
+  }
+  const double none[1] = {0.0};
+  block_partials<2, 0>(acc, none, partials);
+}
+
+__global__ void power_fin_kernel(const double* partials, long nb, double* scale, double* lmax,
+                                 int last) {
+  __shared__ double tot[2];
+  reduce_partials<2, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    const double lam = (tot[1] > 0.0) ? tot[0] / tot[1] : 1.0;
+    *scale = (lam > 0.0) ? 1.0 / lam : 1.0;
+    if (last) *lmax = kPowerSafety * lam;
+  }
+}
+
+__global__ void set_scalar_kernel(double* p, double v) { *p = v; }
+
+// ---------------------------------------------------- coarsest level
+// Dense A (row-major, n = dim * nn): row i = c * nn + node, built by the
+// thread that owns the row from the element matrices
+// K_e[(a,i),(b,j)] = |T| E (lambda g_a,i g_b,j + mu (g_a,j g_b,i + delta_ij g_a.g_b)).
+__global__ void coarse_assemble_kernel(double* A, const double* __restrict__ E, OpDesc o,
+                                       double lam0, double mu0, double vol) {
+  const int n = (int)(o.nn * o.dim);
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const int dim = o.dim;
+  const int node = row % (int)o.nn, ci = row / (int)o.nn;
+  double* Ar = A + (long)row * n;
+  for (int j = 0; j < n; ++j) Ar[j] = 0.0;
+  const int nx1 = o.nx + 1, ny1 = o.ny + 1;
+  const int i = node % nx1, jj = (node / nx1) % ny1, k = dim == 3 ? node / (nx1 * ny1) : 0;
+  if ((o.mask[node] >> ci) & 1) {
+    Ar[row] = 1.0;
+    return;
+  }
+  auto add_cell = [&](int nv, const int* nodes, const int (*g)[3], int av, double e) {
+    const double l = lam0 * e * vol, m = mu0 * e * vol;
+    const int* ga = g[av];
+    double gaga_dummy = 0.0;
+    (void)gaga_dummy;
+    for (int bv = 0; bv < nv; ++bv) {
+      const int* gb = g[bv];
+      double dot = 0.0;
+      for (int a = 0; a < dim; ++a) dot += ga[a] * gb[a];
+      for (int cj = 0; cj < dim; ++cj) {
+        const int col = cj * (int)o.nn + nodes[bv];
+        if ((o.mask[nodes[bv]] >> cj) & 1) continue;
+        Ar[col] += l * ga[ci] * gb[cj] + m * (ga[cj] * gb[ci] + (ci == cj ? dot : 0.0));
+      }
+    }
+  };
+  if (dim == 3) {
+    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int sz = -1; sz <= 0; ++sz)
+      for (int sy = -1; sy <= 0; ++sy)
+        for (int sx = -1; sx <= 0; ++sx) {
+          const int hi = i + sx, hj = jj + sy, hk = k + sz;
+          if (hi < 0 || hi >= o.nx || hj < 0 || hj >= o.ny || hk < 0 || hk >= o.nz) continue;
+          const int corner = (-sx) + 2 * (-sy) + 4 * (-sz);
+          const long h = ((long)hk * o.ny + hj) * o.nx + hi;
+          for (int t = 0; t < 6; ++t) {
+            const int c1 = 1 << perm[t][0];
+            const int c2 = c1 | (1 << perm[t][1]);
+            const int cs[4] = {0, c1, c2, 7};
+            int av = -1;
+            for (int v = 0; v < 4; ++v)
+              if (cs[v] == corner) av = v;
+            if (av < 0) continue;
+            int g[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            g[0][perm[t][0]] = -1;
+            g[1][perm[t][0]] += 1;
+            g[1][perm[t][1]] -= 1;
+            g[2][perm[t][1]] += 1;
+            g[2][perm[t][2]] -= 1;
+            g[3][perm[t][2]] = 1;
+            int nodes[4];
+            for (int v = 0; v < 4; ++v) {
+              const int cc = cs[v];
+              nodes[v] = ((hk + (cc >> 2)) * ny1 + hj + ((cc >> 1) & 1)) * nx1 + hi + (cc & 1);
+            }
+            add_cell(4, nodes, g, av, E[6 * h + t]);
+          }
+        }
+  } else {
+    // (corner, gx, gy) of the three vertices of each triangle type
+    const int tri[4][3][3] = {{{0, -1, 0}, {1, 1, -1}, {3, 0, 1}},
+                              {{0, 0, -1}, {2, -1, 1}, {3, 1, 0}},
+                              {{0, -1, -1}, {1, 1, 0}, {2, 0, 1}},
+                              {{3, 1, 1}, {1, 0, -1}, {2, -1, 0}}};
+    for (int sy = -1; sy <= 0; ++sy)
+      for (int sx = -1; sx <= 0; ++sx) {
+        const int hi = i + sx, hj = jj + sy;
+        if (hi < 0 || hi >= o.nx || hj < 0 || hj >= o.ny) continue;
+        const int corner = (-sx) + 2 * (-sy);
+        const bool da = o.split_uniform || ((hj & 1) == 0);
+        for (int t = 0; t < 2; ++t) {
+          const int type = (da ? 0 : 2) + t;
+          int av = -1;
+          for (int v = 0; v < 3; ++v)
+            if (tri[type][v][0] == corner) av = v;
+          if (av < 0) continue;
+          int g[3][3];
+          int nodes[3];
+          for (int v = 0; v < 3; ++v) {
+            g[v][0] = tri[type][v][1];
+            g[v][1] = tri[type][v][2];
+            g[v][2] = 0;
+            const int cc = tri[type][v][0];
+            nodes[v] = (hj + (cc >> 1)) * nx1 + hi + (cc & 1);
+          }
+          add_cell(3, nodes, g, av, E[2 * ((long)hj * o.nx + hi) + t]);
+        }
+      }
+  }
+}
+
+// In-place Gauss-Jordan inversion of the SPD matrix A (n x n, row-major),
+// one work-group; column k of the eliminated rows is saved first.
+__global__ __launch_bounds__(1024) void gauss_jordan_kernel(double* A, int n) {
+  __shared__ double rowk[128];
+  __shared__ double colk[128];
+  for (int k = 0; k < n; ++k) {
+    const double piv = A[(long)k * n + k];
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      colk[t] = A[(long)t * n + k];
+      rowk[t] = ((t == k) ? 1.0 : A[(long)k * n + t]) / piv;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+      const int i = t / n, j = t % n;
+      if (i == k) {
+        A[t] = rowk[j];
+      } else {
+        const double base = (j == k) ? 0.0 : A[t];
+        A[t] = base - colk[i] * rowk[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// x = A^-1 b for every load case (n <= 128)
+__global__ void coarse_solve_kernel(double* x, const double* __restrict__ b,
+                                    const double* __restrict__ Ainv, int n, int nrhs,
+                                    const int* stop) {
+  if (stop && *stop) return;
+  const int i = threadIdx.x;
+  if (i >= n) return;
+  for (int r = 0; r < nrhs; ++r) {
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += Ainv[(long)i * n + j] * b[(long)r * n + j];
+    x[(long)r * n + i] = acc;
+  }
+}
+
+// ------------------------------------------------------------ drivers
+static const int* stop_flag(Ctx* c) { return &c->scal->pcg.done; }
+
+void gmg_setup(Ctx* c) {
+  hipStream_t s = c->stream;
+  const int L = (int)c->lv.size();
+  for (int l = 1; l < L; ++l) {
+    const GmgLevel& f = c->lv[l - 1];
+    GmgLevel& g = c->lv[l];
+    if (g.op.dim == 3)
+      restrict_E3_kernel<<<cdivu((long)g.op.nx * g.op.ny * g.op.nz, 256), 256, 0, s>>>(
+          g.E, f.E, f.op.nx, f.op.ny, f.op.nz, g.op.nx, g.op.ny, g.op.nz);
+    else
+      restrict_E2_kernel<<<cdivu((long)g.op.nx * g.op.ny, 256), 256, 0, s>>>(
+          g.E, f.E, f.op.nx, f.op.ny, f.op.split_uniform, g.op.nx, g.op.ny);
+  }
+  for (int l = 0; l + 1 < L; ++l) {
+    GmgLevel& g = c->lv[l];
+    launch_diagonal_op(c, g.op, g.E, g.invd, true);
+    const long nd = g.op.nn * g.op.dim;
+    const unsigned nb = red_grid(nd);
+    power_init_kernel<<<cdivu(nd, 256), 256, 0, s>>>(g.pv, g.op.mask, g.op.nn, g.op.dim);
+    set_scalar_kernel<<<1, 1, 0, s>>>(g.pscale, 1.0);
+    for (int it = 0; it < kPowerIters; ++it) {
+      launch_apply_op(c, g.op, g.E, g.pv, g.pw, 1, false, false, nullptr);
+      power_step_kernel<<<nb, 256, 0, s>>>(g.pv, g.pw, g.invd, nd, g.pscale, c->partials);
+      power_fin_kernel<<<1, 256, 0, s>>>(c->partials, nb, g.pscale, g.lmax, it == kPowerIters - 1);
+    }
+  }
+  GmgLevel& cl = c->lv[L - 1];
+  const int n = (int)(cl.op.nn * cl.op.dim);
+  coarse_assemble_kernel<<<cdivu(n, 128), 128, 0, s>>>(cl.Ainv, cl.E, cl.op, c->m.lam0, c->m.mu0,
+                                                      c->m.vol);
+  gauss_jordan_kernel<<<1, 1024, 0, s>>>(cl.Ainv, n);
+}
+
+static void cheb_smooth(Ctx* c, GmgLevel& g, const double* b, double* x, int nrhs, bool from_zero) {
+  hipStream_t s = c->stream;
+  const long nd = g.op.nn * g.op.dim;
+  const unsigned nb = red_grid(nd);
+  const int* stop = stop_flag(c);
+  if (!from_zero) launch_apply_op(c, g.op, g.E, x, g.q, nrhs, false, false, stop);
+  cheb_first_kernel<<<nb, 256, 0, s>>>(x, g.r, g.d, b, g.q, g.invd, g.lmax, nd, nrhs,
+                                       from_zero ? 0 : 1, stop);
+  const double sigma = (1.0 + kChebLowRatio) / (1.0 - kChebLowRatio);
+  double rho_prev = 1.0 / sigma;
+  for (int k = 1; k < kChebDegree; ++k) {
+    const double rho = 1.0 / (2.0 * sigma - rho_prev);
+    launch_apply_op(c, g.op, g.E, g.d, g.q, nrhs, false, false, stop);
+    ChebCoef cf{rho, rho_prev};
+    cheb_next_kernel<<<nb, 256, 0, s>>>(x, g.r, g.d, g.q, g.invd, g.lmax, nd, nrhs, cf, stop);
+    rho_prev = rho;
+  }
+}
+
+static void vcycle_level(Ctx* c, int l, const double* b, double* x, int nrhs) {
+  hipStream_t s = c->stream;
+  const int L = (int)c->lv.size();
+  GmgLevel& g = c->lv[l];
+  const int* stop = stop_flag(c);
+  if (l == L - 1) {
+    const int n = (int)(g.op.nn * g.op.dim);
+    coarse_solve_kernel<<<1, 128, 0, s>>>(x, b, g.Ainv, n, nrhs, stop);
+    return;
+  }
+  GmgLevel& h = c->lv[l + 1];
+  cheb_smooth(c, g, b, x, nrhs, true);
+  launch_apply_op(c, g.op, g.E, x, g.q, nrhs, false, false, stop);
+  restrict_kernel<<<cdivu(h.op.nn, 256), 256, 0, s>>>(h.b, b, g.q, g.op, h.op, nrhs, stop);
+  vcycle_level(c, l + 1, h.b, h.x, nrhs);
+  prolong_add_kernel<<<cdivu(g.op.nn, 256), 256, 0, s>>>(x, h.x, g.op, h.op, nrhs, stop);
+  cheb_smooth(c, g, b, x, nrhs, false);
+}
+
+void gmg_vcycle(Ctx* c, const double* b, double* x, int nrhs) { vcycle_level(c, 0, b, x, nrhs); }
+
+}  // namespace topo

@@ -27,9 +27,7 @@ __device__ __forceinline__ double oc_a(double rho, double s, double eta) {
 __global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__ rho,
                                                       const double* __restrict__ dcf, double* a_out,
                                                       long nc, double move, double eta,
-                                                      double rho_min, double volfrac,
-                                                      double* partials, unsigned* counter,
-                                                      OcState* st, int* status) {
+                                                      double rho_min, double* partials) {
   double acc[3] = {0.0, 0.0, 0.0};
   double mx[1] = {0.0};
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += (long)gridDim.x * blockDim.x) {
@@ -42,30 +40,34 @@ __global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__
     acc[2] += a;
     if (a > 0.0) mx[0] = fmax(mx[0], hi / a);
   }
+  block_partials<3, 1>(acc, mx, partials);
+}
+
+__global__ void oc_init_fin(const double* partials, long nb, long nc, double volfrac, OcState* st,
+                            int* status) {
   __shared__ double tot[4];
-  if (grid_reduce<3, 1>(acc, mx, partials, counter, tot)) {
-    if (threadIdx.x == 0) {
-      const double target = volfrac * (double)nc;
-      st->target = target;
-      st->sum_lo = tot[0];
-      st->sum_hi = tot[1];
-      st->sum_a = tot[2];
-      st->passes = 0;
-      st->infeasible = 0;
-      st->mu_lo = 0.0;
-      st->mu_hi = tot[3];
-      const double tol = 1e-13 * (double)nc;
-      if (target < tot[0] - tol || target > tot[1] + tol || !(tot[2] > 0.0)) {
-        st->infeasible = 1;
-        st->mu = (target < tot[0]) ? 0.0 : tot[3];
-        st->done = 1;
-        *status = TOPO_S_OC_INFEASIBLE;
-      } else {
-        double mu = target / tot[2];
-        if (!(mu < st->mu_hi)) mu = 0.5 * st->mu_hi;
-        st->mu = mu;
-        st->done = 0;
-      }
+  reduce_partials<3, 1>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    const double target = volfrac * (double)nc;
+    st->target = target;
+    st->sum_lo = tot[0];
+    st->sum_hi = tot[1];
+    st->sum_a = tot[2];
+    st->passes = 0;
+    st->infeasible = 0;
+    st->mu_lo = 0.0;
+    st->mu_hi = tot[3];
+    const double tol = 1e-13 * (double)nc;
+    if (target < tot[0] - tol || target > tot[1] + tol || !(tot[2] > 0.0)) {
+      st->infeasible = 1;
+      st->mu = (target < tot[0]) ? 0.0 : tot[3];
+      st->done = 1;
+      *status = TOPO_S_OC_INFEASIBLE;
+    } else {
+      double mu = target / tot[2];
+      if (!(mu < st->mu_hi)) mu = 0.5 * st->mu_hi;
+      st->mu = mu;
+      st->done = 0;
     }
   }
 }
@@ -73,8 +75,7 @@ __global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__
 __global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__ rho,
                                                       const double* __restrict__ a_in, long nc,
                                                       double move, double rho_min,
-                                                      double* partials, unsigned* counter,
-                                                      OcState* st) {
+                                                      double* partials, const OcState* st) {
   if (st->done) return;
   const double mu = st->mu;
   double acc[2] = {0.0, 0.0};
@@ -86,42 +87,46 @@ __global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__
     acc[0] += fmax(lo, fmin(hi, v));
     acc[1] += (v > lo && v < hi) ? a : 0.0;
   }
-  double dummy[1] = {0.0};
+  const double none[1] = {0.0};
+  block_partials<2, 0>(acc, none, partials);
+}
+
+__global__ void oc_pass_fin(const double* partials, long nb, long nc, OcState* st) {
+  if (st->done) return;
   __shared__ double tot[2];
-  if (grid_reduce<2, 0>(acc, dummy, partials, counter, tot)) {
-    if (threadIdx.x == 0) {
-      const double V = tot[0], S = tot[1], T = st->target;
-      st->V = V;
-      st->S = S;
-      st->passes += 1;
-      const double err = V - T;
-      const double tol = 1e-14 * (double)nc;
-      if (fabs(err) <= tol || st->passes >= 200) {
-        st->done = 1;
-        return;
-      }
-      if (err < 0.0) st->mu_lo = mu; else st->mu_hi = mu;
-      double next = 0.5 * (st->mu_lo + st->mu_hi);
-      if (S > 0.0) {
-        const double nw = mu - err / S;
-        if (nw > st->mu_lo && nw < st->mu_hi) next = nw;
-      }
-      if (!(next > st->mu_lo && next < st->mu_hi)) {
-        // the bracket cannot be split further in FP64: keep the last point
-        st->done = 1;
-        return;
-      }
-      st->mu = next;
+  reduce_partials<2, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    const double mu = st->mu;
+    const double V = tot[0], S = tot[1], T = st->target;
+    st->V = V;
+    st->S = S;
+    st->passes += 1;
+    const double err = V - T;
+    const double tol = 1e-14 * (double)nc;
+    if (fabs(err) <= tol || st->passes >= 200) {
+      st->done = 1;
+      return;
     }
+    if (err < 0.0) st->mu_lo = mu; else st->mu_hi = mu;
+    double next = 0.5 * (st->mu_lo + st->mu_hi);
+    if (S > 0.0) {
+      const double nw = mu - err / S;
+      if (nw > st->mu_lo && nw < st->mu_hi) next = nw;
+    }
+    if (!(next > st->mu_lo && next < st->mu_hi)) {
+      // the bracket cannot be split further in FP64: keep the last point
+      st->done = 1;
+      return;
+    }
+    st->mu = next;
   }
 }
 
 __global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict__ rho,
                                                        const double* __restrict__ a_in,
                                                        double* rho_new, long nc, double move,
-                                                       double rho_min, double eta,
-                                                       double* partials, unsigned* counter,
-                                                       OcState* st, double* scalars) {
+                                                       double rho_min, double* partials,
+                                                       const OcState* st) {
   const double mu = st->mu;
   double acc[1] = {0.0};
   double mx[1] = {0.0};
@@ -133,48 +138,47 @@ __global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict_
     acc[0] += v;
     mx[0] = fmax(mx[0], fabs(v - r));
   }
+  block_partials<1, 1>(acc, mx, partials);
+}
+
+__global__ void oc_final_fin(const double* partials, long nb, double eta, OcState* st,
+                             double* scalars) {
   __shared__ double tot[2];
-  if (grid_reduce<1, 1>(acc, mx, partials, counter, tot)) {
-    if (threadIdx.x == 0) {
-      st->vol = tot[0];
-      st->change = tot[1];
-      st->lam = (mu > 0.0) ? pow(mu, -1.0 / eta) : INFINITY;
-      if (scalars) {
-        scalars[0] = st->lam;
-        scalars[1] = tot[0];
-        scalars[2] = tot[1];
-      }
+  reduce_partials<1, 1>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    const double mu = st->mu;
+    st->vol = tot[0];
+    st->change = tot[1];
+    st->lam = (mu > 0.0) ? pow(mu, -1.0 / eta) : INFINITY;
+    if (scalars) {
+      scalars[0] = st->lam;
+      scalars[1] = tot[0];
+      scalars[2] = tot[1];
     }
   }
 }
 
 void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars) {
   const long nc = c->g.nc;
-  long nb = (nc + 255) / 256;
-  if (nb > kRedBlocks) nb = kRedBlocks;
-  if (nb < 1) nb = 1;
+  const unsigned nb = red_grid(nc);
   const topo_problem& p = c->prob;
   OcState* st = &c->scal->oc;
   double* a = c->qsoa;
-  oc_init_kernel<<<(unsigned)nb, 256, 0, c->stream>>>(rho, dcf, a, nc, p.move, p.eta, p.rho_min,
-                                                      p.volfrac, c->partials,
-                                                      &c->scal->counters[CNT_OC_INIT], st,
-                                                      &c->scal->status);
+  hipStream_t s = c->stream;
+  oc_init_kernel<<<nb, 256, 0, s>>>(rho, dcf, a, nc, p.move, p.eta, p.rho_min, c->partials);
+  oc_init_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, p.volfrac, st, &c->scal->status);
   const int batch = 6;
   for (int b = 0; b < 40; ++b) {
-    for (int k = 0; k < batch; ++k)
-      oc_pass_kernel<<<(unsigned)nb, 256, 0, c->stream>>>(rho, a, nc, p.move, p.rho_min,
-                                                          c->partials,
-                                                          &c->scal->counters[CNT_OC_PASS], st);
-    (void)hipMemcpyAsync((void*)&c->pinned[2], &st->done, sizeof(int), hipMemcpyDeviceToHost,
-                         c->stream);
-    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < batch; ++k) {
+      oc_pass_kernel<<<nb, 256, 0, s>>>(rho, a, nc, p.move, p.rho_min, c->partials, st);
+      oc_pass_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, st);
+    }
+    (void)hipMemcpyAsync((void*)&c->pinned[2], &st->done, sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
     if (c->pinned[2]) break;
   }
-  oc_final_kernel<<<(unsigned)nb, 256, 0, c->stream>>>(rho, a, rho_new, nc, p.move, p.rho_min,
-                                                       p.eta, c->partials,
-                                                       &c->scal->counters[CNT_OC_FINAL], st,
-                                                       scalars);
+  oc_final_kernel<<<nb, 256, 0, s>>>(rho, a, rho_new, nc, p.move, p.rho_min, c->partials, st);
+  oc_final_fin<<<1, 256, 0, s>>>(c->partials, nb, p.eta, st, scalars);
 }
 
 }  // namespace topo

@@ -18,8 +18,7 @@ __global__ __launch_bounds__(256) void sens2d_kernel(const double* __restrict__ 
                                                      int nx, int ny, long nn, int nr,
                                                      int split_uniform, double lam0, double mu0,
                                                      double vol, double E0, double Emin,
-                                                     double penal, int paper, double* partials,
-                                                     unsigned* counter, DevScalars* sc) {
+                                                     double penal, int paper, double* partials) {
   const long nsq = (long)nx * ny;
   double acc[2] = {0.0, 0.0};
   for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < nsq; s += (long)gridDim.x * blockDim.x) {
@@ -49,11 +48,8 @@ __global__ __launch_bounds__(256) void sens2d_kernel(const double* __restrict__ 
       acc[1] += Ee * ws[t] / (2.0 * vol);
     }
   }
-  double dummy[1] = {0.0};
-  __shared__ double tot[2];
-  if (grid_reduce<2, 0>(acc, dummy, partials, counter, tot)) {
-    if (threadIdx.x == 0) { sc->c_energy = tot[0]; sc->c_paper = tot[1]; }
-  }
+  const double none[1] = {0.0};
+  block_partials<2, 0>(acc, none, partials);
 }
 
 __global__ __launch_bounds__(256) void sens3d_kernel(const double* __restrict__ rho,
@@ -61,8 +57,7 @@ __global__ __launch_bounds__(256) void sens3d_kernel(const double* __restrict__ 
                                                      int nx, int ny, int nz, long nn, int nr,
                                                      double lam0, double mu0, double vol,
                                                      double E0, double Emin, double penal,
-                                                     int paper, double* partials,
-                                                     unsigned* counter, DevScalars* sc) {
+                                                     int paper, double* partials) {
   const long nh = (long)nx * ny * nz;
   double acc[2] = {0.0, 0.0};
   for (long h = (long)blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += (long)gridDim.x * blockDim.x) {
@@ -95,27 +90,35 @@ __global__ __launch_bounds__(256) void sens3d_kernel(const double* __restrict__ 
       acc[1] += Ee * ws / (2.0 * vol);
     }
   }
-  double dummy[1] = {0.0};
+  const double none[1] = {0.0};
+  block_partials<2, 0>(acc, none, partials);
+}
+
+__global__ void sens_fin(const double* partials, long nb, DevScalars* sc) {
   __shared__ double tot[2];
-  if (grid_reduce<2, 0>(acc, dummy, partials, counter, tot)) {
-    if (threadIdx.x == 0) { sc->c_energy = tot[0]; sc->c_paper = tot[1]; }
+  reduce_partials<2, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    sc->c_energy = tot[0];
+    sc->c_paper = tot[1];
   }
 }
 
 __global__ __launch_bounds__(256) void dot_kernel(const double* __restrict__ a,
                                                   const double* __restrict__ b, long n,
-                                                  double* partials, unsigned* counter, double* out1,
-                                                  double* out2) {
+                                                  double* partials) {
   double acc[1] = {0.0};
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     acc[0] += a[i] * b[i];
-  double dummy[1] = {0.0};
+  const double none[1] = {0.0};
+  block_partials<1, 0>(acc, none, partials);
+}
+
+__global__ void dot_fin(const double* partials, long nb, double* out1, double* out2) {
   __shared__ double tot[1];
-  if (grid_reduce<1, 0>(acc, dummy, partials, counter, tot)) {
-    if (threadIdx.x == 0) {
-      if (out1) *out1 = tot[0];
-      if (out2) *out2 = tot[0];
-    }
+  reduce_partials<1, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    if (out1) *out1 = tot[0];
+    if (out2) *out2 = tot[0];
   }
 }
 
@@ -124,24 +127,21 @@ void launch_sensitivity(Ctx* c, const double* rho, const double* u, double* dc,
   const Grid& g = c->g;
   const Material& m = c->m;
   const long ncells = g.dim == 2 ? (long)g.nx * g.ny : (long)g.nx * g.ny * g.nz;
-  long nb = (ncells + 255) / 256;
-  if (nb > kRedBlocks) nb = kRedBlocks;
-  if (nb < 1) nb = 1;
+  const unsigned nb = red_grid(ncells);
   const int nr = c->prob.nrhs;
   if (g.dim == 2)
-    sens2d_kernel<<<(unsigned)nb, 256, 0, c->stream>>>(
-        rho, u, dc, g.nx, g.ny, g.nn, nr, g.split == TOPO_SPLIT_UNIFORM, m.lam0, m.mu0, m.vol,
-        m.E0, m.Emin, m.penal, m.paper, c->partials, &c->scal->counters[CNT_SENS], c->scal);
+    sens2d_kernel<<<nb, 256, 0, c->stream>>>(rho, u, dc, g.nx, g.ny, g.nn, nr,
+                                            g.split == TOPO_SPLIT_UNIFORM, m.lam0, m.mu0, m.vol,
+                                            m.E0, m.Emin, m.penal, m.paper, c->partials);
   else
-    sens3d_kernel<<<(unsigned)nb, 256, 0, c->stream>>>(
-        rho, u, dc, g.nx, g.ny, g.nz, g.nn, nr, m.lam0, m.mu0, m.vol, m.E0, m.Emin, m.penal,
-        m.paper, c->partials, &c->scal->counters[CNT_SENS], c->scal);
+    sens3d_kernel<<<nb, 256, 0, c->stream>>>(rho, u, dc, g.nx, g.ny, g.nz, g.nn, nr, m.lam0,
+                                            m.mu0, m.vol, m.E0, m.Emin, m.penal, m.paper,
+                                            c->partials);
+  sens_fin<<<1, 256, 0, c->stream>>>(c->partials, nb, c->scal);
   const long n = (long)nr * g.nd;
-  long nb2 = (n + 255) / 256;
-  if (nb2 > kRedBlocks) nb2 = kRedBlocks;
-  dot_kernel<<<(unsigned)nb2, 256, 0, c->stream>>>(c->f, u, n, c->partials,
-                                                  &c->scal->counters[CNT_DOT], compliance,
-                                                  &c->scal->compliance);
+  const unsigned nb2 = red_grid(n);
+  dot_kernel<<<nb2, 256, 0, c->stream>>>(c->f, u, n, c->partials);
+  dot_fin<<<1, 256, 0, c->stream>>>(c->partials, nb2, compliance, &c->scal->compliance);
 }
 
 }  // namespace topo

@@ -96,9 +96,38 @@ struct Material {
   int paper;
 };
 
+// Geometry and boundary mask of one grid level as seen by the operator
+// kernels (the fine grid, or a multigrid level).
+struct OpDesc {
+  int dim, nx, ny, nz;  // cells per axis (nz = 1 in 2D)
+  int64_t nn;           // nodes
+  int split_uniform;    // 2D: 1 = diagonal A everywhere
+  const uint8_t* mask;  // [nn] fixed-component bits
+  int kz;               // z-chunk of the 3D sweep
+};
+
+// One multigrid level (level 0 is the fine grid and borrows the context's
+// moduli, diagonal and mask; its right-hand side and solution are the CG
+// residual and preconditioned residual).
+struct GmgLevel {
+  OpDesc op;
+  int64_t nc;
+  double* E;                   // [nc] moduli
+  double* invd;                // [dim*nn] inverse diagonal
+  double *b, *x, *r, *d, *q;   // [nrhs][dim*nn]
+  double *pv, *pw;             // [dim*nn] power-iteration vectors
+  double* lmax;                // device scalar: lambda_max(D^-1 K) estimate
+  double* pscale;              // device scalar: power-iteration scale
+  double* Ainv;                // coarsest level: dense inverse [n*n]
+  uint8_t* mask;               // [nn]
+  size_t off_E, off_invd, off_b, off_x, off_r, off_d, off_q, off_pv, off_pw, off_mask, off_A;
+};
+
 struct WsLayout {
   size_t mask, f, E, E32, invd, invd32, r, p, q, z, wv, partials, scal, R, taps,
-      qsoa, dc, dcf, rho_new, rho_tmp, ir_x, ir_r32, ir_p32, ir_q32, ir_z32, ir_u32, total;
+      qsoa, dc, dcf, rho_new, rho_tmp, ir_x, ir_r32, ir_p32, ir_q32, ir_z32, ir_u32, gmg_scal,
+      total;
+  std::vector<GmgLevel> levels;   // offsets only (pointers filled at creation)
 };
 
 struct Ctx {
@@ -138,16 +167,28 @@ struct Ctx {
   int64_t t_launches;
   double t_ms;
   int apply_kz;       // z-chunk (node planes) of the 3D apply
+  std::vector<GmgLevel> lv;   // multigrid hierarchy (empty for Jacobi)
 };
 
 // ---- launchers (defined in the .hip files) ----
 void launch_simp_modulus(Ctx* c, const double* rho);
 void launch_apply(Ctx* c, const double* x, double* y, int nrhs, bool fuse_dot);
 void launch_apply_f32(Ctx* c, const float* x, float* y, int nrhs, bool fuse_dot);
+OpDesc fine_op(const Ctx* c);
+long apply_grid_blocks(const OpDesc& d, int nrhs);
+void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, double* y,
+                     int nrhs, bool fuse_dot, bool timed, const int* stop);
+void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
+                         int nrhs, bool timed, const int* stop);
+int pick_kz(int dim, int nx, int ny, int nz);
 void launch_diagonal(Ctx* c, double* d, bool inverse);
+void launch_diagonal_op(Ctx* c, const OpDesc& od, const double* E, double* d, bool inverse);
 void launch_mask_copy(Ctx* c, const double* src, double* dst, int nrhs);
 void launch_fill(Ctx* c, double* dst, double v, int64_t n);
 void pcg_solve(Ctx* c, double* u, double* info);
+unsigned red_grid(long n);
+void gmg_setup(Ctx* c);
+void gmg_vcycle(Ctx* c, const double* b, double* x, int nrhs);
 void launch_sensitivity(Ctx* c, const double* rho, const double* u, double* dc, double* compliance);
 void launch_filter(Ctx* c, const double* rho, const double* dc, double* dcf);
 void launch_filter_rowsums(Ctx* c);

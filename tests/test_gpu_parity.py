@@ -59,16 +59,18 @@ def test_apply_and_diagonal(name, p):
     np.testing.assert_allclose(d.cpu().numpy(), fem.jacobi_diag(K, fixed), rtol=1e-13)
 
 
+@pytest.mark.parametrize("pc", ["jacobi", "gmg"])
 @pytest.mark.parametrize("name,p", _problems())
-def test_solve_matches_direct(name, p):
-    print(f"[solve] {name}", flush=True)
+def test_solve_matches_direct(name, p, pc):
+    from paper_2012_08208_amd import TOPO_PC_GMG, TOPO_PC_JACOBI
+    print(f"[solve] {name} {pc}", flush=True)
     m = M.build(p.dim, p.nel, p.split)
     rho = synth.rho_random(3, m.n_cells, 0.05, 1.0)
     E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
     K = fem.assemble(m, E, p.nu)
     f = p.loads.reshape(p.nrhs, -1)
     u_ref = fem.solve(K, f, p.fixed.ravel())
-    t = _topo(p, rtol=1e-12)
+    t = _topo(p, rtol=1e-12, precond=TOPO_PC_GMG if pc == "gmg" else TOPO_PC_JACOBI)
     u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=DEV)
     info = torch.zeros(6, dtype=torch.float64, device=DEV)
     t.solve(_t(rho), u, info)
@@ -150,6 +152,30 @@ def test_oc_update(nx, ny, vf, seed):
     np.testing.assert_allclose(sc[2], change, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("nel", [(32, 16, 16), (41, 13, 9)])
+def test_gmg_needs_far_fewer_iterations_than_jacobi(nel):
+    from paper_2012_08208_amd import TOPO_PC_GMG, TOPO_PC_JACOBI
+    p = synth.cantilever3d(*nel, nrhs=2, rtol=1e-8)
+    rho = synth.rho_smooth(7, p.n_cells)
+    iters = {}
+    sols = {}
+    for pc, code in (("jacobi", TOPO_PC_JACOBI), ("gmg", TOPO_PC_GMG)):
+        print(f"[gmg-vs-jacobi] {nel} {pc}", flush=True)
+        t = _topo(p, precond=code, maxit=20000)
+        u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=DEV)
+        info = torch.zeros(6, dtype=torch.float64, device=DEV)
+        t.solve(_t(rho), u, info)
+        assert t.sync() == 0
+        info = info.cpu().numpy()
+        assert info[1] == 1.0
+        iters[pc] = info[0]
+        sols[pc] = u.cpu().numpy()
+    print(f"[gmg-vs-jacobi] iterations {iters}", flush=True)
+    assert iters["gmg"] * 5 < iters["jacobi"]
+    rel = np.linalg.norm(sols["gmg"] - sols["jacobi"]) / np.linalg.norm(sols["jacobi"])
+    assert rel < 1e-5
+
+
 def test_oc_infeasible_target_is_flagged():
     # every cell can drop by at most the move limit: with all rho = 0.9 and
     # volfrac 0.3 the target lies below sum(lo) = 0.7 N
@@ -170,6 +196,21 @@ def test_iterate_cantilever_60x30_50_iterations():
     S = simp.setup(p)
     rho_ref, log_ref = simp.iterate(S, 50)
     t = _topo(p, rtol=1e-12)
+    _run_iterate_check(t, p, rho_ref, log_ref)
+
+
+def test_iterate_cantilever_60x30_50_iterations_gmg():
+    from paper_2012_08208_amd import TOPO_PC_GMG
+    p = synth.cantilever2d(60, 30)
+    print("[iterate] cantilever2d 60x30 x50 gmg", flush=True)
+    S = simp.setup(p)
+    rho_ref, log_ref = simp.iterate(S, 50)
+    t = _topo(p, rtol=1e-12, precond=TOPO_PC_GMG)
+    _run_iterate_check(t, p, rho_ref, log_ref)
+
+
+def _run_iterate_check(t, p, rho_ref, log_ref):
+    from paper_2012_08208_amd import LOG_LEN
     rho = torch.full((p.n_cells,), p.volfrac, dtype=torch.float64, device=DEV)
     u = torch.zeros(p.n_dofs, dtype=torch.float64, device=DEV)
     log = torch.zeros(50 * LOG_LEN, dtype=torch.float64, device=DEV)
