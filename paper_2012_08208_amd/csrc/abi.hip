@@ -465,7 +465,8 @@ int topo_iterate(topo_ctx* c, double* rho, double* u, int max_iter, double chang
 int topo_apply(topo_ctx* c, const double* rho, const double* x, double* y) {
   if (!c || !rho || !x || !y || x == y) return TOPO_E_INVALID;
   launch_simp_modulus(c, rho);
-  launch_apply(c, x, y, c->prob.nrhs, false);
+  launch_mask_copy(c, x, c->q, c->prob.nrhs);
+  launch_apply(c, c->q, y, c->prob.nrhs, false);
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
 

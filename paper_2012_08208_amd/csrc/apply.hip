@@ -10,6 +10,9 @@
 // In 3D the block sweeps a chunk of z-planes; the cube layer below a node
 // plane hands its top-corner forces to the layer above in registers.
 // Only owned nodes are written, so every y entry is stored exactly once.
+// Input contract: x is zero on fixed DOFs (every internal vector is; the
+// exported apply masks its input first).  Cells outside the grid get a zero
+// modulus, so the clamped halo reads never reach an owned node.
 #include "common.h"
 #include "element.h"
 #include "topo_internal.h"
@@ -85,13 +88,10 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const T* __restrict__ x, T
     for (int idx = tid; idx < PATCH2; idx += 256) {
       const int a = idx % PATCH, b = idx / PATCH;
       const int gi = i0 - 1 + a, gj = j0 - 1 + b;
-      const bool ok = gi >= 0 && gi <= nx && gj >= 0 && gj <= ny;
-      const long n = (long)gj * (nx + 1) + gi;
-      const int m = ok ? d.mask[n] : 3;
-      const T v0 = ok ? xr[n] : T(0);
-      const T v1 = ok ? xr[nn + n] : T(0);
-      xs[0][idx] = (m & 1) ? T(0) : v0;
-      xs[1][idx] = (m & 2) ? T(0) : v1;
+      const int ci = min(max(gi, 0), nx), cj = min(max(gj, 0), ny);
+      const long n = (long)cj * (nx + 1) + ci;
+      xs[0][idx] = xr[n];
+      xs[1][idx] = xr[nn + n];
     }
   }
   const int hi = i0 - 1 + tx, hj = j0 - 1 + ty;
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const T* __restrict__ x, T
     const T e0 = T(E[e]), e1 = T(E[e + 1]);
     l0 = lam0 * e0; m0 = mu0 * e0; l1 = lam0 * e1; m1 = mu0 * e1;
   }
-  __syncthreads();
+  lds_barrier();
   if (live) {
     const bool diag_a = d.split_uniform || ((hj & 1) == 0);
     const int oi = i0 + tx, oj = j0 + ty;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const T* __restrict__ x, T
       for (int c = 0; c < 2; ++c) X[cy][c] = f[1 + 2 * cy][c] + shift_down1(f[2 * cy][c]);
     ex[0][tid] = X[0][0];
     ex[1][tid] = X[0][1];
-    __syncthreads();
+    lds_barrier();
     if (owner) {
       T* yr = y + (long)rhs * 2 * nn;
 #pragma unroll
@@ -143,8 +143,16 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const T* __restrict__ x, T
 // -------------------------------------------------------------- 3D apply
 // One block: one tile of 15 x 15 node columns, one z-chunk, one load case.
 // Per cube layer: the next node plane is committed from registers to LDS,
-// the plane after it is fetched from memory while the layer is computed,
-// and the cube forces are combined into owned nodes (2 barriers per layer).
+// the plane after it and the next layer's moduli are fetched from memory
+// while the layer is computed, and the cube forces are combined into owned
+// nodes.  Two LDS-only barriers per layer; all loads use clamped (always
+// valid) addresses so they are issued unconditionally.
+template <typename T>
+struct PlaneBuf {
+  T v[2][3];
+  int m[2];
+};
+
 template <typename T, typename TE>
 __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T* __restrict__ y,
                                                       const TE* __restrict__ E, OpDesc d,
@@ -152,6 +160,7 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
                                                       const int* stop) {
   __shared__ T xs[2][3][PATCH2];
   __shared__ T ex[2][6][256];
+  __shared__ uint8_t ms[2][PATCH2];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   if (stop && *stop) return;
@@ -169,59 +178,74 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     const T* xr = x + (long)rhs * 3 * nn;
     T* yr = y + (long)rhs * 3 * nn;
 
-    // each thread stages node idx = tid and idx = tid + 256 (< 289) of a plane
-    T pf[2][3];
-    int pm[2];
-    auto fetch = [&](int kk) {
+    // plane staging: thread handles patch nodes idx = tid and tid + 256
+    long poff[2];
+    bool pin[2];
+    bool pidx[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q;
+      const int a = idx % PATCH, b = idx / PATCH;
+      const int gi = i0 - 1 + a, gj = j0 - 1 + b;
+      pidx[q] = idx < PATCH2;
+      pin[q] = pidx[q] && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny;
+      const int ci = min(max(gi, 0), nx), cj = min(max(gj, 0), ny);
+      poff[q] = (long)cj * (nx + 1) + ci;
+    }
+    auto fetch = [&](int kk, PlaneBuf<T>& pb) {
+      const bool kin = kk >= 0 && kk <= nz;
+      const long base = (long)min(max(kk, 0), nz) * plane;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int idx = tid + 256 * q;
-        const int a = idx % PATCH, b = idx / PATCH;
-        const int gi = i0 - 1 + a, gj = j0 - 1 + b;
-        const bool ok = idx < PATCH2 && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny && kk >= 0 &&
-                        kk <= nz;
-        const long n = (long)kk * plane + (long)gj * (nx + 1) + gi;
-        pm[q] = ok ? d.mask[n] : 7;
+        const long n = base + poff[q];
+        const int m = d.mask[n];
+        pb.m[q] = (pin[q] && kin) ? m : 7;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) pf[q][c] = ok ? xr[c * nn + n] : T(0);
+        for (int c = 0; c < 3; ++c) pb.v[q][c] = xr[c * nn + n];
       }
     };
-    auto commit = [&](int kk) {
+    auto commit = [&](int kk, const PlaneBuf<T>& pb) {
       const int s = kk & 1;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int idx = tid + 256 * q;
-        if (idx < PATCH2) {
+        if (pidx[q]) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) xs[s][c][idx] = ((pm[q] >> c) & 1) ? T(0) : pf[q][c];
+          for (int c = 0; c < 3; ++c) xs[s][c][idx] = pb.v[q][c];
+          ms[s][idx] = (uint8_t)pb.m[q];
         }
       }
     };
 
     const int hi = i0 - 1 + tx, hj = j0 - 1 + ty;
     const bool col_ok = hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+    const long hcol = (long)min(max(hj, 0), ny - 1) * nx + min(max(hi, 0), nx - 1);
+    auto fetch_E = [&](int kk, T (&en)[6]) {
+      const bool ok = col_ok && kk >= 0 && kk < nz;
+      const long h = (long)min(max(kk, 0), nz - 1) * ny * nx + hcol;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const T e = T(E[6 * h + t]);
+        en[t] = ok ? e : T(0);
+      }
+    };
     const int oi = i0 + tx, oj = j0 + ty;
     const bool owner = tx < TILE && ty < TILE && oi <= nx && oj <= ny;
+    const long ocol = (long)oj * (nx + 1) + oi;
     T carry[3] = {0, 0, 0};
 
-    fetch(k0 - 1);
-    commit(k0 - 1);
-    fetch(k0);
+    PlaneBuf<T> pb;
+    fetch(k0 - 1, pb);
+    commit(k0 - 1, pb);
+    fetch(k0, pb);
     for (int kh = k0 - 1; kh < k1; ++kh) {
-      // moduli of this cube layer (independent of LDS, issued early)
-      const bool cell_ok = col_ok && kh >= 0 && kh < nz;
+      // this layer's moduli: issued first, their latency hides behind the
+      // plane commit and the barrier
       T ev[6];
-      if (cell_ok) {
-        const long h = ((long)kh * ny + hj) * nx + hi;
-#pragma unroll
-        for (int t = 0; t < 6; ++t) ev[t] = T(E[6 * h + t]);
-      } else {
-#pragma unroll
-        for (int t = 0; t < 6; ++t) ev[t] = T(0);
-      }
-      commit(kh + 1);
-      __syncthreads();
-      if (kh + 2 <= k1) fetch(kh + 2);
+      fetch_E(kh, ev);
+      commit(kh + 1, pb);
+      lds_barrier();
+      if (kh + 2 <= k1) fetch(kh + 2, pb);
       T lam[6], mu[6];
 #pragma unroll
       for (int t = 0; t < 6; ++t) { lam[t] = lam0 * ev[t]; mu[t] = mu0 * ev[t]; }
@@ -232,10 +256,7 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
         const int li = (ty + ((c >> 1) & 1)) * PATCH + tx + (c & 1);
         const int s = (c >> 2) ? stp : sb;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          u[c][a] = xs[s][a][li];
-          f[c][a] = 0;
-        }
+        for (int a = 0; a < 3; ++a) u[c][a] = xs[s][a][li];
       }
       cube_force<T>(u, lam, mu, f);
       T X[2][2][3];
@@ -251,11 +272,11 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
       for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
         for (int a = 0; a < 3; ++a) ex[eb][cz * 3 + a][tid] = X[0][cz][a];
-      __syncthreads();
+      lds_barrier();
       if (owner) {
+        const int om = ms[sb][(ty + 1) * PATCH + tx + 1];
         const bool store = kh >= k0;
-        const long on = (long)kh * plane + (long)oj * (nx + 1) + oi;
-        const int om = store ? d.mask[on] : 7;
+        const long on = (long)kh * plane + ocol;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           T yb = carry[a] + X[1][0][a] + ex[eb][a][tid + 16];

@@ -14,6 +14,16 @@ namespace topo {
 
 constexpr int kPartStride = 16;
 
+// Work-group barrier that orders LDS only.  __syncthreads() also waits for
+// every outstanding global load and store of the wave, which would drain
+// prefetches issued before the barrier; kernels whose barriers only hand LDS
+// data between waves use this one.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

@@ -129,15 +129,74 @@ __device__ __forceinline__ void square_energy(bool diag_a, const T (&u)[4][2], T
   }
 }
 
+// Stress of one Kuhn tetrahedron (scaled by |T| E through lam, mu) from
+// the three edge differences along its path: column pi_k of grad u is
+// the k-th path edge.
+template <typename T, int P0, int P1, int P2>
+__device__ __forceinline__ void tet_stress(const T (&a)[3], const T (&b)[3], const T (&c)[3], T lam,
+                                           T mu, T (&S)[3][3]) {
+  T G[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    G[k][P0] = a[k];
+    G[k][P1] = b[k];
+    G[k][P2] = c[k];
+  }
+  const T lt = lam * (G[0][0] + G[1][1] + G[2][2]);
+  const T m2 = mu + mu;
+  S[0][0] = lt + m2 * G[0][0];
+  S[1][1] = lt + m2 * G[1][1];
+  S[2][2] = lt + m2 * G[2][2];
+  S[0][1] = S[1][0] = mu * (G[0][1] + G[1][0]);
+  S[0][2] = S[2][0] = mu * (G[0][2] + G[2][0]);
+  S[1][2] = S[2][1] = mu * (G[1][2] + G[2][1]);
+}
+
+// Forces of the six Kuhn tetrahedra of a unit cube on its 8 corners.
+// Tetrahedron t (permutation pi) has path 0 -> e_pi0 -> e_pi0+e_pi1 -> 7 and
+// vertex gradients -e_pi0, e_pi0 - e_pi1, e_pi1 - e_pi2, e_pi2, so corner
+// forces are signed sums of stress columns; each corner's sum is formed
+// once (assignments, no zero-initialised accumulators).
 template <typename T>
 __device__ __forceinline__ void cube_force(const T (&u)[8][3], const T (&lam)[6], const T (&mu)[6],
                                            T (&f)[8][3]) {
-  tet_force<T, 0, 1, 2>(u, lam[0], mu[0], f);
-  tet_force<T, 0, 2, 1>(u, lam[1], mu[1], f);
-  tet_force<T, 1, 0, 2>(u, lam[2], mu[2], f);
-  tet_force<T, 1, 2, 0>(u, lam[3], mu[3], f);
-  tet_force<T, 2, 0, 1>(u, lam[4], mu[4], f);
-  tet_force<T, 2, 1, 0>(u, lam[5], mu[5], f);
+  T e01[3], e02[3], e04[3], e13[3], e15[3], e23[3], e26[3], e45[3], e46[3], e37[3], e57[3], e67[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    e01[k] = u[1][k] - u[0][k];
+    e02[k] = u[2][k] - u[0][k];
+    e04[k] = u[4][k] - u[0][k];
+    e13[k] = u[3][k] - u[1][k];
+    e15[k] = u[5][k] - u[1][k];
+    e23[k] = u[3][k] - u[2][k];
+    e26[k] = u[6][k] - u[2][k];
+    e45[k] = u[5][k] - u[4][k];
+    e46[k] = u[6][k] - u[4][k];
+    e37[k] = u[7][k] - u[3][k];
+    e57[k] = u[7][k] - u[5][k];
+    e67[k] = u[7][k] - u[6][k];
+  }
+  T S0[3][3], S1[3][3], S2[3][3], S3[3][3], S4[3][3], S5[3][3];
+  tet_stress<T, 0, 1, 2>(e01, e13, e37, lam[0], mu[0], S0);  // 0-1-3-7
+  tet_stress<T, 0, 2, 1>(e01, e15, e57, lam[1], mu[1], S1);  // 0-1-5-7
+  tet_stress<T, 1, 0, 2>(e02, e23, e37, lam[2], mu[2], S2);  // 0-2-3-7
+  tet_stress<T, 1, 2, 0>(e02, e26, e67, lam[3], mu[3], S3);  // 0-2-6-7
+  tet_stress<T, 2, 0, 1>(e04, e45, e57, lam[4], mu[4], S4);  // 0-4-5-7
+  tet_stress<T, 2, 1, 0>(e04, e46, e67, lam[5], mu[5], S5);  // 0-4-6-7
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    // corner 0: -sum S_t[:, pi0]; corner 7: sum S_t[:, pi2]
+    f[0][k] = -(((S0[k][0] + S1[k][0]) + (S2[k][1] + S3[k][1])) + (S4[k][2] + S5[k][2]));
+    f[7][k] = ((S0[k][2] + S1[k][1]) + (S2[k][2] + S3[k][0])) + (S4[k][1] + S5[k][0]);
+    // corners e_pi0: S[:, pi0] - S[:, pi1]
+    f[1][k] = (S0[k][0] - S0[k][1]) + (S1[k][0] - S1[k][2]);
+    f[2][k] = (S2[k][1] - S2[k][0]) + (S3[k][1] - S3[k][2]);
+    f[4][k] = (S4[k][2] - S4[k][0]) + (S5[k][2] - S5[k][1]);
+    // corners e_pi0 + e_pi1: S[:, pi1] - S[:, pi2]
+    f[3][k] = (S0[k][1] - S0[k][2]) + (S2[k][0] - S2[k][2]);
+    f[5][k] = (S1[k][2] - S1[k][1]) + (S4[k][0] - S4[k][1]);
+    f[6][k] = (S3[k][2] - S3[k][0]) + (S5[k][1] - S5[k][0]);
+  }
 }
 
 template <typename T>
