@@ -109,8 +109,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cantilever3d")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "gmg"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed-ir"])
+    ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--maxit", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -122,12 +122,12 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2012_08208_amd import (LOG_LEN, TOPO_FP64, TOPO_MIXED_FP32, TOPO_PC_GMG,
-                                      TOPO_PC_JACOBI, Topo)
+    from paper_2012_08208_amd import (LOG_LEN, TOPO_FP64, TOPO_MIXED_FP32, TOPO_MIXED_IR,
+                                      TOPO_PC_GMG, TOPO_PC_JACOBI, Topo)
 
     p = workload(args.workload)
     dev = torch.device("cuda:0")
-    prec = TOPO_FP64 if args.precision == "fp64" else TOPO_MIXED_FP32
+    prec = {"fp64": TOPO_FP64, "mixed": TOPO_MIXED_FP32, "mixed-ir": TOPO_MIXED_IR}[args.precision]
     pc = TOPO_PC_JACOBI if args.precond == "jacobi" else TOPO_PC_GMG
     t = Topo.from_problem(p, precision=prec, precond=pc, maxit=args.maxit, device=dev)
     rho = torch.full((p.n_cells,), p.volfrac, dtype=torch.float64, device=dev)

@@ -77,7 +77,20 @@ enum {
 };
 
 enum { TOPO_SPLIT_ALT_ROWS = 0, TOPO_SPLIT_UNIFORM = 1 };
-enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1 };
+/* Precision of the solve.
+   TOPO_FP64:       everything in FP64.
+   TOPO_MIXED_FP32: FP64 conjugate gradients (operator apply, vectors, dot
+                    products) preconditioned by a multigrid V-cycle whose
+                    operator applies, smoothing and transfers run on FP32
+                    vectors with FP32 moduli; Polak-Ribiere (flexible) beta;
+                    after convergence the FP64 true residual f - K u is
+                    recomputed and CG restarts from u if it exceeds rtol.
+                    With the Jacobi preconditioner this is the FP64 solve.
+   TOPO_MIXED_IR:   FP64 iterative refinement: true residual in FP64, inner
+                    CG on FP32 vectors with the FP32 operator and FP32
+                    preconditioner (FP64 dot products) to 1e-4, u += d in
+                    FP64; falls back to FP64 CG if a step stagnates. */
+enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1, TOPO_MIXED_IR = 2 };
 enum { TOPO_PC_JACOBI = 0, TOPO_PC_GMG = 1 };
 
 /* Problem description (host struct, copied by topo_create). */
@@ -91,8 +104,7 @@ typedef struct topo_problem {
   double volfrac;             /* k in (0, 1] */
   double rmin;                /* filter radius in cell widths, > 0 */
   double move, eta, rho_min;  /* OC move limit m, damping eta, lower bound */
-  int32_t precision;  /* TOPO_FP64 | TOPO_MIXED_FP32 (FP32 operator inside
-                         FP64 iterative refinement) */
+  int32_t precision;  /* TOPO_FP64 | TOPO_MIXED_FP32 | TOPO_MIXED_IR */
   int32_t precond;    /* TOPO_PC_JACOBI | TOPO_PC_GMG */
   double rtol;        /* stop when ||f_r - K u_r|| <= rtol ||f_r|| for each r */
   int32_t maxit;      /* cap on preconditioned CG iterations per solve */

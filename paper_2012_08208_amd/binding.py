@@ -21,6 +21,7 @@ TOPO_SPLIT_ALT_ROWS = 0
 TOPO_SPLIT_UNIFORM = 1
 TOPO_FP64 = 0
 TOPO_MIXED_FP32 = 1
+TOPO_MIXED_IR = 2
 TOPO_PC_JACOBI = 0
 TOPO_PC_GMG = 1
 SOLVE_INFO_LEN = 6

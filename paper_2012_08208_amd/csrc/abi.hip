@@ -29,7 +29,9 @@ static bool valid_problem(const topo_problem* p) {
   if (!(p->E0 > 0.0) || !(p->Emin >= 0.0) || !(p->Emin < p->E0)) return false;
   if (!(p->move > 0.0) || !(p->eta > 0.0) || !(p->rho_min > 0.0 && p->rho_min < 1.0)) return false;
   if (!(p->rtol > 0.0) || p->maxit < 1) return false;
-  if (p->precision != TOPO_FP64 && p->precision != TOPO_MIXED_FP32) return false;
+  if (p->precision != TOPO_FP64 && p->precision != TOPO_MIXED_FP32 &&
+      p->precision != TOPO_MIXED_IR)
+    return false;
   if (p->precond != TOPO_PC_JACOBI && p->precond != TOPO_PC_GMG) return false;
   if (p->dim == 2 && p->split2d != TOPO_SPLIT_ALT_ROWS && p->split2d != TOPO_SPLIT_UNIFORM)
     return false;
@@ -101,7 +103,7 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
     return at;
   };
   const size_t nr = (size_t)p->nrhs;
-  const bool mixed = p->precision == TOPO_MIXED_FP32;
+  const bool mixed = p->precision != TOPO_FP64;
   long nblk = apply_blocks(g, kz, p->nrhs);
   if (nblk < kRedBlocks) nblk = kRedBlocks;
   L.mask = take((size_t)g.nn);
@@ -124,11 +126,19 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.dcf = take((size_t)g.nc * 8);
   L.rho_new = take((size_t)g.nc * 8);
   L.rho_tmp = take((size_t)g.nc * 8);
-  L.ir_x = L.ir_r32 = L.ir_p32 = L.ir_q32 = L.ir_z32 = L.ir_u32 = 0;
+  L.r32 = L.p32 = L.q32 = L.z32 = L.x32 = 0;
+  if (mixed) {
+    L.r32 = take(nr * g.nd * 4);
+    L.p32 = take(nr * g.nd * 4);
+    L.q32 = take(nr * g.nd * 4);
+    L.z32 = take(nr * g.nd * 4);
+    L.x32 = take(nr * g.nd * 4);
+  }
   L.gmg_scal = 0;
   L.levels.clear();
   if (p->precond == TOPO_PC_GMG) {
     L.z = take(nr * g.nd * 8);
+    L.wv = (p->precision == TOPO_MIXED_FP32) ? take(nr * g.nd * 8) : 0;
     const std::vector<LevelDims> plan = gmg_plan(g);
     L.gmg_scal = take(8 * 2 * (plan.size() + 1));
     for (size_t l = 0; l < plan.size(); ++l) {
@@ -142,6 +152,10 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
       if (l > 0) {
         lv.off_E = take((size_t)nc * 8);
         lv.off_invd = take((size_t)nd * 8);
+        if (mixed) {
+          lv.off_E32 = take((size_t)nc * 4);
+          lv.off_invd32 = take((size_t)nd * 4);
+        }
         lv.off_b = take(nr * nd * 8);
         lv.off_x = take(nr * nd * 8);
         lv.off_mask = take((size_t)nn);
@@ -191,6 +205,24 @@ __global__ void log_record_kernel(const DevScalars* sc, double* rec, long nc, in
   rec[7] = (sc->pcg.done && !sc->pcg.breakdown) ? 1.0 : 0.0;
 }
 
+// mixed precision: the iteration count is the total over refinement steps
+// (plus a closing FP64 solve if refinement stagnated), and the residual is
+// the FP64 true residual of the refinement
+__global__ void log_record_mixed_kernel(const DevScalars* sc, double* rec, long nc, int nr) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mx = 0.0;
+  for (int k = 0; k < nr; ++k)
+    if (sc->ir.ff[k] > 0.0) mx = fmax(mx, sqrt(sc->ir.rr[k] / sc->ir.ff[k]));
+  rec[0] = sc->compliance;
+  rec[1] = sc->c_paper;
+  rec[2] = sc->oc.vol / (double)nc;
+  rec[3] = sc->oc.change;
+  rec[4] = sc->oc.lam;
+  rec[5] = sc->ir.inner_total + (sc->ir.stagnated ? sc->pcg.iters : 0);
+  rec[6] = sc->ir.stagnated ? 0.0 : mx;
+  rec[7] = sc->ir.done ? 1.0 : ((sc->pcg.done && !sc->pcg.breakdown) ? 1.0 : 0.0);
+}
+
 }  // namespace topo
 
 struct topo_ctx : public Ctx {};
@@ -234,7 +266,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->r = (double*)(w + L.r);
   c->p = (double*)(w + L.p);
   c->q = (double*)(w + L.q);
-  c->wv = nullptr;
+  c->wv = L.wv ? (double*)(w + L.wv) : nullptr;
   c->partials = (double*)(w + L.partials);
   c->scal = (DevScalars*)(w + L.scal);
   c->R = (double*)(w + L.R);
@@ -245,6 +277,11 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->rho_new = (double*)(w + L.rho_new);
   c->rho_tmp = (double*)(w + L.rho_tmp);
   c->z = L.z ? (double*)(w + L.z) : nullptr;
+  c->r32 = L.r32 ? (float*)(w + L.r32) : nullptr;
+  c->p32 = L.p32 ? (float*)(w + L.p32) : nullptr;
+  c->q32 = L.q32 ? (float*)(w + L.q32) : nullptr;
+  c->z32 = L.z32 ? (float*)(w + L.z32) : nullptr;
+  c->x32 = L.x32 ? (float*)(w + L.x32) : nullptr;
   // material of the unit-modulus element law
   Material& m = c->m;
   const double nu = prob->nu;
@@ -290,11 +327,15 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
       if (l == 0) {
         lv.E = c->E;
         lv.invd = c->invd;
+        lv.E32 = c->E32;
+        lv.invd32 = c->invd32;
         lv.mask = c->mask;
         lv.b = lv.x = nullptr;
       } else {
         lv.E = (double*)(w + lv.off_E);
         lv.invd = (double*)(w + lv.off_invd);
+        lv.E32 = lv.off_E32 ? (float*)(w + lv.off_E32) : nullptr;
+        lv.invd32 = lv.off_invd32 ? (float*)(w + lv.off_invd32) : nullptr;
         lv.b = (double*)(w + lv.off_b);
         lv.x = (double*)(w + lv.off_x);
         lv.mask = (uint8_t*)(w + lv.off_mask);
@@ -444,8 +485,13 @@ int topo_iterate(topo_ctx* c, double* rho, double* u, int max_iter, double chang
     launch_sensitivity(c, rho, u, c->dc, nullptr);
     launch_filter(c, rho, c->dc, c->dcf);
     oc_update(c, rho, c->dcf, c->rho_new, nullptr);
-    if (log) log_record_kernel<<<1, 64, 0, c->stream>>>(c->scal, log + (size_t)it * TOPO_LOG_LEN,
-                                                        c->g.nc, c->prob.nrhs);
+    if (log) {
+      double* rec = log + (size_t)it * TOPO_LOG_LEN;
+      if (c->prob.precision == TOPO_MIXED_IR)
+        log_record_mixed_kernel<<<1, 64, 0, c->stream>>>(c->scal, rec, c->g.nc, c->prob.nrhs);
+      else
+        log_record_kernel<<<1, 64, 0, c->stream>>>(c->scal, rec, c->g.nc, c->prob.nrhs);
+    }
     TOPO_HIP(hipMemcpyAsync(rho, c->rho_new, (size_t)c->g.nc * 8, hipMemcpyDeviceToDevice,
                             c->stream));
     ++done;

@@ -413,7 +413,7 @@ __global__ void fill_kernel(double* dst, double v, long n) {
 
 void launch_simp_modulus(Ctx* c, const double* rho) {
   simp_modulus_kernel<<<cdiv(c->g.nc, 256), 256, 0, c->stream>>>(
-      c->E, c->prob.precision == TOPO_MIXED_FP32 ? c->E32 : nullptr, rho, c->g.nc, c->m.E0,
+      c->E, c->prob.precision != TOPO_FP64 ? c->E32 : nullptr, rho, c->g.nc, c->m.E0,
       c->m.Emin, c->m.penal, c->m.paper);
 }
 
@@ -474,8 +474,39 @@ void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x
   if (slot >= 0) timing_end(c, slot);
 }
 
+void launch_apply_op_f32_dot(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
+                             int nrhs) {
+  int slot = c->timing ? timing_begin(c, nullptr) : -1;
+  apply_dispatch<float, float>(c, d, E, x, y, nrhs, true, &c->scal->pcg.done);
+  if (slot >= 0) timing_end(c, slot);
+}
+
+__global__ void to_f32_cast_kernel(float* dst, const double* __restrict__ src, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+void launch_to_f32(Ctx* c, float* dst, const double* src, int64_t n) {
+  long b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  to_f32_cast_kernel<<<(unsigned)(b < 1 ? 1 : b), 256, 0, c->stream>>>(dst, src, n);
+}
+
+// Timed launches are the fine-level applies in the solve's working
+// precision (FP64 solve: FP64 applies; mixed solves: the FP32 applies).
+__global__ void to_f64_cast_kernel(double* dst, const float* __restrict__ src, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+
+void launch_to_f64(Ctx* c, double* dst, const float* src, int64_t n) {
+  long b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  to_f64_cast_kernel<<<(unsigned)(b < 1 ? 1 : b), 256, 0, c->stream>>>(dst, src, n);
+}
+
 void launch_apply(Ctx* c, const double* x, double* y, int nrhs, bool fuse_dot) {
-  launch_apply_op(c, fine_op(c), c->E, x, y, nrhs, fuse_dot, true,
+  launch_apply_op(c, fine_op(c), c->E, x, y, nrhs, fuse_dot, c->prob.precision == TOPO_FP64,
                   fuse_dot ? &c->scal->pcg.done : nullptr);
 }
 

@@ -21,6 +21,7 @@
 // Coarsest level (<= 128 DOFs): dense matrix assembled per solve and
 // inverted by Gauss-Jordan elimination in one work-group.
 #include <math.h>
+#include <stdlib.h>
 
 #include "common.h"
 #include "element.h"
@@ -28,10 +29,23 @@
 
 namespace topo {
 
-constexpr int kChebDegree = 2;
-constexpr int kPowerIters = 12;
-constexpr double kPowerSafety = 1.2;
-constexpr double kChebLowRatio = 0.09;
+// Smoother parameters (defaults; TOPO_CHEB_DEGREE, TOPO_CHEB_LOW,
+// TOPO_POWER_ITERS and TOPO_POWER_SAFETY override them at context creation)
+struct GmgParams {
+  int cheb_degree = 2;
+  double cheb_low = 0.09;
+  int power_iters = 12;
+  double power_safety = 1.2;
+};
+
+static GmgParams gmg_params() {
+  GmgParams p;
+  if (const char* e = getenv("TOPO_CHEB_DEGREE")) p.cheb_degree = atoi(e) > 0 ? atoi(e) : p.cheb_degree;
+  if (const char* e = getenv("TOPO_CHEB_LOW")) p.cheb_low = atof(e) > 0 ? atof(e) : p.cheb_low;
+  if (const char* e = getenv("TOPO_POWER_ITERS")) p.power_iters = atoi(e) > 0 ? atoi(e) : p.power_iters;
+  if (const char* e = getenv("TOPO_POWER_SAFETY")) p.power_safety = atof(e) > 0 ? atof(e) : p.power_safety;
+  return p;
+}
 
 static inline unsigned cdivu(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
@@ -100,9 +114,9 @@ __global__ void restrict_E2_kernel(double* Ec, const double* __restrict__ Ef, in
 
 // ----------------------------------------------- transfer operators
 // b_c = R (b_f - q_f): restriction of the fine residual
-__global__ void restrict_kernel(double* bc, const double* __restrict__ bf,
-                                const double* __restrict__ qf, OpDesc fo, OpDesc co, int nrhs,
-                                const int* stop) {
+template <typename T>
+__global__ void restrict_kernel(T* bc, const T* __restrict__ bf, const T* __restrict__ qf,
+                                OpDesc fo, OpDesc co, int nrhs, const int* stop) {
   if (stop && *stop) return;
   const long C = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (C >= co.nn) return;
@@ -116,7 +130,7 @@ __global__ void restrict_kernel(double* bc, const double* __restrict__ bf,
   for (int r = 0; r < nrhs; ++r)
     for (int c = 0; c < dim; ++c) {
       const long off = ((long)r * dim + c) * fo.nn;
-      double acc = 0.0;
+      T acc = 0;
       {
         const int fi = 2 * I, fj = 2 * J, fk = 2 * K;
         if (fi <= fo.nx && fj <= fo.ny && fk <= nzf) {
@@ -130,16 +144,17 @@ __global__ void restrict_kernel(double* bc, const double* __restrict__ bf,
           const int fi = 2 * I + sgn * dx, fj = 2 * J + sgn * dy, fk = 2 * K + sgn * dz;
           if (fi < 0 || fj < 0 || fk < 0 || fi > fo.nx || fj > fo.ny || fk > nzf) continue;
           const long n = ((long)fk * nyf1 + fj) * nxf1 + fi;
-          acc += 0.5 * (bf[off + n] - qf[off + n]);
+          acc += T(0.5) * (bf[off + n] - qf[off + n]);
         }
       }
-      bc[((long)r * dim + c) * co.nn + C] = ((cm >> c) & 1) ? 0.0 : acc;
+      bc[((long)r * dim + c) * co.nn + C] = ((cm >> c) & 1) ? T(0) : acc;
     }
 }
 
 // x_f += P x_c (fixed fine DOFs untouched)
-__global__ void prolong_add_kernel(double* xf, const double* __restrict__ xc, OpDesc fo, OpDesc co,
-                                   int nrhs, const int* stop) {
+template <typename T>
+__global__ void prolong_add_kernel(T* xf, const T* __restrict__ xc, OpDesc fo, OpDesc co, int nrhs,
+                                   const int* stop) {
   if (stop && *stop) return;
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= fo.nn) return;
@@ -154,8 +169,8 @@ __global__ void prolong_add_kernel(double* xf, const double* __restrict__ xc, Op
   for (int r = 0; r < nrhs; ++r)
     for (int c = 0; c < dim; ++c) {
       if ((fm >> c) & 1) continue;
-      const double* xcr = xc + ((long)r * dim + c) * co.nn;
-      const double e = even ? xcr[c0] : 0.5 * (xcr[c0] + xcr[c1]);
+      const T* xcr = xc + ((long)r * dim + c) * co.nn;
+      const T e = even ? xcr[c0] : T(0.5) * (xcr[c0] + xcr[c1]);
       xf[((long)r * dim + c) * fo.nn + n] += e;
     }
 }
@@ -165,27 +180,28 @@ struct ChebCoef {
   double r_cur, r_prev;  // rho_k, rho_(k-1) of the Chebyshev recurrence
 };
 
-__device__ __forceinline__ void cheb_interval(double lmax, double& theta, double& delta) {
-  const double hi = lmax, lo = kChebLowRatio * lmax;
+__device__ __forceinline__ void cheb_interval(double lmax, double low, double& theta,
+                                              double& delta) {
+  const double hi = lmax, lo = low * lmax;
   theta = 0.5 * (hi + lo);
   delta = 0.5 * (hi - lo);
 }
 
 // mode 0: x = 0 on entry (r = b);  mode 1: r = b - q with q = K x
-__global__ void cheb_first_kernel(double* x, double* r, double* d, const double* __restrict__ b,
-                                  const double* __restrict__ q, const double* __restrict__ invd,
-                                  const double* lmax, long nd, int nrhs, int mode,
-                                  const int* stop) {
+template <typename T>
+__global__ void cheb_first_kernel(T* x, T* r, T* d, const T* __restrict__ b, const T* __restrict__ q,
+                                  const T* __restrict__ invd, const double* lmax, long nd, int nrhs,
+                                  int mode, double low, const int* stop) {
   if (stop && *stop) return;
   double theta, delta;
-  cheb_interval(*lmax, theta, delta);
-  const double it = 1.0 / theta;
+  cheb_interval(*lmax, low, theta, delta);
+  const T it = T(1.0 / theta);
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
-    const double id = invd[i];
+    const T id = invd[i];
     for (int k = 0; k < nrhs; ++k) {
       const long j = (long)k * nd + i;
-      const double rv = mode ? b[j] - q[j] : b[j];
-      const double dv = it * id * rv;
+      const T rv = mode ? b[j] - q[j] : b[j];
+      const T dv = it * id * rv;
       r[j] = rv;
       d[j] = dv;
       x[j] = mode ? x[j] + dv : dv;
@@ -193,19 +209,20 @@ __global__ void cheb_first_kernel(double* x, double* r, double* d, const double*
   }
 }
 
-__global__ void cheb_next_kernel(double* x, double* r, double* d, const double* __restrict__ q,
-                                 const double* __restrict__ invd, const double* lmax, long nd,
-                                 int nrhs, ChebCoef cf, const int* stop) {
+template <typename T>
+__global__ void cheb_next_kernel(T* x, T* r, T* d, const T* __restrict__ q, const T* __restrict__ invd,
+                                 const double* lmax, long nd, int nrhs, ChebCoef cf, double low,
+                                 const int* stop) {
   if (stop && *stop) return;
   double theta, delta;
-  cheb_interval(*lmax, theta, delta);
-  const double c1 = cf.r_cur * cf.r_prev, c2 = 2.0 * cf.r_cur / delta;
+  cheb_interval(*lmax, low, theta, delta);
+  const T c1 = T(cf.r_cur * cf.r_prev), c2 = T(2.0 * cf.r_cur / delta);
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
-    const double id = invd[i];
+    const T id = invd[i];
     for (int k = 0; k < nrhs; ++k) {
       const long j = (long)k * nd + i;
-      const double rv = r[j] - q[j];
-      const double dv = c1 * d[j] + c2 * id * rv;
+      const T rv = r[j] - q[j];
+      const T dv = c1 * d[j] + c2 * id * rv;
       r[j] = rv;
       d[j] = dv;
       x[j] += dv;
@@ -245,13 +262,13 @@ __global__ __launch_bounds__(256) void power_step_kernel(double* v, const double
 }
 
 __global__ void power_fin_kernel(const double* partials, long nb, double* scale, double* lmax,
-                                 int last) {
+                                 int last, double safety) {
   __shared__ double tot[2];
   reduce_partials<2, 0>(partials, nb, tot);
   if (threadIdx.x == 0) {
     const double lam = (tot[1] > 0.0) ? tot[0] / tot[1] : 1.0;
     *scale = (lam > 0.0) ? 1.0 / lam : 1.0;
-    if (last) *lmax = kPowerSafety * lam;
+    if (last) *lmax = safety * lam;
   }
 }
 
@@ -383,18 +400,23 @@ __global__ __launch_bounds__(1024) void gauss_jordan_kernel(double* A, int n) {
   }
 }
 
-// x = A^-1 b for every load case (n <= 128)
-__global__ void coarse_solve_kernel(double* x, const double* __restrict__ b,
-                                    const double* __restrict__ Ainv, int n, int nrhs,
-                                    const int* stop) {
+// x = A^-1 b for every load case (n <= 128), accumulated in FP64
+template <typename T>
+__global__ void coarse_solve_kernel(T* x, const T* __restrict__ b, const double* __restrict__ Ainv,
+                                    int n, int nrhs, const int* stop) {
   if (stop && *stop) return;
   const int i = threadIdx.x;
   if (i >= n) return;
   for (int r = 0; r < nrhs; ++r) {
     double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc += Ainv[(long)i * n + j] * b[(long)r * n + j];
-    x[(long)r * n + i] = acc;
+    for (int j = 0; j < n; ++j) acc += Ainv[(long)i * n + j] * (double)b[(long)r * n + j];
+    x[(long)r * n + i] = T(acc);
   }
+}
+
+__global__ void to_f32_kernel(float* dst, const double* __restrict__ src, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
 }
 
 // ------------------------------------------------------------ drivers
@@ -420,10 +442,20 @@ void gmg_setup(Ctx* c) {
     const unsigned nb = red_grid(nd);
     power_init_kernel<<<cdivu(nd, 256), 256, 0, s>>>(g.pv, g.op.mask, g.op.nn, g.op.dim);
     set_scalar_kernel<<<1, 1, 0, s>>>(g.pscale, 1.0);
-    for (int it = 0; it < kPowerIters; ++it) {
+    const GmgParams gp = gmg_params();
+    for (int it = 0; it < gp.power_iters; ++it) {
       launch_apply_op(c, g.op, g.E, g.pv, g.pw, 1, false, false, nullptr);
       power_step_kernel<<<nb, 256, 0, s>>>(g.pv, g.pw, g.invd, nd, g.pscale, c->partials);
-      power_fin_kernel<<<1, 256, 0, s>>>(c->partials, nb, g.pscale, g.lmax, it == kPowerIters - 1);
+      power_fin_kernel<<<1, 256, 0, s>>>(c->partials, nb, g.pscale, g.lmax,
+                                         it == gp.power_iters - 1, gp.power_safety);
+    }
+  }
+  if (c->prob.precision != TOPO_FP64) {
+    for (int l = 0; l < L; ++l) {
+      GmgLevel& g = c->lv[l];
+      const long nd = g.op.nn * g.op.dim;
+      if (l > 0) to_f32_kernel<<<red_grid(g.nc), 256, 0, s>>>(g.E32, g.E, g.nc);
+      if (l + 1 < L) to_f32_kernel<<<red_grid(nd), 256, 0, s>>>(g.invd32, g.invd, nd);
     }
   }
   GmgLevel& cl = c->lv[L - 1];
@@ -433,44 +465,84 @@ void gmg_setup(Ctx* c) {
   gauss_jordan_kernel<<<1, 1024, 0, s>>>(cl.Ainv, n);
 }
 
-static void cheb_smooth(Ctx* c, GmgLevel& g, const double* b, double* x, int nrhs, bool from_zero) {
+// per-precision views of a level's operator data
+template <typename T>
+struct LevelOps;
+template <>
+struct LevelOps<double> {
+  static const double* E(const GmgLevel& g) { return g.E; }
+  static const double* invd(const GmgLevel& g) { return g.invd; }
+  static void apply(Ctx* c, const GmgLevel& g, const double* x, double* y, int nrhs,
+                    const int* stop) {
+    launch_apply_op(c, g.op, g.E, x, y, nrhs, false, false, stop);
+  }
+};
+template <>
+struct LevelOps<float> {
+  static const float* E(const GmgLevel& g) { return g.E32; }
+  static const float* invd(const GmgLevel& g) { return g.invd32; }
+  static void apply(Ctx* c, const GmgLevel& g, const float* x, float* y, int nrhs,
+                    const int* stop) {
+    // fine-level FP32 applies are the timed kernel of the mixed solves
+    launch_apply_op_f32(c, g.op, g.E32, x, y, nrhs, g.op.nn == c->g.nn, stop);
+  }
+};
+
+template <typename T>
+static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool from_zero) {
   hipStream_t s = c->stream;
   const long nd = g.op.nn * g.op.dim;
   const unsigned nb = red_grid(nd);
   const int* stop = stop_flag(c);
-  if (!from_zero) launch_apply_op(c, g.op, g.E, x, g.q, nrhs, false, false, stop);
-  cheb_first_kernel<<<nb, 256, 0, s>>>(x, g.r, g.d, b, g.q, g.invd, g.lmax, nd, nrhs,
-                                       from_zero ? 0 : 1, stop);
-  const double sigma = (1.0 + kChebLowRatio) / (1.0 - kChebLowRatio);
+  T* gr = reinterpret_cast<T*>(g.r);
+  T* gd = reinterpret_cast<T*>(g.d);
+  T* gq = reinterpret_cast<T*>(g.q);
+  const T* invd = LevelOps<T>::invd(g);
+  const GmgParams gp = gmg_params();
+  if (!from_zero) LevelOps<T>::apply(c, g, x, gq, nrhs, stop);
+  cheb_first_kernel<T><<<nb, 256, 0, s>>>(x, gr, gd, b, gq, invd, g.lmax, nd, nrhs,
+                                          from_zero ? 0 : 1, gp.cheb_low, stop);
+  const double sigma = (1.0 + gp.cheb_low) / (1.0 - gp.cheb_low);
   double rho_prev = 1.0 / sigma;
-  for (int k = 1; k < kChebDegree; ++k) {
+  for (int k = 1; k < gp.cheb_degree; ++k) {
     const double rho = 1.0 / (2.0 * sigma - rho_prev);
-    launch_apply_op(c, g.op, g.E, g.d, g.q, nrhs, false, false, stop);
+    LevelOps<T>::apply(c, g, gd, gq, nrhs, stop);
     ChebCoef cf{rho, rho_prev};
-    cheb_next_kernel<<<nb, 256, 0, s>>>(x, g.r, g.d, g.q, g.invd, g.lmax, nd, nrhs, cf, stop);
+    cheb_next_kernel<T><<<nb, 256, 0, s>>>(x, gr, gd, gq, invd, g.lmax, nd, nrhs, cf, gp.cheb_low,
+                                           stop);
     rho_prev = rho;
   }
 }
 
-static void vcycle_level(Ctx* c, int l, const double* b, double* x, int nrhs) {
+template <typename T>
+static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
   hipStream_t s = c->stream;
   const int L = (int)c->lv.size();
   GmgLevel& g = c->lv[l];
   const int* stop = stop_flag(c);
   if (l == L - 1) {
     const int n = (int)(g.op.nn * g.op.dim);
-    coarse_solve_kernel<<<1, 128, 0, s>>>(x, b, g.Ainv, n, nrhs, stop);
+    coarse_solve_kernel<T><<<1, 128, 0, s>>>(x, b, g.Ainv, n, nrhs, stop);
     return;
   }
   GmgLevel& h = c->lv[l + 1];
-  cheb_smooth(c, g, b, x, nrhs, true);
-  launch_apply_op(c, g.op, g.E, x, g.q, nrhs, false, false, stop);
-  restrict_kernel<<<cdivu(h.op.nn, 256), 256, 0, s>>>(h.b, b, g.q, g.op, h.op, nrhs, stop);
-  vcycle_level(c, l + 1, h.b, h.x, nrhs);
-  prolong_add_kernel<<<cdivu(g.op.nn, 256), 256, 0, s>>>(x, h.x, g.op, h.op, nrhs, stop);
-  cheb_smooth(c, g, b, x, nrhs, false);
+  T* hb = reinterpret_cast<T*>(h.b);
+  T* hx = reinterpret_cast<T*>(h.x);
+  T* gq = reinterpret_cast<T*>(g.q);
+  cheb_smooth<T>(c, g, b, x, nrhs, true);
+  LevelOps<T>::apply(c, g, x, gq, nrhs, stop);
+  restrict_kernel<T><<<cdivu(h.op.nn, 256), 256, 0, s>>>(hb, b, gq, g.op, h.op, nrhs, stop);
+  vcycle_level<T>(c, l + 1, hb, hx, nrhs);
+  prolong_add_kernel<T><<<cdivu(g.op.nn, 256), 256, 0, s>>>(x, hx, g.op, h.op, nrhs, stop);
+  cheb_smooth<T>(c, g, b, x, nrhs, false);
 }
 
-void gmg_vcycle(Ctx* c, const double* b, double* x, int nrhs) { vcycle_level(c, 0, b, x, nrhs); }
+void gmg_vcycle(Ctx* c, const double* b, double* x, int nrhs) {
+  vcycle_level<double>(c, 0, b, x, nrhs);
+}
+
+void gmg_vcycle_f32(Ctx* c, const float* b, float* x, int nrhs) {
+  vcycle_level<float>(c, 0, b, x, nrhs);
+}
 
 }  // namespace topo

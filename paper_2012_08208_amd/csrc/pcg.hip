@@ -4,7 +4,7 @@
 //
 // One iteration on the context stream:
 //   apply      q = K p and per-block (p,q)        -> alpha_fin: alpha = (r,z)/(p,q)
-//   update     u += alpha p, r -= alpha q, (r,r)  -> update_fin: convergence test
+//   update     x += alpha p, r -= alpha q, (r,r)  -> update_fin: convergence test
 //              (Jacobi: also (r, D^-1 r) and beta, fused)
 //   precond    z = M r (multigrid V-cycle)        -> rz, rz_fin: beta = (r,z)/(r,z)_old
 //   direction  p = z + beta p
@@ -12,6 +12,13 @@
 // in a fixed order, so results are deterministic.  After every load case
 // has converged all kernels return at once; the host polls a pinned copy of
 // the done flag one batch behind the queue, so the device never idles.
+//
+// The vector type TV is double for the FP64 solve and float for the inner
+// solve of mixed-precision iterative refinement: FP32 vectors, FP32
+// operator and V-cycle, FP64 dot products and scalars.  Refinement keeps the
+// solution and the true residual f - K u in FP64 (outer loop below).
+#include <type_traits>
+
 #include "common.h"
 #include "topo_internal.h"
 
@@ -51,6 +58,7 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(const double* __restrict_
   block_partials<2 * NR, 0>(acc, none, partials);
 }
 
+// rr and the reference norm ff come from the partials; tol2 = rtol^2 ff
 template <int NR>
 __global__ void pcg_init_fin(const double* partials, long nb, double rtol, PcgState* st) {
   __shared__ double tot[2 * NR];
@@ -74,21 +82,42 @@ __global__ void pcg_init_fin(const double* partials, long nb, double rtol, PcgSt
   }
 }
 
-// z = D^-1 r (Jacobi) written explicitly, used for the first direction
-template <int NR>
-__global__ __launch_bounds__(256) void jacobi_kernel(double* z, const double* __restrict__ r,
-                                                     const double* __restrict__ invd, long nd) {
+// inner solve start: x = 0, r given; partial (r,r) serves as both rr and ff
+template <int NR, typename TV>
+__global__ __launch_bounds__(256) void inner_init_kernel(TV* x, const TV* __restrict__ r, long nd,
+                                                         double* partials) {
+  double acc[2 * NR];
+#pragma unroll
+  for (int k = 0; k < 2 * NR; ++k) acc[k] = 0.0;
   for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
-    const double id = invd[d];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const long i = (long)q * nd + d;
+      x[i] = TV(0);
+      const double rv = (double)r[i];
+      acc[q] += rv * rv;
+      acc[NR + q] += rv * rv;
+    }
+  }
+  const double none[1] = {0.0};
+  block_partials<2 * NR, 0>(acc, none, partials);
+}
+
+// z = D^-1 r (Jacobi) written explicitly, used for the first direction
+template <int NR, typename TV>
+__global__ __launch_bounds__(256) void jacobi_kernel(TV* z, const TV* __restrict__ r,
+                                                     const TV* __restrict__ invd, long nd) {
+  for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
+    const TV id = invd[d];
 #pragma unroll
     for (int k = 0; k < NR; ++k) z[(long)k * nd + d] = id * r[(long)k * nd + d];
   }
 }
 
 // partial (r, z) per load case
-template <int NR>
-__global__ __launch_bounds__(256) void pcg_rz_kernel(const double* __restrict__ r,
-                                                     const double* __restrict__ z, long nd,
+template <int NR, typename TV>
+__global__ __launch_bounds__(256) void pcg_rz_kernel(const TV* __restrict__ r,
+                                                     const TV* __restrict__ z, long nd,
                                                      double* partials, const PcgState* st) {
   if (st->done) return;
   double acc[NR];
@@ -96,7 +125,8 @@ __global__ __launch_bounds__(256) void pcg_rz_kernel(const double* __restrict__ 
   for (int k = 0; k < NR; ++k) acc[k] = 0.0;
   for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] += r[(long)k * nd + d] * z[(long)k * nd + d];
+    for (int k = 0; k < NR; ++k)
+      acc[k] += (double)r[(long)k * nd + d] * (double)z[(long)k * nd + d];
   }
   const double none[1] = {0.0};
   block_partials<NR, 0>(acc, none, partials);
@@ -124,6 +154,86 @@ __global__ void pcg_rz_fin(const double* partials, long nb, int first, PcgState*
   }
 }
 
+// flexible CG: partial (r, z_new) and (r, z_old) per load case
+template <int NR>
+__global__ __launch_bounds__(256) void pcg_rz2_kernel(const double* __restrict__ r,
+                                                      const double* __restrict__ zn,
+                                                      const double* __restrict__ zo, long nd,
+                                                      double* partials, const PcgState* st) {
+  if (st->done) return;
+  double acc[2 * NR];
+#pragma unroll
+  for (int k = 0; k < 2 * NR; ++k) acc[k] = 0.0;
+  for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const double rv = r[(long)k * nd + d];
+      acc[k] += rv * zn[(long)k * nd + d];
+      acc[NR + k] += rv * zo[(long)k * nd + d];
+    }
+  }
+  const double none[1] = {0.0};
+  block_partials<2 * NR, 0>(acc, none, partials);
+}
+
+// beta = ((r, z_new) - (r, z_old)) / (r_old, z_old)  (Polak-Ribiere)
+template <int NR>
+__global__ void pcg_rz2_fin(const double* partials, long nb, PcgState* st) {
+  if (st->done) return;
+  __shared__ double tot[2 * NR];
+  reduce_partials<2 * NR, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NR; ++k) {
+      if (!st->active[k]) continue;
+      st->rz_old[k] = st->rz[k];
+      st->rz[k] = tot[k];
+      st->beta[k] = (tot[k] - tot[NR + k]) / st->rz_old[k];
+      if (!(tot[k] > 0.0)) { st->breakdown = 1; st->active[k] = 0; }
+    }
+    if (st->breakdown) st->done = 1;
+  }
+}
+
+// FP64 true residual norms: partial (Zf - Ku, Zf - Ku) per load case
+template <int NR>
+__global__ __launch_bounds__(256) void resid64_kernel(const double* __restrict__ f,
+                                                      const double* __restrict__ Ku,
+                                                      const uint8_t* __restrict__ mask, long nn,
+                                                      int dim, double* partials) {
+  const long nd = nn * dim;
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+  for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
+    const long n = d % nn;
+    const int c = (int)(d / nn);
+    if ((mask[n] >> c) & 1) continue;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const double rv = f[(long)k * nd + d] - Ku[(long)k * nd + d];
+      acc[k] += rv * rv;
+    }
+  }
+  const double none[1] = {0.0};
+  block_partials<NR, 0>(acc, none, partials);
+}
+
+// flag[0] = 1 when a load case's true residual exceeds rtol ||f||; the
+// recursive norms are replaced by the true ones
+template <int NR>
+__global__ void resid64_fin(const double* partials, long nb, PcgState* st, int* flag) {
+  __shared__ double tot[NR];
+  reduce_partials<NR, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    int again = 0;
+    for (int k = 0; k < NR; ++k) {
+      st->rr[k] = tot[k];
+      if (st->ff[k] > 0.0 && tot[k] > st->tol2[k]) again = 1;
+    }
+    *flag = again;
+  }
+}
+
 __global__ void pcg_alpha_fin(const double* partials, long nb, PcgState* st) {
   if (st->done) return;
   __shared__ double tot[kMaxRhs];
@@ -141,32 +251,31 @@ __global__ void pcg_alpha_fin(const double* partials, long nb, PcgState* st) {
   }
 }
 
-// u += alpha p, r -= alpha q; partial (r,r) and, for Jacobi, (r, D^-1 r)
-template <int NR, bool JAC>
-__global__ __launch_bounds__(256) void pcg_update_kernel(double* u, double* r,
-                                                         const double* __restrict__ p,
-                                                         const double* __restrict__ q,
-                                                         const double* __restrict__ invd, long nd,
+// x += alpha p, r -= alpha q; partial (r,r) and, for Jacobi, (r, D^-1 r)
+template <int NR, bool JAC, typename TV>
+__global__ __launch_bounds__(256) void pcg_update_kernel(TV* x, TV* r, const TV* __restrict__ p,
+                                                         const TV* __restrict__ q,
+                                                         const TV* __restrict__ invd, long nd,
                                                          double* partials, const PcgState* st) {
   if (st->done) return;
-  double al[NR];
+  TV al[NR];
   bool act[NR];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) { al[k] = st->alpha[k]; act[k] = st->active[k] != 0; }
+  for (int k = 0; k < NR; ++k) { al[k] = TV(st->alpha[k]); act[k] = st->active[k] != 0; }
   double acc[2 * NR];
 #pragma unroll
   for (int k = 0; k < 2 * NR; ++k) acc[k] = 0.0;
   for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
-    const double id = JAC ? invd[d] : 0.0;
+    const TV id = JAC ? invd[d] : TV(0);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       if (!act[k]) continue;
       const long i = (long)k * nd + d;
-      u[i] += al[k] * p[i];
-      const double rv = r[i] - al[k] * q[i];
+      x[i] += al[k] * p[i];
+      const TV rv = r[i] - al[k] * q[i];
       r[i] = rv;
-      acc[k] += rv * rv;
-      if (JAC) acc[NR + k] += rv * (id * rv);
+      acc[k] += (double)rv * (double)rv;
+      if (JAC) acc[NR + k] += (double)rv * (double)(id * rv);
     }
   }
   const double none[1] = {0.0};
@@ -199,24 +308,23 @@ __global__ void pcg_update_fin(const double* partials, long nb, PcgState* st, in
 }
 
 // p = z + beta p (Jacobi: z = D^-1 r on the fly); first: p = z
-template <int NR, bool JAC>
-__global__ __launch_bounds__(256) void pcg_direction_kernel(double* p, const double* __restrict__ z,
-                                                            const double* __restrict__ r,
-                                                            const double* __restrict__ invd,
-                                                            long nd, const PcgState* st,
-                                                            int first) {
+template <int NR, bool JAC, typename TV>
+__global__ __launch_bounds__(256) void pcg_direction_kernel(TV* p, const TV* __restrict__ z,
+                                                            const TV* __restrict__ r,
+                                                            const TV* __restrict__ invd, long nd,
+                                                            const PcgState* st, int first) {
   if (st->done) return;
-  double be[NR];
+  TV be[NR];
   bool act[NR];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) { be[k] = first ? 0.0 : st->beta[k]; act[k] = st->active[k] != 0; }
+  for (int k = 0; k < NR; ++k) { be[k] = first ? TV(0) : TV(st->beta[k]); act[k] = st->active[k] != 0; }
   for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
-    const double id = JAC ? invd[d] : 0.0;
+    const TV id = JAC ? invd[d] : TV(0);
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       if (!act[k]) continue;
       const long i = (long)k * nd + d;
-      const double zv = JAC ? id * r[i] : z[i];
+      const TV zv = JAC ? id * r[i] : z[i];
       p[i] = first ? zv : zv + be[k] * p[i];
     }
   }
@@ -240,53 +348,108 @@ unsigned red_grid(long n) {
   return (unsigned)(b < kRedBlocks ? (b < 1 ? 1 : b) : kRedBlocks);
 }
 
-template <int NR>
-static void pcg_run(Ctx* c, double* u, double* info) {
+// precision-specific operator and preconditioner
+template <typename TV>
+struct Prec;
+template <>
+struct Prec<double> {
+  static void apply_dot(Ctx* c, const double* p, double* q, int nr) {
+    launch_apply(c, p, q, nr, true);
+  }
+  static void vcycle(Ctx* c, const double* r, double* z, int nr) {
+    if (c->prob.precision == TOPO_MIXED_FP32) {
+      // FP32 V-cycle as the preconditioner of the FP64 iteration
+      const int64_t n = (int64_t)nr * c->g.nd;
+      launch_to_f32(c, c->r32, r, n);
+      gmg_vcycle_f32(c, c->r32, c->z32, nr);
+      launch_to_f64(c, z, c->z32, n);
+    } else {
+      gmg_vcycle(c, r, z, nr);
+    }
+  }
+  static const double* invd(Ctx* c) { return c->invd; }
+};
+template <>
+struct Prec<float> {
+  static void apply_dot(Ctx* c, const float* p, float* q, int nr) {
+    launch_apply_op_f32_dot(c, fine_op(c), c->E32, p, q, nr);
+  }
+  static void vcycle(Ctx* c, const float* r, float* z, int nr) { gmg_vcycle_f32(c, r, z, nr); }
+  static const float* invd(Ctx* c) { return c->invd32; }
+};
+
+template <typename TV>
+struct FlexTrait {
+  static bool enabled(Ctx*) { return false; }
+  static TV* second(Ctx*, TV* z) { return z; }
+};
+
+template <>
+struct FlexTrait<double> {
+  static bool enabled(Ctx* c) {
+    return c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG;
+  }
+  static double* second(Ctx* c, double* z) { return c->wv ? c->wv : z; }
+};
+
+// The CG iteration proper, from a state whose rr/ff/tol2/active are set and
+// whose residual r is in place; x accumulates the solution.
+template <int NR, typename TV>
+static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
   const long nd = c->g.nd;
   PcgState* st = &c->scal->pcg;
   int* status = &c->scal->status;
   hipStream_t s = c->stream;
-  const bool warm = c->prob.warm_start != 0;
   const bool gmg = c->prob.precond == TOPO_PC_GMG;
+  const TV* invd = Prec<TV>::invd(c);
   const unsigned gb = red_grid(nd);
   const long nb_apply = apply_grid_blocks(fine_op(c), NR);
-  if (warm) launch_apply(c, u, c->q, NR, false);
-  pcg_init_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, u, c->r, c->mask, c->g.nn, c->g.dim, warm,
-                                         c->partials);
-  pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, c->prob.rtol, st);
-  // first direction p = M r
   if (gmg) {
-    gmg_vcycle(c, c->r, c->z, NR);
-    pcg_rz_kernel<NR><<<gb, 256, 0, s>>>(c->r, c->z, nd, c->partials, st);
+    Prec<TV>::vcycle(c, r, z, NR);
+    pcg_rz_kernel<NR, TV><<<gb, 256, 0, s>>>(r, z, nd, c->partials, st);
     pcg_rz_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, 1, st);
-    pcg_direction_kernel<NR, false><<<gb, 256, 0, s>>>(c->p, c->z, c->r, c->invd, nd, st, 1);
+    pcg_direction_kernel<NR, false, TV><<<gb, 256, 0, s>>>(p, z, r, invd, nd, st, 1);
   } else {
-    jacobi_kernel<NR><<<gb, 256, 0, s>>>(c->p, c->r, c->invd, nd);
-    pcg_rz_kernel<NR><<<gb, 256, 0, s>>>(c->r, c->p, nd, c->partials, st);
+    jacobi_kernel<NR, TV><<<gb, 256, 0, s>>>(p, r, invd, nd);
+    pcg_rz_kernel<NR, TV><<<gb, 256, 0, s>>>(r, p, nd, c->partials, st);
     pcg_rz_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, 1, st);
   }
   const int batch = gmg ? 2 : 8;
-  const int maxit = c->prob.maxit;
+  // flexible CG (mixed-precision preconditioner): z alternates between two
+  // buffers so that (r_new, z_old) is available for the Polak-Ribiere beta
+  const bool flex = FlexTrait<TV>::enabled(c);
+  TV* zbuf[2] = {z, FlexTrait<TV>::second(c, z)};
+  int zi = 0;
   int it = 0, b = 0;
   bool stop = false;
   while (it < maxit && !stop) {
     const int nbt = (maxit - it < batch) ? (maxit - it) : batch;
     for (int k = 0; k < nbt; ++k) {
-      launch_apply(c, c->p, c->q, NR, true);
+      Prec<TV>::apply_dot(c, p, q, NR);
       pcg_alpha_fin<<<1, 256, 0, s>>>(c->partials, nb_apply, st);
-      if (gmg) {
-        pcg_update_kernel<NR, false><<<gb, 256, 0, s>>>(u, c->r, c->p, c->q, c->invd, nd,
-                                                        c->partials, st);
+      if (gmg && flex) {
+        TV* zo = zbuf[zi];
+        TV* zn = zbuf[zi ^ 1];
+        pcg_update_kernel<NR, false, TV><<<gb, 256, 0, s>>>(x, r, p, q, invd, nd, c->partials, st);
         pcg_update_fin<NR, false><<<1, 256, 0, s>>>(c->partials, gb, st, status);
-        gmg_vcycle(c, c->r, c->z, NR);
-        pcg_rz_kernel<NR><<<gb, 256, 0, s>>>(c->r, c->z, nd, c->partials, st);
+        Prec<TV>::vcycle(c, r, zn, NR);
+        if constexpr (std::is_same<TV, double>::value) {
+          pcg_rz2_kernel<NR><<<gb, 256, 0, s>>>(r, zn, zo, nd, c->partials, st);
+          pcg_rz2_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st);
+        }
+        pcg_direction_kernel<NR, false, TV><<<gb, 256, 0, s>>>(p, zn, r, invd, nd, st, 0);
+        zi ^= 1;
+      } else if (gmg) {
+        pcg_update_kernel<NR, false, TV><<<gb, 256, 0, s>>>(x, r, p, q, invd, nd, c->partials, st);
+        pcg_update_fin<NR, false><<<1, 256, 0, s>>>(c->partials, gb, st, status);
+        Prec<TV>::vcycle(c, r, z, NR);
+        pcg_rz_kernel<NR, TV><<<gb, 256, 0, s>>>(r, z, nd, c->partials, st);
         pcg_rz_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, 0, st);
-        pcg_direction_kernel<NR, false><<<gb, 256, 0, s>>>(c->p, c->z, c->r, c->invd, nd, st, 0);
+        pcg_direction_kernel<NR, false, TV><<<gb, 256, 0, s>>>(p, z, r, invd, nd, st, 0);
       } else {
-        pcg_update_kernel<NR, true><<<gb, 256, 0, s>>>(u, c->r, c->p, c->q, c->invd, nd,
-                                                       c->partials, st);
+        pcg_update_kernel<NR, true, TV><<<gb, 256, 0, s>>>(x, r, p, q, invd, nd, c->partials, st);
         pcg_update_fin<NR, true><<<1, 256, 0, s>>>(c->partials, gb, st, status);
-        pcg_direction_kernel<NR, true><<<gb, 256, 0, s>>>(c->p, nullptr, c->r, c->invd, nd, st, 0);
+        pcg_direction_kernel<NR, true, TV><<<gb, 256, 0, s>>>(p, nullptr, r, invd, nd, st, 0);
       }
     }
     it += nbt;
@@ -300,16 +463,212 @@ static void pcg_run(Ctx* c, double* u, double* info) {
     }
     ++b;
   }
-  pcg_info_kernel<<<1, 64, 0, s>>>(st, info, NR, status);
+}
+
+template <int NR>
+static void pcg_run(Ctx* c, double* u, double* info, bool warm) {
+  hipStream_t s = c->stream;
+  PcgState* st = &c->scal->pcg;
+  const unsigned gb = red_grid(c->g.nd);
+  // With the FP32 preconditioner the FP64 true residual is recomputed after
+  // convergence and CG restarts from u while it exceeds rtol ||f||.
+  const bool check = c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG;
+  for (int pass = 0; pass < 4; ++pass) {
+    const bool w = warm || pass > 0;
+    if (w) launch_apply(c, u, c->q, NR, false);
+    pcg_init_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, u, c->r, c->mask, c->g.nn, c->g.dim, w,
+                                           c->partials);
+    pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, c->prob.rtol, st);
+    pcg_iterate<NR, double>(c, u, c->r, c->p, c->q, c->z, c->prob.maxit);
+    if (!check) break;
+    launch_apply(c, u, c->q, NR, false);
+    resid64_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, c->mask, c->g.nn, c->g.dim, c->partials);
+    resid64_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st, &c->scal->restart);
+    (void)hipMemcpyAsync((void*)&c->pinned[8], &c->scal->restart, sizeof(int),
+                         hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    if (!c->pinned[8]) break;
+  }
+  if (info) pcg_info_kernel<<<1, 64, 0, s>>>(st, info, NR, &c->scal->status);
+}
+
+// ------------------------------------------- mixed-precision refinement
+// True residual in FP64: r = Z f - K u; also r32 = (float) r for the inner
+// solve; partial (r,r) and (f,f) per load case.
+template <int NR>
+__global__ __launch_bounds__(256) void ir_residual_kernel(const double* __restrict__ f,
+                                                          const double* __restrict__ Ku,
+                                                          float* r32, const uint8_t* __restrict__ mask,
+                                                          long nn, int dim, const IrState* ir,
+                                                          double* partials) {
+  const long nd = nn * dim;
+  bool act[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) act[k] = ir->outer == 0 || ir->active[k];
+  double acc[2 * NR];
+#pragma unroll
+  for (int k = 0; k < 2 * NR; ++k) acc[k] = 0.0;
+  for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
+    const long n = d % nn;
+    const int c = (int)(d / nn);
+    const bool fixed = (mask[n] >> c) & 1;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const long i = (long)k * nd + d;
+      const double fv = fixed ? 0.0 : f[i];
+      const double rv = fixed ? 0.0 : fv - Ku[i];
+      r32[i] = act[k] ? (float)rv : 0.0f;
+      acc[k] += rv * rv;
+      acc[NR + k] += fv * fv;
+    }
+  }
+  const double none[1] = {0.0};
+  block_partials<2 * NR, 0>(acc, none, partials);
+}
+
+// outer convergence and stagnation test
+template <int NR>
+__global__ void ir_residual_fin(const double* partials, long nb, double rtol, IrState* ir) {
+  __shared__ double tot[2 * NR];
+  reduce_partials<2 * NR, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    int any = 0, stag = 0;
+    for (int k = 0; k < kMaxRhs; ++k) {
+      if (k >= NR) { ir->active[k] = 0; ir->rr[k] = 0; ir->ff[k] = 0; continue; }
+      const double rr = tot[k];
+      if (ir->outer == 0) {
+        ir->ff[k] = tot[NR + k];
+        ir->tol2[k] = rtol * rtol * ir->ff[k];
+        ir->rr_prev[k] = INFINITY;
+      } else {
+        ir->rr_prev[k] = ir->rr[k];
+      }
+      ir->rr[k] = rr;
+      ir->active[k] = (ir->ff[k] > 0.0) && (rr > ir->tol2[k]);
+      if (!isfinite(rr)) { ir->active[k] = 0; stag = 1; }
+      // a refinement step must cut the residual at least in half
+      if (ir->active[k] && ir->outer > 0 && !(rr < 0.25 * ir->rr_prev[k])) stag = 1;
+      any |= ir->active[k];
+    }
+    ir->done = !any;
+    ir->stagnated = stag;
+  }
+}
+
+// u += x32 on the load cases still refining
+template <int NR>
+__global__ __launch_bounds__(256) void ir_accumulate_kernel(double* u, const float* __restrict__ x32,
+                                                            long nd, IrState* ir) {
+  bool act[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) act[k] = ir->active[k] != 0;
+  for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (act[k]) u[(long)k * nd + d] += (double)x32[(long)k * nd + d];
+  }
+}
+
+__global__ void ir_step_done(IrState* ir, const PcgState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ir->outer += 1;
+    ir->inner_total += st->iters;
+  }
+}
+
+__global__ void ir_info_kernel(const IrState* ir, const PcgState* st, double* info, int nr,
+                               int fallback, int* status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (fallback) {
+    // the FP64 solve finished the job: report its residuals
+    if (info) {
+      info[0] = ir->inner_total + st->iters;
+      info[1] = st->done && !st->breakdown;
+      for (int k = 0; k < kMaxRhs; ++k)
+        info[2 + k] = (k < nr && st->ff[k] > 0.0) ? sqrt(st->rr[k] / st->ff[k]) : 0.0;
+    }
+    if (st->breakdown) *status = TOPO_S_NUMERIC;
+    else if (!st->done && *status == 0) *status = TOPO_S_NOT_CONVERGED;
+    return;
+  }
+  if (info) {
+    info[0] = ir->inner_total;
+    info[1] = ir->done;
+    for (int k = 0; k < kMaxRhs; ++k)
+      info[2 + k] = (k < nr && ir->ff[k] > 0.0) ? sqrt(ir->rr[k] / ir->ff[k]) : 0.0;
+  }
+  if (!ir->done && *status == 0) *status = TOPO_S_NOT_CONVERGED;
+}
+
+__global__ void ir_reset(IrState* ir) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ir->outer = 0;
+    ir->inner_total = 0;
+    ir->done = 0;
+    ir->stagnated = 0;
+  }
+}
+
+constexpr double kInnerRtol = 1e-4;
+constexpr int kMaxOuter = 12;
+
+template <int NR>
+static void mixed_run(Ctx* c, double* u, double* info, bool warm) {
+  hipStream_t s = c->stream;
+  PcgState* st = &c->scal->pcg;
+  IrState* ir = &c->scal->ir;
+  const long nd = c->g.nd;
+  const unsigned gb = red_grid(nd);
+  if (!warm) launch_fill(c, u, 0.0, (int64_t)NR * nd);
+  ir_reset<<<1, 1, 0, s>>>(ir);
+  bool fallback = false;
+  for (int outer = 0; outer <= kMaxOuter; ++outer) {
+    launch_apply(c, u, c->q, NR, false);
+    ir_residual_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, c->r32, c->mask, c->g.nn, c->g.dim, ir,
+                                             c->partials);
+    ir_residual_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, c->prob.rtol, ir);
+    (void)hipMemcpyAsync((void*)&c->pinned[6], &ir->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    const int done = c->pinned[6], stag = c->pinned[7];
+    if (done) break;
+    if (stag || outer == kMaxOuter) {
+      fallback = true;
+      break;
+    }
+    // inner FP32 solve of K d = r to kInnerRtol, then u += d
+    inner_init_kernel<NR, float><<<gb, 256, 0, s>>>(c->x32, c->r32, nd, c->partials);
+    pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, kInnerRtol, st);
+    pcg_iterate<NR, float>(c, c->x32, c->r32, c->p32, c->q32, c->z32, c->prob.maxit);
+    ir_accumulate_kernel<NR><<<gb, 256, 0, s>>>(u, c->x32, nd, ir);
+    ir_step_done<<<1, 1, 0, s>>>(ir, st);
+  }
+  if (fallback) {
+    // FP64 PCG from the current iterate
+    pcg_run<NR>(c, u, nullptr, true);
+  }
+  ir_info_kernel<<<1, 64, 0, s>>>(ir, st, info, NR, fallback ? 1 : 0, &c->scal->status);
 }
 
 void pcg_solve(Ctx* c, double* u, double* info) {
   if (c->prob.precond == TOPO_PC_GMG) gmg_setup(c);
+  const bool warm = c->prob.warm_start != 0;
+  const bool mixed = c->prob.precision == TOPO_MIXED_IR;
+  if (mixed) {
+    // FP32 diagonal for the Jacobi variant of the inner solve
+    launch_to_f32(c, c->invd32, c->invd, c->g.nd);
+    switch (c->prob.nrhs) {
+      case 1: mixed_run<1>(c, u, info, warm); break;
+      case 2: mixed_run<2>(c, u, info, warm); break;
+      case 3: mixed_run<3>(c, u, info, warm); break;
+      default: mixed_run<4>(c, u, info, warm); break;
+    }
+    return;
+  }
   switch (c->prob.nrhs) {
-    case 1: pcg_run<1>(c, u, info); break;
-    case 2: pcg_run<2>(c, u, info); break;
-    case 3: pcg_run<3>(c, u, info); break;
-    default: pcg_run<4>(c, u, info); break;
+    case 1: pcg_run<1>(c, u, info, warm); break;
+    case 2: pcg_run<2>(c, u, info, warm); break;
+    case 3: pcg_run<3>(c, u, info, warm); break;
+    default: pcg_run<4>(c, u, info, warm); break;
   }
 }
 

@@ -49,13 +49,25 @@ struct OcState {
   int pad;
 };
 
+// Mixed-precision iterative refinement: FP64 true residual per load case.
+struct IrState {
+  double rr[kMaxRhs], ff[kMaxRhs], tol2[kMaxRhs], rr_prev[kMaxRhs];
+  int active[kMaxRhs];
+  int done;        // all load cases at rtol (read by the host with the next field)
+  int stagnated;   // a refinement step failed to halve a residual norm
+  int outer;
+  int inner_total;
+};
+
 struct DevScalars {
   PcgState pcg;
+  IrState ir;
   OcState oc;
   double compliance;
   double c_energy;
   double c_paper;
   double scratch[8];
+  int restart;      // mixed-precision CG: true residual above tolerance
   int status;       // sticky device status
   int pad;
   unsigned counters[16];  // last-block-done counters, one per reduction site
@@ -114,19 +126,21 @@ struct GmgLevel {
   int64_t nc;
   double* E;                   // [nc] moduli
   double* invd;                // [dim*nn] inverse diagonal
+  float* E32;                  // [nc] FP32 moduli (mixed precision)
+  float* invd32;               // [dim*nn] FP32 inverse diagonal (mixed precision)
   double *b, *x, *r, *d, *q;   // [nrhs][dim*nn]
   double *pv, *pw;             // [dim*nn] power-iteration vectors
   double* lmax;                // device scalar: lambda_max(D^-1 K) estimate
   double* pscale;              // device scalar: power-iteration scale
   double* Ainv;                // coarsest level: dense inverse [n*n]
   uint8_t* mask;               // [nn]
-  size_t off_E, off_invd, off_b, off_x, off_r, off_d, off_q, off_pv, off_pw, off_mask, off_A;
+  size_t off_E, off_invd, off_b, off_x, off_r, off_d, off_q, off_pv, off_pw, off_mask, off_A,
+      off_E32, off_invd32;
 };
 
 struct WsLayout {
   size_t mask, f, E, E32, invd, invd32, r, p, q, z, wv, partials, scal, R, taps,
-      qsoa, dc, dcf, rho_new, rho_tmp, ir_x, ir_r32, ir_p32, ir_q32, ir_z32, ir_u32, gmg_scal,
-      total;
+      qsoa, dc, dcf, rho_new, rho_tmp, r32, p32, q32, z32, x32, gmg_scal, total;
   std::vector<GmgLevel> levels;   // offsets only (pointers filled at creation)
 };
 
@@ -154,9 +168,8 @@ struct Ctx {
   int nclasses;
   double* qsoa;       // [nc] filter input in class-major order
   double *dc, *dcf, *rho_new, *rho_tmp;  // [nc]
-  // mixed-precision inner solve buffers
-  double* ir_x;       // [nrhs][dim][nn] fp64 correction accumulator
-  float *r32, *p32, *q32, *z32, *u32;
+  // mixed-precision inner solve buffers [nrhs][dim][nn]
+  float *r32, *p32, *q32, *z32, *x32;
   bool loads_set;
   // host side
   volatile int* pinned;   // pinned host flags
@@ -180,6 +193,10 @@ void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, 
                      int nrhs, bool fuse_dot, bool timed, const int* stop);
 void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
                          int nrhs, bool timed, const int* stop);
+void launch_apply_op_f32_dot(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
+                             int nrhs);
+void launch_to_f32(Ctx* c, float* dst, const double* src, int64_t n);
+void launch_to_f64(Ctx* c, double* dst, const float* src, int64_t n);
 int pick_kz(int dim, int nx, int ny, int nz);
 void launch_diagonal(Ctx* c, double* d, bool inverse);
 void launch_diagonal_op(Ctx* c, const OpDesc& od, const double* E, double* d, bool inverse);
@@ -189,6 +206,7 @@ void pcg_solve(Ctx* c, double* u, double* info);
 unsigned red_grid(long n);
 void gmg_setup(Ctx* c);
 void gmg_vcycle(Ctx* c, const double* b, double* x, int nrhs);
+void gmg_vcycle_f32(Ctx* c, const float* b, float* x, int nrhs);
 void launch_sensitivity(Ctx* c, const double* rho, const double* u, double* dc, double* compliance);
 void launch_filter(Ctx* c, const double* rho, const double* dc, double* dcf);
 void launch_filter_rowsums(Ctx* c);

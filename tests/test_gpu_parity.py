@@ -59,10 +59,11 @@ def test_apply_and_diagonal(name, p):
     np.testing.assert_allclose(d.cpu().numpy(), fem.jacobi_diag(K, fixed), rtol=1e-13)
 
 
-@pytest.mark.parametrize("pc", ["jacobi", "gmg"])
+@pytest.mark.parametrize("pc", ["jacobi", "gmg", "mixed-gmg", "ir-gmg", "ir-jacobi"])
 @pytest.mark.parametrize("name,p", _problems())
 def test_solve_matches_direct(name, p, pc):
-    from paper_2012_08208_amd import TOPO_PC_GMG, TOPO_PC_JACOBI
+    from paper_2012_08208_amd import (TOPO_FP64, TOPO_MIXED_FP32, TOPO_MIXED_IR, TOPO_PC_GMG,
+                                      TOPO_PC_JACOBI)
     print(f"[solve] {name} {pc}", flush=True)
     m = M.build(p.dim, p.nel, p.split)
     rho = synth.rho_random(3, m.n_cells, 0.05, 1.0)
@@ -70,7 +71,9 @@ def test_solve_matches_direct(name, p, pc):
     K = fem.assemble(m, E, p.nu)
     f = p.loads.reshape(p.nrhs, -1)
     u_ref = fem.solve(K, f, p.fixed.ravel())
-    t = _topo(p, rtol=1e-12, precond=TOPO_PC_GMG if pc == "gmg" else TOPO_PC_JACOBI)
+    t = _topo(p, rtol=1e-12, precond=TOPO_PC_GMG if pc.endswith("gmg") else TOPO_PC_JACOBI,
+              precision={"mixed": TOPO_MIXED_FP32, "ir": TOPO_MIXED_IR}.get(pc.split("-")[0],
+                                                                            TOPO_FP64))
     u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=DEV)
     info = torch.zeros(6, dtype=torch.float64, device=DEV)
     t.solve(_t(rho), u, info)
@@ -209,7 +212,28 @@ def test_iterate_cantilever_60x30_50_iterations_gmg():
     _run_iterate_check(t, p, rho_ref, log_ref)
 
 
-def _run_iterate_check(t, p, rho_ref, log_ref):
+def test_iterate_cantilever_60x30_50_iterations_mixed():
+    # the mixed-precision bar: compliance within rel 1e-7 of the oracle
+    from paper_2012_08208_amd import TOPO_MIXED_FP32, TOPO_PC_GMG
+    p = synth.cantilever2d(60, 30)
+    print("[iterate] cantilever2d 60x30 x50 mixed", flush=True)
+    S = simp.setup(p)
+    rho_ref, log_ref = simp.iterate(S, 50)
+    t = _topo(p, rtol=1e-10, precond=TOPO_PC_GMG, precision=TOPO_MIXED_FP32)
+    _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-7)
+
+
+def test_iterate_cantilever_60x30_50_iterations_mixed_ir():
+    from paper_2012_08208_amd import TOPO_MIXED_IR, TOPO_PC_GMG
+    p = synth.cantilever2d(60, 30)
+    print("[iterate] cantilever2d 60x30 x50 mixed-ir", flush=True)
+    S = simp.setup(p)
+    rho_ref, log_ref = simp.iterate(S, 50)
+    t = _topo(p, rtol=1e-10, precond=TOPO_PC_GMG, precision=TOPO_MIXED_IR)
+    _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-7)
+
+
+def _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-9):
     from paper_2012_08208_amd import LOG_LEN
     rho = torch.full((p.n_cells,), p.volfrac, dtype=torch.float64, device=DEV)
     u = torch.zeros(p.n_dofs, dtype=torch.float64, device=DEV)
@@ -219,7 +243,7 @@ def _run_iterate_check(t, p, rho_ref, log_ref):
     assert t.sync() == 0
     lg = log.cpu().numpy().reshape(50, LOG_LEN)
     c_ref = np.array([r["c"] for r in log_ref])
-    np.testing.assert_allclose(lg[:, 0], c_ref, rtol=1e-9)
+    np.testing.assert_allclose(lg[:, 0], c_ref, rtol=c_rtol)
     np.testing.assert_allclose(lg[:, 2], 0.5, atol=1e-12)
     np.testing.assert_allclose(lg[:, 3], [r["change"] for r in log_ref], atol=1e-6)
     err = np.max(np.abs(rho.cpu().numpy() - rho_ref))
