@@ -7,7 +7,10 @@ clamped, four unit line-load cases solved as four batched right-hand sides
 (compliance summed), volfrac 0.3, p = 3, rmin 2.5 cells, CG relative
 residual 1e-8 per load case.  One step is one full SIMP iteration (solve,
 sensitivity, filter, OC update) on device-resident data; the design evolves
-from step to step as in a real run, starting from rho = volfrac.
+from step to step as in a real run, starting from rho = volfrac, so the
+default 2 warmup + 48 timed steps are iterations 3..50 of a 50-iteration
+run.  Default solve: multigrid-preconditioned CG with the FP32 V-cycle
+inside FP64 flexible CG.
 
 Printed: one JSON line with the throughput, the live roofline of the
 operator-apply kernel (algorithmic bytes per launch / mean launch time from
@@ -106,8 +109,8 @@ def cpu_baseline(p_full, sample_nel=(32, 16, 16)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=48)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cantilever3d")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed-ir"])
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
