@@ -14,11 +14,14 @@ topology optimization in 2D and 3D"):
   eq. filter and eq. filter_cond; Section 4.4, eq. filter_mat);
 * ``oc``    -- the optimality-criteria update with bisection on the
   Lagrange multiplier (Section 3.2, eq. kkt and eq. update; Section 3.2.1);
-* ``simp``  -- the iteration loop (Section 4.3 and the Appendix code).
+* ``simp``  -- the iteration loop (Section 4.3 and the Appendix code);
+* ``net``   -- the convolutional preconditioner network of this library
+  (not in the paper): forward, backward, loss and Adam, in FP64 with
+  optional BF16 rounding at the points where the kernels store.
 
 Only ``tests/``, the entry module's ``smoke()`` and the CPU-baseline leg of
 the benchmark may import this package.  It shares no code with the HIP
 path and imports nothing from it.
 """
 
-from . import mesh, fem, filt, oc, simp  # noqa: F401
+from . import mesh, fem, filt, oc, simp, net  # noqa: F401
