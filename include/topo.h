@@ -72,6 +72,9 @@ enum {
   TOPO_E_WORKSPACE = -7, /* workspace smaller than topo_workspace_size */
   /* sticky device status (topo_sync) */
   TOPO_S_NOT_CONVERGED = 1, /* a solve stopped at maxit; outputs inexact */
+  TOPO_S_LEARNED_FALLBACK = 2, /* the learned-preconditioner CG did not converge
+                                  within its cap; multigrid PCG finished the
+                                  solve (outputs valid) */
   TOPO_S_NUMERIC = -5,      /* NaN/Inf or CG breakdown (p^T K p <= 0) */
   TOPO_S_OC_INFEASIBLE = -6 /* volfrac*N outside [sum lo, sum hi] */
 };
@@ -91,7 +94,21 @@ enum { TOPO_SPLIT_ALT_ROWS = 0, TOPO_SPLIT_UNIFORM = 1 };
                     preconditioner (FP64 dot products) to 1e-4, u += d in
                     FP64; falls back to FP64 CG if a step stagnates. */
 enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1, TOPO_MIXED_IR = 2 };
-enum { TOPO_PC_JACOBI = 0, TOPO_PC_GMG = 1 };
+/* Preconditioner of the CG solve.
+   TOPO_PC_JACOBI:  z = D^-1 r.
+   TOPO_PC_GMG:     one multigrid V-cycle (Chebyshev-Jacobi smoothing,
+                    nested P1 transfers, Galerkin-exact coarse moduli, dense
+                    coarsest solve).
+   TOPO_PC_LEARNED: 3D, TOPO_FP64 only.  Flexible CG (Polak-Ribiere beta)
+                    preconditioned by a two-level cycle whose coarse
+                    correction is the convolutional network of
+                    topo_precond_* below (BF16 MFMA inference); the FP64 true
+                    residual judges convergence, and multigrid PCG takes
+                    over from the current iterate if the flexible CG hits
+                    its iteration cap or breaks down (sticky status
+                    TOPO_S_LEARNED_FALLBACK).  Needs topo_precond_attach and
+                    topo_precond_set_weights before the first solve. */
+enum { TOPO_PC_JACOBI = 0, TOPO_PC_GMG = 1, TOPO_PC_LEARNED = 2 };
 
 /* Problem description (host struct, copied by topo_create). */
 typedef struct topo_problem {
@@ -105,7 +122,7 @@ typedef struct topo_problem {
   double rmin;                /* filter radius in cell widths, > 0 */
   double move, eta, rho_min;  /* OC move limit m, damping eta, lower bound */
   int32_t precision;  /* TOPO_FP64 | TOPO_MIXED_FP32 | TOPO_MIXED_IR */
-  int32_t precond;    /* TOPO_PC_JACOBI | TOPO_PC_GMG */
+  int32_t precond;    /* TOPO_PC_JACOBI | TOPO_PC_GMG | TOPO_PC_LEARNED */
   double rtol;        /* stop when ||f_r - K u_r|| <= rtol ||f_r|| for each r */
   int32_t maxit;      /* cap on preconditioned CG iterations per solve */
   int32_t paper_mode; /* 0: E = Emin + rho^p (E0-Emin), exact dc/drho;
@@ -211,6 +228,89 @@ int topo_sync(topo_ctx* ctx, int* device_status /* host */);
 
 /* Static description of a status or error code. */
 const char* topo_status_string(int code);
+
+/* ------------------------------------------------------------------------
+ * Learned preconditioner (an addition of this library; the paper has no
+ * learned component).  A convolutional encoder-decoder on the FE node grid
+ * (nx+1, ny+1, nz+1) maps (node density, residual) to an approximation of
+ * the error K^{-1} r.  Definition:
+ *   levels: l+1 has ceil(n/2) points per axis, four levels;
+ *   every convolution is 3x3x3, zero padding 1, no bias,
+ *     y[m, co] = sum_t sum_ci W[co][t][ci] x[s*m + d_t - 1, ci],
+ *     tap t = (dz*3 + dy)*3 + dx, stride s in {1, 2};
+ *   activation: leaky ReLU, slope 1/8;
+ *   upsampling: per axis fine[i] = (coarse[i>>1] + coarse[(i+1)>>1]) / 2
+ *     (the second index clamped to the coarse grid);
+ *   layers (flat parameter order, W[co][t][ci] each):
+ *     e0a 8->16, e0b 16->16, d1 16->32 (s2), e1 32->32, d2 32->64 (s2),
+ *     e2 64->64, d3 64->64 (s2), e3 64->64, c2 [up(e3), e2] 128->64,
+ *     c1 [up(c2), e1] 96->32, c0 [up(c1), e0b] 48->16, out 16->3 (linear);
+ *   input channels: mean density of the incident cells, r_c / rms(r)
+ *     (rms = ||r|| / sqrt(3 N_n)), 1 where the node has a fixed component,
+ *     three zeros;
+ *   output: z = gamma * rms(r) * Z N(input) (Z zeroes fixed DOFs).
+ * BF16 weights and activations, FP32 accumulation (MFMA), FP32 master
+ * weights and Adam moments.  Training minimises the K-norm error of the
+ * prediction, L = (g N - e)^T K (g N - e) / (e^T K e) with r = K e and both
+ * scaled by 1/rms(r), by Adam (Kingma and Ba, 2015).
+ * The network state lives in a second caller-owned workspace.  All calls
+ * need a 3D context; vectors are float64 [3][N_n] of one load case.
+ * ---------------------------------------------------------------------- */
+
+/* Number of FP32 parameters of the network. */
+int topo_precond_num_params(int64_t* n /* host */);
+
+/* Bytes of the network workspace for this problem (3D only). */
+int topo_precond_workspace_size(const topo_problem* prob, size_t* bytes /* host */);
+
+/* Attach a network workspace (256-byte aligned, at least the size above) to
+   the context and zero it.  Re-attaching replaces the previous one. */
+int topo_precond_attach(topo_ctx* ctx, void* workspace, size_t ws_bytes);
+
+/* Set the FP32 weights (device [n_params], copied) and reset Adam. */
+int topo_precond_set_weights(topo_ctx* ctx, const float* w);
+
+/* Copy the current FP32 weights to w (device [n_params]). */
+int topo_precond_get_weights(topo_ctx* ctx, float* w);
+
+/* gamma: fixed output gain; fcg_maxit: flexible-CG iterations before the
+   multigrid fallback (>= 1); smooth: 1 = two-level cycle with Chebyshev
+   smoothing around the network, 0 = the network alone. */
+int topo_precond_config(topo_ctx* ctx, double gamma, int fcg_maxit, int smooth);
+
+/* z = gamma * rms(r) * Z N(rho, r): the network alone, one load case.
+   Keeps the activations for topo_precond_backward. */
+int topo_precond_apply(topo_ctx* ctx, const double* rho, const double* r, double* z);
+
+/* Weight gradient of sum(gz * z) for the z of the last topo_precond_apply
+   (gz: float64 [3][N_n]; grad: float32 [n_params], overwritten). */
+int topo_precond_backward(topo_ctx* ctx, const double* gz, float* grad);
+
+/* One training step on the pair (r, e = K^{-1} r) at density rho: forward,
+   loss L (written to *loss, device double), backward, and an Adam step with
+   learning rate lr (lr = 0: gradient only, readable by get_grad). */
+int topo_precond_train_step(topo_ctx* ctx, const double* rho, const double* r, const double* e,
+                            float lr, double* loss);
+
+/* Copy the last weight gradient to grad (device float32 [n_params]). */
+int topo_precond_get_grad(topo_ctx* ctx, float* grad);
+
+/* Training pairs from a multigrid PCG solve of load case 0 (nrhs must be 1)
+   at density rho, from u = 0 to rtol: for each listed iteration k
+   (host array, ascending, k >= 0) the pair e_k = u* - x_k and r_k = K e_k is
+   written to e_out / r_out + i * 3 N_n.  presmooth = 1 replaces each pair by
+   the one the network sees inside the learned cycle: x = S r_k (the
+   fine-level smoother), (r_k - K x, e_k - x).  Returns (>= 0) the number of
+   pairs written, or a TOPO_E_* code; *final_iters (host) = iterations of
+   the solve, so pairs with k >= *final_iters are the converged iterate.
+   Blocks until done. */
+int topo_precond_harvest(topo_ctx* ctx, const double* rho, const int* iters /* host */, int n,
+                         double* r_out, double* e_out, int presmooth,
+                         int* final_iters /* host */);
+
+/* Statistics of the last TOPO_PC_LEARNED solve (host): flexible-CG
+   iterations of its last pass and whether multigrid took over. */
+int topo_precond_stats(topo_ctx* ctx, int* fcg_iters, int* fallback);
 
 #ifdef __cplusplus
 }

@@ -21,6 +21,16 @@ grid are zero.
 
 Activation.  Leaky ReLU with slope 1/8 on the negative side.
 
+Two passes.  The weights are applied twice.  The gate pass feeds the
+density and fixed-node channels (residual channels zeroed) through the
+leaky-ReLU network.  The signal pass feeds the residual channels (density
+and fixed channels zeroed) through the same layers, but each activation is
+replaced by multiplication with the slope the gate pass chose at the same
+unit: 1 where the gate activation is positive, 1/8 elsewhere.  With no
+biases the output is then exactly linear in the residual for a fixed
+design, N(r) = A(rho) r, so inside a solve the preconditioner is one fixed
+linear operator; the density enters through the gates only.
+
 Upsampling.  Nested linear interpolation, per axis:
     fine[i] = (coarse[floor(i/2)] + coarse[ceil(i/2)]) / 2;
 if ceil(i/2) falls off the coarse grid, fine[i] = coarse[floor(i/2)].
@@ -230,67 +240,109 @@ def upsample_transpose(f, coarse_shape):
     return np.einsum("ai,bj,ck,abcq->ijkq", Pz, Py, Px, f)
 
 
-def forward(params, x_in, bf16_round: bool = True):
+def jittered_bf16(rng, eps=1e-7):
+    """BF16 rounding after a random relative perturbation of size eps.  Two
+    evaluations that differ only in FP32-level summation order round a few
+    values the other way; running the oracle with this rounding instead of
+    ``bf16`` measures how far such flips carry (the noise floor of a
+    BF16-storage comparison)."""
+    return lambda a: bf16(np.asarray(a, dtype=np.float64) * (1.0 + eps * rng.standard_normal(np.shape(a))))
+
+
+def _encdec(W, x, S, R, gates):
+    """Encoder-decoder body up to c0.  gates=None: leaky ReLU (the gate
+    pass); otherwise every activation is replaced by the slope the gate
+    pass chose at the same unit (1 where the gate activation is positive,
+    1/8 elsewhere), which keeps the body linear in x."""
+    def act(name, y):
+        if gates is None:
+            return R(lrelu(y))
+        return R(lrelu_grad(gates[name], y))
+
+    a = {"in": x}
+    a["e0a"] = act("e0a", conv(a["in"], W[0], 1, S[0]))
+    a["e0b"] = act("e0b", conv(a["e0a"], W[1], 1, S[0]))
+    a["d1"] = act("d1", conv(a["e0b"], W[2], 2, S[1]))
+    a["e1"] = act("e1", conv(a["d1"], W[3], 1, S[1]))
+    a["d2"] = act("d2", conv(a["e1"], W[4], 2, S[2]))
+    a["e2"] = act("e2", conv(a["d2"], W[5], 1, S[2]))
+    a["d3"] = act("d3", conv(a["e2"], W[6], 2, S[3]))
+    a["e3"] = act("e3", conv(a["d3"], W[7], 1, S[3]))
+    a["cat2"] = np.concatenate([R(upsample(a["e3"], S[2])), a["e2"]], axis=3)
+    a["c2"] = act("c2", conv(a["cat2"], W[8], 1, S[2]))
+    a["cat1"] = np.concatenate([R(upsample(a["c2"], S[1])), a["e1"]], axis=3)
+    a["c1"] = act("c1", conv(a["cat1"], W[9], 1, S[1]))
+    a["cat0"] = np.concatenate([R(upsample(a["c1"], S[0])), a["e0b"]], axis=3)
+    a["c0"] = act("c0", conv(a["cat0"], W[10], 1, S[0]))
+    return a
+
+
+def split_input(x_in):
+    """Gate input (density and fixed-node channels) and signal input
+    (residual channels) of an (nz, ny, nx, 8) input tensor."""
+    xg = np.array(x_in, dtype=np.float64, copy=True)
+    xg[..., 1:4] = 0.0
+    xs = np.zeros_like(xg)
+    xs[..., 1:4] = x_in[..., 1:4]
+    return xg, xs
+
+
+def forward(params, x_in, bf16_round: bool = True, rounder=None):
     """Network forward.  ``params`` is the flat FP32 vector; ``x_in`` is the
-    (nz, ny, nx, 8) input.  Returns (out[..., 3], cache)."""
+    (nz, ny, nx, 8) input.  Two passes share the weights: the gate pass runs
+    the leaky-ReLU network on the density/fixed channels; the signal pass
+    runs it on the residual channels with each activation replaced by the
+    slope the gate pass chose, so the output is linear in the residual.
+    Returns (out[..., 3], cache).  ``rounder`` replaces the BF16 rounding of
+    activations and gradients (weights are always rounded plainly)."""
     R = bf16 if bf16_round else (lambda a: np.asarray(a, dtype=np.float64))
-    W = [R(w) for w in split_params(params)]
+    if rounder is not None:
+        R = rounder
+    W = [(bf16(w) if bf16_round else w) for w in split_params(params)]
     s0 = x_in.shape[:3]
     S = [level_shape(s0, l) for l in range(4)]
-    a = {}
-    a["in"] = R(x_in)
-    a["e0a"] = R(lrelu(conv(a["in"], W[0], 1, S[0])))
-    a["e0b"] = R(lrelu(conv(a["e0a"], W[1], 1, S[0])))
-    a["d1"] = R(lrelu(conv(a["e0b"], W[2], 2, S[1])))
-    a["e1"] = R(lrelu(conv(a["d1"], W[3], 1, S[1])))
-    a["d2"] = R(lrelu(conv(a["e1"], W[4], 2, S[2])))
-    a["e2"] = R(lrelu(conv(a["d2"], W[5], 1, S[2])))
-    a["d3"] = R(lrelu(conv(a["e2"], W[6], 2, S[3])))
-    a["e3"] = R(lrelu(conv(a["d3"], W[7], 1, S[3])))
-    a["cat2"] = np.concatenate([R(upsample(a["e3"], S[2])), a["e2"]], axis=3)
-    a["c2"] = R(lrelu(conv(a["cat2"], W[8], 1, S[2])))
-    a["cat1"] = np.concatenate([R(upsample(a["c2"], S[1])), a["e1"]], axis=3)
-    a["c1"] = R(lrelu(conv(a["cat1"], W[9], 1, S[1])))
-    a["cat0"] = np.concatenate([R(upsample(a["c1"], S[0])), a["e0b"]], axis=3)
-    a["c0"] = R(lrelu(conv(a["cat0"], W[10], 1, S[0])))
+    xg, xs = split_input(x_in)
+    g = _encdec(W, R(xg), S, R, None)
+    a = _encdec(W, R(xs), S, R, g)
     out = conv(a["c0"], W[11], 1, S[0])
-    return out, {"W": W, "a": a, "S": S, "R": R}
+    return out, {"W": W, "a": a, "g": g, "S": S, "R": R}
 
 
 def backward(cache, g_out):
-    """Weight gradient of sum(g_out * out).  Returns the flat FP64 gradient.
-    Activation gradients are rounded where the GPU stores them."""
-    W, a, S, R = cache["W"], cache["a"], cache["S"], cache["R"]
+    """Weight gradient of sum(g_out * out) through the signal pass (the
+    gates are piecewise constant in the weights).  Returns the flat FP64
+    gradient.  Activation gradients are rounded where the GPU stores them."""
+    W, a, G, S, R = cache["W"], cache["a"], cache["g"], cache["S"], cache["R"]
     gW = [None] * len(LAYERS)
     g = np.asarray(g_out, dtype=np.float64)
     gW[11] = conv_grad_weight(a["c0"], g, 1)
-    g = R(lrelu_grad(a["c0"], conv_grad_input(g, W[11], 1, S[0])))      # at c0
+    g = R(lrelu_grad(G["c0"], conv_grad_input(g, W[11], 1, S[0])))      # at c0
     gW[10] = conv_grad_weight(a["cat0"], g, 1)
     gcat0 = R(conv_grad_input(g, W[10], 1, S[0]))
-    g = R(lrelu_grad(a["c1"], upsample_transpose(gcat0[..., :32], S[1])))  # at c1
+    g = R(lrelu_grad(G["c1"], upsample_transpose(gcat0[..., :32], S[1])))  # at c1
     gskip0 = gcat0[..., 32:]
     gW[9] = conv_grad_weight(a["cat1"], g, 1)
     gcat1 = R(conv_grad_input(g, W[9], 1, S[1]))
-    g = R(lrelu_grad(a["c2"], upsample_transpose(gcat1[..., :64], S[2])))  # at c2
+    g = R(lrelu_grad(G["c2"], upsample_transpose(gcat1[..., :64], S[2])))  # at c2
     gskip1 = gcat1[..., 64:]
     gW[8] = conv_grad_weight(a["cat2"], g, 1)
     gcat2 = R(conv_grad_input(g, W[8], 1, S[2]))
-    g = R(lrelu_grad(a["e3"], upsample_transpose(gcat2[..., :64], S[3])))  # at e3
+    g = R(lrelu_grad(G["e3"], upsample_transpose(gcat2[..., :64], S[3])))  # at e3
     gskip2 = gcat2[..., 64:]
     gW[7] = conv_grad_weight(a["d3"], g, 1)
-    g = R(lrelu_grad(a["d3"], conv_grad_input(g, W[7], 1, S[3])))        # at d3
+    g = R(lrelu_grad(G["d3"], conv_grad_input(g, W[7], 1, S[3])))        # at d3
     gW[6] = conv_grad_weight(a["e2"], g, 2)
-    g = R(lrelu_grad(a["e2"], gskip2 + conv_grad_input(g, W[6], 2, S[2])))  # at e2
+    g = R(lrelu_grad(G["e2"], gskip2 + conv_grad_input(g, W[6], 2, S[2])))  # at e2
     gW[5] = conv_grad_weight(a["d2"], g, 1)
-    g = R(lrelu_grad(a["d2"], conv_grad_input(g, W[5], 1, S[2])))        # at d2
+    g = R(lrelu_grad(G["d2"], conv_grad_input(g, W[5], 1, S[2])))        # at d2
     gW[4] = conv_grad_weight(a["e1"], g, 2)
-    g = R(lrelu_grad(a["e1"], gskip1 + conv_grad_input(g, W[4], 2, S[1])))  # at e1
+    g = R(lrelu_grad(G["e1"], gskip1 + conv_grad_input(g, W[4], 2, S[1])))  # at e1
     gW[3] = conv_grad_weight(a["d1"], g, 1)
-    g = R(lrelu_grad(a["d1"], conv_grad_input(g, W[3], 1, S[1])))        # at d1
+    g = R(lrelu_grad(G["d1"], conv_grad_input(g, W[3], 1, S[1])))        # at d1
     gW[2] = conv_grad_weight(a["e0b"], g, 2)
-    g = R(lrelu_grad(a["e0b"], gskip0 + conv_grad_input(g, W[2], 2, S[0])))  # at e0b
+    g = R(lrelu_grad(G["e0b"], gskip0 + conv_grad_input(g, W[2], 2, S[0])))  # at e0b
     gW[1] = conv_grad_weight(a["e0a"], g, 1)
-    g = R(lrelu_grad(a["e0a"], conv_grad_input(g, W[1], 1, S[0])))      # at e0a
+    g = R(lrelu_grad(G["e0a"], conv_grad_input(g, W[1], 1, S[0])))      # at e0a
     gW[0] = conv_grad_weight(a["in"], g, 1)
     return np.concatenate([w.ravel() for w in gW])
 
@@ -325,10 +377,10 @@ def net_input(mesh, rho, r, fixed):
     return x, rms
 
 
-def precondition(mesh, params, gamma, rho, r, fixed, bf16_round=True):
+def precondition(mesh, params, gamma, rho, r, fixed, bf16_round=True, rounder=None):
     """z = gamma * rms(r) * mask * N(input), as a [3][N_n] SoA vector."""
     x, rms = net_input(mesh, rho, r, fixed)
-    out, cache = forward(params, x, bf16_round)
+    out, cache = forward(params, x, bf16_round, rounder)
     z = np.stack([out[..., c].ravel() for c in range(3)])
     free = 1.0 - (np.asarray(fixed).reshape(3, -1) != 0)
     return gamma * rms * free * z, (x, rms, cache)

@@ -24,6 +24,8 @@ TOPO_MIXED_FP32 = 1
 TOPO_MIXED_IR = 2
 TOPO_PC_JACOBI = 0
 TOPO_PC_GMG = 1
+TOPO_PC_LEARNED = 2
+TOPO_S_LEARNED_FALLBACK = 2
 SOLVE_INFO_LEN = 6
 LOG_LEN = 8
 
@@ -32,6 +34,10 @@ EXPORTED = [
     "topo_sensitivity", "topo_filter", "topo_oc_update", "topo_iterate", "topo_apply",
     "topo_diagonal", "topo_filter_rowsums", "topo_timing_enable", "topo_timing_read",
     "topo_sync", "topo_status_string",
+    "topo_precond_num_params", "topo_precond_workspace_size", "topo_precond_attach",
+    "topo_precond_set_weights", "topo_precond_get_weights", "topo_precond_config",
+    "topo_precond_apply", "topo_precond_backward", "topo_precond_train_step",
+    "topo_precond_get_grad", "topo_precond_harvest", "topo_precond_stats",
 ]
 
 
@@ -79,6 +85,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_timing_enable.argtypes = [vp, i32]
     lib.topo_timing_read.argtypes = [vp, P(ctypes.c_int64), P(dbl)]
     lib.topo_sync.argtypes = [vp, P(i32)]
+    lib.topo_precond_num_params.argtypes = [P(ctypes.c_int64)]
+    lib.topo_precond_workspace_size.argtypes = [P(CProblem), P(ctypes.c_size_t)]
+    lib.topo_precond_attach.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.topo_precond_set_weights.argtypes = [vp, vp]
+    lib.topo_precond_get_weights.argtypes = [vp, vp]
+    lib.topo_precond_config.argtypes = [vp, dbl, i32, i32]
+    lib.topo_precond_apply.argtypes = [vp, vp, vp, vp]
+    lib.topo_precond_backward.argtypes = [vp, vp, vp]
+    lib.topo_precond_train_step.argtypes = [vp, vp, vp, vp, ctypes.c_float, vp]
+    lib.topo_precond_get_grad.argtypes = [vp, vp]
+    lib.topo_precond_harvest.argtypes = [vp, vp, P(i32), i32, vp, vp, i32, P(i32)]
+    lib.topo_precond_stats.argtypes = [vp, P(i32), P(i32)]
     lib.topo_status_string.argtypes = [i32]
     lib.topo_status_string.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -259,6 +277,83 @@ class Topo:
         st = ctypes.c_int(0)
         _check(self.lib.topo_sync(self.ctx, ctypes.byref(st)), "topo_sync")
         return int(st.value)
+
+    # ------------------------------------------------- learned preconditioner
+    def precond_attach(self):
+        """Allocates (torch) and attaches the network workspace."""
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib.topo_precond_workspace_size(ctypes.byref(self.prob), ctypes.byref(nbytes)),
+               "topo_precond_workspace_size")
+        self.net_ws = self.torch.empty(int(nbytes.value) + 256, dtype=self.torch.uint8,
+                                       device=self.device)
+        base = self.net_ws.data_ptr()
+        ptr = base + (-base) % 256
+        _check(self.lib.topo_precond_attach(self.ctx, ctypes.c_void_p(ptr), int(nbytes.value)),
+               "topo_precond_attach")
+
+    def precond_set_weights(self, w):
+        _check(self.lib.topo_precond_set_weights(self.ctx, self._ptr(w, num_params(), "w",
+                                                                     self.torch.float32)),
+               "topo_precond_set_weights")
+
+    def precond_get_weights(self, w):
+        _check(self.lib.topo_precond_get_weights(self.ctx, self._ptr(w, num_params(), "w",
+                                                                     self.torch.float32)),
+               "topo_precond_get_weights")
+
+    def precond_config(self, gamma: float = 1.0, fcg_maxit: int = 500, smooth: int = 1):
+        _check(self.lib.topo_precond_config(self.ctx, float(gamma), int(fcg_maxit), int(smooth)),
+               "topo_precond_config")
+
+    def precond_apply(self, rho, r, z):
+        _check(self.lib.topo_precond_apply(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                           self._ptr(r, self.n_dofs, "r"),
+                                           self._ptr(z, self.n_dofs, "z")), "topo_precond_apply")
+
+    def precond_backward(self, gz, grad):
+        _check(self.lib.topo_precond_backward(self.ctx, self._ptr(gz, self.n_dofs, "gz"),
+                                              self._ptr(grad, num_params(), "grad",
+                                                        self.torch.float32)),
+               "topo_precond_backward")
+
+    def precond_train_step(self, rho, r, e, lr: float, loss=None):
+        _check(self.lib.topo_precond_train_step(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                                self._ptr(r, self.n_dofs, "r"),
+                                                self._ptr(e, self.n_dofs, "e"), float(lr),
+                                                self._ptr(loss, 1, "loss")),
+               "topo_precond_train_step")
+
+    def precond_get_grad(self, grad):
+        _check(self.lib.topo_precond_get_grad(self.ctx, self._ptr(grad, num_params(), "grad",
+                                                                  self.torch.float32)),
+               "topo_precond_get_grad")
+
+    def precond_harvest(self, rho, iters, r_out, e_out, presmooth: bool = False):
+        """Returns (pairs written, iterations of the solve)."""
+        it = np.ascontiguousarray(iters, dtype=np.int32)
+        n = it.size
+        fin = ctypes.c_int(0)
+        rc = self.lib.topo_precond_harvest(
+            self.ctx, self._ptr(rho, self.n_cells, "rho"),
+            it.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(n),
+            self._ptr(r_out, n * self.n_dofs, "r_out"), self._ptr(e_out, n * self.n_dofs, "e_out"),
+            int(bool(presmooth)), ctypes.byref(fin))
+        if rc < 0:
+            _check(rc, "topo_precond_harvest")
+        return int(rc), int(fin.value)
+
+    def precond_stats(self):
+        it = ctypes.c_int(0)
+        fb = ctypes.c_int(0)
+        _check(self.lib.topo_precond_stats(self.ctx, ctypes.byref(it), ctypes.byref(fb)),
+               "topo_precond_stats")
+        return int(it.value), int(fb.value)
+
+
+def num_params() -> int:
+    n = ctypes.c_int64(0)
+    _check(load_library().topo_precond_num_params(ctypes.byref(n)), "topo_precond_num_params")
+    return int(n.value)
 
 
 def status_string(code: int) -> str:

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "common.h"
+#include "net.h"
 #include "topo_internal.h"
 
 using namespace topo;
@@ -32,7 +33,9 @@ static bool valid_problem(const topo_problem* p) {
   if (p->precision != TOPO_FP64 && p->precision != TOPO_MIXED_FP32 &&
       p->precision != TOPO_MIXED_IR)
     return false;
-  if (p->precond != TOPO_PC_JACOBI && p->precond != TOPO_PC_GMG) return false;
+  if (p->precond != TOPO_PC_JACOBI && p->precond != TOPO_PC_GMG && p->precond != TOPO_PC_LEARNED)
+    return false;
+  if (p->precond == TOPO_PC_LEARNED && (p->dim != 3 || p->precision != TOPO_FP64)) return false;
   if (p->dim == 2 && p->split2d != TOPO_SPLIT_ALT_ROWS && p->split2d != TOPO_SPLIT_UNIFORM)
     return false;
   return true;
@@ -135,10 +138,16 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
     L.x32 = take(nr * g.nd * 4);
   }
   L.gmg_scal = 0;
+  L.pring = L.qring = 0;
+  if (p->precond == TOPO_PC_LEARNED) {
+    L.pring = take((size_t)kFcgRing * nr * g.nd * 8);
+    L.qring = take((size_t)kFcgRing * nr * g.nd * 8);
+  }
   L.levels.clear();
-  if (p->precond == TOPO_PC_GMG) {
+  if (p->precond != TOPO_PC_JACOBI) {
     L.z = take(nr * g.nd * 8);
-    L.wv = (p->precision == TOPO_MIXED_FP32) ? take(nr * g.nd * 8) : 0;
+    const bool flex = p->precision == TOPO_MIXED_FP32 || p->precond == TOPO_PC_LEARNED;
+    L.wv = flex ? take(nr * g.nd * 8) : 0;
     const std::vector<LevelDims> plan = gmg_plan(g);
     L.gmg_scal = take(8 * 2 * (plan.size() + 1));
     for (size_t l = 0; l < plan.size(); ++l) {
@@ -282,6 +291,8 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->q32 = L.q32 ? (float*)(w + L.q32) : nullptr;
   c->z32 = L.z32 ? (float*)(w + L.z32) : nullptr;
   c->x32 = L.x32 ? (float*)(w + L.x32) : nullptr;
+  c->pring = L.pring ? (double*)(w + L.pring) : nullptr;
+  c->qring = L.qring ? (double*)(w + L.qring) : nullptr;
   // material of the unit-modulus element law
   Material& m = c->m;
   const double nu = prob->nu;
@@ -307,7 +318,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
       if (fixed_mask[(size_t)comp * c->g.nn + n]) bits[n] |= (uint8_t)(1u << comp);
   bool mask_ok = true;
   std::vector<std::vector<uint8_t>> lmasks;
-  if (prob->precond == TOPO_PC_GMG) {
+  if (prob->precond != TOPO_PC_JACOBI) {
     const std::vector<LevelDims> plan = gmg_plan(c->g);
     lmasks.push_back(bits);
     for (size_t l = 0; l < plan.size(); ++l) {
@@ -424,6 +435,7 @@ int topo_destroy(topo_ctx* c) {
   (void)hipEventDestroy(c->ev_poll[0]);
   (void)hipEventDestroy(c->ev_poll[1]);
   (void)hipHostFree((void*)c->pinned);
+  delete c->net;
   delete c;
   return TOPO_OK;
 }
@@ -437,11 +449,16 @@ int topo_set_loads(topo_ctx* c, const double* f, int nrhs) {
 }
 
 static int solve_impl(topo_ctx* c, const double* rho, double* u, double* info, bool warm) {
+  if (c->prob.precond == TOPO_PC_LEARNED && !(c->net && c->net->attached && c->net->weights_set))
+    return TOPO_E_STATE;
   launch_simp_modulus(c, rho);
   launch_diagonal(c, c->invd, true);
   topo_problem saved = c->prob;
   c->prob.warm_start = warm ? 1 : 0;
+  c->cur_rho = rho;
+  if (c->net) c->net->gates_ready = false;   // the gate pass follows the design
   pcg_solve(c, u, info);
+  c->cur_rho = nullptr;
   c->prob = saved;
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
@@ -570,10 +587,105 @@ const char* topo_status_string(int code) {
     case TOPO_E_HIP: return "HIP runtime error";
     case TOPO_E_WORKSPACE: return "workspace too small";
     case TOPO_S_NOT_CONVERGED: return "solve not converged within maxit";
+    case TOPO_S_LEARNED_FALLBACK: return "learned-preconditioner CG fell back to multigrid PCG";
     case TOPO_S_NUMERIC: return "non-finite value or CG breakdown";
     case TOPO_S_OC_INFEASIBLE: return "OC volume target infeasible";
     default: return "unknown status";
   }
+}
+
+// ------------------------------------------------- learned preconditioner
+static bool net_ready(topo_ctx* c) { return c && c->g.dim == 3 && c->net && c->net->attached; }
+
+int topo_precond_num_params(int64_t* n) {
+  if (!n) return TOPO_E_INVALID;
+  *n = 0;
+  const int spec[kNetLayers][2] = {{8, 16},  {16, 16}, {16, 32}, {32, 32}, {32, 64},  {64, 64},
+                                   {64, 64}, {64, 64}, {128, 64}, {96, 32}, {48, 16}, {16, 3}};
+  for (int i = 0; i < kNetLayers; ++i) *n += (int64_t)spec[i][0] * 27 * spec[i][1];
+  return TOPO_OK;
+}
+
+int topo_precond_workspace_size(const topo_problem* prob, size_t* bytes) {
+  if (!valid_problem(prob) || !bytes || prob->dim != 3) return TOPO_E_INVALID;
+  *bytes = net_workspace_bytes(prob->nel[0], prob->nel[1], prob->nel[2]);
+  return TOPO_OK;
+}
+
+int topo_precond_attach(topo_ctx* c, void* ws, size_t bytes) {
+  if (!c || !ws || c->g.dim != 3) return TOPO_E_INVALID;
+  return net_attach(c, ws, bytes);
+}
+
+int topo_precond_set_weights(topo_ctx* c, const float* w) {
+  if (!net_ready(c) || !w) return TOPO_E_INVALID;
+  net_set_weights(c, w);
+  c->net->weights_set = true;
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_precond_get_weights(topo_ctx* c, float* w) {
+  if (!net_ready(c) || !w) return TOPO_E_INVALID;
+  TOPO_HIP(hipMemcpyAsync(w, c->net->w, (size_t)c->net->nparams * 4, hipMemcpyDeviceToDevice,
+                          c->stream));
+  return TOPO_OK;
+}
+
+int topo_precond_config(topo_ctx* c, double gamma, int fcg_maxit, int smooth) {
+  if (!net_ready(c) || !(gamma > 0.0) || fcg_maxit < 1 || (smooth != 0 && smooth != 1))
+    return TOPO_E_INVALID;
+  if (smooth && c->lv.empty()) return TOPO_E_STATE;  // smoothing needs the multigrid level 0
+  c->net->gamma = gamma;
+  c->net->fcg_maxit = fcg_maxit;
+  c->net->smooth = smooth;
+  return TOPO_OK;
+}
+
+int topo_precond_apply(topo_ctx* c, const double* rho, const double* r, double* z) {
+  if (!net_ready(c) || !rho || !r || !z || r == z) return TOPO_E_INVALID;
+  if (!c->net->weights_set) return TOPO_E_STATE;
+  net_precondition(c, rho, r, z, false);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_precond_backward(topo_ctx* c, const double* gz, float* grad) {
+  if (!net_ready(c) || !gz || !grad) return TOPO_E_INVALID;
+  if (!c->net->weights_set) return TOPO_E_STATE;
+  net_backward_from_z(c, gz, grad);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_precond_train_step(topo_ctx* c, const double* rho, const double* r, const double* e,
+                            float lr, double* loss) {
+  if (!net_ready(c) || !rho || !r || !e || !(lr >= 0.f)) return TOPO_E_INVALID;
+  if (!c->net->weights_set) return TOPO_E_STATE;
+  net_train_step(c, rho, r, e, lr, loss);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_precond_get_grad(topo_ctx* c, float* grad) {
+  if (!net_ready(c) || !grad) return TOPO_E_INVALID;
+  TOPO_HIP(hipMemcpyAsync(grad, c->net->grad, (size_t)c->net->nparams * 4, hipMemcpyDeviceToDevice,
+                          c->stream));
+  return TOPO_OK;
+}
+
+int topo_precond_harvest(topo_ctx* c, const double* rho, const int* iters, int n, double* r_out,
+                         double* e_out, int presmooth, int* final_iters) {
+  if (!c || !rho || !iters || n < 1 || !r_out || !e_out) return TOPO_E_INVALID;
+  if (c->prob.nrhs != 1 || c->lv.empty()) return TOPO_E_INVALID;
+  if (!c->loads_set) return TOPO_E_STATE;
+  for (int i = 0; i < n; ++i)
+    if (iters[i] < 0 || (i > 0 && iters[i] <= iters[i - 1])) return TOPO_E_INVALID;
+  if (presmooth != 0 && presmooth != 1) return TOPO_E_INVALID;
+  return pcg_harvest(c, rho, iters, n, r_out, e_out, presmooth, final_iters);
+}
+
+int topo_precond_stats(topo_ctx* c, int* fcg_iters, int* fallback) {
+  if (!net_ready(c)) return TOPO_E_INVALID;
+  if (fcg_iters) *fcg_iters = c->net->last_iters;
+  if (fallback) *fallback = c->net->last_fallback;
+  return TOPO_OK;
 }
 
 }  // extern "C"

@@ -420,7 +420,7 @@ __global__ void to_f32_kernel(float* dst, const double* __restrict__ src, long n
 }
 
 // ------------------------------------------------------------ drivers
-static const int* stop_flag(Ctx* c) { return &c->scal->pcg.done; }
+static const int* stop_flag(Ctx* c) { return c->smooth_always ? nullptr : &c->scal->pcg.done; }
 
 void gmg_setup(Ctx* c) {
   hipStream_t s = c->stream;
@@ -543,6 +543,11 @@ void gmg_vcycle(Ctx* c, const double* b, double* x, int nrhs) {
 
 void gmg_vcycle_f32(Ctx* c, const float* b, float* x, int nrhs) {
   vcycle_level<float>(c, 0, b, x, nrhs);
+}
+
+// the fine-level Chebyshev-Jacobi smoother on its own (FP64)
+void gmg_fine_smooth(Ctx* c, const double* b, double* x, int nrhs, bool from_zero) {
+  cheb_smooth<double>(c, c->lv[0], b, x, nrhs, from_zero);
 }
 
 }  // namespace topo

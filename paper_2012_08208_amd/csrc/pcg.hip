@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "net.h"
 #include "topo_internal.h"
 
 namespace topo {
@@ -357,7 +358,9 @@ struct Prec<double> {
     launch_apply(c, p, q, nr, true);
   }
   static void vcycle(Ctx* c, const double* r, double* z, int nr) {
-    if (c->prob.precision == TOPO_MIXED_FP32) {
+    if (c->prob.precond == TOPO_PC_LEARNED) {
+      learned_precondition(c, r, z, nr);
+    } else if (c->prob.precision == TOPO_MIXED_FP32) {
       // FP32 V-cycle as the preconditioner of the FP64 iteration
       const int64_t n = (int64_t)nr * c->g.nd;
       launch_to_f32(c, c->r32, r, n);
@@ -387,7 +390,8 @@ struct FlexTrait {
 template <>
 struct FlexTrait<double> {
   static bool enabled(Ctx* c) {
-    return c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG;
+    return (c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG) ||
+           c->prob.precond == TOPO_PC_LEARNED;
   }
   static double* second(Ctx* c, double* z) { return c->wv ? c->wv : z; }
 };
@@ -400,8 +404,18 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
   PcgState* st = &c->scal->pcg;
   int* status = &c->scal->status;
   hipStream_t s = c->stream;
-  const bool gmg = c->prob.precond == TOPO_PC_GMG;
+  const bool gmg = c->prob.precond != TOPO_PC_JACOBI;
   const TV* invd = Prec<TV>::invd(c);
+  Capture* cap = std::is_same<TV, double>::value ? c->cap : nullptr;
+  auto capture = [&](int k) {
+    // x_k of a listed iteration (stream-ordered copy of the iterate)
+    if (cap && cap->next < cap->n && cap->iters[cap->next] == k) {
+      (void)hipMemcpyAsync(cap->dst + (long)cap->next * cap->nd, x, sizeof(double) * cap->nd,
+                           hipMemcpyDeviceToDevice, s);
+      cap->next += 1;
+    }
+  };
+  capture(0);
   const unsigned gb = red_grid(nd);
   const long nb_apply = apply_grid_blocks(fine_op(c), NR);
   if (gmg) {
@@ -451,6 +465,7 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
         pcg_update_fin<NR, true><<<1, 256, 0, s>>>(c->partials, gb, st, status);
         pcg_direction_kernel<NR, true, TV><<<gb, 256, 0, s>>>(p, nullptr, r, invd, nd, st, 0);
       }
+      capture(it + k + 1);
     }
     it += nbt;
     // poll the previous batch's flag while this batch runs
@@ -465,29 +480,226 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
   }
 }
 
+// ------------------------------------------- truncated flexible CG
+// Flexible CG with truncated K-orthogonalisation (Notay's FCG(m)) for the
+// learned preconditioner, which varies from one application to the next:
+//   z_k = M(r_k);  p_k = z_k - sum_{j in window} (z_k, q_j) / (p_j, q_j) p_j;
+//   q_k = K p_k;  alpha = (p_k, r_k) / (p_k, q_k);  x += alpha p_k;  r -= alpha q_k
+// over the last m directions (m = min(8, 15 / nrhs)).  With a fixed SPD
+// preconditioner it is PCG in exact arithmetic.
+struct FcgSlots {
+  int n;
+  int slot[kFcgWindow];
+};
+
+template <int NR>
+__global__ __launch_bounds__(256) void fcg_dots_kernel(const double* __restrict__ z,
+                                                       const double* __restrict__ qring, FcgSlots sl,
+                                                       long nd, double* partials, const PcgState* st) {
+  if (st->done) return;
+  double acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const double zv = z[(long)k * nd + i];
+      for (int w = 0; w < sl.n; ++w)
+        acc[w * NR + k] += zv * qring[((long)sl.slot[w] * NR + k) * nd + i];
+    }
+  }
+  const double none[1] = {0.0};
+  block_partials<16, 0>(acc, none, partials);
+}
+
+template <int NR>
+__global__ void fcg_beta_fin(const double* partials, long nb, FcgSlots sl, DevScalars* sc) {
+  if (sc->pcg.done) return;
+  __shared__ double tot[16];
+  reduce_partials<16, 0>(partials, nb, tot);
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kFcgWindow; ++w)
+      for (int k = 0; k < kMaxRhs; ++k) {
+        const double pq = (w < sl.n && k < NR) ? sc->fcg_pq[sl.slot[w]][k] : 0.0;
+        sc->fcg_beta[w][k] = (pq > 0.0) ? tot[w * NR + k] / pq : 0.0;
+      }
+}
+
+// p_cur = z - sum_w beta_w p_slot(w); partial (p_cur, r)
+template <int NR>
+__global__ __launch_bounds__(256) void fcg_direction_kernel(double* pring, const double* __restrict__ z,
+                                                            const double* __restrict__ r, FcgSlots sl,
+                                                            int cur, long nd, const DevScalars* sc,
+                                                            double* partials) {
+  if (sc->pcg.done) return;
+  double be[kFcgWindow][NR];
+  for (int w = 0; w < kFcgWindow; ++w)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) be[w][k] = sc->fcg_beta[w][k];
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      double v = z[(long)k * nd + i];
+      for (int w = 0; w < sl.n; ++w) v -= be[w][k] * pring[((long)sl.slot[w] * NR + k) * nd + i];
+      pring[((long)cur * NR + k) * nd + i] = v;
+      acc[k] += v * r[(long)k * nd + i];
+    }
+  }
+  const double none[1] = {0.0};
+  block_partials<NR, 0>(acc, none, partials);
+}
+
+// (p, r) -> st->rz; a non-positive value is a breakdown
+template <int NR>
+__global__ void fcg_pr_fin(const double* partials, long nb, PcgState* st) {
+  if (st->done) return;
+  __shared__ double tot[NR];
+  reduce_partials<NR, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NR; ++k) {
+      if (!st->active[k]) continue;
+      st->rz[k] = tot[k];
+      if (!(tot[k] > 0.0)) { st->breakdown = 1; st->active[k] = 0; }
+    }
+    if (st->breakdown) st->done = 1;
+  }
+}
+
+// alpha = (p, r) / (p, K p); (p, K p) kept for later orthogonalisations
+__global__ void fcg_alpha_fin(const double* partials, long nb, DevScalars* sc, int cur) {
+  PcgState* st = &sc->pcg;
+  if (st->done) return;
+  __shared__ double tot[kMaxRhs];
+  reduce_partials<kMaxRhs, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    for (int r = 0; r < kMaxRhs; ++r) {
+      st->pq[r] = tot[r];
+      sc->fcg_pq[cur][r] = tot[r];
+      if (st->active[r]) {
+        if (!(tot[r] > 0.0)) { st->breakdown = 1; st->alpha[r] = 0.0; }
+        else st->alpha[r] = st->rz[r] / tot[r];
+      } else {
+        st->alpha[r] = 0.0;
+      }
+    }
+  }
+}
+
+template <int NR>
+static void fcg_iterate(Ctx* c, double* x, double* r, double* z, int maxit) {
+  const long nd = c->g.nd;
+  PcgState* st = &c->scal->pcg;
+  int* status = &c->scal->status;
+  hipStream_t s = c->stream;
+  const unsigned gb = red_grid(nd);
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR);
+  const int m = kFcgWindow < 15 / NR ? kFcgWindow : 15 / NR;
+  int it = 0, b = 0, k = 0;
+  bool stop = false;
+  const int batch = 2;
+  while (it < maxit && !stop) {
+    const int nbt = (maxit - it < batch) ? (maxit - it) : batch;
+    for (int q = 0; q < nbt; ++q, ++k) {
+      const int cur = k % kFcgRing;
+      FcgSlots sl;
+      sl.n = k < m ? k : m;
+      for (int w = 0; w < sl.n; ++w) sl.slot[w] = (k - 1 - w) % kFcgRing;
+      for (int w = sl.n; w < kFcgWindow; ++w) sl.slot[w] = 0;
+      learned_precondition(c, r, z, NR);
+      if (sl.n > 0) {
+        fcg_dots_kernel<NR><<<gb, 256, 0, s>>>(z, c->qring, sl, nd, c->partials, st);
+        fcg_beta_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, sl, c->scal);
+      }
+      fcg_direction_kernel<NR><<<gb, 256, 0, s>>>(c->pring, z, r, sl, cur, nd, c->scal, c->partials);
+      fcg_pr_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st);
+      double* pc = c->pring + (long)cur * NR * nd;
+      double* qc = c->qring + (long)cur * NR * nd;
+      launch_apply(c, pc, qc, NR, true);
+      fcg_alpha_fin<<<1, 256, 0, s>>>(c->partials, nb_apply, c->scal, cur);
+      pcg_update_kernel<NR, false, double><<<gb, 256, 0, s>>>(x, r, pc, qc, nullptr, nd, c->partials, st);
+      pcg_update_fin<NR, false><<<1, 256, 0, s>>>(c->partials, gb, st, status);
+    }
+    it += nbt;
+    const int sl2 = b & 1;
+    (void)hipMemcpyAsync((void*)&c->pinned[sl2], &st->done, sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipEventRecord(c->ev_poll[sl2], s);
+    if (b > 0) {
+      (void)hipEventSynchronize(c->ev_poll[sl2 ^ 1]);
+      if (c->pinned[sl2 ^ 1]) stop = true;
+    }
+    ++b;
+  }
+}
+
+__global__ void iters_mark_kernel(PcgState* st, int mode, int* status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (mode == 0) {
+    st->iters_prev = 0;
+  } else if (mode == 1) {
+    // learned run abandoned: keep its count, clear the breakdown flag
+    st->iters_prev = st->iters;
+    st->breakdown = 0;
+  } else {
+    st->iters += st->iters_prev;
+    if (*status == 0) *status = TOPO_S_LEARNED_FALLBACK;
+  }
+}
+
 template <int NR>
 static void pcg_run(Ctx* c, double* u, double* info, bool warm) {
   hipStream_t s = c->stream;
   PcgState* st = &c->scal->pcg;
   const unsigned gb = red_grid(c->g.nd);
-  // With the FP32 preconditioner the FP64 true residual is recomputed after
-  // convergence and CG restarts from u while it exceeds rtol ||f||.
-  const bool check = c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG;
+  const bool learned = c->prob.precond == TOPO_PC_LEARNED;
+  // With a variable (FP32 or learned) preconditioner the FP64 true residual
+  // is recomputed after convergence and CG restarts from u while it exceeds
+  // rtol ||f||.
+  const bool check =
+      (c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG) || learned;
+  int maxit = c->prob.maxit;
+  if (learned && c->net->fcg_maxit < maxit) maxit = c->net->fcg_maxit;
+  bool fallback = false;
+  if (learned) iters_mark_kernel<<<1, 1, 0, s>>>(st, 0, &c->scal->status);
   for (int pass = 0; pass < 4; ++pass) {
     const bool w = warm || pass > 0;
     if (w) launch_apply(c, u, c->q, NR, false);
     pcg_init_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, u, c->r, c->mask, c->g.nn, c->g.dim, w,
                                            c->partials);
     pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, c->prob.rtol, st);
-    pcg_iterate<NR, double>(c, u, c->r, c->p, c->q, c->z, c->prob.maxit);
+    if (learned) fcg_iterate<NR>(c, u, c->r, c->z, maxit);
+    else pcg_iterate<NR, double>(c, u, c->r, c->p, c->q, c->z, maxit);
     if (!check) break;
     launch_apply(c, u, c->q, NR, false);
     resid64_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, c->mask, c->g.nn, c->g.dim, c->partials);
     resid64_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st, &c->scal->restart);
     (void)hipMemcpyAsync((void*)&c->pinned[8], &c->scal->restart, sizeof(int),
                          hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync((void*)&c->pinned[9], &st->done, 3 * sizeof(int), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
-    if (!c->pinned[8]) break;
+    if (learned) {
+      // pinned[9..11] = done, iters, breakdown
+      c->net->last_iters = c->pinned[10];
+      if (!c->pinned[8] && !c->pinned[11]) break;
+      if (!c->pinned[9] || c->pinned[11] || pass == 3) {
+        fallback = true;   // FCG hit its cap or broke down: multigrid PCG judges
+        break;
+      }
+    } else if (!c->pinned[8]) {
+      break;
+    }
+  }
+  if (fallback) {
+    iters_mark_kernel<<<1, 1, 0, s>>>(st, 1, &c->scal->status);
+    c->prob.precond = TOPO_PC_GMG;
+    pcg_run<NR>(c, u, nullptr, true);
+    c->prob.precond = TOPO_PC_LEARNED;
+    iters_mark_kernel<<<1, 1, 0, s>>>(st, 2, &c->scal->status);
+    c->net->last_fallback = 1;
+  } else if (learned) {
+    c->net->last_fallback = 0;
   }
   if (info) pcg_info_kernel<<<1, 64, 0, s>>>(st, info, NR, &c->scal->status);
 }
@@ -649,8 +861,78 @@ static void mixed_run(Ctx* c, double* u, double* info, bool warm) {
   ir_info_kernel<<<1, 64, 0, s>>>(ir, st, info, NR, fallback ? 1 : 0, &c->scal->status);
 }
 
+// Training data: GMG-PCG on load case 0 from u = 0; the iterate x_k of each
+// listed iteration k is kept, and after convergence the pair
+// e_k = u* - x_k, r_k = K e_k is written out (exact pairs, r = K e).
+__global__ void harvest_error_kernel(double* e, const double* __restrict__ u,
+                                     const uint8_t* __restrict__ mask, long nn, int dim) {
+  for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nn * dim;
+       d += (long)gridDim.x * blockDim.x) {
+    const long n = d % nn;
+    const int cc = (int)(d / nn);
+    e[d] = ((mask[n] >> cc) & 1) ? 0.0 : u[d] - e[d];
+  }
+}
+
+// (r, e) <- (r - K x, e - x) on free DOFs: the pre-smoothed pair
+__global__ void presmooth_pair_kernel(double* r, double* e, const double* __restrict__ x,
+                                      const double* __restrict__ Kx, const uint8_t* __restrict__ mask,
+                                      long nn, int dim) {
+  for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nn * dim;
+       d += (long)gridDim.x * blockDim.x) {
+    const long n = d % nn;
+    const int cc = (int)(d / nn);
+    if ((mask[n] >> cc) & 1) continue;
+    r[d] -= Kx[d];
+    e[d] -= x[d];
+  }
+}
+
+int pcg_harvest(Ctx* c, const double* rho, const int* iters, int n, double* r_out, double* e_out,
+                int presmooth, int* final_iters) {
+  hipStream_t s = c->stream;
+  const long nd = c->g.nd;
+  const topo_problem saved = c->prob;
+  c->prob.precond = TOPO_PC_GMG;
+  c->prob.precision = TOPO_FP64;
+  launch_simp_modulus(c, rho);
+  launch_diagonal(c, c->invd, true);
+  gmg_setup(c);
+  // the iterate u lives in r_out's first slot until the pairs are formed
+  double* u = r_out;
+  Capture cap{iters, n, 0, e_out, nd};
+  c->cap = &cap;
+  pcg_run<1>(c, u, nullptr, false);
+  c->cap = nullptr;
+  c->prob = saved;
+  // r_out[0] holds u*; form the errors first, then overwrite r_out in reverse
+  for (int k = 0; k < cap.next; ++k)
+    harvest_error_kernel<<<red_grid(nd), 256, 0, s>>>(e_out + (long)k * nd, u, c->mask, c->g.nn,
+                                                      c->g.dim);
+  for (int k = cap.next - 1; k >= 0; --k)
+    launch_apply_op(c, fine_op(c), c->E, e_out + (long)k * nd, r_out + (long)k * nd, 1, false, false,
+                    nullptr);
+  if (presmooth) {
+    // the pair the network sees inside the learned two-level cycle:
+    // x = S r, r1 = r - K x, e1 = e - x (still r1 = K e1)
+    c->smooth_always = true;
+    for (int k = 0; k < cap.next; ++k) {
+      double* rk = r_out + (long)k * nd;
+      gmg_fine_smooth(c, rk, c->p, 1, true);
+      launch_apply_op(c, fine_op(c), c->E, c->p, c->q, 1, false, false, nullptr);
+      presmooth_pair_kernel<<<red_grid(nd), 256, 0, s>>>(rk, e_out + (long)k * nd, c->p, c->q,
+                                                         c->mask, c->g.nn, c->g.dim);
+    }
+    c->smooth_always = false;
+  }
+  (void)hipMemcpyAsync((void*)&c->pinned[12], &c->scal->pcg.iters, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return TOPO_E_HIP;
+  if (final_iters) *final_iters = c->pinned[12];
+  return cap.next;
+}
+
 void pcg_solve(Ctx* c, double* u, double* info) {
-  if (c->prob.precond == TOPO_PC_GMG) gmg_setup(c);
+  if (c->prob.precond != TOPO_PC_JACOBI) gmg_setup(c);
   const bool warm = c->prob.warm_start != 0;
   const bool mixed = c->prob.precision == TOPO_MIXED_IR;
   if (mixed) {

@@ -17,6 +17,8 @@ constexpr int kMaxRhs = 4;
 constexpr int kRedBlocks = 1024;   // fixed block count of grid-stride reductions
 constexpr int kMaxFilterTaps = 2048;
 constexpr int kMaxFilterClasses = 6;
+constexpr int kFcgWindow = 8;                 // directions kept by truncated flexible CG
+constexpr int kFcgRing = kFcgWindow + 1;      // ring slots (window + the new direction)
 
 // Scalars that live in device memory (part of the workspace).
 struct PcgState {
@@ -32,7 +34,7 @@ struct PcgState {
   int done;
   int iters;
   int breakdown;
-  int pad;
+  int iters_prev;   // iterations of an abandoned learned-preconditioner run
 };
 
 struct OcState {
@@ -71,6 +73,8 @@ struct DevScalars {
   int status;       // sticky device status
   int pad;
   unsigned counters[16];  // last-block-done counters, one per reduction site
+  double fcg_pq[kFcgRing][kMaxRhs];       // (p_j, K p_j) of the ring slots
+  double fcg_beta[kFcgWindow][kMaxRhs];   // orthogonalisation coefficients
 };
 
 enum CounterId {
@@ -140,8 +144,20 @@ struct GmgLevel {
 
 struct WsLayout {
   size_t mask, f, E, E32, invd, invd32, r, p, q, z, wv, partials, scal, R, taps,
-      qsoa, dc, dcf, rho_new, rho_tmp, r32, p32, q32, z32, x32, gmg_scal, total;
+      qsoa, dc, dcf, rho_new, rho_tmp, r32, p32, q32, z32, x32, gmg_scal, pring, qring, total;
   std::vector<GmgLevel> levels;   // offsets only (pointers filled at creation)
+};
+
+struct NetState;
+
+// Snapshots of the CG iterate x_k at chosen iterations k (training-data
+// harvest): x_k of the i-th listed iteration goes to dst + i * nd.
+struct Capture {
+  const int* iters;  // host, ascending
+  int n;
+  int next;
+  double* dst;
+  long nd;
 };
 
 struct Ctx {
@@ -170,6 +186,7 @@ struct Ctx {
   double *dc, *dcf, *rho_new, *rho_tmp;  // [nc]
   // mixed-precision inner solve buffers [nrhs][dim][nn]
   float *r32, *p32, *q32, *z32, *x32;
+  double *pring, *qring;   // truncated flexible CG: [kFcgRing][nrhs][dim][nn]
   bool loads_set;
   // host side
   volatile int* pinned;   // pinned host flags
@@ -181,6 +198,11 @@ struct Ctx {
   double t_ms;
   int apply_kz;       // z-chunk (node planes) of the 3D apply
   std::vector<GmgLevel> lv;   // multigrid hierarchy (empty for Jacobi)
+  NetState* net;              // learned preconditioner (attached on request)
+  const int* net_stop;        // device flag that makes network kernels return
+  const double* cur_rho;      // density of the solve in progress
+  Capture* cap;               // harvest of CG iterates (null otherwise)
+  bool smooth_always;         // multigrid kernels ignore the CG stop flag
 };
 
 // ---- launchers (defined in the .hip files) ----
@@ -207,6 +229,10 @@ unsigned red_grid(long n);
 void gmg_setup(Ctx* c);
 void gmg_vcycle(Ctx* c, const double* b, double* x, int nrhs);
 void gmg_vcycle_f32(Ctx* c, const float* b, float* x, int nrhs);
+void gmg_fine_smooth(Ctx* c, const double* b, double* x, int nrhs, bool from_zero);
+void learned_precondition(Ctx* c, const double* r, double* z, int nrhs);
+int pcg_harvest(Ctx* c, const double* rho, const int* iters, int n, double* r_out, double* e_out,
+                int presmooth, int* final_iters);
 void launch_sensitivity(Ctx* c, const double* rho, const double* u, double* dc, double* compliance);
 void launch_filter(Ctx* c, const double* rho, const double* dc, double* dcf);
 void launch_filter_rowsums(Ctx* c);

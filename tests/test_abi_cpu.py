@@ -55,3 +55,23 @@ def test_workspace_size_and_validation():
     bad = b.make_problem(2, (8, 4), volfrac=0.0)
     assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == -1
     assert lib.topo_status_string(-7) == b"workspace too small"
+
+
+def test_network_parameter_count_and_workspace():
+    from oracle import net
+    b = _lib()
+    lib = b.load_library()
+    assert b.num_params() == net.n_params()
+    p = b.make_problem(3, (128, 64, 64), nrhs=1, precond=b.TOPO_PC_LEARNED)
+    n = ctypes.c_size_t(0)
+    assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    assert lib.topo_precond_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    v0 = 129 * 65 * 65
+    assert n.value > v0 * 2 * (8 + 16 + 48 + 16)   # level-0 activations
+    assert n.value < 4 * 1024 ** 3
+    # the learned preconditioner is 3D and FP64 only
+    bad = b.make_problem(2, (8, 4), precond=b.TOPO_PC_LEARNED)
+    assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == -1
+    bad = b.make_problem(3, (8, 4, 4), precond=b.TOPO_PC_LEARNED, precision=b.TOPO_MIXED_FP32)
+    assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == -1
+    assert b"learned" in lib.topo_status_string(2)

@@ -172,3 +172,25 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(w1, w - 0.01 * np.sign(g), rtol=1e-14)
     np.testing.assert_allclose(m, 0.1 * g)
     np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_output_is_linear_in_the_residual():
+    """The signal pass is gated by the density-only pass, so for a fixed
+    design the network is a linear map of the residual channels."""
+    shape = (5, 5, 9)
+    params = net.init_params(21).astype(np.float64)
+    base = _rand(shape + (8,), 22)
+    x1, x2 = base.copy(), base.copy()
+    x2[..., 1:4] = _rand(shape + (3,), 23)
+    a, b = 0.7, -2.3
+    x3 = base.copy()
+    x3[..., 1:4] = a * x1[..., 1:4] + b * x2[..., 1:4]
+    o1, _ = net.forward(params, x1, bf16_round=False)
+    o2, _ = net.forward(params, x2, bf16_round=False)
+    o3, _ = net.forward(params, x3, bf16_round=False)
+    np.testing.assert_allclose(o3, a * o1 + b * o2, rtol=1e-11, atol=1e-12 * np.abs(o3).max())
+    # the density channel changes the gates (and so the map), not an offset
+    x4 = x1.copy()
+    x4[..., 1:4] = 0.0
+    o4, _ = net.forward(params, x4, bf16_round=False)
+    assert np.all(o4 == 0.0)
