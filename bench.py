@@ -98,12 +98,176 @@ def cpu_baseline(p_full, sample_nel=(32, 16, 16)):
         "unit": "SIMP iter/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"one oracle SIMP iteration (sparse LU solve of 4 load cases, k-d tree "
+        "sample": (f"one oracle SIMP iteration (sparse LU solve of {p.nrhs} load case(s), k-d tree "
                    f"filter, bisection OC) on {sample_nel[0]}x{sample_nel[1]}x{sample_nel[2]} "
                    f"cubes ({p.n_cells} cells, {p.n_dofs} DOFs) in {dt:.2f} s; rate scaled by "
                    f"the cell ratio {scale:.3e}; SuperLU and NumPy single-threaded; host "
                    f"{platform.processor() or platform.machine()}, {os.cpu_count()} cores visible"),
     }
+
+
+def conv_flops_per_pass(nel) -> float:
+    """Algorithmic FLOPs of one signal pass of the preconditioner network:
+    2 * voxels_out * 27 * cin * cout per convolution, channel counts as the
+    network defines them (upsampling is not counted)."""
+    dims = [tuple(n + 1 for n in nel)]
+    for _ in range(3):
+        dims.append(tuple((n + 1) // 2 for n in dims[-1]))
+    V = [d[0] * d[1] * d[2] for d in dims]
+    layers = [(0, 8, 16), (0, 16, 16), (1, 16, 32), (1, 32, 32), (2, 32, 64), (2, 64, 64),
+              (3, 64, 64), (3, 64, 64), (2, 128, 64), (1, 96, 32), (0, 48, 16), (0, 16, 3)]
+    return float(sum(2.0 * V[lo] * 27 * ci * co for lo, ci, co in layers))
+
+
+def bench_learned(args):
+    """Learned-preconditioner workload: 128 x 64 x 64 cubes (6 tets each,
+    1,635,075 DOFs), load case 1, rtol 1e-8.  Untimed set-up: pairs
+    harvested from FP64 multigrid PCG along three seeded SIMP histories
+    (the canonical problem and two with volfrac ~ U[0.3, 0.5], rmin ~
+    U[1.5, 3]), then on-GPU training.  Reported: time to solution on a
+    held-out later design for FP64 multigrid PCG, mixed multigrid PCG, the
+    learned flexible CG and the same cycle without the network; timed: SIMP
+    iterations with the learned preconditioner."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2012_08208_amd import (LOG_LEN, TOPO_FP64, TOPO_MIXED_FP32, TOPO_PC_GMG, Topo,
+                                      learned)
+    dev = torch.device("cuda:0")
+    p = synth.learned3d(rtol=1e-8)
+    its = [1, 2, 4, 8, 16, 24]
+    t = learned.gmg_context(p, rtol=1e-8, device=dev)
+    t0 = time.perf_counter()
+    sets = [learned.harvest_history(t, n_designs=5, simp_steps=4, harvest_iters=its)]
+    rng = np.random.default_rng(20120820)
+    for v in range(2):
+        pv = synth.learned3d(rtol=1e-8, volfrac=float(rng.uniform(0.3, 0.5)),
+                             rmin=float(rng.uniform(1.5, 3.0)))
+        tv = learned.gmg_context(pv, rtol=1e-8, device=dev)
+        sets.append(learned.harvest_history(tv, n_designs=4, simp_steps=5, harvest_iters=its))
+        tv.close()
+    ps = learned.PairSet(
+        rhos=[r for s_ in sets for r in s_.rhos],
+        R=torch.cat([s_.R for s_ in sets]), E=torch.cat([s_.E for s_ in sets]),
+        design=np.concatenate([s_.design + sum(len(x.rhos) for x in sets[:i])
+                               for i, s_ in enumerate(sets)]),
+        iters=[k for s_ in sets for k in s_.iters])
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    print(f"[bench] harvested {ps.R.shape[0]} pairs in {t_harvest:.1f} s", file=sys.stderr, flush=True)
+    gamma = learned.choose_gamma(ps)
+    rho_test = sets[0].rhos[-1].clone()
+    u = torch.zeros(p.n_dofs, dtype=torch.float64, device=dev)
+    t.iterate(rho_test, u, 4)            # a later design than any trained on
+    w = learned.init_weights(60, dev)
+    t.precond_set_weights(w)
+    t.precond_config(gamma, 500, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = learned.train(t, ps, steps=args.train_steps, lr=1e-3, seed=61, lr_final=1e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    L = losses.cpu().numpy()
+    print(f"[bench] trained {args.train_steps} steps in {t_train:.1f} s, loss {L[:100].mean():.3f} -> "
+          f"{L[-100:].mean():.3f}", file=sys.stderr, flush=True)
+    t.precond_get_weights(w)
+    t.close()
+
+    def tts(tt, reps=3):
+        best = None
+        for _ in range(reps):
+            uu = torch.zeros(p.n_dofs, dtype=torch.float64, device=dev)
+            info = torch.zeros(6, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            tt.solve(rho_test, uu, info)
+            st = tt.sync()
+            dt = time.perf_counter() - a
+            if best is None or dt < best[0]:
+                best = (dt, info.cpu().numpy(), st)
+        return {"iters": int(best[1][0]), "ms": 1e3 * best[0], "relres": float(best[1][2]),
+                "status": int(best[2])}
+
+    res = {}
+    for name, prec in (("gmg_fp64", TOPO_FP64), ("gmg_mixed_fp32", TOPO_MIXED_FP32)):
+        tg = Topo.from_problem(p, precond=TOPO_PC_GMG, precision=prec, rtol=1e-8, device=dev)
+        res[name] = tts(tg)
+        tg.close()
+    tz = learned.learned_context(p, torch.zeros_like(w), gamma, 5000, 1, rtol=1e-8, device=dev)
+    res["cycle_without_network"] = tts(tz, reps=1)
+    tz.close()
+    tl = learned.learned_context(p, w, gamma, 5000, 1, rtol=1e-8, device=dev)
+    res["learned_fcg"] = tts(tl)
+    for k, v in res.items():
+        print(f"[bench] time to solution {k}: {v}", file=sys.stderr, flush=True)
+    # timed SIMP iterations with the learned preconditioner
+    rho = rho_test.clone()
+    uu = torch.zeros(p.n_dofs, dtype=torch.float64, device=dev)
+    log = torch.zeros(max(1, args.steps) * LOG_LEN, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        tl.iterate(rho, uu, 1, 0.0, None)
+    tl.timing_enable(True)
+    tl.timing_read()
+    tl.timing_read_net()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for s_ in range(args.steps):
+        tl.iterate(rho, uu, 1, 0.0, log[s_ * LOG_LEN:(s_ + 1) * LOG_LEN])
+        print(f"[bench] timed step {s_ + 1}/{args.steps} queued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - a
+    n_pass, pass_ms = tl.timing_read_net()
+    status = tl.sync()
+    lg = log.cpu().numpy().reshape(-1, LOG_LEN)
+    flops = conv_flops_per_pass(p.nel)
+    achieved = flops / (pass_ms / n_pass * 1e-3) / 1e12 if n_pass else None
+    rec = {
+        "metric": METRIC,
+        "value": args.steps / dt,
+        "unit": "SIMP iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"learned3d: {'x'.join(map(str, p.nel))} cells ({p.n_cells} simplices, "
+                         f"{p.n_dofs} DOFs), load case 1, volfrac {p.volfrac}, rmin {p.rmin}, "
+                         f"CG rtol {p.rtol}; learned preconditioner in truncated flexible CG"),
+            "precond": "learned",
+            "status": int(status),
+            "cg_iters_per_step": lg[:, 5].tolist(),
+            "time_to_solution_heldout": res,
+            "training": {"pairs": int(ps.R.shape[0]), "steps": args.train_steps,
+                         "ms_per_step": 1e3 * t_train / max(1, args.train_steps),
+                         "loss_first100": float(L[:100].mean()), "loss_last100": float(L[-100:].mean()),
+                         "harvest_s": t_harvest, "gamma": gamma},
+        },
+        "roofline": {
+            "kernel": "network signal pass (12 MFMA convolutions)",
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": 2500.0,
+            "unit": "TFLOP/s",
+            "frac": (achieved / 2500.0) if achieved else None,
+            "traffic": None,
+            "algorithmic_flops_per_pass": flops,
+            "passes": n_pass,
+            "pass_ms_mean": (pass_ms / n_pass) if n_pass else None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(p)
+    else:
+        rec["cpu_baseline"] = None
+    tl.close()
+    print(json.dumps(rec))
+    return 0
 
 
 def main():
@@ -116,12 +280,17 @@ def main():
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--maxit", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=3000,
+                    help="learned3d workload: on-GPU training steps before the timed run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design note, not an implemented path",
               file=sys.stderr)
         return 2
+
+    if args.workload == "learned3d":
+        return bench_learned(args)
 
     import numpy as np
     import torch

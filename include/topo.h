@@ -220,6 +220,9 @@ int topo_filter_rowsums(topo_ctx* ctx, double* R);
    reset, and resets.  Reading synchronises the stream. */
 int topo_timing_enable(topo_ctx* ctx, int enable);
 int topo_timing_read(topo_ctx* ctx, int64_t* launches /* host */, double* total_ms /* host */);
+/* The same for the signal passes of the preconditioner network (the twelve
+   convolutions and three upsamplings of one application). */
+int topo_timing_read_net(topo_ctx* ctx, int64_t* passes /* host */, double* total_ms /* host */);
 
 /* Waits for the context stream; *device_status (host, may be NULL) gets the
    sticky device status (TOPO_OK or a TOPO_S_* value), which is then

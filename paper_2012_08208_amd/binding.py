@@ -37,7 +37,7 @@ EXPORTED = [
     "topo_precond_num_params", "topo_precond_workspace_size", "topo_precond_attach",
     "topo_precond_set_weights", "topo_precond_get_weights", "topo_precond_config",
     "topo_precond_apply", "topo_precond_backward", "topo_precond_train_step",
-    "topo_precond_get_grad", "topo_precond_harvest", "topo_precond_stats",
+    "topo_precond_get_grad", "topo_precond_harvest", "topo_precond_stats", "topo_timing_read_net",
 ]
 
 
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_filter_rowsums.argtypes = [vp, vp]
     lib.topo_timing_enable.argtypes = [vp, i32]
     lib.topo_timing_read.argtypes = [vp, P(ctypes.c_int64), P(dbl)]
+    lib.topo_timing_read_net.argtypes = [vp, P(ctypes.c_int64), P(dbl)]
     lib.topo_sync.argtypes = [vp, P(i32)]
     lib.topo_precond_num_params.argtypes = [P(ctypes.c_int64)]
     lib.topo_precond_workspace_size.argtypes = [P(CProblem), P(ctypes.c_size_t)]
@@ -271,6 +272,13 @@ class Topo:
         ms = ctypes.c_double(0.0)
         _check(self.lib.topo_timing_read(self.ctx, ctypes.byref(n), ctypes.byref(ms)),
                "topo_timing_read")
+        return int(n.value), float(ms.value)
+
+    def timing_read_net(self):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check(self.lib.topo_timing_read_net(self.ctx, ctypes.byref(n), ctypes.byref(ms)),
+               "topo_timing_read_net")
         return int(n.value), float(ms.value)
 
     def sync(self) -> int:

@@ -185,19 +185,36 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   return L;
 }
 
-int timing_begin(Ctx* c, hipEvent_t*) {
-  if (c->tev_used >= c->tev.size()) {
+int timing_begin(Ctx* c, int chan) {
+  auto& tv = c->tev[chan];
+  if (c->tev_used[chan] >= tv.size()) {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return -1;
     if (hipEventCreate(&b) != hipSuccess) return -1;
-    c->tev.push_back({a, b});
+    tv.push_back({a, b});
   }
-  const int slot = (int)c->tev_used++;
-  (void)hipEventRecord(c->tev[slot].first, c->stream);
+  const int slot = (int)c->tev_used[chan]++;
+  (void)hipEventRecord(tv[slot].first, c->stream);
   return slot;
 }
 
-void timing_end(Ctx* c, int slot) { (void)hipEventRecord(c->tev[slot].second, c->stream); }
+void timing_end(Ctx* c, int chan, int slot) {
+  (void)hipEventRecord(c->tev[chan][slot].second, c->stream);
+}
+
+static int timing_read_chan(Ctx* c, int chan, int64_t* launches, double* total_ms) {
+  TOPO_HIP(hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i < c->tev_used[chan]; ++i) {
+    float ms = 0.f;
+    TOPO_HIP(hipEventElapsedTime(&ms, c->tev[chan][i].first, c->tev[chan][i].second));
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)c->tev_used[chan];
+  if (total_ms) *total_ms = tot;
+  c->tev_used[chan] = 0;
+  return TOPO_OK;
+}
 
 __global__ void log_record_kernel(const DevScalars* sc, double* rec, long nc, int nr) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -418,7 +435,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   }
   c->loads_set = false;
   c->timing = false;
-  c->tev_used = 0;
+  c->tev_used[0] = c->tev_used[1] = 0;
   c->t_launches = 0;
   c->t_ms = 0.0;
   *out = c;
@@ -428,10 +445,11 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
 int topo_destroy(topo_ctx* c) {
   if (!c) return TOPO_E_INVALID;
   (void)hipStreamSynchronize(c->stream);
-  for (auto& e : c->tev) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
+  for (auto& tv : c->tev)
+    for (auto& e : tv) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
   (void)hipEventDestroy(c->ev_poll[0]);
   (void)hipEventDestroy(c->ev_poll[1]);
   (void)hipHostFree((void*)c->pinned);
@@ -554,17 +572,12 @@ int topo_timing_enable(topo_ctx* c, int enable) {
 
 int topo_timing_read(topo_ctx* c, int64_t* launches, double* total_ms) {
   if (!c) return TOPO_E_INVALID;
-  TOPO_HIP(hipStreamSynchronize(c->stream));
-  double tot = 0.0;
-  for (size_t i = 0; i < c->tev_used; ++i) {
-    float ms = 0.f;
-    TOPO_HIP(hipEventElapsedTime(&ms, c->tev[i].first, c->tev[i].second));
-    tot += ms;
-  }
-  if (launches) *launches = (int64_t)c->tev_used;
-  if (total_ms) *total_ms = tot;
-  c->tev_used = 0;
-  return TOPO_OK;
+  return timing_read_chan(c, 0, launches, total_ms);
+}
+
+int topo_timing_read_net(topo_ctx* c, int64_t* passes, double* total_ms) {
+  if (!c) return TOPO_E_INVALID;
+  return timing_read_chan(c, 1, passes, total_ms);
 }
 
 int topo_sync(topo_ctx* c, int* device_status) {

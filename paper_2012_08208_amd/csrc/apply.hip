@@ -462,23 +462,23 @@ static void apply_dispatch(Ctx* c, const OpDesc& d, const TE* E, const T* x, T* 
 
 void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, double* y,
                      int nrhs, bool fuse_dot, bool timed, const int* stop) {
-  int slot = (timed && c->timing) ? timing_begin(c, nullptr) : -1;
+  int slot = (timed && c->timing) ? timing_begin(c, 0) : -1;
   apply_dispatch<double, double>(c, d, E, x, y, nrhs, fuse_dot, stop);
-  if (slot >= 0) timing_end(c, slot);
+  if (slot >= 0) timing_end(c, 0, slot);
 }
 
 void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
                          int nrhs, bool timed, const int* stop) {
-  int slot = (timed && c->timing) ? timing_begin(c, nullptr) : -1;
+  int slot = (timed && c->timing) ? timing_begin(c, 0) : -1;
   apply_dispatch<float, float>(c, d, E, x, y, nrhs, false, stop);
-  if (slot >= 0) timing_end(c, slot);
+  if (slot >= 0) timing_end(c, 0, slot);
 }
 
 void launch_apply_op_f32_dot(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
                              int nrhs) {
-  int slot = c->timing ? timing_begin(c, nullptr) : -1;
+  int slot = c->timing ? timing_begin(c, 0) : -1;
   apply_dispatch<float, float>(c, d, E, x, y, nrhs, true, &c->scal->pcg.done);
-  if (slot >= 0) timing_end(c, slot);
+  if (slot >= 0) timing_end(c, 0, slot);
 }
 
 __global__ void to_f32_cast_kernel(float* dst, const double* __restrict__ src, long n) {

@@ -990,7 +990,9 @@ void net_signal(Ctx* c, const double* r) {
   rms_fin<<<1, 256, 0, c->stream>>>(c->partials, gb, 3 * nn, n->scal, stop);
   prep_signal_kernel<<<cdiv(nn, 256) < 8192 ? cdiv(nn, 256) : 8192, 256, 0, c->stream>>>(
       r, n->scal, n->fs.X0, nn, stop);
+  const int slot = c->timing ? timing_begin(c, 1) : -1;
   net_pass(c, n->fs, &n->fg);
+  if (slot >= 0) timing_end(c, 1, slot);
 }
 
 void net_precondition(Ctx* c, const double* rho, const double* r, double* z, bool reuse_gates) {

@@ -192,8 +192,10 @@ struct Ctx {
   volatile int* pinned;   // pinned host flags
   hipEvent_t ev_poll[2];
   bool timing;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
-  size_t tev_used;
+  // HIP events around timed launches: channel 0 = fine-level operator
+  // applies, channel 1 = signal passes of the preconditioner network
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[2];
+  size_t tev_used[2];
   int64_t t_launches;
   double t_ms;
   int apply_kz;       // z-chunk (node planes) of the 3D apply
@@ -239,8 +241,8 @@ void launch_filter_rowsums(Ctx* c);
 void build_filter_taps(Ctx* c);
 void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars);
 void launch_log_record(Ctx* c, double* rec, const double* info);
-int timing_begin(Ctx* c, hipEvent_t* e1);
-void timing_end(Ctx* c, int slot);
+int timing_begin(Ctx* c, int chan);
+void timing_end(Ctx* c, int chan, int slot);
 
 }  // namespace topo
 
