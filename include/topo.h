@@ -315,6 +315,59 @@ int topo_precond_harvest(topo_ctx* ctx, const double* rho, const int* iters /* h
    iterations of its last pass and whether multigrid took over. */
 int topo_precond_stats(topo_ctx* ctx, int* fcg_iters, int* fallback);
 
+/* ------------------------------------------------------------------------
+ * Batched 2D instances: many independent SIMP problems of different sizes
+ * advanced together (the loop of Sec. 4.3 and the Appendix for every
+ * instance).  Every instance has its own grid, loads, supports, volume
+ * fraction, filter radius and convergence; kernels are batched across
+ * instances and one SIMP round for all of them is three captured HIP graphs
+ * (set-up, CG continuation replayed until every instance has converged,
+ * update).  Instances stop individually when max |rho_new - rho| falls below
+ * the tolerance.  Restrictions: dim 2, nrhs 1, TOPO_FP64, TOPO_PC_GMG, no
+ * paper mode, nel >= 2 per axis and more than 128 DOFs per instance.
+ * Concatenated layouts (instance order): loads and displacements
+ * [inst][2][N_n,i], densities [inst][N_c,i], masks [inst][2][N_n,i].
+ * The batch runs on its own stream ordered after the caller's stream; every
+ * call below returns after the batch stream has finished its work.
+ * ---------------------------------------------------------------------- */
+typedef struct topo_batch topo_batch;
+
+/* per-instance record of topo_batch_iterate (doubles): [0] SIMP iterations
+   done, [1] last change max|rho_new - rho|, [2] compliance at the last
+   solve, [3] volume fraction of the last design, [4] CG iterations summed
+   over the run, [5] stopped by the change tolerance (1/0) */
+#define TOPO_BATCH_REC_LEN 6
+
+int topo_batch_workspace_size(const topo_problem* probs /* host [count] */, int count,
+                              size_t* bytes /* host */);
+/* fixed_masks: host, concatenated [inst][2][N_n,i], nonzero = fixed.  The
+   create call also measures the fine-level apply for each supported tile
+   shape on these grids and keeps the fastest (topo_batch_tile_shape). */
+int topo_batch_create(const topo_problem* probs /* host [count] */, int count,
+                      const uint8_t* fixed_masks /* host */, void* workspace, size_t ws_bytes,
+                      void* stream, topo_batch** out /* host */);
+int topo_batch_destroy(topo_batch* batch);
+int topo_batch_set_loads(topo_batch* batch, const double* f /* concatenated */);
+/* Runs up to max_iter SIMP rounds; rho (concatenated, in/out) starts each
+   instance from the given design.  change_tol > 0: an instance stops once
+   its change is below it; the call returns when every instance has stopped
+   or after max_iter rounds.  Displacements restart from zero and are warm
+   started from one round to the next.  record: device
+   [count][TOPO_BATCH_REC_LEN] or NULL; *rounds (host) = rounds run. */
+int topo_batch_iterate(topo_batch* batch, double* rho, int max_iter, double change_tol,
+                       double* record, int* rounds /* host */);
+/* displacements of the last solve (concatenated [inst][2][N_n,i]) */
+int topo_batch_solution(topo_batch* batch, double* u);
+/* chosen fine-level tile shape (threads per block along x and y) and the
+   measured apply time of each shape 16x16, 32x8, 64x4 (host, microseconds) */
+int topo_batch_tile_shape(topo_batch* batch, int* bx /* host */, int* by /* host */,
+                          double* us_per_shape /* host [3] or NULL */);
+/* sticky status over instances (TOPO_OK or the most severe TOPO_S_*) */
+int topo_batch_sync(topo_batch* batch, int* device_status /* host */);
+/* 1 when the rounds run as captured HIP graphs, 0 when capture was not
+   available and the kernels are launched directly */
+int topo_batch_uses_graphs(topo_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

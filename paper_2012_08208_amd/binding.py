@@ -38,7 +38,11 @@ EXPORTED = [
     "topo_precond_set_weights", "topo_precond_get_weights", "topo_precond_config",
     "topo_precond_apply", "topo_precond_backward", "topo_precond_train_step",
     "topo_precond_get_grad", "topo_precond_harvest", "topo_precond_stats", "topo_timing_read_net",
+    "topo_batch_workspace_size", "topo_batch_create", "topo_batch_destroy", "topo_batch_set_loads",
+    "topo_batch_iterate", "topo_batch_solution", "topo_batch_tile_shape", "topo_batch_sync",
+    "topo_batch_uses_graphs",
 ]
+BATCH_REC_LEN = 6
 
 
 class TopoError(RuntimeError):
@@ -98,6 +102,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_precond_get_grad.argtypes = [vp, vp]
     lib.topo_precond_harvest.argtypes = [vp, vp, P(i32), i32, vp, vp, i32, P(i32)]
     lib.topo_precond_stats.argtypes = [vp, P(i32), P(i32)]
+    lib.topo_batch_workspace_size.argtypes = [P(CProblem), i32, P(ctypes.c_size_t)]
+    lib.topo_batch_create.argtypes = [P(CProblem), i32, vp, vp, ctypes.c_size_t, vp, P(vp)]
+    lib.topo_batch_destroy.argtypes = [vp]
+    lib.topo_batch_set_loads.argtypes = [vp, vp]
+    lib.topo_batch_iterate.argtypes = [vp, vp, i32, dbl, vp, P(i32)]
+    lib.topo_batch_solution.argtypes = [vp, vp]
+    lib.topo_batch_tile_shape.argtypes = [vp, P(i32), P(i32), P(dbl)]
+    lib.topo_batch_sync.argtypes = [vp, P(i32)]
+    lib.topo_batch_uses_graphs.argtypes = [vp]
     lib.topo_status_string.argtypes = [i32]
     lib.topo_status_string.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -362,6 +375,104 @@ def num_params() -> int:
     n = ctypes.c_int64(0)
     _check(load_library().topo_precond_num_params(ctypes.byref(n)), "topo_precond_num_params")
     return int(n.value)
+
+
+class Batch:
+    """Many independent 2D problems advanced together (one library batch on
+    its own stream).  Vectors are concatenated in instance order."""
+
+    def __init__(self, problems, rtol=None, maxit: int = 20000, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device)
+        n = len(problems)
+        arr = (CProblem * n)()
+        for i, p in enumerate(problems):
+            if p.dim != 2 or p.loads.shape[0] != 1:
+                raise TopoError("batched instances must be 2D with one load case")
+            arr[i] = make_problem(p.dim, p.nel, 1, p.split, p.E0, p.Emin, p.nu, p.penal, p.volfrac,
+                                  p.rmin, p.move, p.eta, p.rho_min, TOPO_FP64, TOPO_PC_GMG,
+                                  p.rtol if rtol is None else rtol, maxit, p.paper_mode, False)
+        self._arr = arr
+        self.count = n
+        self.n_cells = [int(p.n_cells) for p in problems]
+        self.n_dofs = [int(p.n_dofs) for p in problems]
+        self.cell_off = np.concatenate([[0], np.cumsum(self.n_cells)]).astype(np.int64)
+        self.dof_off = np.concatenate([[0], np.cumsum(self.n_dofs)]).astype(np.int64)
+        masks = np.ascontiguousarray(np.concatenate([np.asarray(p.fixed, np.uint8).ravel()
+                                                     for p in problems]))
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib.topo_batch_workspace_size(arr, n, ctypes.byref(nbytes)),
+               "topo_batch_workspace_size")
+        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        ptr = base + (-base) % 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.topo_batch_create(arr, n, masks.ctypes.data, ctypes.c_void_p(ptr),
+                                          int(nbytes.value), ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(h)), "topo_batch_create")
+        self.h = h
+        f = np.concatenate([np.asarray(p.loads, np.float64).ravel() for p in problems])
+        self.set_loads(torch.as_tensor(f, device=self.device))
+
+    def _ptr(self, t, numel, name):
+        torch = self.torch
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64 \
+                or not t.is_contiguous() or t.numel() != numel:
+            raise TopoError(f"{name} must be a contiguous float64 CUDA tensor of {numel} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    @property
+    def total_cells(self):
+        return int(self.cell_off[-1])
+
+    @property
+    def total_dofs(self):
+        return int(self.dof_off[-1])
+
+    def set_loads(self, f):
+        _check(self.lib.topo_batch_set_loads(self.h, self._ptr(f, self.total_dofs, "f")),
+               "topo_batch_set_loads")
+
+    def iterate(self, rho, max_iter: int, change_tol: float = 0.0, record=None) -> int:
+        rounds = ctypes.c_int(0)
+        rec = None if record is None else self._ptr(record, self.count * BATCH_REC_LEN, "record")
+        _check(self.lib.topo_batch_iterate(self.h, self._ptr(rho, self.total_cells, "rho"),
+                                           int(max_iter), float(change_tol), rec,
+                                           ctypes.byref(rounds)), "topo_batch_iterate")
+        return int(rounds.value)
+
+    def solution(self, u):
+        _check(self.lib.topo_batch_solution(self.h, self._ptr(u, self.total_dofs, "u")),
+               "topo_batch_solution")
+
+    def tile_shape(self):
+        bx, by = ctypes.c_int(0), ctypes.c_int(0)
+        us = (ctypes.c_double * 3)()
+        _check(self.lib.topo_batch_tile_shape(self.h, ctypes.byref(bx), ctypes.byref(by), us),
+               "topo_batch_tile_shape")
+        return int(bx.value), int(by.value), [float(v) for v in us]
+
+    def uses_graphs(self) -> bool:
+        return self.lib.topo_batch_uses_graphs(self.h) == 1
+
+    def sync(self) -> int:
+        st = ctypes.c_int(0)
+        _check(self.lib.topo_batch_sync(self.h, ctypes.byref(st)), "topo_batch_sync")
+        return int(st.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.topo_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def status_string(code: int) -> str:

@@ -72,23 +72,48 @@ static int pick_kz(const Grid& g) { return pick_kz(g.dim, g.nx, g.ny, g.nz); }
 
 // Multigrid levels: halve (rounding up) every axis until the level has at
 // most 128 DOFs, the size the dense coarsest solve handles.
-struct LevelDims {
-  int nx, ny, nz;
-};
-
-static std::vector<LevelDims> gmg_plan(const Grid& g) {
+std::vector<LevelDims> gmg_plan_dims(int dim, int nx, int ny, int nz) {
   std::vector<LevelDims> out;
-  LevelDims d{g.nx, g.ny, g.dim == 3 ? g.nz : 1};
+  LevelDims d{nx, ny, dim == 3 ? nz : 1};
   out.push_back(d);
   for (int l = 0; l < 24; ++l) {
-    const long nn = (long)(d.nx + 1) * (d.ny + 1) * (g.dim == 3 ? (d.nz + 1) : 1);
-    if (nn * g.dim <= 128) break;
-    LevelDims e{(d.nx + 1) / 2, (d.ny + 1) / 2, g.dim == 3 ? (d.nz + 1) / 2 : 1};
+    const long nn = (long)(d.nx + 1) * (d.ny + 1) * (dim == 3 ? (d.nz + 1) : 1);
+    if (nn * dim <= 128) break;
+    LevelDims e{(d.nx + 1) / 2, (d.ny + 1) / 2, dim == 3 ? (d.nz + 1) / 2 : 1};
     if (e.nx == d.nx && e.ny == d.ny && e.nz == d.nz) break;
     d = e;
     out.push_back(d);
   }
   return out;
+}
+
+static std::vector<LevelDims> gmg_plan(const Grid& g) { return gmg_plan_dims(g.dim, g.nx, g.ny, g.nz); }
+
+// Coarse node mask: a component is fixed when any fine node of the support
+// of the coarse basis function has it fixed.
+std::vector<uint8_t> coarse_mask_host(const std::vector<uint8_t>& fm, const LevelDims& f,
+                                      const LevelDims& d, int dim) {
+  std::vector<uint8_t> cm((size_t)(d.nx + 1) * (d.ny + 1) * (dim == 3 ? (d.nz + 1) : 1), 0);
+  const int nzf = dim == 3 ? f.nz : 0, nzc = dim == 3 ? d.nz : 0;
+  for (int K = 0; K <= nzc; ++K)
+    for (int J = 0; J <= d.ny; ++J)
+      for (int I = 0; I <= d.nx; ++I) {
+        uint8_t m = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              if (dim == 2 && dz != 0) continue;
+              // only the 2C +- d offsets with d in {0,1}^dim
+              const bool pos = dx >= 0 && dy >= 0 && dz >= 0;
+              const bool neg = dx <= 0 && dy <= 0 && dz <= 0;
+              if (!pos && !neg) continue;
+              const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
+              if (fi < 0 || fj < 0 || fk < 0 || fi > f.nx || fj > f.ny || fk > nzf) continue;
+              m |= fm[((size_t)fk * (f.ny + 1) + fj) * (f.nx + 1) + fi];
+            }
+        cm[((size_t)K * (d.ny + 1) + J) * (d.nx + 1) + I] = m;
+      }
+  return cm;
 }
 
 static long apply_blocks(const Grid& g, int kz, int nrhs) {
@@ -368,29 +393,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
         lv.x = (double*)(w + lv.off_x);
         lv.mask = (uint8_t*)(w + lv.off_mask);
         // coarse mask: fixed when any fine node of the basis support is fixed
-        const LevelDims& f = plan[l - 1];
-        const std::vector<uint8_t>& fm = lmasks[l - 1];
-        std::vector<uint8_t> cm((size_t)lv.op.nn, 0);
-        const int dim = c->g.dim;
-        const int nzf = dim == 3 ? f.nz : 0, nzc = dim == 3 ? d.nz : 0;
-        for (int K = 0; K <= nzc; ++K)
-          for (int J = 0; J <= d.ny; ++J)
-            for (int I = 0; I <= d.nx; ++I) {
-              uint8_t m = 0;
-              for (int dz = -1; dz <= 1; ++dz)
-                for (int dy = -1; dy <= 1; ++dy)
-                  for (int dx = -1; dx <= 1; ++dx) {
-                    if (dim == 2 && dz != 0) continue;
-                    // only the 2C +- d offsets with d in {0,1}^dim
-                    const bool pos = dx >= 0 && dy >= 0 && dz >= 0;
-                    const bool neg = dx <= 0 && dy <= 0 && dz <= 0;
-                    if (!pos && !neg) continue;
-                    const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
-                    if (fi < 0 || fj < 0 || fk < 0 || fi > f.nx || fj > f.ny || fk > nzf) continue;
-                    m |= fm[((size_t)fk * (f.ny + 1) + fj) * (f.nx + 1) + fi];
-                  }
-              cm[((size_t)K * (d.ny + 1) + J) * (d.nx + 1) + I] = m;
-            }
+        std::vector<uint8_t> cm = coarse_mask_host(lmasks[l - 1], plan[l - 1], d, c->g.dim);
         lmasks.push_back(cm);
         mask_ok = mask_ok && hipMemcpy(lv.mask, cm.data(), cm.size(), hipMemcpyHostToDevice) == hipSuccess;
       }

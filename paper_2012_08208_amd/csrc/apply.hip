@@ -15,6 +15,7 @@
 // modulus, so the clamped halo reads never reach an owned node.
 #include "common.h"
 #include "element.h"
+#include "shared_dev.h"
 #include "topo_internal.h"
 
 namespace topo {
@@ -71,72 +72,11 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const T* __restrict__ x, T
                                                       const TE* __restrict__ E, OpDesc d,
                                                       TileMap tm, T lam0, T mu0, double* partials,
                                                       const int* stop) {
-  __shared__ T xs[2][PATCH2];
-  __shared__ T ex[2][256];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
   if (stop && *stop) return;
   int bx, by, bz, rhs;
   const bool live = map_block(tm, bx, by, bz, rhs);
   if (!live && !partials) return;
-  const int nx = d.nx, ny = d.ny;
-  const long nn = d.nn;
-  const int i0 = bx * TILE, j0 = by * TILE;
-  const T* xr = x + (long)rhs * 2 * nn;
-  double dot = 0.0;
-  if (live) {
-    for (int idx = tid; idx < PATCH2; idx += 256) {
-      const int a = idx % PATCH, b = idx / PATCH;
-      const int gi = i0 - 1 + a, gj = j0 - 1 + b;
-      const int ci = min(max(gi, 0), nx), cj = min(max(gj, 0), ny);
-      const long n = (long)cj * (nx + 1) + ci;
-      xs[0][idx] = xr[n];
-      xs[1][idx] = xr[nn + n];
-    }
-  }
-  const int hi = i0 - 1 + tx, hj = j0 - 1 + ty;
-  const bool cell_ok = live && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
-  T l0 = 0, m0 = 0, l1 = 0, m1 = 0;
-  if (cell_ok) {
-    const long e = 2 * ((long)hj * nx + hi);
-    const T e0 = T(E[e]), e1 = T(E[e + 1]);
-    l0 = lam0 * e0; m0 = mu0 * e0; l1 = lam0 * e1; m1 = mu0 * e1;
-  }
-  lds_barrier();
-  if (live) {
-    const bool diag_a = d.split_uniform || ((hj & 1) == 0);
-    const int oi = i0 + tx, oj = j0 + ty;
-    const bool owner = tx < TILE && ty < TILE && oi <= nx && oj <= ny;
-    const long on = (long)oj * (nx + 1) + oi;
-    const int om = owner ? d.mask[on] : 3;
-    T u[4][2], f[4][2];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int li = (ty + (c >> 1)) * PATCH + tx + (c & 1);
-      u[c][0] = xs[0][li];
-      u[c][1] = xs[1][li];
-      f[c][0] = 0; f[c][1] = 0;
-    }
-    square_force<T>(diag_a, u, l0, m0, l1, m1, f);
-    T X[2][2];
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) X[cy][c] = f[1 + 2 * cy][c] + shift_down1(f[2 * cy][c]);
-    ex[0][tid] = X[0][0];
-    ex[1][tid] = X[0][1];
-    lds_barrier();
-    if (owner) {
-      T* yr = y + (long)rhs * 2 * nn;
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        T v = X[1][c] + ex[c][tid + 16];
-        if ((om >> c) & 1) v = 0;
-        yr[c * nn + on] = v;
-        dot += (double)v * (double)u[3][c];
-      }
-    }
-  }
+  const double dot = apply2d_tile<T, TE, 16, 16>(live, bx, by, rhs, x, y, E, d, lam0, mu0);
   if (partials) dot_partials(dot, live ? rhs : 0, partials);
 }
 
@@ -294,51 +234,11 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
 }
 
 // ------------------------------------------------------------- diagonal
-// diag K at node a, component c: sum over cells of
-// |T| E (lambda g_c^2 + mu (g_c^2 + |g|^2)) with g = grad N_a.
-__device__ __forceinline__ void diag_add(double (&d)[3], int dim, const int* g, double lam,
-                                         double mu) {
-  double gg = 0.0;
-  for (int a = 0; a < dim; ++a) gg += g[a] * g[a];
-  for (int c = 0; c < dim; ++c) d[c] += lam * g[c] * g[c] + mu * (g[c] * g[c] + gg);
-}
-
 __global__ void diag2d_kernel(double* d, const double* E, OpDesc od, double lam0, double mu0,
                               double vol, int inverse) {
-  const int nx = od.nx, ny = od.ny;
-  const long nn = od.nn;
-  const int split_uniform = od.split_uniform;
-  const uint8_t* mask = od.mask;
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
-  const int i = (int)(n % (nx + 1)), j = (int)(n / (nx + 1));
-  // (corner, gx, gy) of the three vertices of each triangle type
-  const int tri[4][3][3] = {{{0, -1, 0}, {1, 1, -1}, {3, 0, 1}},
-                            {{0, 0, -1}, {2, -1, 1}, {3, 1, 0}},
-                            {{0, -1, -1}, {1, 1, 0}, {2, 0, 1}},
-                            {{3, 1, 1}, {1, 0, -1}, {2, -1, 0}}};
-  double acc[3] = {0, 0, 0};
-  for (int sy = -1; sy <= 0; ++sy)
-    for (int sx = -1; sx <= 0; ++sx) {
-      const int hi = i + sx, hj = j + sy;
-      if (hi < 0 || hi >= nx || hj < 0 || hj >= ny) continue;
-      const int corner = (-sx) + 2 * (-sy);
-      const bool a = split_uniform || ((hj & 1) == 0);
-      for (int t = 0; t < 2; ++t) {
-        const int type = (a ? 0 : 2) + t;
-        const double e = E[2 * ((long)hj * nx + hi) + t] * vol;
-        for (int v = 0; v < 3; ++v)
-          if (tri[type][v][0] == corner) {
-            const int g[2] = {tri[type][v][1], tri[type][v][2]};
-            diag_add(acc, 2, g, lam0 * e, mu0 * e);
-          }
-      }
-    }
-  const int m = mask[n];
-  for (int c = 0; c < 2; ++c) {
-    double v = ((m >> c) & 1) ? 1.0 : acc[c];
-    d[c * nn + n] = inverse ? 1.0 / v : v;
-  }
+  if (n >= od.nn) return;
+  diag2d_node(n, d, E, od, lam0, mu0, vol, inverse);
 }
 
 __global__ void diag3d_kernel(double* d, const double* E, OpDesc od, double lam0, double mu0,

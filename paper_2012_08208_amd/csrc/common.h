@@ -68,10 +68,12 @@ __device__ inline void block_partials(const double (&v)[NV], const double (&vm)[
   }
 }
 
-// Stage 2, called by every thread of a single block: totals of nb blocks'
-// partials in a fixed order (thread-strided over blocks, then a fixed tree).
+// Stage 2, called by every thread of a single block: totals of the partials
+// of blocks [b0, b1) in a fixed order (thread-strided over blocks, then a
+// fixed tree).
 template <int NV, int NM = 0>
-__device__ inline void reduce_partials(const double* partials, long nb, double (&tot)[NV + NM]) {
+__device__ inline void reduce_partials_range(const double* partials, long b0, long b1,
+                                             double (&tot)[NV + NM]) {
   constexpr int NT = NV + NM;
   __shared__ double wtmp[16][NT];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -79,7 +81,7 @@ __device__ inline void reduce_partials(const double* partials, long nb, double (
   double acc[NT];
 #pragma unroll
   for (int k = 0; k < NT; ++k) acc[k] = 0.0;
-  for (long b = threadIdx.x; b < nb; b += blockDim.x) {
+  for (long b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
       const double x = partials[b * kPartStride + k];
@@ -99,6 +101,11 @@ __device__ inline void reduce_partials(const double* partials, long nb, double (
     tot[k] = s;
   }
   __syncthreads();
+}
+
+template <int NV, int NM = 0>
+__device__ inline void reduce_partials(const double* partials, long nb, double (&tot)[NV + NM]) {
+  reduce_partials_range<NV, NM>(partials, 0, nb, tot);
 }
 
 }  // namespace topo

@@ -15,16 +15,18 @@
 #include <math.h>
 
 #include "common.h"
+#include "shared_dev.h"
 #include "topo_internal.h"
 
 namespace topo {
 
-void build_filter_taps(Ctx* c) {
-  const Grid& g = c->g;
-  const double rmin = c->prob.rmin;
+// Host tap table of every cell class: (offset, neighbour class, weight),
+// kMaxFilterTaps entries per class; returns the number of classes.
+int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& tab, int* ntaps) {
   const int reach = (int)ceil(rmin) + 1;
-  std::vector<FilterTap> tab;
-  if (g.dim == 3) {
+  int nclasses = 0;
+  tab.clear();
+  if (dim == 3) {
     static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
     double cen[6][3];
     for (int t = 0; t < 6; ++t) {
@@ -32,7 +34,7 @@ void build_filter_taps(Ctx* c) {
       cen[t][perm[t][1]] = 0.5;
       cen[t][perm[t][2]] = 0.25;
     }
-    c->nclasses = 6;
+    nclasses = 6;
     for (int ta = 0; ta < 6; ++ta) {
       int n = 0;
       for (int dk = -reach; dk <= reach; ++dk)
@@ -48,7 +50,7 @@ void build_filter_taps(Ctx* c) {
                 ++n;
               }
             }
-      c->ntaps[ta] = n;
+      ntaps[ta] = n;
       tab.resize((size_t)(ta + 1) * kMaxFilterTaps);
     }
   } else {
@@ -56,9 +58,9 @@ void build_filter_taps(Ctx* c) {
     // diagonal A and diagonal B
     const double cA[2][2] = {{2.0 / 3.0, 1.0 / 3.0}, {1.0 / 3.0, 2.0 / 3.0}};
     const double cB[2][2] = {{1.0 / 3.0, 1.0 / 3.0}, {2.0 / 3.0, 2.0 / 3.0}};
-    const bool alt = g.split == TOPO_SPLIT_ALT_ROWS;
-    c->nclasses = alt ? 4 : 2;
-    for (int cls = 0; cls < c->nclasses; ++cls) {
+    const bool alt = split == TOPO_SPLIT_ALT_ROWS;
+    nclasses = alt ? 4 : 2;
+    for (int cls = 0; cls < nclasses; ++cls) {
       const int ta = cls & 1, par = cls >> 1;  // row parity of the target
       const double* ca = (alt && par) ? cB[ta] : cA[ta];
       int n = 0;
@@ -75,10 +77,16 @@ void build_filter_taps(Ctx* c) {
               ++n;
             }
           }
-      c->ntaps[cls] = n;
+      ntaps[cls] = n;
       tab.resize((size_t)(cls + 1) * kMaxFilterTaps);
     }
   }
+  return nclasses;
+}
+
+void build_filter_taps(Ctx* c) {
+  std::vector<FilterTap> tab;
+  c->nclasses = filter_taps_host(c->g.dim, c->g.split, c->prob.rmin, tab, c->ntaps);
   (void)hipMemcpy(c->taps, tab.data(), tab.size() * sizeof(FilterTap), hipMemcpyHostToDevice);
   (void)hipMemcpy(c->taps + (size_t)8 * kMaxFilterTaps, c->ntaps, sizeof(c->ntaps),
                   hipMemcpyHostToDevice);
@@ -103,25 +111,8 @@ __global__ __launch_bounds__(256) void filter_kernel(double* out, const double* 
                                                      int ny, int nz, int ncls, int alt, int rowsum) {
   const long nblk = (long)nx * ny * nz;
   const long h = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int t = blockIdx.y;
   if (h >= nblk) return;
-  const int i = (int)(h % nx);
-  const int j = (int)((h / nx) % ny);
-  const int k = (int)(h / ((long)nx * ny));
-  const int cls = (dim == 2 && alt) ? t + 2 * (j & 1) : t;
-  const FilterTap* tp = taps + (long)cls * kMaxFilterTaps;
-  const int nt = ntaps[cls];
-  double acc = 0.0;
-  for (int s = 0; s < nt; ++s) {
-    const FilterTap tap = tp[s];
-    const int ii = i + tap.di, jj = j + tap.dj, kk = k + tap.dk;
-    if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) continue;
-    const long hb = ((long)kk * ny + jj) * nx + ii;
-    acc += tap.w * q[(long)tap.tb * nblk + hb];
-  }
-  const long e = h * ncls + t;
-  if (rowsum) out[e] = acc;
-  else out[e] = acc / (rho[e] * R[e]);
+  filter_cell(h, blockIdx.y, out, q, rho, R, taps, ntaps, dim, nx, ny, nz, ncls, alt, rowsum);
 }
 
 static void filter_launch(Ctx* c, const double* rho, const double* dc, double* out, bool rowsum) {

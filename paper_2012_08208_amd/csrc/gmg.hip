@@ -25,6 +25,7 @@
 
 #include "common.h"
 #include "element.h"
+#include "shared_dev.h"
 #include "topo_internal.h"
 
 namespace topo {
@@ -90,103 +91,29 @@ __global__ void restrict_E2_kernel(double* Ec, const double* __restrict__ Ef, in
                                    int uniform_f, int nxc, int nyc) {
   const long S = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (S >= (long)nxc * nyc) return;
-  const int I = (int)(S % nxc), J = (int)(S / nxc);
-  double acc[2] = {0, 0};
-  for (int dy = 0; dy < 2; ++dy)
-    for (int dx = 0; dx < 2; ++dx) {
-      const int fi = 2 * I + dx, fj = 2 * J + dy;
-      if (fi >= nxf || fj >= nyf) continue;
-      const bool a = uniform_f || ((fj & 1) == 0);
-      // triangle centroids x3: A: (2,1), (1,2); B: (1,1), (2,2)
-      const int cx[2] = {a ? 2 : 1, a ? 1 : 2};
-      const int cy[2] = {a ? 1 : 1, a ? 2 : 2};
-      for (int t = 0; t < 2; ++t) {
-        const double e = Ef[2 * ((long)fj * nxf + fi) + t];
-        const int qx = 3 * dx + cx[t], qy = 3 * dy + cy[t];
-        if (qx > qy) acc[0] += e;
-        else if (qx < qy) acc[1] += e;
-        else { acc[0] += 0.5 * e; acc[1] += 0.5 * e; }
-      }
-    }
-  Ec[2 * S] = acc[0] * 0.25;
-  Ec[2 * S + 1] = acc[1] * 0.25;
+  restrict_E2_square(S, Ec, Ef, nxf, nyf, uniform_f, nxc);
 }
 
 // ----------------------------------------------- transfer operators
-// b_c = R (b_f - q_f): restriction of the fine residual
 template <typename T>
 __global__ void restrict_kernel(T* bc, const T* __restrict__ bf, const T* __restrict__ qf,
                                 OpDesc fo, OpDesc co, int nrhs, const int* stop) {
   if (stop && *stop) return;
   const long C = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (C >= co.nn) return;
-  const int dim = co.dim;
-  const int nxc1 = co.nx + 1, nyc1 = co.ny + 1;
-  const int I = (int)(C % nxc1), J = (int)((C / nxc1) % nyc1), K = dim == 3 ? (int)(C / ((long)nxc1 * nyc1)) : 0;
-  const int nxf1 = fo.nx + 1, nyf1 = fo.ny + 1;
-  const int nzf = dim == 3 ? fo.nz : 0;
-  const int cm = co.mask[C];
-  const int ndir = dim == 3 ? 7 : 3;
-  for (int r = 0; r < nrhs; ++r)
-    for (int c = 0; c < dim; ++c) {
-      const long off = ((long)r * dim + c) * fo.nn;
-      T acc = 0;
-      {
-        const int fi = 2 * I, fj = 2 * J, fk = 2 * K;
-        if (fi <= fo.nx && fj <= fo.ny && fk <= nzf) {
-          const long n = ((long)fk * nyf1 + fj) * nxf1 + fi;
-          acc += bf[off + n] - qf[off + n];
-        }
-      }
-      for (int dd = 1; dd <= ndir; ++dd) {
-        const int dx = dd & 1, dy = (dd >> 1) & 1, dz = (dd >> 2) & 1;
-        for (int sgn = -1; sgn <= 1; sgn += 2) {
-          const int fi = 2 * I + sgn * dx, fj = 2 * J + sgn * dy, fk = 2 * K + sgn * dz;
-          if (fi < 0 || fj < 0 || fk < 0 || fi > fo.nx || fj > fo.ny || fk > nzf) continue;
-          const long n = ((long)fk * nyf1 + fj) * nxf1 + fi;
-          acc += T(0.5) * (bf[off + n] - qf[off + n]);
-        }
-      }
-      bc[((long)r * dim + c) * co.nn + C] = ((cm >> c) & 1) ? T(0) : acc;
-    }
+  restrict_node<T>(C, bc, bf, qf, fo, co, nrhs);
 }
 
-// x_f += P x_c (fixed fine DOFs untouched)
 template <typename T>
 __global__ void prolong_add_kernel(T* xf, const T* __restrict__ xc, OpDesc fo, OpDesc co, int nrhs,
                                    const int* stop) {
   if (stop && *stop) return;
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= fo.nn) return;
-  const int dim = fo.dim;
-  const int nxf1 = fo.nx + 1, nyf1 = fo.ny + 1;
-  const int i = (int)(n % nxf1), j = (int)((n / nxf1) % nyf1), k = dim == 3 ? (int)(n / ((long)nxf1 * nyf1)) : 0;
-  const int nxc1 = co.nx + 1, nyc1 = co.ny + 1;
-  const long c0 = ((long)(k >> 1) * nyc1 + (j >> 1)) * nxc1 + (i >> 1);
-  const long c1 = ((long)((k + 1) >> 1) * nyc1 + ((j + 1) >> 1)) * nxc1 + ((i + 1) >> 1);
-  const bool even = ((i | j | k) & 1) == 0;
-  const int fm = fo.mask[n];
-  for (int r = 0; r < nrhs; ++r)
-    for (int c = 0; c < dim; ++c) {
-      if ((fm >> c) & 1) continue;
-      const T* xcr = xc + ((long)r * dim + c) * co.nn;
-      const T e = even ? xcr[c0] : T(0.5) * (xcr[c0] + xcr[c1]);
-      xf[((long)r * dim + c) * fo.nn + n] += e;
-    }
+  prolong_node<T>(n, xf, xc, fo, co, nrhs);
 }
 
 // ------------------------------------------------------- smoother
-struct ChebCoef {
-  double r_cur, r_prev;  // rho_k, rho_(k-1) of the Chebyshev recurrence
-};
-
-__device__ __forceinline__ void cheb_interval(double lmax, double low, double& theta,
-                                              double& delta) {
-  const double hi = lmax, lo = low * lmax;
-  theta = 0.5 * (hi + lo);
-  delta = 0.5 * (hi - lo);
-}
-
 // mode 0: x = 0 on entry (r = b);  mode 1: r = b - q with q = K x
 template <typename T>
 __global__ void cheb_first_kernel(T* x, T* r, T* d, const T* __restrict__ b, const T* __restrict__ q,
@@ -275,143 +202,24 @@ __global__ void power_fin_kernel(const double* partials, long nb, double* scale,
 __global__ void set_scalar_kernel(double* p, double v) { *p = v; }
 
 // ---------------------------------------------------- coarsest level
-// Dense A (row-major, n = dim * nn): row i = c * nn + node, built by the
-// thread that owns the row from the element matrices
-// K_e[(a,i),(b,j)] = |T| E (lambda g_a,i g_b,j + mu (g_a,j g_b,i + delta_ij g_a.g_b)).
 __global__ void coarse_assemble_kernel(double* A, const double* __restrict__ E, OpDesc o,
                                        double lam0, double mu0, double vol) {
-  const int n = (int)(o.nn * o.dim);
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  const int dim = o.dim;
-  const int node = row % (int)o.nn, ci = row / (int)o.nn;
-  double* Ar = A + (long)row * n;
-  for (int j = 0; j < n; ++j) Ar[j] = 0.0;
-  const int nx1 = o.nx + 1, ny1 = o.ny + 1;
-  const int i = node % nx1, jj = (node / nx1) % ny1, k = dim == 3 ? node / (nx1 * ny1) : 0;
-  if ((o.mask[node] >> ci) & 1) {
-    Ar[row] = 1.0;
-    return;
-  }
-  auto add_cell = [&](int nv, const int* nodes, const int (*g)[3], int av, double e) {
-    const double l = lam0 * e * vol, m = mu0 * e * vol;
-    const int* ga = g[av];
-    double gaga_dummy = 0.0;
-    (void)gaga_dummy;
-    for (int bv = 0; bv < nv; ++bv) {
-      const int* gb = g[bv];
-      double dot = 0.0;
-      for (int a = 0; a < dim; ++a) dot += ga[a] * gb[a];
-      for (int cj = 0; cj < dim; ++cj) {
-        const int col = cj * (int)o.nn + nodes[bv];
-        if ((o.mask[nodes[bv]] >> cj) & 1) continue;
-        Ar[col] += l * ga[ci] * gb[cj] + m * (ga[cj] * gb[ci] + (ci == cj ? dot : 0.0));
-      }
-    }
-  };
-  if (dim == 3) {
-    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-    for (int sz = -1; sz <= 0; ++sz)
-      for (int sy = -1; sy <= 0; ++sy)
-        for (int sx = -1; sx <= 0; ++sx) {
-          const int hi = i + sx, hj = jj + sy, hk = k + sz;
-          if (hi < 0 || hi >= o.nx || hj < 0 || hj >= o.ny || hk < 0 || hk >= o.nz) continue;
-          const int corner = (-sx) + 2 * (-sy) + 4 * (-sz);
-          const long h = ((long)hk * o.ny + hj) * o.nx + hi;
-          for (int t = 0; t < 6; ++t) {
-            const int c1 = 1 << perm[t][0];
-            const int c2 = c1 | (1 << perm[t][1]);
-            const int cs[4] = {0, c1, c2, 7};
-            int av = -1;
-            for (int v = 0; v < 4; ++v)
-              if (cs[v] == corner) av = v;
-            if (av < 0) continue;
-            int g[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-            g[0][perm[t][0]] = -1;
-            g[1][perm[t][0]] += 1;
-            g[1][perm[t][1]] -= 1;
-            g[2][perm[t][1]] += 1;
-            g[2][perm[t][2]] -= 1;
-            g[3][perm[t][2]] = 1;
-            int nodes[4];
-            for (int v = 0; v < 4; ++v) {
-              const int cc = cs[v];
-              nodes[v] = ((hk + (cc >> 2)) * ny1 + hj + ((cc >> 1) & 1)) * nx1 + hi + (cc & 1);
-            }
-            add_cell(4, nodes, g, av, E[6 * h + t]);
-          }
-        }
-  } else {
-    // (corner, gx, gy) of the three vertices of each triangle type
-    const int tri[4][3][3] = {{{0, -1, 0}, {1, 1, -1}, {3, 0, 1}},
-                              {{0, 0, -1}, {2, -1, 1}, {3, 1, 0}},
-                              {{0, -1, -1}, {1, 1, 0}, {2, 0, 1}},
-                              {{3, 1, 1}, {1, 0, -1}, {2, -1, 0}}};
-    for (int sy = -1; sy <= 0; ++sy)
-      for (int sx = -1; sx <= 0; ++sx) {
-        const int hi = i + sx, hj = jj + sy;
-        if (hi < 0 || hi >= o.nx || hj < 0 || hj >= o.ny) continue;
-        const int corner = (-sx) + 2 * (-sy);
-        const bool da = o.split_uniform || ((hj & 1) == 0);
-        for (int t = 0; t < 2; ++t) {
-          const int type = (da ? 0 : 2) + t;
-          int av = -1;
-          for (int v = 0; v < 3; ++v)
-            if (tri[type][v][0] == corner) av = v;
-          if (av < 0) continue;
-          int g[3][3];
-          int nodes[3];
-          for (int v = 0; v < 3; ++v) {
-            g[v][0] = tri[type][v][1];
-            g[v][1] = tri[type][v][2];
-            g[v][2] = 0;
-            const int cc = tri[type][v][0];
-            nodes[v] = (hj + (cc >> 1)) * nx1 + hi + (cc & 1);
-          }
-          add_cell(3, nodes, g, av, E[2 * ((long)hj * o.nx + hi) + t]);
-        }
-      }
-  }
+  if (row >= (int)(o.nn * o.dim)) return;
+  coarse_assemble_row(row, A, E, o, lam0, mu0, vol);
 }
 
-// In-place Gauss-Jordan inversion of the SPD matrix A (n x n, row-major),
-// one work-group; column k of the eliminated rows is saved first.
 __global__ __launch_bounds__(1024) void gauss_jordan_kernel(double* A, int n) {
-  __shared__ double rowk[128];
-  __shared__ double colk[128];
-  for (int k = 0; k < n; ++k) {
-    const double piv = A[(long)k * n + k];
-    __syncthreads();
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      colk[t] = A[(long)t * n + k];
-      rowk[t] = ((t == k) ? 1.0 : A[(long)k * n + t]) / piv;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
-      const int i = t / n, j = t % n;
-      if (i == k) {
-        A[t] = rowk[j];
-      } else {
-        const double base = (j == k) ? 0.0 : A[t];
-        A[t] = base - colk[i] * rowk[j];
-      }
-    }
-    __syncthreads();
-  }
+  gauss_jordan_block(A, n);
 }
 
-// x = A^-1 b for every load case (n <= 128), accumulated in FP64
 template <typename T>
 __global__ void coarse_solve_kernel(T* x, const T* __restrict__ b, const double* __restrict__ Ainv,
                                     int n, int nrhs, const int* stop) {
   if (stop && *stop) return;
   const int i = threadIdx.x;
   if (i >= n) return;
-  for (int r = 0; r < nrhs; ++r) {
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc += Ainv[(long)i * n + j] * (double)b[(long)r * n + j];
-    x[(long)r * n + i] = T(acc);
-  }
+  coarse_solve_thread<T>(i, x, b, Ainv, n, nrhs);
 }
 
 __global__ void to_f32_kernel(float* dst, const double* __restrict__ src, long n) {

@@ -15,14 +15,10 @@
 #include <math.h>
 
 #include "common.h"
+#include "shared_dev.h"
 #include "topo_internal.h"
 
 namespace topo {
-
-__device__ __forceinline__ double oc_a(double rho, double s, double eta) {
-  const double ns = s < 0.0 ? -s : 0.0;
-  return rho * (eta == 0.5 ? sqrt(ns) : pow(ns, eta));
-}
 
 __global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__ rho,
                                                       const double* __restrict__ dcf, double* a_out,
@@ -47,29 +43,7 @@ __global__ void oc_init_fin(const double* partials, long nb, long nc, double vol
                             int* status) {
   __shared__ double tot[4];
   reduce_partials<3, 1>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    const double target = volfrac * (double)nc;
-    st->target = target;
-    st->sum_lo = tot[0];
-    st->sum_hi = tot[1];
-    st->sum_a = tot[2];
-    st->passes = 0;
-    st->infeasible = 0;
-    st->mu_lo = 0.0;
-    st->mu_hi = tot[3];
-    const double tol = 1e-13 * (double)nc;
-    if (target < tot[0] - tol || target > tot[1] + tol || !(tot[2] > 0.0)) {
-      st->infeasible = 1;
-      st->mu = (target < tot[0]) ? 0.0 : tot[3];
-      st->done = 1;
-      *status = TOPO_S_OC_INFEASIBLE;
-    } else {
-      double mu = target / tot[2];
-      if (!(mu < st->mu_hi)) mu = 0.5 * st->mu_hi;
-      st->mu = mu;
-      st->done = 0;
-    }
-  }
+  if (threadIdx.x == 0) oc_init_finish(tot, nc, volfrac, st, status);
 }
 
 __global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__ rho,
@@ -95,31 +69,7 @@ __global__ void oc_pass_fin(const double* partials, long nb, long nc, OcState* s
   if (st->done) return;
   __shared__ double tot[2];
   reduce_partials<2, 0>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    const double mu = st->mu;
-    const double V = tot[0], S = tot[1], T = st->target;
-    st->V = V;
-    st->S = S;
-    st->passes += 1;
-    const double err = V - T;
-    const double tol = 1e-14 * (double)nc;
-    if (fabs(err) <= tol || st->passes >= 200) {
-      st->done = 1;
-      return;
-    }
-    if (err < 0.0) st->mu_lo = mu; else st->mu_hi = mu;
-    double next = 0.5 * (st->mu_lo + st->mu_hi);
-    if (S > 0.0) {
-      const double nw = mu - err / S;
-      if (nw > st->mu_lo && nw < st->mu_hi) next = nw;
-    }
-    if (!(next > st->mu_lo && next < st->mu_hi)) {
-      // the bracket cannot be split further in FP64: keep the last point
-      st->done = 1;
-      return;
-    }
-    st->mu = next;
-  }
+  if (threadIdx.x == 0) oc_pass_finish(tot, nc, st);
 }
 
 __global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict__ rho,
@@ -145,17 +95,7 @@ __global__ void oc_final_fin(const double* partials, long nb, double eta, OcStat
                              double* scalars) {
   __shared__ double tot[2];
   reduce_partials<1, 1>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    const double mu = st->mu;
-    st->vol = tot[0];
-    st->change = tot[1];
-    st->lam = (mu > 0.0) ? pow(mu, -1.0 / eta) : INFINITY;
-    if (scalars) {
-      scalars[0] = st->lam;
-      scalars[1] = tot[0];
-      scalars[2] = tot[1];
-    }
-  }
+  if (threadIdx.x == 0) oc_final_finish(tot, eta, st, scalars);
 }
 
 void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars) {

@@ -21,6 +21,7 @@
 
 #include "common.h"
 #include "net.h"
+#include "shared_dev.h"
 #include "topo_internal.h"
 
 namespace topo {
@@ -64,23 +65,7 @@ template <int NR>
 __global__ void pcg_init_fin(const double* partials, long nb, double rtol, PcgState* st) {
   __shared__ double tot[2 * NR];
   reduce_partials<2 * NR, 0>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    int any = 0;
-    for (int q = 0; q < kMaxRhs; ++q) {
-      const bool has = q < NR;
-      st->rr[q] = has ? tot[q] : 0.0;
-      st->ff[q] = has ? tot[NR + q] : 0.0;
-      st->tol2[q] = rtol * rtol * st->ff[q];
-      st->active[q] = has && (st->ff[q] > 0.0) && (st->rr[q] > st->tol2[q]);
-      st->alpha[q] = 0.0;
-      st->beta[q] = 0.0;
-      st->rz[q] = 0.0;
-      any |= st->active[q];
-    }
-    st->done = !any;
-    st->iters = 0;
-    st->breakdown = 0;
-  }
+  if (threadIdx.x == 0) pcg_init_finish<NR>(tot, rtol, st);
 }
 
 // inner solve start: x = 0, r given; partial (r,r) serves as both rr and ff
@@ -138,21 +123,7 @@ __global__ void pcg_rz_fin(const double* partials, long nb, int first, PcgState*
   if (st->done) return;
   __shared__ double tot[NR];
   reduce_partials<NR, 0>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < NR; ++k) {
-      if (!st->active[k]) continue;
-      if (first) {
-        st->rz[k] = tot[k];
-        st->beta[k] = 0.0;
-      } else {
-        st->rz_old[k] = st->rz[k];
-        st->rz[k] = tot[k];
-        st->beta[k] = tot[k] / st->rz_old[k];
-      }
-      if (!(tot[k] > 0.0)) { st->breakdown = 1; st->active[k] = 0; }
-    }
-    if (st->breakdown) st->done = 1;
-  }
+  if (threadIdx.x == 0) pcg_rz_finish<NR>(tot, first, st);
 }
 
 // flexible CG: partial (r, z_new) and (r, z_old) per load case
@@ -239,17 +210,7 @@ __global__ void pcg_alpha_fin(const double* partials, long nb, PcgState* st) {
   if (st->done) return;
   __shared__ double tot[kMaxRhs];
   reduce_partials<kMaxRhs, 0>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    for (int r = 0; r < kMaxRhs; ++r) {
-      st->pq[r] = tot[r];
-      if (st->active[r]) {
-        if (!(tot[r] > 0.0)) { st->breakdown = 1; st->alpha[r] = 0.0; }
-        else st->alpha[r] = st->rz[r] / tot[r];
-      } else {
-        st->alpha[r] = 0.0;
-      }
-    }
-  }
+  if (threadIdx.x == 0) pcg_alpha_finish(tot, st);
 }
 
 // x += alpha p, r -= alpha q; partial (r,r) and, for Jacobi, (r, D^-1 r)
@@ -288,24 +249,7 @@ __global__ void pcg_update_fin(const double* partials, long nb, PcgState* st, in
   if (st->done) return;
   __shared__ double tot[2 * NR];
   reduce_partials<2 * NR, 0>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    int any = 0;
-    for (int k = 0; k < NR; ++k) {
-      if (!st->active[k]) continue;
-      st->rr[k] = tot[k];
-      if (JAC) {
-        st->rz_old[k] = st->rz[k];
-        st->rz[k] = tot[NR + k];
-        st->beta[k] = tot[NR + k] / st->rz_old[k];
-      }
-      if (!(tot[k] > st->tol2[k])) st->active[k] = 0;
-      if (!isfinite(tot[k])) { st->breakdown = 1; st->active[k] = 0; }
-      any |= st->active[k];
-    }
-    st->iters += 1;
-    if (st->breakdown) { *status = TOPO_S_NUMERIC; any = 0; }
-    st->done = !any;
-  }
+  if (threadIdx.x == 0) pcg_update_finish<NR, JAC>(tot, st, status);
 }
 
 // p = z + beta p (Jacobi: z = D^-1 r on the fly); first: p = z

@@ -9,6 +9,7 @@
 // listing's objective sum_e E_e w_e / (2|T|).
 #include "common.h"
 #include "element.h"
+#include "shared_dev.h"
 #include "topo_internal.h"
 
 namespace topo {
@@ -21,33 +22,9 @@ __global__ __launch_bounds__(256) void sens2d_kernel(const double* __restrict__ 
                                                      double penal, int paper, double* partials) {
   const long nsq = (long)nx * ny;
   double acc[2] = {0.0, 0.0};
-  for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < nsq; s += (long)gridDim.x * blockDim.x) {
-    const int i = (int)(s % nx), j = (int)(s / nx);
-    const bool a = split_uniform || ((j & 1) == 0);
-    double w0 = 0.0, w1 = 0.0;
-    for (int r = 0; r < nr; ++r) {
-      double uc[4][2];
-      for (int c = 0; c < 4; ++c) {
-        const long n = (long)(j + (c >> 1)) * (nx + 1) + i + (c & 1);
-        uc[c][0] = u[((long)r * 2 + 0) * nn + n];
-        uc[c][1] = u[((long)r * 2 + 1) * nn + n];
-      }
-      double e0, e1;
-      square_energy<double>(a, uc, lam0, mu0, e0, e1);
-      w0 += e0;
-      w1 += e1;
-    }
-    const double ws[2] = {w0 * vol, w1 * vol};
-    for (int t = 0; t < 2; ++t) {
-      const long e = 2 * s + t;
-      const double rv = rho[e];
-      const double rp1 = (penal == 3.0) ? rv * rv : pow(rv, penal - 1.0);
-      const double Ee = paper ? rp1 * rv : Emin + rp1 * rv * (E0 - Emin);
-      dc[e] = paper ? -penal * rp1 * ws[t] / (2.0 * vol) : -penal * rp1 * (E0 - Emin) * ws[t];
-      acc[0] += Ee * ws[t];
-      acc[1] += Ee * ws[t] / (2.0 * vol);
-    }
-  }
+  for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < nsq; s += (long)gridDim.x * blockDim.x)
+    sens2d_square(s, rho, u, dc, nx, nn, nr, split_uniform, lam0, mu0, vol, E0, Emin, penal, paper,
+                  acc);
   const double none[1] = {0.0};
   block_partials<2, 0>(acc, none, partials);
 }

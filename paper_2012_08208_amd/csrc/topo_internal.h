@@ -160,6 +160,13 @@ struct Capture {
   long nd;
 };
 
+struct LevelDims {
+  int nx, ny, nz;
+};
+std::vector<LevelDims> gmg_plan_dims(int dim, int nx, int ny, int nz);
+std::vector<uint8_t> coarse_mask_host(const std::vector<uint8_t>& fm, const LevelDims& f,
+                                      const LevelDims& d, int dim);
+
 struct Ctx {
   topo_problem prob;
   Grid g;
@@ -239,6 +246,7 @@ void launch_sensitivity(Ctx* c, const double* rho, const double* u, double* dc, 
 void launch_filter(Ctx* c, const double* rho, const double* dc, double* dcf);
 void launch_filter_rowsums(Ctx* c);
 void build_filter_taps(Ctx* c);
+int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& tab, int* ntaps);
 void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars);
 void launch_log_record(Ctx* c, double* rec, const double* info);
 int timing_begin(Ctx* c, int chan);

@@ -75,3 +75,26 @@ def test_network_parameter_count_and_workspace():
     bad = b.make_problem(3, (8, 4, 4), precond=b.TOPO_PC_LEARNED, precision=b.TOPO_MIXED_FP32)
     assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == -1
     assert b"learned" in lib.topo_status_string(2)
+
+
+def test_batch_workspace_and_validation():
+    import synth
+    b = _lib()
+    lib = b.load_library()
+    probs = synth.batch2d(count=4, nx_lo=12, nx_hi=30)
+    arr = (b.CProblem * 4)()
+    for i, p in enumerate(probs):
+        arr[i] = b.make_problem(2, p.nel, 1, p.split, volfrac=p.volfrac, rmin=p.rmin,
+                                precond=b.TOPO_PC_GMG)
+    n = ctypes.c_size_t(0)
+    assert lib.topo_batch_workspace_size(arr, 4, ctypes.byref(n)) == 0
+    cells = sum(p.n_cells for p in probs)
+    assert n.value > cells * 8 * 8
+    # 3D, several load cases, Jacobi or mixed precision are rejected
+    bad = (b.CProblem * 1)(b.make_problem(3, (4, 2, 2), precond=b.TOPO_PC_GMG))
+    assert lib.topo_batch_workspace_size(bad, 1, ctypes.byref(n)) == -1
+    bad = (b.CProblem * 1)(b.make_problem(2, (8, 4), nrhs=2, precond=b.TOPO_PC_GMG))
+    assert lib.topo_batch_workspace_size(bad, 1, ctypes.byref(n)) == -1
+    bad = (b.CProblem * 1)(b.make_problem(2, (8, 4), precond=b.TOPO_PC_JACOBI))
+    assert lib.topo_batch_workspace_size(bad, 1, ctypes.byref(n)) == -1
+    assert lib.topo_batch_workspace_size(arr, 0, ctypes.byref(n)) == -1
