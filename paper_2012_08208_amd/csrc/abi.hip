@@ -154,12 +154,13 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.dcf = take((size_t)g.nc * 8);
   L.rho_new = take((size_t)g.nc * 8);
   L.rho_tmp = take((size_t)g.nc * 8);
-  L.r32 = L.p32 = L.q32 = L.z32 = L.x32 = 0;
+  L.r32 = L.p32 = L.q32 = L.z32 = L.z32b = L.x32 = 0;
   if (mixed) {
     L.r32 = take(nr * g.nd * 4);
     L.p32 = take(nr * g.nd * 4);
     L.q32 = take(nr * g.nd * 4);
     L.z32 = take(nr * g.nd * 4);
+    L.z32b = take(nr * g.nd * 4);
     L.x32 = take(nr * g.nd * 4);
   }
   L.gmg_scal = 0;
@@ -332,6 +333,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->p32 = L.p32 ? (float*)(w + L.p32) : nullptr;
   c->q32 = L.q32 ? (float*)(w + L.q32) : nullptr;
   c->z32 = L.z32 ? (float*)(w + L.z32) : nullptr;
+  c->z32b = L.z32b ? (float*)(w + L.z32b) : nullptr;
   c->x32 = L.x32 ? (float*)(w + L.x32) : nullptr;
   c->pring = L.pring ? (double*)(w + L.pring) : nullptr;
   c->qring = L.qring ? (double*)(w + L.qring) : nullptr;

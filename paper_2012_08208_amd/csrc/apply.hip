@@ -93,11 +93,25 @@ struct PlaneBuf {
   int m[2];
 };
 
-template <typename T, typename TE>
+// EPI = 2: the whole degree-2 Chebyshev smoothing from x = 0 in one kernel.
+// The operator input is d0 = D^-1 b / theta, formed while staging the
+// patch; at each owned node the epilogue forms r = b - K d0,
+// d1 = c1 d0 + c2 D^-1 r and writes x = d0 + d1 (r and the increments are
+// not needed afterwards), so r and d are never stored.
+template <typename T>
+struct ChebEpi {
+  T* x;
+  const T* invd;
+  const T* b;
+  const double* lmax;
+  double r_cur, r_prev, low;
+};
+
+template <typename T, typename TE, int EPI>
 __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T* __restrict__ y,
                                                       const TE* __restrict__ E, OpDesc d,
                                                       TileMap tm, T lam0, T mu0, double* partials,
-                                                      const int* stop) {
+                                                      const int* stop, ChebEpi<T> ce) {
   __shared__ T xs[2][3][PATCH2];
   __shared__ T ex[2][6][256];
   __shared__ uint8_t ms[2][PATCH2];
@@ -117,6 +131,13 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     const long plane = (long)(nx + 1) * (ny + 1);
     const T* xr = x + (long)rhs * 3 * nn;
     T* yr = y + (long)rhs * 3 * nn;
+    const T* br = EPI == 2 ? ce.b + (long)rhs * 3 * nn : nullptr;
+    T it0 = 0;
+    if (EPI == 2) {
+      double theta, delta;
+      cheb_interval(*ce.lmax, ce.low, theta, delta);
+      it0 = T(1.0 / theta);
+    }
 
     // plane staging: thread handles patch nodes idx = tid and tid + 256
     long poff[2];
@@ -141,7 +162,8 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
         const int m = d.mask[n];
         pb.m[q] = (pin[q] && kin) ? m : 7;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) pb.v[q][c] = xr[c * nn + n];
+        for (int c = 0; c < 3; ++c)
+          pb.v[q][c] = EPI == 2 ? it0 * ce.invd[c * nn + n] * br[c * nn + n] : xr[c * nn + n];
       }
     };
     auto commit = [&](int kk, const PlaneBuf<T>& pb) {
@@ -173,6 +195,15 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     const bool owner = tx < TILE && ty < TILE && oi <= nx && oj <= ny;
     const long ocol = (long)oj * (nx + 1) + oi;
     T carry[3] = {0, 0, 0};
+    T c1 = 0, c2 = 0;
+    T* ex_ = nullptr;
+    if (EPI == 2) {
+      double theta, delta;
+      cheb_interval(*ce.lmax, ce.low, theta, delta);
+      c1 = T(ce.r_cur * ce.r_prev);
+      c2 = T(2.0 * ce.r_cur / delta);
+      ex_ = ce.x + (long)rhs * 3 * nn;
+    }
 
     PlaneBuf<T> pb;
     fetch(k0 - 1, pb);
@@ -183,6 +214,17 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
       // plane commit and the barrier
       T ev[6];
       fetch_E(kh, ev);
+      // smoothing epilogue: this layer's b and D^-1 at the owned node, issued
+      // now so their latency hides behind the layer's arithmetic
+      T pb_[3], pi[3];
+      if (EPI == 2) {
+        const long on = (long)min(max(kh, 0), nz) * plane + (owner ? ocol : 0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          pb_[a] = br[a * nn + on];
+          pi[a] = ce.invd[a * nn + on];
+        }
+      }
       commit(kh + 1, pb);
       lds_barrier();
       if (kh + 2 <= k1) fetch(kh + 2, pb);
@@ -223,8 +265,14 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
           carry[a] = X[1][1][a] + ex[eb][3 + a][tid + 16];
           if (store) {
             if ((om >> a) & 1) yb = 0;
-            yr[a * nn + on] = yb;
-            dot += (double)yb * (double)u[3][a];
+            if (EPI == 0) {
+              yr[a * nn + on] = yb;
+              dot += (double)yb * (double)u[3][a];
+            } else {
+              // u[3][a] = d0 at the owned node; r = b - K d0
+              const T rv = pb_[a] - yb;
+              ex_[a * nn + on] = u[3][a] + (c1 * u[3][a] + c2 * pi[a] * rv);
+            }
           }
         }
       }
@@ -357,8 +405,30 @@ static void apply_dispatch(Ctx* c, const OpDesc& d, const TE* E, const T* x, T* 
   if (d.dim == 2)
     apply2d_kernel<T, TE><<<blocks, 256, 0, c->stream>>>(x, y, E, d, tm, lam, mu, part, st);
   else
-    apply3d_kernel<T, TE><<<blocks, 256, 0, c->stream>>>(x, y, E, d, tm, lam, mu, part, st);
+    apply3d_kernel<T, TE, 0><<<blocks, 256, 0, c->stream>>>(x, y, E, d, tm, lam, mu, part, st,
+                                                            ChebEpi<T>{});
 }
+
+// degree-2 smoothing from x = 0 (3D): x = d0 + c1 d0 + c2 D^-1 (b - K d0),
+// d0 = D^-1 b / theta
+template <typename T>
+void launch_apply_cheb_pre3d(Ctx* c, const OpDesc& d, const T* E, const T* b, T* x, const T* invd,
+                             const double* lmax, double r_cur, double r_prev, double low, int nrhs,
+                             const int* stop) {
+  const T lam = T(c->m.lam0 * c->m.vol), mu = T(c->m.mu0 * c->m.vol);
+  const TileMap tm = make_tilemap(d, nrhs);
+  const unsigned blocks = (unsigned)(8L * tm.per_xcd * nrhs);
+  ChebEpi<T> ce{x, invd, b, lmax, r_cur, r_prev, low};
+  apply3d_kernel<T, T, 2><<<blocks, 256, 0, c->stream>>>(nullptr, nullptr, E, d, tm, lam, mu, nullptr,
+                                                         stop, ce);
+}
+
+template void launch_apply_cheb_pre3d<float>(Ctx*, const OpDesc&, const float*, const float*, float*,
+                                             const float*, const double*, double, double, double, int,
+                                             const int*);
+template void launch_apply_cheb_pre3d<double>(Ctx*, const OpDesc&, const double*, const double*,
+                                              double*, const double*, const double*, double, double,
+                                              double, int, const int*);
 
 void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, double* y,
                      int nrhs, bool fuse_dot, bool timed, const int* stop) {

@@ -279,9 +279,7 @@ __global__ void b_prolong(const BJob* jobs, const BSlot* slots, const BState* st
 __global__ void b_coarse_solve(const int* list, const BSlot* slots, const BState* st) {
   const BSlot& s = slots[list[blockIdx.x]];
   if (!b_live(st, s.inst, true)) return;
-  const int n = (int)(s.op.nn * 2);
-  for (int i = threadIdx.x; i < n; i += blockDim.x)
-    coarse_solve_thread<double>(i, s.v[BV_X], s.v[BV_B], s.Ainv, n, 1);
+  coarse_solve_block<double>(s.v[BV_X], s.v[BV_B], s.Ainv, (int)(s.op.nn * 2), 1);
 }
 
 // ------------------------------------------------------------------ CG
@@ -1183,6 +1181,13 @@ void autotune(BatchCtx* b) {
       b->shape = sh;
       break;
     }
+  // TOPO_BATCH_TILE=0|1|2 pins the shape (the measurements are still made):
+  // shapes block the CG dot products differently, so two batches compare
+  // bit for bit only with the same shape
+  if (const char* e = getenv("TOPO_BATCH_TILE")) {
+    const int sh = atoi(e);
+    if (sh >= 0 && sh < kBShapes) b->shape = sh;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }

@@ -95,6 +95,65 @@ __global__ void restrict_E2_kernel(double* Ec, const double* __restrict__ Ef, in
 }
 
 // ----------------------------------------------- transfer operators
+// 3D restriction tiled through LDS: a block owns an 8 x 8 x 4 tile of coarse
+// nodes; for each (load case, component) it stages the 17 x 17 x 9 fine
+// nodes of (b - q) that the tile's basis supports cover (coalesced along x),
+// then every thread sums its coarse node's 15 support points (the centre
+// with weight 1, the 7 lattice directions d in {0,1}^3 \ 0 at +-d with
+// weight 1/2) from LDS.  Same arithmetic and summation order as
+// restrict_node.
+constexpr int kRcx = 8, kRcy = 8, kRcz = 4;
+constexpr int kRfx = 2 * kRcx + 1, kRfy = 2 * kRcy + 1, kRfz = 2 * kRcz + 1;
+
+template <typename T>
+__global__ __launch_bounds__(256) void restrict3d_tiled_kernel(T* bc, const T* __restrict__ bf,
+                                                               const T* __restrict__ qf, OpDesc fo,
+                                                               OpDesc co, int nrhs, const int* stop) {
+  if (stop && *stop) return;
+  __shared__ T tile[kRfz * kRfy * kRfx];
+  const int tid = threadIdx.x;
+  const int gx = (co.nx + 1 + kRcx - 1) / kRcx, gy = (co.ny + 1 + kRcy - 1) / kRcy;
+  // blockIdx.y = load case * 3 + component: one staged field per block
+  const int b = blockIdx.x;
+  const int I0 = (b % gx) * kRcx, J0 = ((b / gx) % gy) * kRcy, K0 = (b / (gx * gy)) * kRcz;
+  const int tx = tid % kRcx, ty = (tid / kRcx) % kRcy, tz = tid / (kRcx * kRcy);
+  const int I = I0 + tx, J = J0 + ty, K = K0 + tz;
+  const bool own = I <= co.nx && J <= co.ny && K <= co.nz;
+  const long C = ((long)K * (co.ny + 1) + J) * (co.nx + 1) + I;
+  const int cm = own ? co.mask[C] : 7;
+  const int fx0 = 2 * I0 - 1, fy0 = 2 * J0 - 1, fz0 = 2 * K0 - 1;
+  const int nxf1 = fo.nx + 1, nyf1 = fo.ny + 1;
+  {
+    {
+      const int r = blockIdx.y / 3, c = blockIdx.y % 3;
+      const long off = ((long)r * 3 + c) * fo.nn;
+      for (int idx = tid; idx < kRfz * kRfy * kRfx; idx += 256) {
+        const int a = idx % kRfx, bb = (idx / kRfx) % kRfy, cc = idx / (kRfx * kRfy);
+        const int fi = fx0 + a, fj = fy0 + bb, fk = fz0 + cc;
+        T v = T(0);
+        if (fi >= 0 && fj >= 0 && fk >= 0 && fi <= fo.nx && fj <= fo.ny && fk <= fo.nz) {
+          const long n = ((long)fk * nyf1 + fj) * nxf1 + fi;
+          v = bf[off + n] - qf[off + n];
+        }
+        tile[idx] = v;
+      }
+      lds_barrier();
+      if (own) {
+        // local fine coordinates of the centre 2I, 2J, 2K
+        const int li = 2 * tx + 1, lj = 2 * ty + 1, lk = 2 * tz + 1;
+        T acc = tile[(lk * kRfy + lj) * kRfx + li];
+        for (int dd = 1; dd <= 7; ++dd) {
+          const int dx = dd & 1, dy = (dd >> 1) & 1, dz = (dd >> 2) & 1;
+          for (int sgn = -1; sgn <= 1; sgn += 2)
+            acc += T(0.5) * tile[((lk + sgn * dz) * kRfy + lj + sgn * dy) * kRfx + li + sgn * dx];
+        }
+        bc[((long)r * 3 + c) * co.nn + C] = ((cm >> c) & 1) ? T(0) : acc;
+      }
+    }
+  }
+  (void)nrhs;
+}
+
 template <typename T>
 __global__ void restrict_kernel(T* bc, const T* __restrict__ bf, const T* __restrict__ qf,
                                 OpDesc fo, OpDesc co, int nrhs, const int* stop) {
@@ -214,12 +273,11 @@ __global__ __launch_bounds__(1024) void gauss_jordan_kernel(double* A, int n) {
 }
 
 template <typename T>
-__global__ void coarse_solve_kernel(T* x, const T* __restrict__ b, const double* __restrict__ Ainv,
-                                    int n, int nrhs, const int* stop) {
+__global__ __launch_bounds__(512) void coarse_solve_kernel(T* x, const T* __restrict__ b,
+                                                           const double* __restrict__ Ainv, int n,
+                                                           int nrhs, const int* stop) {
   if (stop && *stop) return;
-  const int i = threadIdx.x;
-  if (i >= n) return;
-  coarse_solve_thread<T>(i, x, b, Ainv, n, nrhs);
+  coarse_solve_block<T>(x, b, Ainv, n, nrhs);
 }
 
 __global__ void to_f32_kernel(float* dst, const double* __restrict__ src, long n) {
@@ -307,6 +365,14 @@ static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool fr
   T* gq = reinterpret_cast<T*>(g.q);
   const T* invd = LevelOps<T>::invd(g);
   const GmgParams gp = gmg_params();
+  if (from_zero && g.op.dim == 3 && gp.cheb_degree == 2) {
+    // the whole degree-2 smoothing from zero in one kernel
+    const double sigma = (1.0 + gp.cheb_low) / (1.0 - gp.cheb_low);
+    const double rho_prev = 1.0 / sigma, rho = 1.0 / (2.0 * sigma - rho_prev);
+    launch_apply_cheb_pre3d<T>(c, g.op, LevelOps<T>::E(g), b, x, invd, g.lmax, rho, rho_prev,
+                               gp.cheb_low, nrhs, stop);
+    return;
+  }
   if (!from_zero) LevelOps<T>::apply(c, g, x, gq, nrhs, stop);
   cheb_first_kernel<T><<<nb, 256, 0, s>>>(x, gr, gd, b, gq, invd, g.lmax, nd, nrhs,
                                           from_zero ? 0 : 1, gp.cheb_low, stop);
@@ -330,7 +396,7 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
   const int* stop = stop_flag(c);
   if (l == L - 1) {
     const int n = (int)(g.op.nn * g.op.dim);
-    coarse_solve_kernel<T><<<1, 128, 0, s>>>(x, b, g.Ainv, n, nrhs, stop);
+    coarse_solve_kernel<T><<<1, 512, 0, s>>>(x, b, g.Ainv, n, nrhs, stop);
     return;
   }
   GmgLevel& h = c->lv[l + 1];
@@ -339,7 +405,13 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
   T* gq = reinterpret_cast<T*>(g.q);
   cheb_smooth<T>(c, g, b, x, nrhs, true);
   LevelOps<T>::apply(c, g, x, gq, nrhs, stop);
-  restrict_kernel<T><<<cdivu(h.op.nn, 256), 256, 0, s>>>(hb, b, gq, g.op, h.op, nrhs, stop);
+  if (g.op.dim == 3) {
+    const long tiles = (long)cdivu(h.op.nx + 1, kRcx) * cdivu(h.op.ny + 1, kRcy) * cdivu(h.op.nz + 1, kRcz);
+    restrict3d_tiled_kernel<T><<<dim3((unsigned)tiles, 3 * nrhs), 256, 0, s>>>(hb, b, gq, g.op, h.op,
+                                                                              nrhs, stop);
+  } else {
+    restrict_kernel<T><<<cdivu(h.op.nn, 256), 256, 0, s>>>(hb, b, gq, g.op, h.op, nrhs, stop);
+  }
   vcycle_level<T>(c, l + 1, hb, hx, nrhs);
   prolong_add_kernel<T><<<cdivu(g.op.nn, 256), 256, 0, s>>>(x, hx, g.op, h.op, nrhs, stop);
   cheb_smooth<T>(c, g, b, x, nrhs, false);

@@ -101,9 +101,9 @@ __global__ __launch_bounds__(256) void jacobi_kernel(TV* z, const TV* __restrict
 }
 
 // partial (r, z) per load case
-template <int NR, typename TV>
+template <int NR, typename TV, typename TZ = TV>
 __global__ __launch_bounds__(256) void pcg_rz_kernel(const TV* __restrict__ r,
-                                                     const TV* __restrict__ z, long nd,
+                                                     const TZ* __restrict__ z, long nd,
                                                      double* partials, const PcgState* st) {
   if (st->done) return;
   double acc[NR];
@@ -127,10 +127,10 @@ __global__ void pcg_rz_fin(const double* partials, long nb, int first, PcgState*
 }
 
 // flexible CG: partial (r, z_new) and (r, z_old) per load case
-template <int NR>
+template <int NR, typename TZ = double>
 __global__ __launch_bounds__(256) void pcg_rz2_kernel(const double* __restrict__ r,
-                                                      const double* __restrict__ zn,
-                                                      const double* __restrict__ zo, long nd,
+                                                      const TZ* __restrict__ zn,
+                                                      const TZ* __restrict__ zo, long nd,
                                                       double* partials, const PcgState* st) {
   if (st->done) return;
   double acc[2 * NR];
@@ -140,8 +140,8 @@ __global__ __launch_bounds__(256) void pcg_rz2_kernel(const double* __restrict__
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       const double rv = r[(long)k * nd + d];
-      acc[k] += rv * zn[(long)k * nd + d];
-      acc[NR + k] += rv * zo[(long)k * nd + d];
+      acc[k] += rv * (double)zn[(long)k * nd + d];
+      acc[NR + k] += rv * (double)zo[(long)k * nd + d];
     }
   }
   const double none[1] = {0.0};
@@ -214,11 +214,13 @@ __global__ void pcg_alpha_fin(const double* partials, long nb, PcgState* st) {
 }
 
 // x += alpha p, r -= alpha q; partial (r,r) and, for Jacobi, (r, D^-1 r)
+// r32 (optional): FP32 copy of the updated residual for the FP32 V-cycle
 template <int NR, bool JAC, typename TV>
 __global__ __launch_bounds__(256) void pcg_update_kernel(TV* x, TV* r, const TV* __restrict__ p,
                                                          const TV* __restrict__ q,
                                                          const TV* __restrict__ invd, long nd,
-                                                         double* partials, const PcgState* st) {
+                                                         double* partials, const PcgState* st,
+                                                         float* r32 = nullptr) {
   if (st->done) return;
   TV al[NR];
   bool act[NR];
@@ -236,6 +238,7 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(TV* x, TV* r, const TV*
       x[i] += al[k] * p[i];
       const TV rv = r[i] - al[k] * q[i];
       r[i] = rv;
+      if (r32) r32[i] = (float)rv;
       acc[k] += (double)rv * (double)rv;
       if (JAC) acc[NR + k] += (double)rv * (double)(id * rv);
     }
@@ -253,8 +256,8 @@ __global__ void pcg_update_fin(const double* partials, long nb, PcgState* st, in
 }
 
 // p = z + beta p (Jacobi: z = D^-1 r on the fly); first: p = z
-template <int NR, bool JAC, typename TV>
-__global__ __launch_bounds__(256) void pcg_direction_kernel(TV* p, const TV* __restrict__ z,
+template <int NR, bool JAC, typename TV, typename TZ = TV>
+__global__ __launch_bounds__(256) void pcg_direction_kernel(TV* p, const TZ* __restrict__ z,
                                                             const TV* __restrict__ r,
                                                             const TV* __restrict__ invd, long nd,
                                                             const PcgState* st, int first) {
@@ -269,7 +272,7 @@ __global__ __launch_bounds__(256) void pcg_direction_kernel(TV* p, const TV* __r
     for (int k = 0; k < NR; ++k) {
       if (!act[k]) continue;
       const long i = (long)k * nd + d;
-      const TV zv = JAC ? id * r[i] : z[i];
+      const TV zv = JAC ? id * r[i] : TV(z[i]);
       p[i] = first ? zv : zv + be[k] * p[i];
     }
   }
@@ -340,6 +343,54 @@ struct FlexTrait<double> {
   static double* second(Ctx* c, double* z) { return c->wv ? c->wv : z; }
 };
 
+// Flexible CG with the FP32 multigrid V-cycle: FP64 x, r, p, q and dot
+// products; the V-cycle reads the FP32 residual written by the update
+// kernel and returns the preconditioned residual in FP32.
+template <int NR>
+static void mixed_flex_iterate(Ctx* c, double* x, double* r, double* p, double* q, int maxit) {
+  const long nd = c->g.nd;
+  PcgState* st = &c->scal->pcg;
+  int* status = &c->scal->status;
+  hipStream_t s = c->stream;
+  const unsigned gb = red_grid(nd);
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR);
+  float* zb[2] = {c->z32, c->z32b};
+  launch_to_f32(c, c->r32, r, (int64_t)NR * nd);
+  gmg_vcycle_f32(c, c->r32, zb[0], NR);
+  pcg_rz_kernel<NR, double, float><<<gb, 256, 0, s>>>(r, zb[0], nd, c->partials, st);
+  pcg_rz_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, 1, st);
+  pcg_direction_kernel<NR, false, double, float><<<gb, 256, 0, s>>>(p, zb[0], r, nullptr, nd, st, 1);
+  const int batch = 2;
+  int zi = 0, it = 0, b = 0;
+  bool stop = false;
+  while (it < maxit && !stop) {
+    const int nbt = (maxit - it < batch) ? (maxit - it) : batch;
+    for (int k = 0; k < nbt; ++k) {
+      launch_apply(c, p, q, NR, true);
+      pcg_alpha_fin<<<1, 256, 0, s>>>(c->partials, nb_apply, st);
+      pcg_update_kernel<NR, false, double><<<gb, 256, 0, s>>>(x, r, p, q, nullptr, nd, c->partials, st,
+                                                              c->r32);
+      pcg_update_fin<NR, false><<<1, 256, 0, s>>>(c->partials, gb, st, status);
+      float* zo = zb[zi];
+      float* zn = zb[zi ^ 1];
+      gmg_vcycle_f32(c, c->r32, zn, NR);
+      pcg_rz2_kernel<NR, float><<<gb, 256, 0, s>>>(r, zn, zo, nd, c->partials, st);
+      pcg_rz2_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st);
+      pcg_direction_kernel<NR, false, double, float><<<gb, 256, 0, s>>>(p, zn, r, nullptr, nd, st, 0);
+      zi ^= 1;
+    }
+    it += nbt;
+    const int sl = b & 1;
+    (void)hipMemcpyAsync((void*)&c->pinned[sl], &st->done, sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipEventRecord(c->ev_poll[sl], s);
+    if (b > 0) {
+      (void)hipEventSynchronize(c->ev_poll[sl ^ 1]);
+      if (c->pinned[sl ^ 1]) stop = true;
+    }
+    ++b;
+  }
+}
+
 // The CG iteration proper, from a state whose rr/ff/tol2/active are set and
 // whose residual r is in place; x accumulates the solution.
 template <int NR, typename TV>
@@ -373,6 +424,15 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
     pcg_rz_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, 1, st);
   }
   const int batch = gmg ? 2 : 8;
+  // FP32 V-cycle inside the FP64 iteration: the preconditioned residual stays
+  // FP32 (two buffers, new and old, for the Polak-Ribiere beta), the update
+  // kernel writes the FP32 residual the V-cycle reads
+  if constexpr (std::is_same<TV, double>::value) {
+    if (c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG) {
+      mixed_flex_iterate<NR>(c, x, r, p, q, maxit);
+      return;
+    }
+  }
   // flexible CG (mixed-precision preconditioner): z alternates between two
   // buffers so that (r_new, z_old) is available for the Polak-Ribiere beta
   const bool flex = FlexTrait<TV>::enabled(c);
@@ -407,7 +467,7 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
       } else {
         pcg_update_kernel<NR, true, TV><<<gb, 256, 0, s>>>(x, r, p, q, invd, nd, c->partials, st);
         pcg_update_fin<NR, true><<<1, 256, 0, s>>>(c->partials, gb, st, status);
-        pcg_direction_kernel<NR, true, TV><<<gb, 256, 0, s>>>(p, nullptr, r, invd, nd, st, 0);
+        pcg_direction_kernel<NR, true, TV><<<gb, 256, 0, s>>>(p, (const TV*)nullptr, r, invd, nd, st, 0);
       }
       capture(it + k + 1);
     }

@@ -353,14 +353,28 @@ __device__ inline void gauss_jordan_block(double* A, int n) {
   }
 }
 
-// x = A^-1 b for every load case (n <= 128), accumulated in FP64
+// x = A^-1 b for every load case (n <= 128, nrhs <= 4), accumulated in
+// FP64, by one work-group: b is staged in LDS, thread t computes row
+// i = t % n of load case t / n, and since the inverse of the symmetric
+// coarse matrix is symmetric it reads column i (consecutive threads read
+// consecutive addresses).
 template <typename T>
-__device__ inline void coarse_solve_thread(int i, T* x, const T* __restrict__ b,
-                                    const double* __restrict__ Ainv, int n, int nrhs) {
-  for (int r = 0; r < nrhs; ++r) {
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc += Ainv[(long)i * n + j] * (double)b[(long)r * n + j];
-    x[(long)r * n + i] = T(acc);
+__device__ inline void coarse_solve_block(T* x, const T* __restrict__ b,
+                                          const double* __restrict__ Ainv, int n, int nrhs) {
+  __shared__ double bs[kMaxRhs * 128];
+  for (int t = threadIdx.x; t < n * nrhs; t += blockDim.x) bs[t] = (double)b[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < n * nrhs; t += blockDim.x) {
+    const int r = t / n, i = t - r * n;
+    const double* br = bs + r * n;
+    double acc0 = 0.0, acc1 = 0.0;
+    int j = 0;
+    for (; j + 1 < n; j += 2) {
+      acc0 += Ainv[(long)j * n + i] * br[j];
+      acc1 += Ainv[(long)(j + 1) * n + i] * br[j + 1];
+    }
+    if (j < n) acc0 += Ainv[(long)j * n + i] * br[j];
+    x[t] = T(acc0 + acc1);
   }
 }
 

@@ -144,7 +144,7 @@ struct GmgLevel {
 
 struct WsLayout {
   size_t mask, f, E, E32, invd, invd32, r, p, q, z, wv, partials, scal, R, taps,
-      qsoa, dc, dcf, rho_new, rho_tmp, r32, p32, q32, z32, x32, gmg_scal, pring, qring, total;
+      qsoa, dc, dcf, rho_new, rho_tmp, r32, p32, q32, z32, z32b, x32, gmg_scal, pring, qring, total;
   std::vector<GmgLevel> levels;   // offsets only (pointers filled at creation)
 };
 
@@ -192,7 +192,7 @@ struct Ctx {
   double* qsoa;       // [nc] filter input in class-major order
   double *dc, *dcf, *rho_new, *rho_tmp;  // [nc]
   // mixed-precision inner solve buffers [nrhs][dim][nn]
-  float *r32, *p32, *q32, *z32, *x32;
+  float *r32, *p32, *q32, *z32, *z32b, *x32;
   double *pring, *qring;   // truncated flexible CG: [kFcgRing][nrhs][dim][nn]
   bool loads_set;
   // host side
@@ -226,6 +226,10 @@ void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x
                          int nrhs, bool timed, const int* stop);
 void launch_apply_op_f32_dot(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
                              int nrhs);
+template <typename T>
+void launch_apply_cheb_pre3d(Ctx* c, const OpDesc& d, const T* E, const T* b, T* x, const T* invd,
+                             const double* lmax, double r_cur, double r_prev, double low, int nrhs,
+                             const int* stop);
 void launch_to_f32(Ctx* c, float* dst, const double* src, int64_t n);
 void launch_to_f64(Ctx* c, double* dst, const float* src, int64_t n);
 int pick_kz(int dim, int nx, int ny, int nz);
