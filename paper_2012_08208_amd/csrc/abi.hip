@@ -70,6 +70,21 @@ int pick_kz(int dim, int nx, int ny, int nz) {
 
 static int pick_kz(const Grid& g) { return pick_kz(g.dim, g.nx, g.ny, g.nz); }
 
+// z-chunk of a coarse multigrid level
+static int pick_kz_coarse(int dim, int nx, int ny, int nz) {
+  if (dim == 2) return 1;
+  int lo = 2;   // short sweeps: the small levels are latency-bound
+  if (const char* e = getenv("TOPO_COARSE_KZMIN")) {
+    const int v = atoi(e);
+    if (v >= 1 && v <= 16) lo = v;
+  }
+  const long cols = (long)((nx + 15) / 15) * ((ny + 15) / 15);
+  long kz = (long)(nz + 1) * cols / 1024;
+  if (kz < lo) kz = lo;
+  if (kz > 16) kz = 16;
+  return (int)kz;
+}
+
 // Multigrid levels: halve (rounding up) every axis until the level has at
 // most 128 DOFs, the size the dense coarsest solve handles.
 std::vector<LevelDims> gmg_plan_dims(int dim, int nx, int ny, int nz) {
@@ -374,7 +389,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
       lv.op.nz = d.nz;
       lv.op.nn = (int64_t)(d.nx + 1) * (d.ny + 1) * (c->g.dim == 3 ? (d.nz + 1) : 1);
       lv.op.split_uniform = l == 0 ? (c->g.split == TOPO_SPLIT_UNIFORM) : 1;
-      lv.op.kz = l == 0 ? c->apply_kz : pick_kz(c->g.dim, d.nx, d.ny, d.nz);
+      lv.op.kz = l == 0 ? c->apply_kz : pick_kz_coarse(c->g.dim, d.nx, d.ny, d.nz);
       lv.nc = (int64_t)d.nx * d.ny * (c->g.dim == 3 ? d.nz * 6 : 2);
       double* gs = (double*)(w + L.gmg_scal);
       lv.lmax = gs + 2 * l;

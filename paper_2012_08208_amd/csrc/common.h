@@ -81,7 +81,23 @@ __device__ inline void reduce_partials_range(const double* partials, long b0, lo
   double acc[NT];
 #pragma unroll
   for (int k = 0; k < NT; ++k) acc[k] = 0.0;
-  for (long b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
+  // eight blocks' partials are loaded before any is added (independent
+  // loads in flight); the additions keep the block order
+  constexpr int U = 8;
+  const long step = blockDim.x;
+  long b = b0 + threadIdx.x;
+  for (; b + (U - 1) * step < b1; b += U * step) {
+    double xv[U][NT];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NT; ++k) xv[u][k] = partials[(b + u * step) * kPartStride + k];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NT; ++k) acc[k] = (k < NV) ? acc[k] + xv[u][k] : fmax(acc[k], xv[u][k]);
+  }
+  for (; b < b1; b += step) {
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
       const double x = partials[b * kPartStride + k];

@@ -30,10 +30,11 @@
 
 namespace topo {
 
-// Smoother parameters (defaults; TOPO_CHEB_DEGREE, TOPO_CHEB_LOW,
+// Smoother parameters (defaults; TOPO_CHEB_DEGREE, TOPO_CHEB_POST, TOPO_CHEB_LOW,
 // TOPO_POWER_ITERS and TOPO_POWER_SAFETY override them at context creation)
 struct GmgParams {
   int cheb_degree = 2;
+  int post_degree = -1;   // post-smoothing degree (-1: cheb_degree)
   double cheb_low = 0.09;
   int power_iters = 12;
   double power_safety = 1.2;
@@ -45,6 +46,8 @@ static GmgParams gmg_params() {
   if (const char* e = getenv("TOPO_CHEB_LOW")) p.cheb_low = atof(e) > 0 ? atof(e) : p.cheb_low;
   if (const char* e = getenv("TOPO_POWER_ITERS")) p.power_iters = atoi(e) > 0 ? atoi(e) : p.power_iters;
   if (const char* e = getenv("TOPO_POWER_SAFETY")) p.power_safety = atof(e) > 0 ? atof(e) : p.power_safety;
+  if (const char* e = getenv("TOPO_CHEB_POST")) p.post_degree = atoi(e);
+  if (p.post_degree < 0) p.post_degree = p.cheb_degree;
   return p;
 }
 
@@ -373,12 +376,14 @@ static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool fr
                                gp.cheb_low, nrhs, stop);
     return;
   }
+  const int degree = from_zero ? gp.cheb_degree : gp.post_degree;
+  if (degree == 0) return;
   if (!from_zero) LevelOps<T>::apply(c, g, x, gq, nrhs, stop);
   cheb_first_kernel<T><<<nb, 256, 0, s>>>(x, gr, gd, b, gq, invd, g.lmax, nd, nrhs,
                                           from_zero ? 0 : 1, gp.cheb_low, stop);
   const double sigma = (1.0 + gp.cheb_low) / (1.0 - gp.cheb_low);
   double rho_prev = 1.0 / sigma;
-  for (int k = 1; k < gp.cheb_degree; ++k) {
+  for (int k = 1; k < degree; ++k) {
     const double rho = 1.0 / (2.0 * sigma - rho_prev);
     LevelOps<T>::apply(c, g, gd, gq, nrhs, stop);
     ChebCoef cf{rho, rho_prev};

@@ -58,6 +58,7 @@ struct NetState {
   uint16_t *wf, *wb;        // BF16 forward / input-gradient weight copies
   float* dw_part;           // [chunks][cout*27*cin] weight-gradient partials
   long dw_part_len;
+  long conv_big_min;        // output voxels from which stride-1 layers use 8x8x4 tiles
   // activations (BF16, channels last): gate pass and signal pass
   FwdBufs fg, fs;
   bool gates_ready;         // fg holds the gate pass of the current design

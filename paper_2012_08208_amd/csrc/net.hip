@@ -10,7 +10,9 @@
 // from the channels-last activation.  The weight gradient reduces over
 // voxels instead; its two operands are staged through LDS transposed so
 // that the voxel run of a channel is contiguous.
+#include <limits.h>
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -197,6 +199,323 @@ static void conv_dispatch(int nct, dim3 g, hipStream_t s, const ConvArgs& a) {
     case 6: conv_kernel<MODE, 6><<<g, 256, 0, s>>>(a); break;
     default: conv_kernel<MODE, 8><<<g, 256, 0, s>>>(a); break;
   }
+}
+
+// ------------------------------------------------ tiled forward convolution
+// The forward layers run as implicit GEMMs over LDS-staged input tiles: a
+// block owns a TX x TY x TZ box of output voxels and stages the input voxels
+// it reads (its box plus the one-voxel halo; for stride 2 the box at twice
+// the spacing), 32 channels at a time, zero outside the grid.  Every tap
+// then reads its MFMA operand from LDS at a fixed offset from the lane's
+// voxel, so each input voxel comes from L2 once per block and channel chunk
+// instead of once per tap.  The K loop runs over the chunk's taps, unrolled
+// at compile time (LDS and weight offsets are instruction immediates): with
+// 32 staged channels one MFMA step is one tap; with 16 (8) channels one step
+// covers 2 (4) consecutive taps, the lanes of K group kg taking tap
+// t0 + kg*8/CC.  On large grids a block computes all output channels of an
+// 8x8x4 box, one wave per 64 voxels.  On small grids (few boxes) a block
+// computes 16 output channels of a 4x4x4 box and its 4 waves take every
+// fourth K step; their FP32 sums are added through LDS in wave order.  The
+// epilogue transposes each wave's C tile through LDS so that a lane stores
+// 8 channels of a voxel at once.  The weights keep the wf layout
+// [co][tap*cin + ci].
+
+template <int V>
+struct IC {
+  static constexpr int value = V;
+};
+
+// lane offset (staged voxels) of tap t inside the input box
+template <int MODE, int IX, int IY>
+__host__ __device__ constexpr int tap_off(int t) {
+  return ((t / 9) * IY + (t / 3) % 3) * IX + t % 3;
+}
+
+template <int MODE, int CIN, int NCT, int TX, int TY, int TZ, int WK>
+__global__ __launch_bounds__(256) void convt_kernel(ConvArgs a) {
+  constexpr int S = MODE == 1 ? 2 : 1;
+  constexpr int IX = MODE == 1 ? 2 * TX + 1 : TX + 2;
+  constexpr int IY = MODE == 1 ? 2 * TY + 1 : TY + 2;
+  constexpr int IZ = MODE == 1 ? 2 * TZ + 1 : TZ + 2;
+  constexpr int VI = IX * IY * IZ;
+  constexpr int MTILES = TX * TY * TZ / 16;
+  constexpr int WM = 4 / WK;
+  constexpr int MT = MTILES / WM;
+  constexpr int NCH = (CIN + 31) / 32;
+  constexpr int CC0 = CIN < 32 ? CIN : 32;   // channels of the first (widest) chunk
+  constexpr int PC = CC0 / 8;                 // staged 16-byte pieces per voxel
+  constexpr int kLP = CC0 + 8;                // LDS pitch (bf16) of a staged voxel
+  constexpr int VB = kLP * 2;                 // ... in bytes
+  constexpr int NQ = (VI * PC + 255) / 256;   // staged pieces per thread
+  constexpr int KPAD = (27 * CIN + 31) / 32 * 32;
+  constexpr int NSPLIT = WK;
+  constexpr int RED = WK > 1 ? (WK - 1) * MT * NCT * 4 * 64 : 0;   // floats
+  constexpr int EPI = (WK > 1 ? 1 : WM) * MT * 16 * (NCT * 16 + 4);  // floats
+  constexpr int LDS1 = VI * VB > RED * 4 ? VI * VB : RED * 4;
+  constexpr int LDSB = LDS1 > EPI * 4 ? LDS1 : EPI * 4;
+  static_assert(MTILES % WM == 0, "tile does not split over the waves");
+  static_assert(CIN % 8 == 0, "channels must be a multiple of 8");
+  static_assert(NCH <= 4 && NSPLIT <= 4, "unsupported layer shape");
+  __shared__ __attribute__((aligned(16))) char smem[LDSB];
+  const int stopped = a.stop ? *a.stop : 0;   // checked once the first tile loads are in flight
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WK, wk = wave % WK;
+  const int row = lane & 15, kg = lane >> 4;
+  const int gx = (a.onx + TX - 1) / TX, gy = (a.ony + TY - 1) / TY;
+  const int tile = blockIdx.x;
+  const int X0 = (tile % gx) * TX, Y0 = ((tile / gx) % gy) * TY, Z0 = (tile / (gx * gy)) * TZ;
+  const int cb = blockIdx.y;   // output channels cb*NCT*16 .. +NCT*16
+  const int q = wk;            // this wave's share of the K steps (uniform)
+
+  // staging: thread tid moves pieces tid + 256 j (voxel, 16-byte piece);
+  // offsets past the buffer (outside the grid) load zeros
+  const int ix0 = S * X0 - 1, iy0 = S * Y0 - 1, iz0 = S * Z0 - 1;
+  const unsigned nbytes = (unsigned)((long)a.inx * a.iny * a.inz * a.xpitch * 2);
+  const __amdgpu_buffer_rsrc_t xr =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(a.x), 0, (int)nbytes, 0x00020000);
+  int voff[NQ];
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    const int it = tid + 256 * j;
+    const int v = it / PC, pc = it % PC;
+    const int vx = v % IX, vy = (v / IX) % IY, vz = v / (IX * IY);
+    const int sx = ix0 + vx, sy = iy0 + vy, sz = iz0 + vz;
+    const bool ok = it < VI * PC && sx >= 0 && sx < a.inx && sy >= 0 && sy < a.iny && sz >= 0 &&
+                    sz < a.inz;
+    voff[j] = ok ? (((sz * a.iny + sy) * a.inx + sx) * a.xpitch + a.xoff + 8 * pc) * 2
+                 : (int)0x80000000;
+  }
+  const int ldsw = (tid / PC) * VB + (tid % PC) * 16;
+
+  int la[MT];   // LDS byte address of the lane's output voxel at tap (0,0,0), per M tile
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int ml = (wm * MT + mt) * 16 + row;
+    const int x = ml % TX, y = (ml / TX) % TY, z = ml / (TX * TY);
+    la[mt] = (((S * z) * IY + S * y) * IX + S * x) * VB;
+  }
+  f32x4 acc[MT][NCT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) acc[mt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto chunk = [&](auto cc) {
+    constexpr int C = decltype(cc)::value;
+    constexpr int CC = (CIN - 32 * C) >= 32 ? 32 : (CIN - 32 * C);
+    constexpr int TPS = 32 / CC;                  // taps per K step
+    constexpr int NS = (27 + TPS - 1) / TPS;      // K steps of this chunk
+    if (C > 0) __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      if (j < NQ - 1 || tid + 256 * j < VI * PC) {
+        const uint4 h = __builtin_bit_cast(
+            uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, voff[j] + 64 * C, 0, 0));
+        *reinterpret_cast<uint4*>(smem + ldsw + j * (256 / PC) * VB) = h;
+      }
+    }
+    if (C == 0 && stopped) return;   // uniform over the block
+    __syncthreads();
+    const int jl = (kg * 8) / CC;   // the lane's tap within a step
+    const int cl = (kg * 8) % CC;   // the lane's channel offset within the chunk
+    int lac[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) lac[mt] = la[mt] + cl * 2;
+    const unsigned wl = (unsigned)((row * KPAD + jl * CIN + 32 * C + cl) * 2);
+    auto steps = [&](auto qq) {
+      constexpr int Q = decltype(qq)::value;
+#pragma unroll
+      for (int s = Q; s < NS; s += NSPLIT) {
+        const int t0 = s * TPS;
+        const bool last = t0 + TPS > 27;          // some lanes' tap is past the end
+        const bool tok = !last || jl < 27 - t0;
+        // B: weights of the lane's tap
+        bf16x8 bv[NCT];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const char* wb =
+              reinterpret_cast<const char*>(a.w) + ((cb * NCT + ct) * 16 * KPAD + t0 * CIN) * 2;
+          const unsigned o = tok ? wl : 0u;
+          bv[ct] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wb + o));
+        }
+        // A: the lane's staged voxel at that tap
+        int toff = tap_off<MODE, IX, IY>(t0 < 27 ? t0 : 26);
+        if (TPS >= 2) toff = jl >= 1 ? tap_off<MODE, IX, IY>(t0 + 1 < 27 ? t0 + 1 : 26) : toff;
+        if (TPS >= 4) {
+          toff = jl >= 2 ? tap_off<MODE, IX, IY>(t0 + 2 < 27 ? t0 + 2 : 26) : toff;
+          toff = jl >= 3 ? tap_off<MODE, IX, IY>(t0 + 3 < 27 ? t0 + 3 : 26) : toff;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          uint4 av = *reinterpret_cast<const uint4*>(smem + lac[mt] + toff * VB);
+          if (last && !tok) av = make_uint4(0, 0, 0, 0);
+          const bf16x8 ab = __builtin_bit_cast(bf16x8, av);
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct)
+            acc[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bv[ct], acc[mt][ct], 0, 0, 0);
+        }
+      }
+    };
+    switch (q) {
+#define TOPO_Q(QV) \
+  case QV:         \
+    if constexpr (QV < NSPLIT) steps(IC<QV>{}); \
+    break;
+      TOPO_Q(0) TOPO_Q(1) TOPO_Q(2) TOPO_Q(3) TOPO_Q(4) TOPO_Q(5) TOPO_Q(6) TOPO_Q(7)
+      TOPO_Q(8) TOPO_Q(9) TOPO_Q(10) TOPO_Q(11) TOPO_Q(12) TOPO_Q(13) TOPO_Q(14) TOPO_Q(15)
+#undef TOPO_Q
+      default: break;
+    }
+  };
+  chunk(IC<0>{});
+  if (stopped) return;
+  if constexpr (NCH > 1) chunk(IC<1>{});
+  if constexpr (NCH > 2) chunk(IC<2>{});
+  if constexpr (NCH > 3) chunk(IC<3>{});
+
+  // sums of the WK waves that share these voxels, in wave order
+  __syncthreads();   // the staged tile is dead from here on
+  if (WK > 1) {
+    float* red = reinterpret_cast<float*>(smem);
+    if (wk > 0) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            red[((((wk - 1) * MT + mt) * NCT + ct) * 4 + i) * 64 + lane] = acc[mt][ct][i];
+    }
+    __syncthreads();
+    if (wk > 0) return;
+#pragma unroll 1
+    for (int w = 0; w < WK - 1; ++w)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            acc[mt][ct][i] += red[(((w * MT + mt) * NCT + ct) * 4 + i) * 64 + lane];
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // Epilogue: the wave turns its C tile (lane = channel, rows = voxels)
+  // into [voxel][channel] rows in LDS, then each lane handles whole groups
+  // of 8 channels of a voxel: 16-byte loads of the gate and accumulated
+  // values, 16-byte stores.
+  constexpr int CP = NCT * 16 + 4;            // floats per voxel row (16-byte aligned)
+  constexpr int GPV = NCT * 2;                // 8-channel groups per voxel
+  constexpr int ITEMS = MT * 16 * GPV;        // per wave
+  float* eo = reinterpret_cast<float*>(smem) + (WK > 1 ? 0 : wm * (MT * 16 * CP));
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) eo[(mt * 16 + 4 * kg + i) * CP + ct * 16 + row] = acc[mt][ct][i];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int it0 = 0; it0 < ITEMS; it0 += 64) {
+    const int it = it0 + lane;
+    const int vl = it / GPV, gc = it % GPV;
+    const int ml = wm * MT * 16 + vl;
+    const int x = X0 + ml % TX, y = Y0 + (ml / TX) % TY, z = Z0 + ml / (TX * TY);
+    if (x >= a.onx || y >= a.ony || z >= a.onz) continue;
+    const int m = (z * a.ony + y) * a.onx + x;
+    const float4 v0 = *reinterpret_cast<const float4*>(eo + vl * CP + gc * 8);
+    const float4 v1 = *reinterpret_cast<const float4*>(eo + vl * CP + gc * 8 + 4);
+    float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    const int c0 = cb * NCT * 16 + gc * 8;   // first of the item's 8 output channels
+    if (a.ysoa) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (c0 + k < a.cout) a.ysoa[(long)(c0 + k) * a.nout + m] = v[k];
+      continue;
+    }
+    // channels c0 .. +8 < C of the output and gate views (C is a multiple of 16)
+    uint16_t* yp = a.y + (long)m * a.ypitch + a.yoff + c0;
+    if (a.accum) {
+      const uint4 h = *reinterpret_cast<const uint4*>(yp);
+      const uint16_t* hs = reinterpret_cast<const uint16_t*>(&h);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] += bf2f(hs[k]);
+    }
+    if (a.gate) {
+      const uint4 h = *reinterpret_cast<const uint4*>(a.gate + (long)m * a.gpitch + a.goff + c0);
+      const uint16_t* hs = reinterpret_cast<const uint16_t*>(&h);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (!(bf2f(hs[k]) > 0.f)) v[k] *= kSlope;
+    }
+    if (a.act) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (!(v[k] > 0.f)) v[k] *= kSlope;
+    }
+    uint4 o;
+    uint32_t* ow = reinterpret_cast<uint32_t*>(&o);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      ow[k] = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * k]) |
+              ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v[2 * k + 1]) << 16);
+    *reinterpret_cast<uint4*>(yp) = o;
+  }
+}
+
+// tile shape of a forward layer with output grid od: 8x8x4 boxes with all
+// output channels per block (one wave per 64 voxels), or 4x4x4 boxes with
+// one block per 16 output channels and the K steps dealt over 4 waves
+struct ConvPlan {
+  bool big;
+  int tiles;
+};
+
+// big_min: output voxels from which stride-1 layers use the 8x8x4 boxes
+static ConvPlan conv_plan(int mode, const int* od, long big_min) {
+  ConvPlan p;
+  const long nout = (long)od[0] * od[1] * od[2];
+  p.big = mode == 0 && nout >= big_min;
+  const int T[3] = {p.big ? 8 : 4, p.big ? 8 : 4, 4};
+  p.tiles = (int)(((od[0] + T[0] - 1) / T[0]) * (long)((od[1] + T[1] - 1) / T[1]) *
+                  ((od[2] + T[2] - 1) / T[2]));
+  return p;
+}
+
+template <int MODE, int CIN, int NCT>
+static void convt_go(const ConvPlan& p, hipStream_t s, const ConvArgs& a) {
+  if constexpr (MODE == 0) {
+    if (p.big) {
+      convt_kernel<MODE, CIN, NCT, 8, 8, 4, 1><<<dim3((unsigned)p.tiles, 1), 256, 0, s>>>(a);
+      return;
+    }
+  }
+  convt_kernel<MODE, CIN, 1, 4, 4, 4, 4><<<dim3((unsigned)p.tiles, NCT), 256, 0, s>>>(a);
+}
+
+// forward layers by (mode, cin, output channel tiles); false if not covered
+static bool convt_dispatch(int mode, int cin, int nct, const ConvPlan& p, hipStream_t s,
+                           const ConvArgs& a) {
+#define TOPO_CONVT(M, C, N)                                  \
+  if (mode == M && cin == C && nct == N) {                   \
+    convt_go<M, C, N>(p, s, a);                              \
+    return true;                                             \
+  }
+  TOPO_CONVT(0, 8, 1)
+  TOPO_CONVT(0, 16, 1)
+  TOPO_CONVT(0, 48, 1)
+  TOPO_CONVT(0, 32, 2)
+  TOPO_CONVT(0, 96, 2)
+  TOPO_CONVT(0, 64, 4)
+  TOPO_CONVT(0, 128, 4)
+  TOPO_CONVT(1, 16, 2)
+  TOPO_CONVT(1, 32, 4)
+  TOPO_CONVT(1, 64, 4)
+#undef TOPO_CONVT
+  return false;
 }
 
 // ----------------------------------------------------------- weight gradient
@@ -713,6 +1032,11 @@ int net_attach(Ctx* c, void* ws, size_t bytes) {
   n->wb = (uint16_t*)(w + o.wb);
   n->dw_part = (float*)(w + o.dwp);
   n->dw_part_len = o.dwp_len;
+  {
+    // TOPO_CONV_BIG_MIN: output voxels from which stride-1 layers use 8x8x4 boxes
+    const char* b = getenv("TOPO_CONV_BIG_MIN");
+    n->conv_big_min = b && atol(b) > 0 ? atol(b) : 131072;
+  }
   n->scal = (double*)(w + o.scal);
   for (int ps = 0; ps < 2; ++ps) {
     FwdBufs& f = ps == 0 ? n->fg : n->fs;
@@ -805,6 +1129,12 @@ static void conv_launch(Ctx* c, int mode, const Act& in, const Act& out, const u
   a.accum = accum;
   a.stop = stop;
   const int nct = (int)(round_up(ysoa ? 16 : out.C, 16) / 16);
+  if (mode != 2) {
+    const ConvPlan p = conv_plan(mode, n->dims[out.level], n->conv_big_min);
+    // the tiled kernel assumes weight rows of round_up(27 cin, 32)
+    if (kpad != (int)round_up(27L * in.C, 32)) abort();
+    if (convt_dispatch(mode, in.C, nct, p, c->stream, a)) return;
+  }
   const dim3 g(cdiv(a.nout, 128));
   if (mode == 0) conv_dispatch<0>(nct, g, c->stream, a);
   else if (mode == 1) conv_dispatch<1>(nct, g, c->stream, a);

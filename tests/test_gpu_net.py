@@ -68,9 +68,15 @@ def _bar(err, floor, cap):
     return err <= min(max(2.5 * floor, 1e-4), cap)
 
 
+@pytest.mark.parametrize("tiles", ["auto", "big"])
 @pytest.mark.parametrize("name,nel", CASES)
-def test_forward_and_backward_match_oracle(name, nel):
-    print(f"[net fwd/bwd] {name} nel={nel}", flush=True)
+def test_forward_and_backward_match_oracle(name, nel, tiles, monkeypatch):
+    """``big``: every stride-1 layer on the 8x8x4 output boxes the library
+    uses on large grids (at these sizes it would pick 4x4x4 boxes with split
+    K sums)."""
+    print(f"[net fwd/bwd] {name} nel={nel} tiles={tiles}", flush=True)
+    if tiles == "big":
+        monkeypatch.setenv("TOPO_CONV_BIG_MIN", "1")
     p, m, rho, r, w = _setup(nel, 10)
     gamma = 1.7
     t = _ctx(p)
@@ -268,7 +274,7 @@ def test_training_on_gpu_cuts_fcg_iterations():
     w0 = learned.init_weights(60, DEV)
     t.precond_set_weights(w0)
     t.precond_config(gamma, 500, 1)
-    losses = learned.train(t, ps, steps=3000, lr=1e-3, seed=61, lr_final=1e-4)
+    losses = learned.train(t, ps, steps=3000, lr=3e-4, seed=61, lr_final=3e-5)
     w = torch.zeros_like(w0)
     t.precond_get_weights(w)
     assert t.sync() == 0
