@@ -131,8 +131,8 @@ def bench_learned(args):
     import numpy as np
     import torch
     import synth
-    from paper_2012_08208_amd import (LOG_LEN, TOPO_FP64, TOPO_MIXED_FP32, TOPO_PC_GMG, Topo,
-                                      learned)
+    from paper_2012_08208_amd import (LOG_LEN, TOPO_FP64, TOPO_MIXED_FP32, TOPO_PC_GMG,
+                                      TOPO_PC_JACOBI, Topo, learned)
     dev = torch.device("cuda:0")
     p = synth.learned3d(rtol=1e-8)
     its = [1, 2, 4, 8, 16, 24]
@@ -175,14 +175,16 @@ def bench_learned(args):
     t.precond_get_weights(w)
     t.close()
 
-    def tts(tt, reps=3):
+    def tts(tt, reps=3, rho=None, n_u=None):
         best = None
+        rho = rho_test if rho is None else rho
+        n_u = p.n_dofs if n_u is None else n_u
         for _ in range(reps):
-            uu = torch.zeros(p.n_dofs, dtype=torch.float64, device=dev)
+            uu = torch.zeros(n_u, dtype=torch.float64, device=dev)
             info = torch.zeros(6, dtype=torch.float64, device=dev)
             torch.cuda.synchronize()
             a = time.perf_counter()
-            tt.solve(rho_test, uu, info)
+            tt.solve(rho, uu, info)
             st = tt.sync()
             dt = time.perf_counter() - a
             if best is None or dt < best[0]:
@@ -202,6 +204,75 @@ def bench_learned(args):
     res["learned_fcg"] = tts(tl)
     for k, v in res.items():
         print(f"[bench] time to solution {k}: {v}", file=sys.stderr, flush=True)
+    # Time to solution on the 192x96x96 cantilever with its 4 load cases
+    # (5.45M DOFs), at a held-out later design of its own SIMP history: FP64
+    # Jacobi-PCG, FP64 and mixed multigrid PCG, and learned flexible CG with a
+    # network trained (same recipe) on pairs of all 4 load cases harvested
+    # along the first iterations of that history.
+    res3 = {}
+    if args.full:
+        import dataclasses
+        p3 = synth.cantilever3d(rtol=1e-8)
+        n_u3 = p3.nrhs * p3.n_dofs
+        rho3 = torch.full((p3.n_cells,), p3.volfrac, dtype=torch.float64, device=dev)
+        u3 = torch.zeros(n_u3, dtype=torch.float64, device=dev)
+        tg = Topo.from_problem(p3, precond=TOPO_PC_GMG, precision=TOPO_FP64, rtol=1e-8, device=dev)
+        cases = [learned.gmg_context(dataclasses.replace(p3, loads=p3.loads[k:k + 1].copy()),
+                                     rtol=1e-8, device=dev) for k in range(p3.nrhs)]
+        a3 = time.perf_counter()
+        R3, E3, rhos3, des3 = [], [], [], []
+        for d in range(4):
+            tg.iterate(rho3, u3, 3)
+            rhos3.append(rho3.clone())
+            for tk in cases:
+                R = torch.empty(len(its) * p3.n_dofs, dtype=torch.float64, device=dev)
+                E = torch.empty_like(R)
+                n_h, fin = tk.precond_harvest(rho3, its, R, E, True)
+                keep = [i for i in range(n_h) if its[i] < fin]
+                R3.append(R.view(len(its), p3.n_dofs)[keep])
+                E3.append(E.view(len(its), p3.n_dofs)[keep])
+                des3 += [d] * len(keep)
+        ps3 = learned.PairSet(rhos=rhos3, R=torch.cat(R3), E=torch.cat(E3),
+                              design=np.asarray(des3, dtype=np.int64), iters=[])
+        tg.iterate(rho3, u3, 4)               # the held-out design: 4 iterations later
+        tg.sync()
+        tg.close()
+        gamma3 = learned.choose_gamma(ps3)
+        ttr = cases[0]
+        w3 = learned.init_weights(62, dev)
+        ttr.precond_set_weights(w3)
+        ttr.precond_config(gamma3, 500, 1)
+        L3 = learned.train(ttr, ps3, steps=args.train_steps, lr=3e-4, seed=63,
+                           lr_final=3e-5).cpu().numpy()
+        ttr.precond_get_weights(w3)
+        torch.cuda.synchronize()
+        setup3 = time.perf_counter() - a3
+        for tk in cases:
+            tk.close()
+        del ps3, R3, E3
+        print(f"[bench] 192x96x96: {len(des3)} pairs, trained {args.train_steps} steps, loss "
+              f"{L3[:100].mean():.3f} -> {L3[-100:].mean():.3f}, set-up {setup3:.1f} s",
+              file=sys.stderr, flush=True)
+        for name, prec, pc, reps in (("jacobi_fp64", TOPO_FP64, TOPO_PC_JACOBI, 1),
+                                     ("gmg_fp64", TOPO_FP64, TOPO_PC_GMG, 3),
+                                     ("gmg_mixed_fp32", TOPO_MIXED_FP32, TOPO_PC_GMG, 3)):
+            tt = Topo.from_problem(p3, precond=pc, precision=prec, rtol=1e-8, maxit=args.maxit,
+                                   device=dev)
+            res3[name] = tts(tt, reps, rho3, n_u3)
+            tt.close()
+        tz3 = learned.learned_context(p3, torch.zeros_like(w3), gamma3, 8000, 1, rtol=1e-8,
+                                      device=dev)
+        res3["cycle_without_network"] = tts(tz3, 1, rho3, n_u3)
+        tz3.close()
+        tl3 = learned.learned_context(p3, w3, gamma3, 8000, 1, rtol=1e-8, device=dev)
+        res3["learned_fcg"] = tts(tl3, 1, rho3, n_u3)
+        tl3.close()
+        res3["training"] = {"pairs": len(des3), "steps": args.train_steps,
+                            "loss_first100": float(L3[:100].mean()),
+                            "loss_last100": float(L3[-100:].mean()), "gamma": gamma3,
+                            "setup_s": setup3}
+        for k, v in res3.items():
+            print(f"[bench] 192x96x96 time to solution {k}: {v}", file=sys.stderr, flush=True)
     # timed SIMP iterations with the learned preconditioner
     rho = rho_test.clone()
     uu = torch.zeros(p.n_dofs, dtype=torch.float64, device=dev)
@@ -244,6 +315,7 @@ def bench_learned(args):
             "status": int(status),
             "cg_iters_per_step": lg[:, 5].tolist(),
             "time_to_solution_heldout": res,
+            "time_to_solution_192x96x96_4rhs": res3 or None,
             "training": {"pairs": int(ps.R.shape[0]), "steps": args.train_steps,
                          "ms_per_step": 1e3 * t_train / max(1, args.train_steps),
                          "loss_first100": float(L[:100].mean()), "loss_last100": float(L[-100:].mean()),
@@ -391,6 +463,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--train-steps", type=int, default=3000,
                     help="learned3d workload: on-GPU training steps before the timed run")
+    ap.add_argument("--no-full", dest="full", action="store_false",
+                    help="learned3d: skip the 192x96x96 time-to-solution comparison")
     ap.add_argument("--batch-converge", action="store_true",
                     help="batch2d workload: also run every instance to max change < 0.01")
     args = ap.parse_args()

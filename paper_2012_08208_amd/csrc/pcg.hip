@@ -489,11 +489,14 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
 // learned preconditioner, which varies from one application to the next:
 //   z_k = M(r_k);  p_k = z_k - sum_{j in window} (z_k, q_j) / (p_j, q_j) p_j;
 //   q_k = K p_k;  alpha = (p_k, r_k) / (p_k, q_k);  x += alpha p_k;  r -= alpha q_k
-// over the last m directions (m = min(8, 15 / nrhs)).  With a fixed SPD
-// preconditioner it is PCG in exact arithmetic.
+// over the last m = 8 directions.  With a fixed SPD preconditioner it is
+// PCG in exact arithmetic.  The (z, q_j) sums of one launch fill at most 16
+// partial slots per block, so the window is covered by launches of 16/nrhs
+// directions each (w0 .. w0+nw).
 struct FcgSlots {
   int n;
   int slot[kFcgWindow];
+  int w0, nw;   // the directions of one dot-product launch
 };
 
 template <int NR>
@@ -508,8 +511,8 @@ __global__ __launch_bounds__(256) void fcg_dots_kernel(const double* __restrict_
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       const double zv = z[(long)k * nd + i];
-      for (int w = 0; w < sl.n; ++w)
-        acc[w * NR + k] += zv * qring[((long)sl.slot[w] * NR + k) * nd + i];
+      for (int w = 0; w < sl.nw; ++w)
+        acc[w * NR + k] += zv * qring[((long)sl.slot[sl.w0 + w] * NR + k) * nd + i];
     }
   }
   const double none[1] = {0.0};
@@ -522,10 +525,10 @@ __global__ void fcg_beta_fin(const double* partials, long nb, FcgSlots sl, DevSc
   __shared__ double tot[16];
   reduce_partials<16, 0>(partials, nb, tot);
   if (threadIdx.x == 0)
-    for (int w = 0; w < kFcgWindow; ++w)
+    for (int w = 0; w < sl.nw; ++w)
       for (int k = 0; k < kMaxRhs; ++k) {
-        const double pq = (w < sl.n && k < NR) ? sc->fcg_pq[sl.slot[w]][k] : 0.0;
-        sc->fcg_beta[w][k] = (pq > 0.0) ? tot[w * NR + k] / pq : 0.0;
+        const double pq = k < NR ? sc->fcg_pq[sl.slot[sl.w0 + w]][k] : 0.0;
+        sc->fcg_beta[sl.w0 + w][k] = (pq > 0.0) ? tot[w * NR + k] / pq : 0.0;
       }
 }
 
@@ -600,7 +603,8 @@ static void fcg_iterate(Ctx* c, double* x, double* r, double* z, int maxit) {
   hipStream_t s = c->stream;
   const unsigned gb = red_grid(nd);
   const long nb_apply = apply_grid_blocks(fine_op(c), NR);
-  const int m = kFcgWindow < 15 / NR ? kFcgWindow : 15 / NR;
+  const int m = kFcgWindow;
+  constexpr int per = 16 / NR;   // directions per dot-product launch
   int it = 0, b = 0, k = 0;
   bool stop = false;
   const int batch = 2;
@@ -610,12 +614,17 @@ static void fcg_iterate(Ctx* c, double* x, double* r, double* z, int maxit) {
       const int cur = k % kFcgRing;
       FcgSlots sl;
       sl.n = k < m ? k : m;
+      sl.w0 = 0;
+      sl.nw = sl.n;
       for (int w = 0; w < sl.n; ++w) sl.slot[w] = (k - 1 - w) % kFcgRing;
       for (int w = sl.n; w < kFcgWindow; ++w) sl.slot[w] = 0;
       learned_precondition(c, r, z, NR);
-      if (sl.n > 0) {
-        fcg_dots_kernel<NR><<<gb, 256, 0, s>>>(z, c->qring, sl, nd, c->partials, st);
-        fcg_beta_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, sl, c->scal);
+      for (int w0 = 0; w0 < sl.n; w0 += per) {
+        FcgSlots sp = sl;
+        sp.w0 = w0;
+        sp.nw = sl.n - w0 < per ? sl.n - w0 : per;
+        fcg_dots_kernel<NR><<<gb, 256, 0, s>>>(z, c->qring, sp, nd, c->partials, st);
+        fcg_beta_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, sp, c->scal);
       }
       fcg_direction_kernel<NR><<<gb, 256, 0, s>>>(c->pring, z, r, sl, cur, nd, c->scal, c->partials);
       fcg_pr_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st);

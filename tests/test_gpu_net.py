@@ -219,25 +219,27 @@ def _solve(t, p, rho):
     return u.cpu().numpy().reshape(p.nrhs, -1), info.cpu().numpy(), st
 
 
+@pytest.mark.parametrize("nrhs", [2, 4])
 @pytest.mark.parametrize("weights", ["zero", "random"])
-def test_learned_fcg_solves_to_direct(weights):
+def test_learned_fcg_solves_to_direct(weights, nrhs):
+    """nrhs 4: the 8-direction window needs two dot-product launches."""
     from paper_2012_08208_amd import TOPO_S_LEARNED_FALLBACK, learned
-    p = synth.cantilever3d(16, 8, 8, nrhs=2)
+    p = synth.cantilever3d(16, 8, 8, nrhs=nrhs)
     m = M.build(3, p.nel)
     rho = synth.rho_random(40, m.n_cells, 0.05, 1.0)
-    u_ref = fem.solve(fem.assemble(m, fem.simp_modulus(rho), p.nu), p.loads.reshape(2, -1),
+    u_ref = fem.solve(fem.assemble(m, fem.simp_modulus(rho), p.nu), p.loads.reshape(nrhs, -1),
                       p.fixed.ravel())
     w = np.zeros(net.n_params(), np.float32) if weights == "zero" else net.init_params(41)
     t = learned.learned_context(p, _t(w, torch.float32), 1.0, 400, 1, rtol=1e-10, device=DEV)
     u, info, st = _solve(t, p, rho)
     fcg, fb = t.precond_stats()
-    print(f"[learned fcg] {weights}: iters {info[0]:.0f} fcg {fcg} fallback {fb} status {st}",
-          flush=True)
+    print(f"[learned fcg] {weights} nrhs {nrhs}: iters {info[0]:.0f} fcg {fcg} fallback {fb} "
+          f"status {st}", flush=True)
     assert st in (0, TOPO_S_LEARNED_FALLBACK)
     if weights == "zero":
         assert st == 0 and fb == 0
     assert info[1] == 1.0 and max(info[2:4]) <= 1e-10
-    for k in range(2):
+    for k in range(nrhs):
         assert _rel(u[k], u_ref[k]) <= 1e-7
 
 
