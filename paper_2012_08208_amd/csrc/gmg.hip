@@ -157,6 +157,97 @@ __global__ __launch_bounds__(256) void restrict3d_tiled_kernel(T* bc, const T* _
   (void)nrhs;
 }
 
+// 3D restriction b_c = P^T (b - q) as a z-sweep: a block owns 32 x 8 coarse
+// nodes of kRsZ coarse planes for one (load case, component); the fine
+// residuals of its 65 x 17 fine columns pass through a ring of three fine
+// planes in LDS, two new planes per coarse plane, rows loaded whole
+// (coalesced).  Sums in the order of restrict_node.
+constexpr int kRsX = 32, kRsY = 8, kRsZ = 8;
+constexpr int kRsFx = 2 * kRsX + 1, kRsFy = 2 * kRsY + 1;
+constexpr int kRsPlane = kRsFx * kRsFy;
+
+template <typename T>
+__global__ __launch_bounds__(256) void restrict3d_sweep_kernel(T* bc, const T* __restrict__ bf,
+                                                               const T* __restrict__ qf, OpDesc fo,
+                                                               OpDesc co, const int* stop) {
+  if (stop && *stop) return;
+  __shared__ T ring[3][kRsPlane];
+  const int tid = threadIdx.x;
+  const int gx = (co.nx + kRsX) / kRsX, gy = (co.ny + kRsY) / kRsY;
+  const int b = blockIdx.x;
+  const int I0 = (b % gx) * kRsX, J0 = ((b / gx) % gy) * kRsY, K0 = (b / (gx * gy)) * kRsZ;
+  const int K1 = min(K0 + kRsZ, co.nz + 1);
+  const int r = blockIdx.y / 3, c = blockIdx.y % 3;
+  const long off = ((long)r * 3 + c) * fo.nn;
+  const int nxf1 = fo.nx + 1, nyf1 = fo.ny + 1;
+  const int fx0 = 2 * I0 - 1, fy0 = 2 * J0 - 1;
+  // a fine plane in registers: b and q of the thread's plane slots
+  constexpr int NQ = (kRsPlane + 255) / 256;
+  struct Pl {
+    T b[NQ], q[NQ];
+  };
+  auto fetch = [&](int fk, Pl& v) {
+    const bool kin = fk >= 0 && fk <= fo.nz;
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const int idx = tid + 256 * j;
+      const int a = idx % kRsFx, bb = idx / kRsFx;
+      const int fi = fx0 + a, fj = fy0 + bb;
+      v.b[j] = T(0);
+      v.q[j] = T(0);
+      if (idx < kRsPlane && kin && fi >= 0 && fj >= 0 && fi <= fo.nx && fj <= fo.ny) {
+        const long n = ((long)fk * nyf1 + fj) * nxf1 + fi;
+        v.b[j] = bf[off + n];
+        v.q[j] = qf[off + n];
+      }
+    }
+  };
+  auto store = [&](int fk, const Pl& v) {
+    T* pl = ring[(fk + 3) % 3];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const int idx = tid + 256 * j;
+      if (idx < kRsPlane) pl[idx] = v.b[j] - v.q[j];
+    }
+  };
+  const int tx = tid % kRsX, ty = tid / kRsX;
+  const int I = I0 + tx, J = J0 + ty;
+  const bool colok = I <= co.nx && J <= co.ny;
+  Pl va, vb;
+  fetch(2 * K0 - 1, va);
+  store(2 * K0 - 1, va);
+  fetch(2 * K0, va);
+  fetch(2 * K0 + 1, vb);
+  for (int K = K0; K < K1; ++K) {
+    store(2 * K, va);
+    store(2 * K + 1, vb);
+    __syncthreads();
+    if (K + 1 < K1) {   // the next two planes load while this one is summed
+      fetch(2 * K + 2, va);
+      fetch(2 * K + 3, vb);
+    }
+    if (colok) {
+      const int li = 2 * tx + 1, lj = 2 * ty + 1;
+      const T* pm = ring[(2 * K - 1 + 3) % 3];
+      const T* p0 = ring[(2 * K) % 3];
+      const T* pp = ring[(2 * K + 1) % 3];
+      T acc = p0[lj * kRsFx + li];
+#pragma unroll
+      for (int dd = 1; dd <= 7; ++dd) {
+        const int dx = dd & 1, dy = (dd >> 1) & 1, dz = (dd >> 2) & 1;
+        const T* lo = dz ? pm : p0;
+        const T* hi = dz ? pp : p0;
+        acc += T(0.5) * lo[(lj - dy) * kRsFx + li - dx];
+        acc += T(0.5) * hi[(lj + dy) * kRsFx + li + dx];
+      }
+      const long C = ((long)K * (co.ny + 1) + J) * (co.nx + 1) + I;
+      const int cm = co.mask[C];
+      bc[((long)r * 3 + c) * co.nn + C] = ((cm >> c) & 1) ? T(0) : acc;
+    }
+    __syncthreads();   // the plane 2K+1 stays; the other two are overwritten next
+  }
+}
+
 template <typename T>
 __global__ void restrict_kernel(T* bc, const T* __restrict__ bf, const T* __restrict__ qf,
                                 OpDesc fo, OpDesc co, int nrhs, const int* stop) {
@@ -410,7 +501,13 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
   T* gq = reinterpret_cast<T*>(g.q);
   cheb_smooth<T>(c, g, b, x, nrhs, true);
   LevelOps<T>::apply(c, g, x, gq, nrhs, stop);
-  if (g.op.dim == 3) {
+  if (g.op.dim == 3 && h.op.nn >= 65536) {
+    // large coarse grids: the z-sweep (fine planes read once, whole rows)
+    const long tiles = (long)cdivu(h.op.nx + 1, kRsX) * cdivu(h.op.ny + 1, kRsY) * cdivu(h.op.nz + 1, kRsZ);
+    restrict3d_sweep_kernel<T><<<dim3((unsigned)tiles, 3 * nrhs), 256, 0, s>>>(hb, b, gq, g.op, h.op,
+                                                                              stop);
+  } else if (g.op.dim == 3) {
+    // small coarse grids: one 8 x 8 x 4 tile per block, more blocks
     const long tiles = (long)cdivu(h.op.nx + 1, kRcx) * cdivu(h.op.ny + 1, kRcy) * cdivu(h.op.nz + 1, kRcz);
     restrict3d_tiled_kernel<T><<<dim3((unsigned)tiles, 3 * nrhs), 256, 0, s>>>(hb, b, gq, g.op, h.op,
                                                                               nrhs, stop);

@@ -1,0 +1,199 @@
+"""Parity at the benchmark's full size: the 192x96x96 cantilever with its 4
+load cases (10,616,832 Kuhn tetrahedra, 5,447,811 DOFs per case), called
+through the C ABI with the launch configuration bench.py times (the
+library's own z-chunk and tile maps for this grid).
+
+The oracle cannot assemble or factor a mesh of this size inside a test, so
+it computes sampled outputs one at a time, with its own element matrices:
+  * rows of y = Z K(rho) Z x at sampled nodes (interior, clamped face,
+    loaded edge, grid corners), summed over the node's incident
+    tetrahedra (Sec. 3.1, eq. fe_form; Kuhn split of Sec. 4.2);
+  * element energies and sensitivities of sampled cells from the GPU
+    displacement (Sec. 2, eq. str_energy; Sec. 3.2);
+  * filtered sensitivities of sampled cells by brute force over their
+    neighbours within rmin (Sec. 3.2.2, eq. filter);
+  * the OC design of sampled cells at the GPU's multiplier (Sec. 3.2,
+    eq. update).
+Solves are judged by properties that hold at any size: the FP64 true
+residual against rtol, and the mixed-precision compliance against the FP64
+solve within the mixed-path bar (rel 1e-7).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fem, filt, mesh as M, oc
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def full():
+    p = synth.cantilever3d()          # 192 x 96 x 96, 4 load cases (the bench workload)
+    assert p.nel == (192, 96, 96) and p.nrhs == 4
+    nx, ny, nz = p.nel
+    kk, jj, ii = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    coords = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1).astype(np.float64)
+    mesh = M.Mesh(3, p.nel, coords, np.zeros((0, 4), np.int64))
+    # mean density = volfrac, so that one move-limited OC step can meet the volume
+    rho = synth.rho_random(71, p.n_cells, 0.05, 0.55)
+    return p, mesh, rho
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _ctx(p, precision, rtol=1e-8):
+    from paper_2012_08208_amd import TOPO_PC_GMG, Topo
+    return Topo.from_problem(p, precision=precision, precond=TOPO_PC_GMG, rtol=rtol, device=DEV)
+
+
+def _sample_nodes(nel):
+    nx, ny, nz = nel
+    rng = np.random.default_rng(72)
+    pts = [(0, 0, 0), (nx, ny, nz), (nx, 0, 0), (0, ny, nz), (nx, ny // 2, nz // 2),
+           (0, ny // 2, nz // 3), (nx, 0, nz // 2), (nx, ny, 7), (nx // 2, 0, nz), (1, 1, 1),
+           (nx - 1, ny - 1, nz - 1), (96, 48, 48)]
+    pts += [tuple(int(v) for v in (rng.integers(0, nx + 1), rng.integers(0, ny + 1),
+                                   rng.integers(0, nz + 1))) for _ in range(36)]
+    return pts
+
+
+def _oracle_rows(p, mesh, rho, x, pts):
+    """y = Z K Z x at the sampled nodes, from their incident tetrahedra."""
+    nx, ny, nz = p.nel
+    N = mesh.n_nodes
+    free = (p.fixed.reshape(3, N) == 0)
+    xz = x * free[None]
+    E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
+    out = np.zeros((p.nrhs, 3, len(pts)))
+    for q, (i, j, k) in enumerate(pts):
+        n = (k * (ny + 1) + j) * (nx + 1) + i
+        cells, ids = [], []
+        for ck in (k - 1, k):
+            for cj in (j - 1, j):
+                for ci in (i - 1, i):
+                    if not (0 <= ci < nx and 0 <= cj < ny and 0 <= ck < nz):
+                        continue
+                    h = (ck * ny + cj) * nx + ci
+                    for t, tet in enumerate(M.cube_cells(ci, cj, ck, nx, ny)):
+                        if n in tet:
+                            cells.append(tet)
+                            ids.append(6 * h + t)
+        cells = np.asarray(cells, dtype=np.int64)
+        K0 = fem.element_K0(mesh, p.nu, cells=cells)
+        dofs = fem.element_dofs(mesh, cells)
+        for e in range(len(cells)):
+            a = int(np.nonzero(cells[e] == n)[0][0])
+            for r in range(p.nrhs):
+                xe = xz[r].ravel()[dofs[e]]
+                for c in range(3):
+                    out[r, c, q] += E[ids[e]] * (K0[e, a * 3 + c] @ xe)
+        out[:, :, q] *= free[:, n][None, :]
+    return out
+
+
+def test_fullsize_apply_sampled_rows(full):
+    from paper_2012_08208_amd import TOPO_FP64
+    p, mesh, rho = full
+    print("[fullsize] apply 192x96x96 x4", flush=True)
+    N = mesh.n_nodes
+    x = np.random.default_rng(73).standard_normal((p.nrhs, 3, N))
+    t = _ctx(p, TOPO_FP64)
+    y = torch.zeros(p.nrhs * 3 * N, dtype=torch.float64, device=DEV)
+    t.apply(_t(rho), _t(x), y)
+    assert t.sync() == 0
+    y = y.cpu().numpy().reshape(p.nrhs, 3, N)
+    t.close()
+    pts = _sample_nodes(p.nel)
+    ref = _oracle_rows(p, mesh, rho, x, pts)
+    nx, ny, _ = p.nel
+    idx = [(k * (ny + 1) + j) * (nx + 1) + i for (i, j, k) in pts]
+    got = y[:, :, idx]
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    print(f"  max |y - y_oracle| = {err:.3e} (scale {scale:.3e}) over {len(pts)} nodes x 12", flush=True)
+    assert err <= 1e-12 * scale
+    # clamped face rows are exactly zero
+    assert np.all(got[:, :, [q for q, pt in enumerate(pts) if pt[0] == 0]] == 0.0)
+
+
+def test_fullsize_solves_sensitivity_filter_oc(full):
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_FP32
+    p, mesh, rho = full
+    print("[fullsize] FP64 and mixed solves 192x96x96 x4, rtol 1e-10", flush=True)
+    N = mesh.n_nodes
+    f = p.loads.reshape(p.nrhs, 3 * N)
+    res = {}
+    for name, prec in (("fp64", TOPO_FP64), ("mixed", TOPO_MIXED_FP32)):
+        t = _ctx(p, prec, rtol=1e-10)
+        u = torch.zeros(p.nrhs * 3 * N, dtype=torch.float64, device=DEV)
+        info = torch.zeros(6, dtype=torch.float64, device=DEV)
+        t.solve(_t(rho), u, info)
+        assert t.sync() == 0
+        # FP64 true residual with the library's FP64 apply (checked above)
+        Ku = torch.zeros_like(u)
+        t.apply(_t(rho), u, Ku)
+        assert t.sync() == 0
+        r = f - Ku.cpu().numpy().reshape(p.nrhs, 3 * N) * (p.fixed.reshape(-1) == 0)[None]
+        rel = np.linalg.norm(r, axis=1) / np.linalg.norm(f, axis=1)
+        info = info.cpu().numpy()
+        print(f"  {name}: iters {info[0]:.0f} true relres {rel.max():.2e}", flush=True)
+        assert info[1] == 1.0 and rel.max() <= 1.05e-10
+        res[name] = (t, u)
+    c64 = [float(f[r] @ res["fp64"][1].cpu().numpy().reshape(p.nrhs, -1)[r]) for r in range(p.nrhs)]
+    cmx = [float(f[r] @ res["mixed"][1].cpu().numpy().reshape(p.nrhs, -1)[r]) for r in range(p.nrhs)]
+    for a, b in zip(cmx, c64):
+        assert abs(a - b) <= 1e-7 * abs(b)
+    res["mixed"][0].close()
+
+    # sensitivity, filter and OC on the FP64 state
+    t, u = res["fp64"]
+    dc = torch.zeros(p.n_cells, dtype=torch.float64, device=DEV)
+    comp = torch.zeros(1, dtype=torch.float64, device=DEV)
+    t.sensitivity(_t(rho), u, dc, comp)
+    dcf = torch.zeros_like(dc)
+    t.filter(_t(rho), dc, dcf)
+    rho_new = torch.zeros_like(dc)
+    sc = torch.zeros(3, dtype=torch.float64, device=DEV)
+    t.oc_update(_t(rho), dcf, rho_new, sc)
+    assert t.sync() == 0
+    dc, dcf, rho_new, sc = (v.cpu().numpy() for v in (dc, dcf, rho_new, sc))
+    uu = u.cpu().numpy().reshape(p.nrhs, 3 * N)
+    t.close()
+    assert abs(float(comp.cpu()[0]) - sum(c64)) <= 1e-10 * sum(c64)
+
+    rng = np.random.default_rng(74)
+    cells = np.unique(np.concatenate([rng.integers(0, p.n_cells, 60),
+                                      [0, 5, p.n_cells - 1, p.n_cells - 6, 6 * 191, 6 * 192 * 95]]))
+    nx, ny, nz = p.nel
+    tets = np.asarray([M.cube_cells(h % nx, (h // nx) % ny, h // (nx * ny), nx, ny)[e % 6]
+                       for e in cells for h in [e // 6]], dtype=np.int64)
+    w = fem.element_energy(mesh, uu, p.nu, cells=tets)
+    s_ref = fem.sensitivity(rho[cells], w, p.E0, p.Emin, p.penal)
+    es = np.max(np.abs(dc[cells] - s_ref) / np.abs(s_ref))
+    print(f"  sensitivity: max rel {es:.2e} over {len(cells)} cells", flush=True)
+    assert es <= 1e-10
+
+    # filter rows by brute force over neighbours (centroids of the Kuhn cells)
+    cent_all = M.centroids(M.grid3d(nx, ny, nz))
+    fr, _ = filt.apply_rows(cent_all, p.rmin, rho, dc, cells)
+    ef = np.max(np.abs(dcf[cells] - fr) / np.abs(fr))
+    print(f"  filter: max rel {ef:.2e}", flush=True)
+    assert ef <= 1e-10
+
+    # OC: volume, bounds, and the sampled design at the GPU's multiplier
+    lam = sc[0]
+    assert abs(rho_new.sum() - p.volfrac * p.n_cells) <= 1e-9 * p.volfrac * p.n_cells
+    assert rho_new.min() >= p.rho_min - 1e-15 and rho_new.max() <= 1.0 + 1e-15
+    assert np.max(np.abs(rho_new - rho)) <= p.move + 1e-12
+    d_ref = oc._design(rho[cells], np.maximum(0.0, -dcf[cells]), lam, p.move, p.eta, p.rho_min)
+    eo = np.max(np.abs(rho_new[cells] - d_ref))
+    print(f"  OC: lambda {lam:.6e}, volume {rho_new.sum() / p.n_cells:.12f}, sampled design err {eo:.2e}",
+          flush=True)
+    assert eo <= 1e-12
