@@ -164,6 +164,7 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.scal = take(sizeof(DevScalars));
   L.R = take((size_t)g.nc * 8);
   L.taps = take((size_t)8 * kMaxFilterTaps * sizeof(FilterTap) + 64);
+  L.ttaps = g.dim == 3 ? take((size_t)6 * kMaxFilterTaps * sizeof(TiledTap)) : 0;
   L.qsoa = take((size_t)g.nc * 8);
   L.dc = take((size_t)g.nc * 8);
   L.dcf = take((size_t)g.nc * 8);
@@ -338,6 +339,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->scal = (DevScalars*)(w + L.scal);
   c->R = (double*)(w + L.R);
   c->taps = (FilterTap*)(w + L.taps);
+  c->ttaps = L.ttaps ? (TiledTap*)(w + L.ttaps) : nullptr;
   c->qsoa = (double*)(w + L.qsoa);
   c->dc = (double*)(w + L.dc);
   c->dcf = (double*)(w + L.dcf);

@@ -13,6 +13,9 @@
 // walk the same tap list (uniform table reads); the filter input rho*dc is
 // first gathered into class-major order so neighbour reads are coalesced.
 #include <math.h>
+#include <stdlib.h>
+
+#include <algorithm>
 
 #include "common.h"
 #include "shared_dev.h"
@@ -84,12 +87,87 @@ int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& ta
   return nclasses;
 }
 
+// The 3D filter on LDS boxes: a block owns kFtX x kFtY x kFtZ cubes (all six
+// cell classes) and stages rho*dc of those cubes and a kFtH-cube halo,
+// zero outside the grid; each cell then sums its taps from LDS.  A tap is a
+// precomputed box offset and a weight, read uniformly by the wave (the
+// wave's cells share a class).  Taps landing outside the grid read a staged
+// zero, so the sums are those of the checked loop, term by term.
+constexpr int kFtX = 8, kFtY = 4, kFtZ = 4, kFtH = 2;
+constexpr int kFtIX = kFtX + 2 * kFtH, kFtIY = kFtY + 2 * kFtH, kFtIZ = kFtZ + 2 * kFtH;
+constexpr int kFtV = kFtIX * kFtIY * kFtIZ;
+
 void build_filter_taps(Ctx* c) {
   std::vector<FilterTap> tab;
   c->nclasses = filter_taps_host(c->g.dim, c->g.split, c->prob.rmin, tab, c->ntaps);
   (void)hipMemcpy(c->taps, tab.data(), tab.size() * sizeof(FilterTap), hipMemcpyHostToDevice);
   (void)hipMemcpy(c->taps + (size_t)8 * kMaxFilterTaps, c->ntaps, sizeof(c->ntaps),
                   hipMemcpyHostToDevice);
+  c->filter_tiled = false;
+  if (c->g.dim == 3 && c->ttaps) {
+    int reach = 0;
+    for (int t = 0; t < 6; ++t)
+      for (int s = 0; s < c->ntaps[t]; ++s) {
+        const FilterTap& f = tab[(size_t)t * kMaxFilterTaps + s];
+        reach = std::max(reach, std::max(std::abs(f.di), std::max(std::abs(f.dj), std::abs(f.dk))));
+      }
+    if (reach <= kFtH) {
+      std::vector<TiledTap> tt((size_t)6 * kMaxFilterTaps, TiledTap{0, 0, 0.0});
+      for (int t = 0; t < 6; ++t)
+        for (int s = 0; s < c->ntaps[t]; ++s) {
+          const FilterTap& f = tab[(size_t)t * kMaxFilterTaps + s];
+          tt[(size_t)t * kMaxFilterTaps + s] =
+              TiledTap{((f.dk * kFtIY + f.dj) * kFtIX + f.di) * 6 + f.tb, 0, f.w};
+        }
+      (void)hipMemcpy(c->ttaps, tt.data(), tt.size() * sizeof(TiledTap), hipMemcpyHostToDevice);
+      c->filter_tiled = true;
+    }
+  }
+}
+
+// out[e] = sum_taps w q / (rho_e R_e) (rowsum: the plain sum with q = 1)
+__global__ __launch_bounds__(256) void filter3d_tiled_kernel(double* out, const double* __restrict__ rho,
+                                                             const double* __restrict__ dc,
+                                                             const double* __restrict__ R,
+                                                             const TiledTap* __restrict__ tt,
+                                                             const int* __restrict__ ntaps, int nx,
+                                                             int ny, int nz, int rowsum) {
+  __shared__ double q[kFtV * 6];
+  const int tid = threadIdx.x;
+  const int gx = (nx + kFtX - 1) / kFtX, gy = (ny + kFtY - 1) / kFtY;
+  const int b = blockIdx.x;
+  const int X0 = (b % gx) * kFtX, Y0 = ((b / gx) % gy) * kFtY, Z0 = (b / (gx * gy)) * kFtZ;
+  for (int idx = tid; idx < kFtV * 6; idx += 256) {
+    const int v = idx / 6, t = idx - v * 6;
+    const int gi = X0 - kFtH + v % kFtIX, gj = Y0 - kFtH + (v / kFtIX) % kFtIY,
+              gk = Z0 - kFtH + v / (kFtIX * kFtIY);
+    double val = 0.0;
+    if (gi >= 0 && gi < nx && gj >= 0 && gj < ny && gk >= 0 && gk < nz) {
+      const long e = (((long)gk * ny + gj) * nx + gi) * 6 + t;
+      val = rowsum ? 1.0 : rho[e] * dc[e];
+    }
+    q[idx] = val;
+  }
+  __syncthreads();
+  const int cbx = tid & (kFtX * kFtY * kFtZ - 1);   // 128 cubes
+  const int half = __builtin_amdgcn_readfirstlane(tid >> 7);
+  const int x = cbx % kFtX, y = (cbx / kFtX) % kFtY, z = cbx / (kFtX * kFtY);
+  const int base = (((z + kFtH) * kFtIY + (y + kFtH)) * kFtIX + (x + kFtH)) * 6;
+  const int gi = X0 + x, gj = Y0 + y, gk = Z0 + z;
+  const bool in = gi < nx && gj < ny && gk < nz;
+  const long h = ((long)gk * ny + gj) * nx + gi;
+#pragma unroll 1
+  for (int r = 0; r < 3; ++r) {
+    const int t = half + 2 * r;   // uniform over the wave
+    const TiledTap* tp = tt + (long)t * kMaxFilterTaps;
+    const int nt = ntaps[t];
+    double acc = 0.0;
+    for (int s = 0; s < nt; ++s) acc += tp[s].w * q[base + tp[s].off];
+    if (in) {
+      const long e = h * 6 + t;
+      out[e] = rowsum ? acc : acc / (rho[e] * R[e]);
+    }
+  }
 }
 
 // q[t][h] = rho[e] * dc[e] (class-major); with rho == nullptr, q = 1.
@@ -117,6 +195,14 @@ __global__ __launch_bounds__(256) void filter_kernel(double* out, const double* 
 
 static void filter_launch(Ctx* c, const double* rho, const double* dc, double* out, bool rowsum) {
   const Grid& g = c->g;
+  if (g.dim == 3 && c->filter_tiled) {
+    const long tiles = (long)((g.nx + kFtX - 1) / kFtX) * ((g.ny + kFtY - 1) / kFtY) *
+                       ((g.nz + kFtZ - 1) / kFtZ);
+    filter3d_tiled_kernel<<<(unsigned)tiles, 256, 0, c->stream>>>(
+        out, rho, dc, c->R, c->ttaps, (const int*)(c->taps + (size_t)8 * kMaxFilterTaps), g.nx, g.ny,
+        g.nz, rowsum ? 1 : 0);
+    return;
+  }
   const int ncls = g.dim == 2 ? 2 : 6;
   const int nz = g.dim == 2 ? 1 : g.nz;
   const long nblk = (long)g.nx * g.ny * nz;

@@ -96,6 +96,12 @@ struct FilterTap {
   double w;
 };
 
+// 3D filter tap as an offset into the LDS box of filter3d_tiled_kernel
+struct TiledTap {
+  int32_t off, pad;
+  double w;
+};
+
 struct Grid {
   int dim;
   int nx, ny, nz;      // cells per axis (nz = 1 in 2D for sizing convenience)
@@ -143,7 +149,7 @@ struct GmgLevel {
 };
 
 struct WsLayout {
-  size_t mask, f, E, E32, invd, invd32, r, p, q, z, wv, partials, scal, R, taps,
+  size_t mask, f, E, E32, invd, invd32, r, p, q, z, wv, partials, scal, R, taps, ttaps,
       qsoa, dc, dcf, rho_new, rho_tmp, r32, p32, q32, z32, z32b, x32, gmg_scal, pring, qring, total;
   std::vector<GmgLevel> levels;   // offsets only (pointers filled at creation)
 };
@@ -189,6 +195,8 @@ struct Ctx {
   FilterTap* taps;    // [classes][kMaxFilterTaps]
   int ntaps[8];
   int nclasses;
+  TiledTap* ttaps;    // 3D: [6][kMaxFilterTaps] offsets into the tiled filter's LDS box
+  bool filter_tiled;  // 3D and every tap within the box's halo
   double* qsoa;       // [nc] filter input in class-major order
   double *dc, *dcf, *rho_new, *rho_tmp;  // [nc]
   // mixed-precision inner solve buffers [nrhs][dim][nn]
