@@ -44,6 +44,8 @@ def workload(name: str):
         return synth.cantilever3d(48, 24, 24, nrhs=4, volfrac=0.3, rmin=2.5, rtol=1e-8)
     if name == "cantilever2d":
         return synth.cantilever2d(60, 30, rtol=1e-10)
+    if name == "mbb2d":
+        return synth.mbb2d(1200, 400, volfrac=0.4, rmin=3.0, rtol=1e-8)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -86,8 +88,14 @@ def cpu_baseline(p_full, sample_nel=(32, 16, 16)):
     sparse LU grows faster than linearly)."""
     import synth
     from oracle import simp
-    p = synth.cantilever3d(*sample_nel, nrhs=p_full.nrhs, volfrac=p_full.volfrac,
-                           rmin=p_full.rmin)
+    if p_full.dim == 2:
+        # the MBB beam: a 600x200 sub-beam with the same supports, load and rmin
+        # (about 8 s of oracle work)
+        sample_nel = (600, 200)
+        p = synth.mbb2d(*sample_nel, volfrac=p_full.volfrac, rmin=p_full.rmin)
+    else:
+        p = synth.cantilever3d(*sample_nel, nrhs=p_full.nrhs, volfrac=p_full.volfrac,
+                               rmin=p_full.rmin)
     S = simp.setup(p)
     t0 = time.perf_counter()
     simp.iterate(S, 1)
@@ -99,8 +107,9 @@ def cpu_baseline(p_full, sample_nel=(32, 16, 16)):
         "cores": 1,
         "kind": "oracle",
         "sample": (f"one oracle SIMP iteration (sparse LU solve of {p.nrhs} load case(s), k-d tree "
-                   f"filter, bisection OC) on {sample_nel[0]}x{sample_nel[1]}x{sample_nel[2]} "
-                   f"cubes ({p.n_cells} cells, {p.n_dofs} DOFs) in {dt:.2f} s; rate scaled by "
+                   f"filter, bisection OC) on {'x'.join(map(str, sample_nel))} "
+                   f"{'cubes' if p.dim == 3 else 'squares'} ({p.n_cells} cells, {p.n_dofs} DOFs) in "
+                   f"{dt:.2f} s; rate scaled by "
                    f"the cell ratio {scale:.3e}; SuperLU and NumPy single-threaded; host "
                    f"{platform.processor() or platform.machine()}, {os.cpu_count()} cores visible"),
     }
@@ -553,7 +562,7 @@ def main():
             "algorithmic_bytes_per_launch": bytes_apply,
         },
     }
-    if not args.no_cpu_baseline and p.dim == 3:
+    if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p)
     else:

@@ -647,6 +647,15 @@ static void fcg_iterate(Ctx* c, double* x, double* r, double* z, int maxit) {
   }
 }
 
+// iteration totals over the restart passes of one run: 0 clear, 1 add the
+// pass just finished, 2 report the total as the run's count
+__global__ void iters_sum_kernel(PcgState* st, int mode) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (mode == 0) st->iters_sum = 0;
+  else if (mode == 1) st->iters_sum += st->iters;
+  else st->iters = st->iters_sum;
+}
+
 __global__ void iters_mark_kernel(PcgState* st, int mode, int* status) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (mode == 0) {
@@ -667,15 +676,18 @@ static void pcg_run(Ctx* c, double* u, double* info, bool warm) {
   PcgState* st = &c->scal->pcg;
   const unsigned gb = red_grid(c->g.nd);
   const bool learned = c->prob.precond == TOPO_PC_LEARNED;
-  // With a variable (FP32 or learned) preconditioner the FP64 true residual
-  // is recomputed after convergence and CG restarts from u while it exceeds
-  // rtol ||f||.
-  const bool check =
-      (c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG) || learned;
+  // After convergence the FP64 true residual f - K u is recomputed and CG
+  // restarts from u while it exceeds rtol ||f||: with a variable (FP32 or
+  // learned) preconditioner, and also in FP64, where on ill-conditioned
+  // designs the recursively updated residual drifts from the true one (2D
+  // MBB 1200x400: recursive 1e-12, true 3e-9 after 58 iterations).  The
+  // reported residual is the true one.
+  const bool check = true;
   int maxit = c->prob.maxit;
   if (learned && c->net->fcg_maxit < maxit) maxit = c->net->fcg_maxit;
   bool fallback = false;
   if (learned) iters_mark_kernel<<<1, 1, 0, s>>>(st, 0, &c->scal->status);
+  iters_sum_kernel<<<1, 1, 0, s>>>(st, 0);
   for (int pass = 0; pass < 4; ++pass) {
     const bool w = warm || pass > 0;
     if (w) launch_apply(c, u, c->q, NR, false);
@@ -684,6 +696,7 @@ static void pcg_run(Ctx* c, double* u, double* info, bool warm) {
     pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, c->prob.rtol, st);
     if (learned) fcg_iterate<NR>(c, u, c->r, c->z, maxit);
     else pcg_iterate<NR, double>(c, u, c->r, c->p, c->q, c->z, maxit);
+    iters_sum_kernel<<<1, 1, 0, s>>>(st, 1);
     if (!check) break;
     launch_apply(c, u, c->q, NR, false);
     resid64_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, c->mask, c->g.nn, c->g.dim, c->partials);
@@ -704,6 +717,7 @@ static void pcg_run(Ctx* c, double* u, double* info, bool warm) {
       break;
     }
   }
+  iters_sum_kernel<<<1, 1, 0, s>>>(st, 2);
   if (fallback) {
     iters_mark_kernel<<<1, 1, 0, s>>>(st, 1, &c->scal->status);
     c->prob.precond = TOPO_PC_GMG;

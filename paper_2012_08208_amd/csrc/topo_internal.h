@@ -35,6 +35,7 @@ struct PcgState {
   int iters;
   int breakdown;
   int iters_prev;   // iterations of an abandoned learned-preconditioner run
+  int iters_sum;    // iterations of the restart passes of one run
 };
 
 struct OcState {
