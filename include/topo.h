@@ -206,6 +206,13 @@ int topo_iterate(topo_ctx* ctx, double* rho, double* u, int max_iter, double cha
    and measurement. */
 int topo_apply(topo_ctx* ctx, const double* rho, const double* x, double* y);
 
+/* The same apply in FP32 as the mixed-precision V-cycle runs it on the fine
+   level (FP32 moduli and vectors, FP32 arithmetic): x, y [nrhs][dim][N_n]
+   float.  Contexts of TOPO_MIXED_FP32 or TOPO_MIXED_IR only (else
+   TOPO_E_STATE); exported for checks and measurement (the launch is timed
+   when timing is enabled). */
+int topo_apply_f32(topo_ctx* ctx, const double* rho, const float* x, float* y);
+
 /* Jacobi diagonal d = diag(K(rho)) on free DOFs and 1 on fixed DOFs,
    d [dim][N_n]. */
 int topo_diagonal(topo_ctx* ctx, const double* rho, double* d);

@@ -32,7 +32,7 @@ LOG_LEN = 8
 EXPORTED = [
     "topo_workspace_size", "topo_create", "topo_destroy", "topo_set_loads", "topo_solve",
     "topo_sensitivity", "topo_filter", "topo_oc_update", "topo_iterate", "topo_apply",
-    "topo_diagonal", "topo_filter_rowsums", "topo_timing_enable", "topo_timing_read",
+    "topo_apply_f32", "topo_diagonal", "topo_filter_rowsums", "topo_timing_enable", "topo_timing_read",
     "topo_sync", "topo_status_string",
     "topo_precond_num_params", "topo_precond_workspace_size", "topo_precond_attach",
     "topo_precond_set_weights", "topo_precond_get_weights", "topo_precond_config",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_oc_update.argtypes = [vp, vp, vp, vp, vp]
     lib.topo_iterate.argtypes = [vp, vp, vp, i32, dbl, vp, P(i32)]
     lib.topo_apply.argtypes = [vp, vp, vp, vp]
+    lib.topo_apply_f32.argtypes = [vp, vp, vp, vp]
     lib.topo_diagonal.argtypes = [vp, vp, vp]
     lib.topo_filter_rowsums.argtypes = [vp, vp]
     lib.topo_timing_enable.argtypes = [vp, i32]
@@ -268,6 +269,13 @@ class Topo:
         _check(self.lib.topo_apply(self.ctx, self._ptr(rho, self.n_cells, "rho"),
                                    self._ptr(x, self.vec_numel(), "x"),
                                    self._ptr(y, self.vec_numel(), "y")), "topo_apply")
+
+    def apply_f32(self, rho, x, y):
+        """FP32 apply of the mixed V-cycle's fine level (x, y float32)."""
+        f32 = self.torch.float32
+        _check(self.lib.topo_apply_f32(self.ctx, self._ptr(rho, self.n_cells, "rho"),
+                                       self._ptr(x, self.vec_numel(), "x", f32),
+                                       self._ptr(y, self.vec_numel(), "y", f32)), "topo_apply_f32")
 
     def diagonal(self, rho, d):
         _check(self.lib.topo_diagonal(self.ctx, self._ptr(rho, self.n_cells, "rho"),

@@ -573,6 +573,15 @@ int topo_apply(topo_ctx* c, const double* rho, const double* x, double* y) {
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
 
+int topo_apply_f32(topo_ctx* c, const double* rho, const float* x, float* y) {
+  if (!c || !rho || !x || !y || (const void*)x == (const void*)y) return TOPO_E_INVALID;
+  if (c->prob.precision == TOPO_FP64 || !c->E32 || !c->p32) return TOPO_E_STATE;
+  launch_simp_modulus(c, rho);
+  launch_mask_copy_f32(c, x, c->p32, c->prob.nrhs);
+  launch_apply_op_f32(c, fine_op(c), c->E32, c->p32, y, c->prob.nrhs, true, nullptr);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
 int topo_diagonal(topo_ctx* c, const double* rho, double* d) {
   if (!c || !rho || !d) return TOPO_E_INVALID;
   launch_simp_modulus(c, rho);

@@ -343,13 +343,14 @@ __global__ void simp_modulus_kernel(double* E, float* E32, const double* rho, lo
   if (E32) E32[e] = (float)v;
 }
 
-__global__ void mask_copy_kernel(const double* src, double* dst, const uint8_t* mask, long nn,
-                                 int dim, long total) {
+template <typename T>
+__global__ void mask_copy_kernel(const T* src, T* dst, const uint8_t* mask, long nn, int dim,
+                                 long total) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   const long n = i % nn;
   const int c = (int)((i / nn) % dim);
-  dst[i] = ((mask[n] >> c) & 1) ? 0.0 : src[i];
+  dst[i] = ((mask[n] >> c) & 1) ? T(0) : src[i];
 }
 
 __global__ void fill_kernel(double* dst, double v, long n) {
@@ -500,8 +501,14 @@ void launch_diagonal(Ctx* c, double* d, bool inverse) {
 
 void launch_mask_copy(Ctx* c, const double* src, double* dst, int nrhs) {
   const long total = (long)nrhs * c->g.nd;
-  mask_copy_kernel<<<cdiv(total, 256), 256, 0, c->stream>>>(src, dst, c->mask, c->g.nn, c->g.dim,
-                                                            total);
+  mask_copy_kernel<double><<<cdiv(total, 256), 256, 0, c->stream>>>(src, dst, c->mask, c->g.nn,
+                                                                    c->g.dim, total);
+}
+
+void launch_mask_copy_f32(Ctx* c, const float* src, float* dst, int nrhs) {
+  const long total = (long)nrhs * c->g.nd;
+  mask_copy_kernel<float><<<cdiv(total, 256), 256, 0, c->stream>>>(src, dst, c->mask, c->g.nn,
+                                                                   c->g.dim, total);
 }
 
 void launch_fill(Ctx* c, double* dst, double v, int64_t n) {

@@ -245,6 +245,7 @@ int pick_kz(int dim, int nx, int ny, int nz);
 void launch_diagonal(Ctx* c, double* d, bool inverse);
 void launch_diagonal_op(Ctx* c, const OpDesc& od, const double* E, double* d, bool inverse);
 void launch_mask_copy(Ctx* c, const double* src, double* dst, int nrhs);
+void launch_mask_copy_f32(Ctx* c, const float* src, float* dst, int nrhs);
 void launch_fill(Ctx* c, double* dst, double v, int64_t n);
 void pcg_solve(Ctx* c, double* u, double* info);
 unsigned red_grid(long n);

@@ -123,6 +123,32 @@ def test_fullsize_apply_sampled_rows(full):
     assert np.all(got[:, :, [q for q, pt in enumerate(pts) if pt[0] == 0]] == 0.0)
 
 
+def test_fullsize_apply_f32_matches_fp64(full):
+    """The mixed V-cycle's FP32 fine-level apply (FP32 moduli, vectors and
+    arithmetic) against the FP64 apply checked above: FP32 rounding of about
+    27 terms per row, relative to the row scale."""
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_FP32
+    p, mesh, rho = full
+    print("[fullsize] apply f32 192x96x96 x4", flush=True)
+    N = mesh.n_nodes
+    x = np.random.default_rng(75).standard_normal((p.nrhs, 3, N))
+    t64 = _ctx(p, TOPO_FP64)
+    y64 = torch.zeros(p.nrhs * 3 * N, dtype=torch.float64, device=DEV)
+    t64.apply(_t(rho), _t(x), y64)
+    assert t64.sync() == 0
+    t64.close()
+    t32 = _ctx(p, TOPO_MIXED_FP32)
+    y32 = torch.zeros(p.nrhs * 3 * N, dtype=torch.float32, device=DEV)
+    t32.apply_f32(_t(rho), _t(x, torch.float32), y32)
+    assert t32.sync() == 0
+    t32.close()
+    a = y32.double().cpu().numpy()
+    b = y64.cpu().numpy()
+    err = np.max(np.abs(a - b)) / np.max(np.abs(b))
+    print(f"  max |y32 - y64| / max |y64| = {err:.2e}", flush=True)
+    assert err <= 2e-6
+
+
 def test_fullsize_solves_sensitivity_filter_oc(full):
     from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_FP32
     p, mesh, rho = full
