@@ -52,15 +52,16 @@ def workload(name: str):
 def apply_bytes(p, precision: str) -> int:
     """Algorithmic bytes of one operator apply over all load cases: read x,
     write y (nrhs x N_d values each), read one modulus per cell, read the
-    one-byte node mask."""
+    one-byte node mask.  FP64: 8-byte vectors and moduli; mixed: 4-byte
+    vectors and moduli; mixed-bf16: 4-byte vectors, 2-byte moduli."""
     sv = 8 if precision == "fp64" else 4
-    se = 8 if precision == "fp64" else 4
+    se = {"fp64": 8, "mixed-bf16": 2}.get(precision, 4)
     return p.nrhs * p.n_dofs * sv * 2 + p.n_cells * se + p.n_nodes
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("apply.hip", "element.h"):
+    for f in ("apply.hip", "element.h", "common.h"):
         with open(os.path.join(ROOT, "paper_2012_08208_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -136,14 +137,15 @@ def conv_flops_per_pass(nel) -> float:
 
 def bench_apply(args):
     """Operator-apply microbenchmark on the 192x96x96 Kuhn mesh: FP64
-    (topo_apply) and FP32 (topo_apply_f32, the mixed V-cycle's fine-level
-    apply) for 1 and 4 load cases.  In-loop: 20 launches back to back;
+    (topo_apply), FP32 (topo_apply_f32, the mixed V-cycle's fine-level
+    apply) and FP32 with BF16 moduli (the same call in a TOPO_MIXED_BF16
+    context) for 1 and 4 load cases.  In-loop: 20 launches back to back;
     isolated: each launch after a 512 MB device write that evicts the 256 MB
     Infinity Cache.  Launch times come from the library's HIP events on its
     own stream.  value = FP32, 4 load cases, isolated, algorithmic GB/s."""
     import torch
     import synth
-    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_FP32, TOPO_PC_JACOBI, Topo
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_BF16, TOPO_MIXED_FP32, TOPO_PC_JACOBI, Topo
     dev = torch.device("cuda:0")
     scratch = torch.empty(1 << 26, dtype=torch.float64, device=dev)   # 512 MB
     rows = []
@@ -152,7 +154,8 @@ def bench_apply(args):
         rho = torch.full((p.n_cells,), p.volfrac, dtype=torch.float64, device=dev)
         g = torch.Generator(device="cpu").manual_seed(20120821)
         x64 = torch.randn(nrhs * p.n_dofs, generator=g, dtype=torch.float64).to(dev)
-        for prec_name, prec in (("fp64", TOPO_FP64), ("fp32", TOPO_MIXED_FP32)):
+        for prec_name, prec in (("fp64", TOPO_FP64), ("fp32", TOPO_MIXED_FP32),
+                                ("fp32-bf16E", TOPO_MIXED_BF16)):
             t = Topo.from_problem(p, precision=prec, precond=TOPO_PC_JACOBI, device=dev)
             if prec == TOPO_FP64:
                 x, y, call = x64, torch.empty_like(x64), t.apply
@@ -178,7 +181,7 @@ def bench_apply(args):
                 ms_iso += ms
             t.sync()
             t.close()
-            alg = apply_bytes(p, "fp64" if prec == TOPO_FP64 else "mixed")
+            alg = apply_bytes(p, {TOPO_FP64: "fp64", TOPO_MIXED_BF16: "mixed-bf16"}.get(prec, "mixed"))
             for mode, n, ms in (("in-loop", n_in, ms_in), ("isolated", n_iso, ms_iso)):
                 us = 1e3 * ms / n
                 gbs = alg / (us * 1e-6) / 1e9
@@ -553,7 +556,7 @@ def main():
     ap.add_argument("--steps", type=int, default=48)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cantilever3d")
-    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed-ir"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed-ir", "mixed-bf16"])
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
     ap.add_argument("--maxit", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -579,12 +582,13 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2012_08208_amd import (LOG_LEN, TOPO_FP64, TOPO_MIXED_FP32, TOPO_MIXED_IR,
-                                      TOPO_PC_GMG, TOPO_PC_JACOBI, Topo)
+    from paper_2012_08208_amd import (LOG_LEN, TOPO_FP64, TOPO_MIXED_BF16, TOPO_MIXED_FP32,
+                                      TOPO_MIXED_IR, TOPO_PC_GMG, TOPO_PC_JACOBI, Topo)
 
     p = workload(args.workload)
     dev = torch.device("cuda:0")
-    prec = {"fp64": TOPO_FP64, "mixed": TOPO_MIXED_FP32, "mixed-ir": TOPO_MIXED_IR}[args.precision]
+    prec = {"fp64": TOPO_FP64, "mixed": TOPO_MIXED_FP32, "mixed-ir": TOPO_MIXED_IR,
+            "mixed-bf16": TOPO_MIXED_BF16}[args.precision]
     pc = TOPO_PC_JACOBI if args.precond == "jacobi" else TOPO_PC_GMG
     t = Topo.from_problem(p, precision=prec, precond=pc, maxit=args.maxit, device=dev)
     rho = torch.full((p.n_cells,), p.volfrac, dtype=torch.float64, device=dev)
@@ -625,7 +629,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "mixed-bf16": "f32+bf16+f64"}.get(args.precision, "f32+f64"),
         "data": "synthetic",
         "config": {
             "workload": (f"{args.workload}: {'x'.join(map(str, p.nel))} cells "

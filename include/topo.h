@@ -92,8 +92,17 @@ enum { TOPO_SPLIT_ALT_ROWS = 0, TOPO_SPLIT_UNIFORM = 1 };
    TOPO_MIXED_IR:   FP64 iterative refinement: true residual in FP64, inner
                     CG on FP32 vectors with the FP32 operator and FP32
                     preconditioner (FP64 dot products) to 1e-4, u += d in
-                    FP64; falls back to FP64 CG if a step stagnates. */
-enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1, TOPO_MIXED_IR = 2 };
+                    FP64; falls back to FP64 CG if a step stagnates.
+   TOPO_MIXED_BF16: TOPO_MIXED_FP32 with the V-cycle's fine-level moduli
+                    stored in BF16 (each FP64 modulus rounded to nearest,
+                    ties to even, 8 significant bits): the fine-level applies
+                    and smoothing read 2 bytes per cell instead of 4; vectors
+                    and arithmetic stay FP32, coarse levels keep FP32 moduli,
+                    and the FP64 outer iteration and true-residual check are
+                    unchanged, so the solution meets rtol as in the other
+                    modes.  With the Jacobi preconditioner this is the FP64
+                    solve. */
+enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1, TOPO_MIXED_IR = 2, TOPO_MIXED_BF16 = 3 };
 /* Preconditioner of the CG solve.
    TOPO_PC_JACOBI:  z = D^-1 r.
    TOPO_PC_GMG:     one multigrid V-cycle (Chebyshev-Jacobi smoothing,
@@ -121,7 +130,7 @@ typedef struct topo_problem {
   double volfrac;             /* k in (0, 1] */
   double rmin;                /* filter radius in cell widths, > 0 */
   double move, eta, rho_min;  /* OC move limit m, damping eta, lower bound */
-  int32_t precision;  /* TOPO_FP64 | TOPO_MIXED_FP32 | TOPO_MIXED_IR */
+  int32_t precision;  /* TOPO_FP64 | TOPO_MIXED_FP32 | TOPO_MIXED_IR | TOPO_MIXED_BF16 */
   int32_t precond;    /* TOPO_PC_JACOBI | TOPO_PC_GMG | TOPO_PC_LEARNED */
   double rtol;        /* stop when ||f_r - K u_r|| <= rtol ||f_r|| for each r */
   int32_t maxit;      /* cap on preconditioned CG iterations per solve */
@@ -207,10 +216,10 @@ int topo_iterate(topo_ctx* ctx, double* rho, double* u, int max_iter, double cha
 int topo_apply(topo_ctx* ctx, const double* rho, const double* x, double* y);
 
 /* The same apply in FP32 as the mixed-precision V-cycle runs it on the fine
-   level (FP32 moduli and vectors, FP32 arithmetic): x, y [nrhs][dim][N_n]
-   float.  Contexts of TOPO_MIXED_FP32 or TOPO_MIXED_IR only (else
-   TOPO_E_STATE); exported for checks and measurement (the launch is timed
-   when timing is enabled). */
+   level (FP32 vectors and arithmetic; FP32 moduli, or BF16 moduli in a
+   TOPO_MIXED_BF16 context): x, y [nrhs][dim][N_n] float.  Mixed-precision
+   contexts only (else TOPO_E_STATE); exported for checks and measurement
+   (the launch is timed when timing is enabled). */
 int topo_apply_f32(topo_ctx* ctx, const double* rho, const float* x, float* y);
 
 /* Jacobi diagonal d = diag(K(rho)) on free DOFs and 1 on fixed DOFs,

@@ -112,6 +112,20 @@ def simp_modulus(rho, E0=1.0, Emin=1e-9, penal=3.0, paper_mode=False):
     return Emin + rho ** penal * (E0 - Emin)
 
 
+def bf16_modulus(E):
+    """The BF16 copy of the moduli that the BF16 mixed-precision mode keeps
+    for its FP32 multigrid cycle: each FP64 value rounded once to the
+    nearest number with 8 significant bits, ties to even, returned as FP64.
+    Written with frexp: E = m 2^e with m in [0.5, 1), so the kept
+    significand is round(m * 256) (NumPy rounds halves to even).  Values
+    must lie in BF16's normal range, [2^-126, 2^128)."""
+    E = np.asarray(E, dtype=np.float64)
+    a = np.abs(E)
+    assert np.all((a == 0) | ((a >= 2.0 ** -126) & (a < 2.0 ** 128)))
+    m, e = np.frexp(E)
+    return np.ldexp(np.round(m * 256.0), e - 8)
+
+
 def assemble(mesh: Mesh, E, nu, paper_mode=False, K0=None):
     """Global stiffness sum_e E_e K0_e as CSR (duplicates summed)."""
     if K0 is None:

@@ -22,6 +22,7 @@ TOPO_SPLIT_UNIFORM = 1
 TOPO_FP64 = 0
 TOPO_MIXED_FP32 = 1
 TOPO_MIXED_IR = 2
+TOPO_MIXED_BF16 = 3
 TOPO_PC_JACOBI = 0
 TOPO_PC_GMG = 1
 TOPO_PC_LEARNED = 2
@@ -271,7 +272,8 @@ class Topo:
                                    self._ptr(y, self.vec_numel(), "y")), "topo_apply")
 
     def apply_f32(self, rho, x, y):
-        """FP32 apply of the mixed V-cycle's fine level (x, y float32)."""
+        """FP32 apply of the mixed V-cycle's fine level (x, y float32; BF16
+        moduli in a TOPO_MIXED_BF16 context, FP32 moduli otherwise)."""
         f32 = self.torch.float32
         _check(self.lib.topo_apply_f32(self.ctx, self._ptr(rho, self.n_cells, "rho"),
                                        self._ptr(x, self.vec_numel(), "x", f32),

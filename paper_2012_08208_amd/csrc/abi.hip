@@ -31,7 +31,7 @@ static bool valid_problem(const topo_problem* p) {
   if (!(p->move > 0.0) || !(p->eta > 0.0) || !(p->rho_min > 0.0 && p->rho_min < 1.0)) return false;
   if (!(p->rtol > 0.0) || p->maxit < 1) return false;
   if (p->precision != TOPO_FP64 && p->precision != TOPO_MIXED_FP32 &&
-      p->precision != TOPO_MIXED_IR)
+      p->precision != TOPO_MIXED_IR && p->precision != TOPO_MIXED_BF16)
     return false;
   if (p->precond != TOPO_PC_JACOBI && p->precond != TOPO_PC_GMG && p->precond != TOPO_PC_LEARNED)
     return false;
@@ -153,6 +153,7 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.f = take(nr * g.nd * 8);
   L.E = take((size_t)g.nc * 8);
   L.E32 = mixed ? take((size_t)g.nc * 4) : 0;
+  L.E16 = p->precision == TOPO_MIXED_BF16 ? take((size_t)g.nc * 2) : 0;
   L.invd = take((size_t)g.nd * 8);
   L.invd32 = mixed ? take((size_t)g.nd * 4) : 0;
   L.r = take(nr * g.nd * 8);
@@ -188,7 +189,7 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.levels.clear();
   if (p->precond != TOPO_PC_JACOBI) {
     L.z = take(nr * g.nd * 8);
-    const bool flex = p->precision == TOPO_MIXED_FP32 || p->precond == TOPO_PC_LEARNED;
+    const bool flex = flex_mixed(*p) || p->precond == TOPO_PC_LEARNED;
     L.wv = flex ? take(nr * g.nd * 8) : 0;
     const std::vector<LevelDims> plan = gmg_plan(g);
     L.gmg_scal = take(8 * 2 * (plan.size() + 1));
@@ -329,6 +330,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->f = (double*)(w + L.f);
   c->E = (double*)(w + L.E);
   c->E32 = L.E32 ? (float*)(w + L.E32) : nullptr;
+  c->E16 = L.E16 ? (uint16_t*)(w + L.E16) : nullptr;
   c->invd = (double*)(w + L.invd);
   c->invd32 = L.invd32 ? (float*)(w + L.invd32) : nullptr;
   c->r = (double*)(w + L.r);
@@ -400,6 +402,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
         lv.E = c->E;
         lv.invd = c->invd;
         lv.E32 = c->E32;
+        lv.E16 = c->E16;
         lv.invd32 = c->invd32;
         lv.mask = c->mask;
         lv.b = lv.x = nullptr;
@@ -407,6 +410,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
         lv.E = (double*)(w + lv.off_E);
         lv.invd = (double*)(w + lv.off_invd);
         lv.E32 = lv.off_E32 ? (float*)(w + lv.off_E32) : nullptr;
+        lv.E16 = nullptr;
         lv.invd32 = lv.off_invd32 ? (float*)(w + lv.off_invd32) : nullptr;
         lv.b = (double*)(w + lv.off_b);
         lv.x = (double*)(w + lv.off_x);
@@ -578,7 +582,10 @@ int topo_apply_f32(topo_ctx* c, const double* rho, const float* x, float* y) {
   if (c->prob.precision == TOPO_FP64 || !c->E32 || !c->p32) return TOPO_E_STATE;
   launch_simp_modulus(c, rho);
   launch_mask_copy_f32(c, x, c->p32, c->prob.nrhs);
-  launch_apply_op_f32(c, fine_op(c), c->E32, c->p32, y, c->prob.nrhs, true, nullptr);
+  if (c->E16)
+    launch_apply_op_bf16(c, fine_op(c), c->E16, c->p32, y, c->prob.nrhs, true, nullptr);
+  else
+    launch_apply_op_f32(c, fine_op(c), c->E32, c->p32, y, c->prob.nrhs, true, nullptr);
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
 

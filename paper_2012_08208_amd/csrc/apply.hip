@@ -185,10 +185,21 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     auto fetch_E = [&](int kk, T (&en)[6]) {
       const bool ok = col_ok && kk >= 0 && kk < nz;
       const long h = (long)min(max(kk, 0), nz - 1) * ny * nx + hcol;
+      if constexpr (sizeof(TE) == 2) {
+        // BF16 moduli: the cube's six are 12 bytes, read as three dwords
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(E + 6 * h);
 #pragma unroll
-      for (int t = 0; t < 6; ++t) {
-        const T e = T(E[6 * h + t]);
-        en[t] = ok ? e : T(0);
+        for (int q = 0; q < 3; ++q) {
+          const uint32_t v = w[q];
+          en[2 * q] = ok ? T(__uint_as_float(v << 16)) : T(0);
+          en[2 * q + 1] = ok ? T(__uint_as_float(v & 0xffff0000u)) : T(0);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+          const T e = T(E[6 * h + t]);
+          en[t] = ok ? e : T(0);
+        }
       }
     };
     const int oi = i0 + tx, oj = j0 + ty;
@@ -332,8 +343,8 @@ __global__ void diag3d_kernel(double* d, const double* E, OpDesc od, double lam0
 }
 
 // ---------------------------------------------------- elementwise helpers
-__global__ void simp_modulus_kernel(double* E, float* E32, const double* rho, long nc, double E0,
-                                    double Emin, double penal, int paper) {
+__global__ void simp_modulus_kernel(double* E, float* E32, uint16_t* E16, const double* rho, long nc,
+                                    double E0, double Emin, double penal, int paper) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nc) return;
   const double r = rho[e];
@@ -341,6 +352,7 @@ __global__ void simp_modulus_kernel(double* E, float* E32, const double* rho, lo
   const double v = paper ? rp : Emin + rp * (E0 - Emin);
   E[e] = v;
   if (E32) E32[e] = (float)v;
+  if (E16) E16[e] = bf16_from_f64(v);
 }
 
 template <typename T>
@@ -362,7 +374,7 @@ __global__ void fill_kernel(double* dst, double v, long n) {
 
 void launch_simp_modulus(Ctx* c, const double* rho) {
   simp_modulus_kernel<<<cdiv(c->g.nc, 256), 256, 0, c->stream>>>(
-      c->E, c->prob.precision != TOPO_FP64 ? c->E32 : nullptr, rho, c->g.nc, c->m.E0,
+      c->E, c->prob.precision != TOPO_FP64 ? c->E32 : nullptr, c->E16, rho, c->g.nc, c->m.E0,
       c->m.Emin, c->m.penal, c->m.paper);
 }
 
@@ -412,16 +424,30 @@ static void apply_dispatch(Ctx* c, const OpDesc& d, const TE* E, const T* x, T* 
 
 // degree-2 smoothing from x = 0 (3D): x = d0 + c1 d0 + c2 D^-1 (b - K d0),
 // d0 = D^-1 b / theta
-template <typename T>
-void launch_apply_cheb_pre3d(Ctx* c, const OpDesc& d, const T* E, const T* b, T* x, const T* invd,
-                             const double* lmax, double r_cur, double r_prev, double low, int nrhs,
-                             const int* stop) {
+template <typename T, typename TE>
+static void cheb_pre3d(Ctx* c, const OpDesc& d, const TE* E, const T* b, T* x, const T* invd,
+                       const double* lmax, double r_cur, double r_prev, double low, int nrhs,
+                       const int* stop) {
   const T lam = T(c->m.lam0 * c->m.vol), mu = T(c->m.mu0 * c->m.vol);
   const TileMap tm = make_tilemap(d, nrhs);
   const unsigned blocks = (unsigned)(8L * tm.per_xcd * nrhs);
   ChebEpi<T> ce{x, invd, b, lmax, r_cur, r_prev, low};
-  apply3d_kernel<T, T, 2><<<blocks, 256, 0, c->stream>>>(nullptr, nullptr, E, d, tm, lam, mu, nullptr,
-                                                         stop, ce);
+  apply3d_kernel<T, TE, 2><<<blocks, 256, 0, c->stream>>>(nullptr, nullptr, E, d, tm, lam, mu,
+                                                          nullptr, stop, ce);
+}
+
+template <typename T>
+void launch_apply_cheb_pre3d(Ctx* c, const OpDesc& d, const T* E, const T* b, T* x, const T* invd,
+                             const double* lmax, double r_cur, double r_prev, double low, int nrhs,
+                             const int* stop) {
+  cheb_pre3d<T, T>(c, d, E, b, x, invd, lmax, r_cur, r_prev, low, nrhs, stop);
+}
+
+void launch_apply_cheb_pre3d_bf16(Ctx* c, const OpDesc& d, const uint16_t* E16, const float* b,
+                                  float* x, const float* invd, const double* lmax, double r_cur,
+                                  double r_prev, double low, int nrhs, const int* stop) {
+  cheb_pre3d<float, bf16m>(c, d, reinterpret_cast<const bf16m*>(E16), b, x, invd, lmax, r_cur,
+                           r_prev, low, nrhs, stop);
 }
 
 template void launch_apply_cheb_pre3d<float>(Ctx*, const OpDesc&, const float*, const float*, float*,
@@ -442,6 +468,13 @@ void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x
                          int nrhs, bool timed, const int* stop) {
   int slot = (timed && c->timing) ? timing_begin(c, 0) : -1;
   apply_dispatch<float, float>(c, d, E, x, y, nrhs, false, stop);
+  if (slot >= 0) timing_end(c, 0, slot);
+}
+
+void launch_apply_op_bf16(Ctx* c, const OpDesc& d, const uint16_t* E16, const float* x, float* y,
+                          int nrhs, bool timed, const int* stop) {
+  int slot = (timed && c->timing) ? timing_begin(c, 0) : -1;
+  apply_dispatch<float, bf16m>(c, d, reinterpret_cast<const bf16m*>(E16), x, y, nrhs, false, stop);
   if (slot >= 0) timing_end(c, 0, slot);
 }
 

@@ -1,4 +1,5 @@
-// Device helpers shared by the kernels: deterministic two-stage reductions.
+// Device helpers shared by the kernels: deterministic two-stage reductions
+// and the BF16 storage of moduli.
 //
 // Stage 1 (inside a wide kernel): every block reduces its values in a fixed
 // order and writes them to partials[linear block id * 16 + k].
@@ -13,6 +14,32 @@
 namespace topo {
 
 constexpr int kPartStride = 16;
+
+// A modulus stored in BF16: the upper 16 bits of an IEEE single.
+struct bf16m {
+  uint16_t bits;
+  __device__ __forceinline__ explicit operator float() const {
+    return __uint_as_float((uint32_t)bits << 16);
+  }
+  __device__ __forceinline__ explicit operator double() const { return (double)float(*this); }
+};
+
+// Nearest BF16 of an FP64 value, ties to even, rounded once from the FP64
+// bits (no intermediate FP32 rounding).  Values below the smallest normal
+// BF16 give a signed zero, values above the largest finite BF16 a signed
+// infinity; NaN is not expected (moduli are finite and non-negative).
+__device__ inline uint16_t bf16_from_f64(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t sign = (u >> 63) << 15;
+  const uint64_t mag = u & 0x7fffffffffffffffull;
+  // keep 7 of the 52 fraction bits: add half an ulp minus one, plus the kept
+  // lowest bit (ties to even), and drop the 45 low bits
+  const uint64_t r = (mag + 0xfffffffffffull + ((mag >> 45) & 1)) >> 45;
+  const int64_t e = (int64_t)(r >> 7) - 1023 + 127;   // BF16 biased exponent
+  if (e <= 0) return (uint16_t)sign;
+  if (e >= 255) return (uint16_t)(sign | 0x7f80);
+  return (uint16_t)(sign | (uint64_t)(r - ((uint64_t)(1023 - 127) << 7)));
+}
 
 // Work-group barrier that orders LDS only.  __syncthreads() also waits for
 // every outstanding global load and store of the wave, which would drain

@@ -23,6 +23,8 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "element.h"
 #include "shared_dev.h"
@@ -444,7 +446,10 @@ struct LevelOps<float> {
   static void apply(Ctx* c, const GmgLevel& g, const float* x, float* y, int nrhs,
                     const int* stop) {
     // fine-level FP32 applies are the timed kernel of the mixed solves
-    launch_apply_op_f32(c, g.op, g.E32, x, y, nrhs, g.op.nn == c->g.nn, stop);
+    if (g.E16)
+      launch_apply_op_bf16(c, g.op, g.E16, x, y, nrhs, g.op.nn == c->g.nn, stop);
+    else
+      launch_apply_op_f32(c, g.op, g.E32, x, y, nrhs, g.op.nn == c->g.nn, stop);
   }
 };
 
@@ -463,6 +468,13 @@ static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool fr
     // the whole degree-2 smoothing from zero in one kernel
     const double sigma = (1.0 + gp.cheb_low) / (1.0 - gp.cheb_low);
     const double rho_prev = 1.0 / sigma, rho = 1.0 / (2.0 * sigma - rho_prev);
+    if constexpr (std::is_same<T, float>::value) {
+      if (g.E16) {
+        launch_apply_cheb_pre3d_bf16(c, g.op, g.E16, b, x, invd, g.lmax, rho, rho_prev,
+                                     gp.cheb_low, nrhs, stop);
+        return;
+      }
+    }
     launch_apply_cheb_pre3d<T>(c, g.op, LevelOps<T>::E(g), b, x, invd, g.lmax, rho, rho_prev,
                                gp.cheb_low, nrhs, stop);
     return;

@@ -307,7 +307,7 @@ struct Prec<double> {
   static void vcycle(Ctx* c, const double* r, double* z, int nr) {
     if (c->prob.precond == TOPO_PC_LEARNED) {
       learned_precondition(c, r, z, nr);
-    } else if (c->prob.precision == TOPO_MIXED_FP32) {
+    } else if (flex_mixed(c->prob)) {
       // FP32 V-cycle as the preconditioner of the FP64 iteration
       const int64_t n = (int64_t)nr * c->g.nd;
       launch_to_f32(c, c->r32, r, n);
@@ -337,7 +337,7 @@ struct FlexTrait {
 template <>
 struct FlexTrait<double> {
   static bool enabled(Ctx* c) {
-    return (c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG) ||
+    return (flex_mixed(c->prob) && c->prob.precond == TOPO_PC_GMG) ||
            c->prob.precond == TOPO_PC_LEARNED;
   }
   static double* second(Ctx* c, double* z) { return c->wv ? c->wv : z; }
@@ -428,7 +428,7 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
   // FP32 (two buffers, new and old, for the Polak-Ribiere beta), the update
   // kernel writes the FP32 residual the V-cycle reads
   if constexpr (std::is_same<TV, double>::value) {
-    if (c->prob.precision == TOPO_MIXED_FP32 && c->prob.precond == TOPO_PC_GMG) {
+    if (flex_mixed(c->prob) && c->prob.precond == TOPO_PC_GMG) {
       mixed_flex_iterate<NR>(c, x, r, p, q, maxit);
       return;
     }

@@ -13,6 +13,11 @@
 
 namespace topo {
 
+// Mixed modes whose FP32 V-cycle preconditions the FP64 flexible CG.
+inline bool flex_mixed(const topo_problem& p) {
+  return p.precision == TOPO_MIXED_FP32 || p.precision == TOPO_MIXED_BF16;
+}
+
 constexpr int kMaxRhs = 4;
 constexpr int kRedBlocks = 1024;   // fixed block count of grid-stride reductions
 constexpr int kMaxFilterTaps = 2048;
@@ -138,6 +143,7 @@ struct GmgLevel {
   double* E;                   // [nc] moduli
   double* invd;                // [dim*nn] inverse diagonal
   float* E32;                  // [nc] FP32 moduli (mixed precision)
+  const uint16_t* E16;         // [nc] BF16 moduli (fine level of TOPO_MIXED_BF16, else null)
   float* invd32;               // [dim*nn] FP32 inverse diagonal (mixed precision)
   double *b, *x, *r, *d, *q;   // [nrhs][dim*nn]
   double *pv, *pw;             // [dim*nn] power-iteration vectors
@@ -150,7 +156,7 @@ struct GmgLevel {
 };
 
 struct WsLayout {
-  size_t mask, f, E, E32, invd, invd32, r, p, q, z, wv, partials, scal, R, taps, ttaps,
+  size_t mask, f, E, E32, E16, invd, invd32, r, p, q, z, wv, partials, scal, R, taps, ttaps,
       qsoa, dc, dcf, rho_new, rho_tmp, r32, p32, q32, z32, z32b, x32, gmg_scal, pring, qring, total;
   std::vector<GmgLevel> levels;   // offsets only (pointers filled at creation)
 };
@@ -187,6 +193,7 @@ struct Ctx {
   double* f;          // [nrhs][dim][nn]
   double* E;          // [nc]
   float* E32;         // [nc] (mixed precision)
+  uint16_t* E16;      // [nc] BF16 bits (TOPO_MIXED_BF16)
   double* invd;       // [dim][nn]
   float* invd32;      // [dim][nn]
   double *r, *p, *q, *z, *wv;  // [nrhs][dim][nn]
@@ -233,6 +240,11 @@ void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, 
                      int nrhs, bool fuse_dot, bool timed, const int* stop);
 void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
                          int nrhs, bool timed, const int* stop);
+void launch_apply_op_bf16(Ctx* c, const OpDesc& d, const uint16_t* E16, const float* x, float* y,
+                          int nrhs, bool timed, const int* stop);
+void launch_apply_cheb_pre3d_bf16(Ctx* c, const OpDesc& d, const uint16_t* E16, const float* b,
+                                  float* x, const float* invd, const double* lmax, double r_cur,
+                                  double r_prev, double low, int nrhs, const int* stop);
 void launch_apply_op_f32_dot(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
                              int nrhs);
 template <typename T>

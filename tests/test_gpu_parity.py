@@ -59,11 +59,48 @@ def test_apply_and_diagonal(name, p):
     np.testing.assert_allclose(d.cpu().numpy(), fem.jacobi_diag(K, fixed), rtol=1e-13)
 
 
-@pytest.mark.parametrize("pc", ["jacobi", "gmg", "mixed-gmg", "ir-gmg", "ir-jacobi"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name,p", _problems())
+def test_apply_f32_and_bf16_moduli(name, p, prec):
+    """The V-cycle's fine-level apply in FP32 arithmetic: with FP32 moduli
+    against the oracle's FP64 operator, and with BF16 moduli against the
+    oracle's operator assembled from its own BF16 rounding of the moduli.
+    Bar: 2e-6 of the largest |y| (FP32 rounding of up to about 40 terms per
+    row); BF16 moduli move y by about 2^-9 relative, so the BF16 case must
+    match the BF16 operator and not the FP64 one."""
+    from paper_2012_08208_amd import TOPO_MIXED_BF16, TOPO_MIXED_FP32
+    print(f"[apply-{prec}] {name} nel={p.nel} nrhs={p.nrhs}", flush=True)
+    m = M.build(p.dim, p.nel, p.split)
+    rho = synth.rho_random(21, m.n_cells, 0.05, 1.0)
+    E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
+    fixed = p.fixed.ravel()
+    x = synth.vec_random(22, (p.nrhs, p.dim, m.n_nodes)).astype(np.float32).astype(np.float64)
+    K = fem.assemble(m, E, p.nu)
+    y64 = np.stack([fem.apply_operator(K, x[r].ravel(), fixed) for r in range(p.nrhs)])
+    if prec == "bf16":
+        Kb = fem.assemble(m, fem.bf16_modulus(E), p.nu)
+        y_ref = np.stack([fem.apply_operator(Kb, x[r].ravel(), fixed) for r in range(p.nrhs)])
+    else:
+        y_ref = y64
+    t = _topo(p, precision=TOPO_MIXED_BF16 if prec == "bf16" else TOPO_MIXED_FP32)
+    y = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float32, device=DEV)
+    t.apply_f32(_t(rho), torch.as_tensor(x.astype(np.float32).ravel(), device=DEV), y)
+    assert t.sync() == 0
+    t.close()
+    y = y.double().cpu().numpy().reshape(p.nrhs, -1)
+    scale = np.max(np.abs(y_ref))
+    err = np.max(np.abs(y - y_ref)) / scale
+    print(f"  max |y - y_ref| / max |y_ref| = {err:.2e}", flush=True)
+    assert err <= 2e-6
+    if prec == "bf16":
+        assert np.max(np.abs(y64 - y_ref)) / scale > 10 * err
+
+
+@pytest.mark.parametrize("pc", ["jacobi", "gmg", "mixed-gmg", "bf16-gmg", "ir-gmg", "ir-jacobi"])
 @pytest.mark.parametrize("name,p", _problems())
 def test_solve_matches_direct(name, p, pc):
-    from paper_2012_08208_amd import (TOPO_FP64, TOPO_MIXED_FP32, TOPO_MIXED_IR, TOPO_PC_GMG,
-                                      TOPO_PC_JACOBI)
+    from paper_2012_08208_amd import (TOPO_FP64, TOPO_MIXED_BF16, TOPO_MIXED_FP32, TOPO_MIXED_IR,
+                                      TOPO_PC_GMG, TOPO_PC_JACOBI)
     print(f"[solve] {name} {pc}", flush=True)
     m = M.build(p.dim, p.nel, p.split)
     rho = synth.rho_random(3, m.n_cells, 0.05, 1.0)
@@ -72,8 +109,8 @@ def test_solve_matches_direct(name, p, pc):
     f = p.loads.reshape(p.nrhs, -1)
     u_ref = fem.solve(K, f, p.fixed.ravel())
     t = _topo(p, rtol=1e-12, precond=TOPO_PC_GMG if pc.endswith("gmg") else TOPO_PC_JACOBI,
-              precision={"mixed": TOPO_MIXED_FP32, "ir": TOPO_MIXED_IR}.get(pc.split("-")[0],
-                                                                            TOPO_FP64))
+              precision={"mixed": TOPO_MIXED_FP32, "ir": TOPO_MIXED_IR,
+                         "bf16": TOPO_MIXED_BF16}.get(pc.split("-")[0], TOPO_FP64))
     u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=DEV)
     info = torch.zeros(6, dtype=torch.float64, device=DEV)
     t.solve(_t(rho), u, info)

@@ -217,3 +217,33 @@ def test_matvec_ebe_matches_assembled():
     x = synth.vec_random(8, (2, 3, m.n_nodes)).reshape(2, -1)
     y = fem.matvec_ebe(m, E, x, p.nu, chunk=37)
     np.testing.assert_allclose(y, (K @ x.T).T, rtol=1e-13, atol=1e-13)
+
+
+def test_bf16_modulus_rounding():
+    """The BF16 copy of the moduli: against torch's FP32 -> BF16 conversion
+    (nearest, ties to even) on FP32-exact values, which one rounding of the
+    FP64 value must reproduce; and hand cases where rounding through FP32
+    first would differ (double rounding), plus ties both ways."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(11)
+    x = np.concatenate([rng.uniform(1e-9, 1.0, 4000), 10.0 ** rng.uniform(-30, 3, 4000)])
+    x32 = x.astype(np.float32).astype(np.float64)
+    ref = torch.from_numpy(x32.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(fem.bf16_modulus(x32), ref)
+    one = 1.0
+    cases = [
+        (one + 2.0 ** -8, one),                            # tie, kept bit even: down
+        (one + 3 * 2.0 ** -8, one + 2.0 ** -6),            # tie, kept bit odd: up
+        (one + 2.0 ** -8 + 2.0 ** -40, one + 2.0 ** -7),   # above the tie only in FP64
+        (one + 2.0 ** -8 - 2.0 ** -40, one),               # below the tie
+        (0.75 * (1 + 2.0 ** -9), 0.75),                    # well below the tie
+        (2.0 ** -30, 2.0 ** -30),                          # a power of two is exact
+    ]
+    for v, want in cases:
+        assert fem.bf16_modulus(np.array([v]))[0] == want, v
+    # the FP32 route gets the third case wrong, so one rounding is required
+    v = np.float32(one + 2.0 ** -8 + 2.0 ** -40)
+    assert torch.tensor([float(v)], dtype=torch.float32).to(torch.bfloat16).item() == 1.0
+    # relative error at most half a BF16 ulp (2^-8 of the value)
+    y = fem.bf16_modulus(x)
+    assert np.all(np.abs(y - x) <= 2.0 ** -8 * np.abs(x))
