@@ -46,6 +46,12 @@ def workload(name: str):
         return synth.cantilever2d(60, 30, rtol=1e-10)
     if name == "mbb2d":
         return synth.mbb2d(1200, 400, volfrac=0.4, rmin=3.0, rtol=1e-8)
+    if name == "hole2d":
+        # the passive-elements example: 180 x 60, volfrac 0.5, rmin 3, a void disc
+        return synth.cantilever2d_hole(180, 60, volfrac=0.5, rmin=3.0, rtol=1e-10)
+    if name == "propped2d":
+        # the pointwise-prop example: 180 x 60, volfrac 0.5, rmin 3
+        return synth.propped_cantilever2d(180, 60, volfrac=0.5, rmin=3.0, rtol=1e-10)
     raise SystemExit(f"unknown workload {name}")
 
 

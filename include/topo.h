@@ -229,6 +229,18 @@ int topo_diagonal(topo_ctx* ctx, const double* rho, double* d);
 /* Filter row sums R [N_c] computed at creation. */
 int topo_filter_rowsums(topo_ctx* ctx, double* R);
 
+/* Passive cells (Sec. 5.4): zones whose density is fixed throughout the
+   iteration.  passive is a HOST array [N_c] of TOPO_PASSIVE_* values (cell
+   order as rho); it is copied into the workspace before the call returns
+   (the call synchronises the context's stream), and NULL removes the set.
+   From then on every OC update gives void cells rho_min and solid cells 1
+   inside each multiplier evaluation, so the volume constraint counts them
+   (they add no slope and do not move the multiplier's bracket); the solve,
+   sensitivity and filter see them like any other cell.  Returns
+   TOPO_E_INVALID for a value above TOPO_PASSIVE_SOLID. */
+enum { TOPO_PASSIVE_FREE = 0, TOPO_PASSIVE_VOID = 1, TOPO_PASSIVE_SOLID = 2 };
+int topo_set_passive(topo_ctx* ctx, const uint8_t* passive);
+
 /* Kernel timing (host outputs).  When enabled, every launch of the
    operator-apply kernel inside topo_solve/topo_apply is bracketed by HIP
    events on the context stream; topo_timing_read returns the number of

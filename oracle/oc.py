@@ -15,6 +15,12 @@ volume constraint holds to rounding.  If the volume at the upper end still
 exceeds the target, the upper end is multiplied by 10 until it does not.
 The returned design is the one evaluated at the last midpoint, and the
 change is the max-norm of rho_new - rho (Section 4.3 / Appendix loop).
+
+Passive cells (Section 5.4): cells marked void are set to the lower density
+bound (the paper writes 0.001, its rho_min) and cells marked solid to 1.
+The setting is done inside every bisection evaluation, before the volume
+sum, so the constraint counts them (the paper adds the assignment to the
+OC loop without saying where; this is the reading taken).
 """
 
 from __future__ import annotations
@@ -22,22 +28,30 @@ from __future__ import annotations
 import numpy as np
 
 
-def _design(rho, neg_s, lam, move, eta, rho_min):
+VOID, SOLID = 1, 2
+
+
+def _design(rho, neg_s, lam, move, eta, rho_min, passive=None):
     lo = np.maximum(rho_min, rho - move)
     hi = np.minimum(1.0, rho + move)
-    return np.maximum(lo, np.minimum(hi, rho * (neg_s / lam) ** eta))
+    out = np.maximum(lo, np.minimum(hi, rho * (neg_s / lam) ** eta))
+    if passive is not None:
+        out[passive == VOID] = rho_min
+        out[passive == SOLID] = 1.0
+    return out
 
 
 def update(rho, s_filtered, volfrac, move=0.2, eta=0.5, rho_min=1e-3,
-           l1=0.0, l2=1e5, max_expand=60):
-    """Returns (rho_new, lam, volume_sum, change, n_passes)."""
+           l1=0.0, l2=1e5, max_expand=60, passive=None):
+    """Returns (rho_new, lam, volume_sum, change, n_passes).  ``passive`` is
+    None or one code per cell: 0 free, 1 void, 2 solid."""
     rho = np.asarray(rho, dtype=np.float64)
     neg_s = np.maximum(0.0, -np.asarray(s_filtered, dtype=np.float64))
     target = volfrac * rho.size
     passes = 0
     for _ in range(max_expand):
         passes += 1
-        if _design(rho, neg_s, l2, move, eta, rho_min).sum() - target > 0:
+        if _design(rho, neg_s, l2, move, eta, rho_min, passive).sum() - target > 0:
             l1, l2 = l2, l2 * 10.0
         else:
             break
@@ -49,7 +63,7 @@ def update(rho, s_filtered, volfrac, move=0.2, eta=0.5, rho_min=1e-3,
             break
         passes += 1
         lam = mid
-        rho_new = _design(rho, neg_s, mid, move, eta, rho_min)
+        rho_new = _design(rho, neg_s, mid, move, eta, rho_min, passive)
         if rho_new.sum() - target > 0:
             l1 = mid
         else:
@@ -59,18 +73,25 @@ def update(rho, s_filtered, volfrac, move=0.2, eta=0.5, rho_min=1e-3,
     return rho_new, lam, vol, change, passes
 
 
-def exact_root(rho, s_filtered, volfrac, move=0.2, rho_min=1e-3):
+def exact_root(rho, s_filtered, volfrac, move=0.2, rho_min=1e-3, passive=None):
     """Independent exact solution for eta = 1/2, used as a pin.
 
     With mu = lambda^(-1/2) each cell is clamp(a_e mu, lo_e, hi_e) with
     a_e = rho_e sqrt(-s~_e); the volume is piecewise linear and
     non-decreasing in mu.  Sorting the breakpoints and solving the linear
     piece that brackets the target gives the root exactly (up to rounding).
-    Returns (rho_new, lam)."""
+    Passive cells enter as a zero coefficient with both bounds at their fixed
+    value (a constant term of the volume).  Returns (rho_new, lam)."""
     rho = np.asarray(rho, dtype=np.float64)
     a = rho * np.sqrt(np.maximum(0.0, -np.asarray(s_filtered, dtype=np.float64)))
     lo = np.maximum(rho_min, rho - move)
     hi = np.minimum(1.0, rho + move)
+    if passive is not None:
+        fixed = np.where(passive == SOLID, 1.0, rho_min)
+        pas = passive != 0
+        a = np.where(pas, 0.0, a)
+        lo = np.where(pas, fixed, lo)
+        hi = np.where(pas, fixed, hi)
     target = volfrac * rho.size
     pos = a > 0
     bps = np.unique(np.concatenate([lo[pos] / a[pos], hi[pos] / a[pos]]))

@@ -74,7 +74,8 @@ def iterate(S: Setup, n_iter: int, rho0=None, change_tol: float = 0.0) -> tuple:
         c_paper = float(np.sum(E * w / (2.0 * vol_cell)))
         sf = filt.apply(S.W, S.R, rho, s)
         rho_new, lam, vol, change, passes = oc.update(rho, sf, p.volfrac, p.move, p.eta,
-                                                      p.rho_min)
+                                                      p.rho_min,
+                                                      passive=getattr(p, "passive", None))
         log.append(dict(it=it + 1, c=c, c_paper=c_paper, vol=vol / rho.size, change=change,
                         lam=lam, passes=passes))
         rho = rho_new

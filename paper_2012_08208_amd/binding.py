@@ -23,6 +23,9 @@ TOPO_FP64 = 0
 TOPO_MIXED_FP32 = 1
 TOPO_MIXED_IR = 2
 TOPO_MIXED_BF16 = 3
+TOPO_PASSIVE_FREE = 0
+TOPO_PASSIVE_VOID = 1
+TOPO_PASSIVE_SOLID = 2
 TOPO_PC_JACOBI = 0
 TOPO_PC_GMG = 1
 TOPO_PC_LEARNED = 2
@@ -33,7 +36,7 @@ LOG_LEN = 8
 EXPORTED = [
     "topo_workspace_size", "topo_create", "topo_destroy", "topo_set_loads", "topo_solve",
     "topo_sensitivity", "topo_filter", "topo_oc_update", "topo_iterate", "topo_apply",
-    "topo_apply_f32", "topo_diagonal", "topo_filter_rowsums", "topo_timing_enable", "topo_timing_read",
+    "topo_apply_f32", "topo_set_passive", "topo_diagonal", "topo_filter_rowsums", "topo_timing_enable", "topo_timing_read",
     "topo_sync", "topo_status_string",
     "topo_precond_num_params", "topo_precond_workspace_size", "topo_precond_attach",
     "topo_precond_set_weights", "topo_precond_get_weights", "topo_precond_config",
@@ -88,6 +91,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_apply_f32.argtypes = [vp, vp, vp, vp]
     lib.topo_diagonal.argtypes = [vp, vp, vp]
     lib.topo_filter_rowsums.argtypes = [vp, vp]
+    lib.topo_set_passive.argtypes = [vp, vp]
     lib.topo_timing_enable.argtypes = [vp, i32]
     lib.topo_timing_read.argtypes = [vp, P(ctypes.c_int64), P(dbl)]
     lib.topo_timing_read_net.argtypes = [vp, P(ctypes.c_int64), P(dbl)]
@@ -197,6 +201,8 @@ class Topo:
         import torch
         t.set_loads(torch.as_tensor(np.ascontiguousarray(p.loads), dtype=torch.float64,
                                     device=t.device))
+        if getattr(p, "passive", None) is not None:
+            t.set_passive(p.passive)
         return t
 
     # ---------------------------------------------------------------- utils
@@ -278,6 +284,19 @@ class Topo:
         _check(self.lib.topo_apply_f32(self.ctx, self._ptr(rho, self.n_cells, "rho"),
                                        self._ptr(x, self.vec_numel(), "x", f32),
                                        self._ptr(y, self.vec_numel(), "y", f32)), "topo_apply_f32")
+
+    def set_passive(self, passive):
+        """Installs passive cells (host uint8 [N_c] of TOPO_PASSIVE_*), or
+        removes them with None."""
+        if passive is None:
+            _check(self.lib.topo_set_passive(self.ctx, None), "topo_set_passive")
+            return
+        a = np.ascontiguousarray(passive, dtype=np.uint8).reshape(-1)
+        if a.size != self.n_cells:
+            raise TopoError("passive must have one entry per cell")
+        self._passive = a
+        _check(self.lib.topo_set_passive(self.ctx, a.ctypes.data_as(ctypes.c_void_p)),
+               "topo_set_passive")
 
     def diagonal(self, rho, d):
         _check(self.lib.topo_diagonal(self.ctx, self._ptr(rho, self.n_cells, "rho"),

@@ -171,6 +171,7 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.dcf = take((size_t)g.nc * 8);
   L.rho_new = take((size_t)g.nc * 8);
   L.rho_tmp = take((size_t)g.nc * 8);
+  L.passive = take((size_t)g.nc);
   L.r32 = L.p32 = L.q32 = L.z32 = L.z32b = L.x32 = 0;
   if (mixed) {
     L.r32 = take(nr * g.nd * 4);
@@ -347,6 +348,8 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->dcf = (double*)(w + L.dcf);
   c->rho_new = (double*)(w + L.rho_new);
   c->rho_tmp = (double*)(w + L.rho_tmp);
+  c->passive = (uint8_t*)(w + L.passive);
+  c->has_passive = false;
   c->z = L.z ? (double*)(w + L.z) : nullptr;
   c->r32 = L.r32 ? (float*)(w + L.r32) : nullptr;
   c->p32 = L.p32 ? (float*)(w + L.p32) : nullptr;
@@ -599,6 +602,24 @@ int topo_diagonal(topo_ctx* c, const double* rho, double* d) {
 int topo_filter_rowsums(topo_ctx* c, double* R) {
   if (!c || !R) return TOPO_E_INVALID;
   TOPO_HIP(hipMemcpyAsync(R, c->R, (size_t)c->g.nc * 8, hipMemcpyDeviceToDevice, c->stream));
+  return TOPO_OK;
+}
+
+int topo_set_passive(topo_ctx* c, const uint8_t* passive) {
+  if (!c) return TOPO_E_INVALID;
+  if (!passive) {
+    c->has_passive = false;
+    return TOPO_OK;
+  }
+  const long nc = (long)c->g.nc;
+  long marked = 0;
+  for (long e = 0; e < nc; ++e) {
+    if (passive[e] > TOPO_PASSIVE_SOLID) return TOPO_E_INVALID;
+    marked += passive[e] != TOPO_PASSIVE_FREE;
+  }
+  TOPO_HIP(hipMemcpyAsync(c->passive, passive, (size_t)nc, hipMemcpyHostToDevice, c->stream));
+  TOPO_HIP(hipStreamSynchronize(c->stream));
+  c->has_passive = marked > 0;
   return TOPO_OK;
 }
 

@@ -12,6 +12,11 @@
 // clamped set is right, one Newton step lands on the root to rounding.
 // Each pass is one kernel with a fused single-pass reduction; the host
 // polls the done flag between batches of passes.
+//
+// Passive cells (Sec. 5.4: zones of fixed density) take lo_e = hi_e = their
+// fixed value (rho_min for a void, 1 for solid material) in every
+// evaluation, so the volume at each multiplier counts them; they contribute
+// nothing to the slope, the first multiplier or the bracket.
 #include <math.h>
 
 #include "common.h"
@@ -20,17 +25,33 @@
 
 namespace topo {
 
+// move-limit bounds of cell e, pinned to the fixed value on passive cells
+__device__ __forceinline__ void oc_bounds(long e, double r, double move, double rho_min,
+                                          const uint8_t* __restrict__ passive, double& lo,
+                                          double& hi) {
+  lo = fmax(rho_min, r - move);
+  hi = fmin(1.0, r + move);
+  if (passive) {
+    const int pv = passive[e];
+    if (pv == TOPO_PASSIVE_VOID) lo = hi = rho_min;
+    if (pv == TOPO_PASSIVE_SOLID) lo = hi = 1.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__ rho,
                                                       const double* __restrict__ dcf, double* a_out,
                                                       long nc, double move, double eta,
-                                                      double rho_min, double* partials) {
+                                                      double rho_min,
+                                                      const uint8_t* __restrict__ passive,
+                                                      double* partials) {
   double acc[3] = {0.0, 0.0, 0.0};
   double mx[1] = {0.0};
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += (long)gridDim.x * blockDim.x) {
     const double r = rho[e];
-    const double a = oc_a(r, dcf[e], eta);
+    double lo, hi;
+    oc_bounds(e, r, move, rho_min, passive, lo, hi);
+    const double a = (passive && passive[e]) ? 0.0 : oc_a(r, dcf[e], eta);
     a_out[e] = a;
-    const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
     acc[0] += lo;
     acc[1] += (a > 0.0) ? hi : lo;  // volume once mu is large
     acc[2] += a;
@@ -49,6 +70,7 @@ __global__ void oc_init_fin(const double* partials, long nb, long nc, double vol
 __global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__ rho,
                                                       const double* __restrict__ a_in, long nc,
                                                       double move, double rho_min,
+                                                      const uint8_t* __restrict__ passive,
                                                       double* partials, const OcState* st) {
   if (st->done) return;
   const double mu = st->mu;
@@ -56,7 +78,8 @@ __global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += (long)gridDim.x * blockDim.x) {
     const double r = rho[e];
     const double a = a_in[e];
-    const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
+    double lo, hi;
+    oc_bounds(e, r, move, rho_min, passive, lo, hi);
     const double v = a * mu;
     acc[0] += fmax(lo, fmin(hi, v));
     acc[1] += (v > lo && v < hi) ? a : 0.0;
@@ -75,14 +98,16 @@ __global__ void oc_pass_fin(const double* partials, long nb, long nc, OcState* s
 __global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict__ rho,
                                                        const double* __restrict__ a_in,
                                                        double* rho_new, long nc, double move,
-                                                       double rho_min, double* partials,
-                                                       const OcState* st) {
+                                                       double rho_min,
+                                                       const uint8_t* __restrict__ passive,
+                                                       double* partials, const OcState* st) {
   const double mu = st->mu;
   double acc[1] = {0.0};
   double mx[1] = {0.0};
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += (long)gridDim.x * blockDim.x) {
     const double r = rho[e];
-    const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
+    double lo, hi;
+    oc_bounds(e, r, move, rho_min, passive, lo, hi);
     const double v = fmax(lo, fmin(hi, a_in[e] * mu));
     rho_new[e] = v;
     acc[0] += v;
@@ -104,20 +129,21 @@ void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, do
   const topo_problem& p = c->prob;
   OcState* st = &c->scal->oc;
   double* a = c->qsoa;
+  const uint8_t* pas = c->has_passive ? c->passive : nullptr;
   hipStream_t s = c->stream;
-  oc_init_kernel<<<nb, 256, 0, s>>>(rho, dcf, a, nc, p.move, p.eta, p.rho_min, c->partials);
+  oc_init_kernel<<<nb, 256, 0, s>>>(rho, dcf, a, nc, p.move, p.eta, p.rho_min, pas, c->partials);
   oc_init_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, p.volfrac, st, &c->scal->status);
   const int batch = 6;
   for (int b = 0; b < 40; ++b) {
     for (int k = 0; k < batch; ++k) {
-      oc_pass_kernel<<<nb, 256, 0, s>>>(rho, a, nc, p.move, p.rho_min, c->partials, st);
+      oc_pass_kernel<<<nb, 256, 0, s>>>(rho, a, nc, p.move, p.rho_min, pas, c->partials, st);
       oc_pass_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, st);
     }
     (void)hipMemcpyAsync((void*)&c->pinned[2], &st->done, sizeof(int), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
     if (c->pinned[2]) break;
   }
-  oc_final_kernel<<<nb, 256, 0, s>>>(rho, a, rho_new, nc, p.move, p.rho_min, c->partials, st);
+  oc_final_kernel<<<nb, 256, 0, s>>>(rho, a, rho_new, nc, p.move, p.rho_min, pas, c->partials, st);
   oc_final_fin<<<1, 256, 0, s>>>(c->partials, nb, p.eta, st, scalars);
 }
 

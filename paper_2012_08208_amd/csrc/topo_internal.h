@@ -157,7 +157,7 @@ struct GmgLevel {
 
 struct WsLayout {
   size_t mask, f, E, E32, E16, invd, invd32, r, p, q, z, wv, partials, scal, R, taps, ttaps,
-      qsoa, dc, dcf, rho_new, rho_tmp, r32, p32, q32, z32, z32b, x32, gmg_scal, pring, qring, total;
+      qsoa, dc, dcf, rho_new, rho_tmp, passive, r32, p32, q32, z32, z32b, x32, gmg_scal, pring, qring, total;
   std::vector<GmgLevel> levels;   // offsets only (pointers filled at creation)
 };
 
@@ -207,6 +207,8 @@ struct Ctx {
   bool filter_tiled;  // 3D and every tap within the box's halo
   double* qsoa;       // [nc] filter input in class-major order
   double *dc, *dcf, *rho_new, *rho_tmp;  // [nc]
+  uint8_t* passive;   // [nc] TOPO_PASSIVE_* per cell
+  bool has_passive;   // a passive set is installed (else the OC ignores the array)
   // mixed-precision inner solve buffers [nrhs][dim][nn]
   float *r32, *p32, *q32, *z32, *z32b, *x32;
   double *pring, *qring;   // truncated flexible CG: [kFcgRing][nrhs][dim][nn]

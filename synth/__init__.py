@@ -20,6 +20,8 @@ Layout convention (shared interface, stated once here):
 from .problems import (  # noqa: F401
     Problem,
     cantilever2d,
+    cantilever2d_hole,
+    propped_cantilever2d,
     mbb2d,
     cantilever3d,
     bar2d,

@@ -75,6 +75,7 @@ class Problem:
     paper_mode: bool = False
     rtol: float = 1e-10
     n_iter: int = 50
+    passive: object = None   # None, or uint8 [N_c]: 0 free, 1 void, 2 solid
 
     @property
     def nrhs(self) -> int:
@@ -131,6 +132,34 @@ def cantilever2d(nelx=60, nely=30, volfrac=0.5, rmin=1.5, load_pos=None,
     f = _edge_point_load(nel, {0: nelx}, 1, pos, 1, -1.0, 2)
     return Problem("cantilever2d", 2, nel, split, fixed, f[None].copy(),
                    volfrac=volfrac, rmin=rmin, n_iter=n_iter, rtol=rtol, **kw)
+
+
+def cantilever2d_hole(nelx=180, nely=60, volfrac=0.5, rmin=3.0, **kw) -> Problem:
+    """The cantilever of ``cantilever2d`` with a circular hole of passive void
+    cells (Section 5.4's example: centre (nelx/3, nely/2), radius nely/4, at
+    180 x 60, volfrac 0.5, rmin 3).  A cell is passive when all four corners
+    of its unit square lie in the closed disc, so both triangles of a square
+    share the mark."""
+    p = cantilever2d(nelx, nely, volfrac=volfrac, rmin=rmin, **kw)
+    x0, y0, r = nelx / 3.0, nely / 2.0, nely / 4.0
+    i = np.arange(nelx)[None, :]
+    j = np.arange(nely)[:, None]
+    inside = np.ones((nely, nelx), bool)
+    for di in (0, 1):
+        for dj in (0, 1):
+            inside &= (i + di - x0) ** 2 + (j + dj - y0) ** 2 <= r * r
+    p.passive = np.repeat(inside.reshape(-1).astype(np.uint8), 2)   # cells 2s, 2s + 1
+    p.name = "cantilever2d_hole"
+    return p
+
+
+def propped_cantilever2d(nelx=180, nely=60, volfrac=0.5, rmin=3.0, **kw) -> Problem:
+    """The cantilever of ``cantilever2d`` with a prop: u_y = 0 at the single
+    node (nelx, 0) (Section 5.2's pointwise support)."""
+    p = cantilever2d(nelx, nely, volfrac=volfrac, rmin=rmin, **kw)
+    p.fixed[1, node_id(p.nel, nelx, 0)] = 1
+    p.name = "propped_cantilever2d"
+    return p
 
 
 def mbb2d(nelx=1200, nely=400, volfrac=0.4, rmin=3.0, split=SPLIT_UNIFORM,

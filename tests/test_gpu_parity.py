@@ -192,6 +192,45 @@ def test_oc_update(nx, ny, vf, seed):
     np.testing.assert_allclose(sc[2], change, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_oc_update_passive(dim):
+    """Passive cells (Section 5.4) in the OC update against the oracle:
+    void cells at rho_min, solid cells at 1, the volume counted with them."""
+    from paper_2012_08208_amd import TopoError
+    p = synth.cantilever2d(53, 21, volfrac=0.4) if dim == 2 else \
+        synth.cantilever3d(13, 7, 5, nrhs=1, volfrac=0.4)
+    print(f"[oc-passive] {dim}D nel={p.nel}", flush=True)
+    rng = np.random.default_rng(40 + dim)
+    n = p.n_cells
+    rho = np.clip(rng.uniform(0.0, 0.8, n), 0.001, 1.0)
+    dcf = -rng.lognormal(0, 2, n)
+    passive = np.zeros(n, np.uint8)
+    passive[rng.choice(n, n // 10, replace=False)] = oc.VOID
+    passive[rng.choice(np.flatnonzero(passive == 0), n // 20, replace=False)] = oc.SOLID
+    ref, lam, vol, change, _ = oc.update(rho, dcf, 0.4, passive=passive)
+    t = _topo(p)
+    with pytest.raises(TopoError):
+        t.set_passive(np.full(n, 3, np.uint8))
+    t.set_passive(passive)
+    rn = torch.zeros(n, dtype=torch.float64, device=DEV)
+    sc = torch.zeros(3, dtype=torch.float64, device=DEV)
+    t.oc_update(_t(rho), _t(dcf), rn, sc)
+    assert t.sync() == 0
+    got = rn.cpu().numpy()
+    scv = sc.cpu().numpy()
+    assert np.all(got[passive == oc.VOID] == p.rho_min) and np.all(got[passive == oc.SOLID] == 1.0)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(scv[0], lam, rtol=1e-9)
+    np.testing.assert_allclose(scv[2], change, rtol=0, atol=1e-12)
+    # removing the set gives the plain update again
+    t.set_passive(None)
+    t.oc_update(_t(rho), _t(dcf), rn, sc)
+    assert t.sync() == 0
+    ref0, *_ = oc.update(rho, dcf, 0.4)
+    np.testing.assert_allclose(rn.cpu().numpy(), ref0, rtol=0, atol=1e-12)
+    t.close()
+
+
 @pytest.mark.parametrize("nel", [(32, 16, 16), (41, 13, 9)])
 def test_gmg_needs_far_fewer_iterations_than_jacobi(nel):
     from paper_2012_08208_amd import TOPO_PC_GMG, TOPO_PC_JACOBI
@@ -270,6 +309,23 @@ def test_iterate_cantilever_60x30_50_iterations_mixed_ir():
     _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-7)
 
 
+@pytest.mark.parametrize("case", ["hole", "propped"])
+def test_iterate_extensions_60x30_50_iterations(case):
+    """The paper's extensions on the 60 x 30 cantilever, 50 iterations
+    against the oracle: a hole of passive void cells (Section 5.4) and a
+    pointwise prop u_y = 0 at the bottom-right node (Section 5.2)."""
+    from paper_2012_08208_amd import TOPO_PC_GMG
+    p = synth.cantilever2d_hole(60, 30, rmin=1.5) if case == "hole" else \
+        synth.propped_cantilever2d(60, 30, rmin=1.5)
+    print(f"[iterate] {p.name} 60x30 x50", flush=True)
+    S = simp.setup(p)
+    rho_ref, log_ref = simp.iterate(S, 50)
+    t = _topo(p, rtol=1e-12, precond=TOPO_PC_GMG)
+    rho = _run_iterate_check(t, p, rho_ref, log_ref)
+    if case == "hole":
+        assert np.all(rho[p.passive == oc.VOID] == p.rho_min)
+
+
 def _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-9):
     from paper_2012_08208_amd import LOG_LEN
     rho = torch.full((p.n_cells,), p.volfrac, dtype=torch.float64, device=DEV)
@@ -286,3 +342,4 @@ def _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-9):
     err = np.max(np.abs(rho.cpu().numpy() - rho_ref))
     print(f"[iterate] max |rho - rho_oracle| = {err:.3e}", flush=True)
     assert err <= 1e-4
+    return rho.cpu().numpy()

@@ -234,3 +234,55 @@ def test_loop_cantilever_mirror_symmetry_and_volume():
     S1 = simp.setup(p)
     _, c_unit, *_ = simp.solve_state(S1, np.ones(S1.mesh.n_cells))
     np.testing.assert_allclose(cs[0], c_unit / E_half, rtol=1e-9)
+
+
+def test_oc_passive_cells():
+    """Passive cells (Section 5.4): void cells at rho_min and solid cells at
+    1 after the update; the volume constraint counts them; free cells obey
+    the OC formula at the returned multiplier; and the bisection (which
+    overwrites passive cells after the clamp) agrees with the exact
+    breakpoint root written with pinned bounds and zero coefficients."""
+    rng = np.random.default_rng(19)
+    n = 500
+    rho = rng.uniform(0.001, 1.0, n)
+    sf = -rng.lognormal(0.0, 2.0, n)
+    passive = np.zeros(n, np.uint8)
+    passive[rng.choice(n, 60, replace=False)] = oc.VOID
+    passive[rng.choice(np.flatnonzero(passive == 0), 25, replace=False)] = oc.SOLID
+    vf = 0.4
+    rn, lam, vol, change, _ = oc.update(rho, sf, vf, passive=passive)
+    assert np.all(rn[passive == oc.VOID] == 1e-3)
+    assert np.all(rn[passive == oc.SOLID] == 1.0)
+    assert abs(rn.sum() - vf * n) <= 1e-12 * n
+    lo = np.maximum(1e-3, rho - 0.2)
+    hi = np.minimum(1.0, rho + 0.2)
+    free = (passive == 0) & (rn > lo) & (rn < hi)
+    assert free.sum() > 10
+    np.testing.assert_allclose(rn[free], rho[free] * np.sqrt(-sf[free] / lam), rtol=1e-12)
+    re, lam_e = oc.exact_root(rho, sf, vf, passive=passive)
+    np.testing.assert_allclose(rn, re, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(lam, lam_e, rtol=1e-10)
+    # an all-free mask is the plain update
+    r0, l0, *_ = oc.update(rho, sf, vf, passive=np.zeros(n, np.uint8))
+    r1, l1, *_ = oc.update(rho, sf, vf)
+    assert np.array_equal(r0, r1) and l0 == l1
+    # the multiplier moves: the free cells carry the volume the passive ones do not
+    _, lam_free, *_ = oc.update(rho, sf, vf)
+    assert lam != lam_free
+
+
+def test_loop_hole_keeps_passive_void():
+    """The hole example at 60 x 30 (same rule, disc at (20, 15), radius 7.5):
+    every passive cell is at rho_min after each iteration, the volume is
+    held, and the design stays mirror-symmetric (the disc is symmetric about
+    y = 15 and the alternating-rows mesh is too)."""
+    p = synth.cantilever2d_hole(60, 30, rmin=1.5)
+    assert p.passive.sum() > 0
+    S = simp.setup(p)
+    perm = _mirror_perm(S.mesh)
+    assert np.array_equal(p.passive, p.passive[perm])
+    rho, log = simp.iterate(S, 12)
+    assert np.all(rho[p.passive == oc.VOID] == p.rho_min)
+    for rec in log:
+        assert abs(rec["vol"] - p.volfrac) <= 1e-12
+    np.testing.assert_allclose(rho, rho[perm], atol=1e-8)
