@@ -21,6 +21,7 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -564,6 +565,8 @@ def main():
     ap.add_argument("--workload", default="cantilever3d")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed-ir", "mixed-bf16"])
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
+    ap.add_argument("--filter", default="distance", choices=["distance", "helmholtz"],
+                    help="sensitivity filter: distance-weighted (Sec. 3.2.2) or Helmholtz PDE (Sec. 6.3)")
     ap.add_argument("--maxit", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--train-steps", type=int, default=3000,
@@ -592,6 +595,8 @@ def main():
                                       TOPO_MIXED_IR, TOPO_PC_GMG, TOPO_PC_JACOBI, Topo)
 
     p = workload(args.workload)
+    if args.filter == "helmholtz":
+        p = dataclasses.replace(p, filter=1)
     dev = torch.device("cuda:0")
     prec = {"fp64": TOPO_FP64, "mixed": TOPO_MIXED_FP32, "mixed-ir": TOPO_MIXED_IR,
             "mixed-bf16": TOPO_MIXED_BF16}[args.precision]
@@ -643,6 +648,7 @@ def main():
                          f"volfrac {p.volfrac}, p {p.penal}, rmin {p.rmin}, CG rtol {p.rtol}"),
             "precision": args.precision,
             "precond": args.precond,
+            "filter": args.filter,
             "status": int(status),
             "cg_iters_per_step": lg[:, 5].tolist(),
             "compliance": lg[:, 0].tolist(),

@@ -119,6 +119,25 @@ enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1, TOPO_MIXED_IR = 2, TOPO_MIXED_BF16 = 
                     topo_precond_set_weights before the first solve. */
 enum { TOPO_PC_JACOBI = 0, TOPO_PC_GMG = 1, TOPO_PC_LEARNED = 2 };
 
+/* Sensitivity filter used by topo_filter and topo_iterate.
+   TOPO_FILTER_DISTANCE:  the distance-weighted filter of Sec. 3.2.2,
+                          s~_a = sum_b W_ab rho_b s_b / (rho_a sum_b W_ab),
+                          W_ab = max(0, rmin - |x_a - x_b|), truncated at the
+                          domain boundary.
+   TOPO_FILTER_HELMHOLTZ: the PDE filter Sec. 6.3 adopts for parallel runs
+                          (Lazarov and Sigmund 2011): the P1 solution x of
+                          (r^2 K + M) x = T (rho s) with zero normal
+                          derivative on the boundary, r = rmin / (2 sqrt 3),
+                          K the P1 Laplacian, M the consistent P1 mass,
+                          T_ne = |T_e| / (d+1) at the vertices of e; then
+                          s~_e = (mean of x over the vertices of e) / rho_e.
+                          Solved by Jacobi-preconditioned FP64 CG to a
+                          relative residual of 1e-12 (the call synchronises
+                          with the stream between batches of iterations, as
+                          topo_solve does); a solve that stops at its cap of
+                          4000 iterations sets TOPO_S_NOT_CONVERGED. */
+enum { TOPO_FILTER_DISTANCE = 0, TOPO_FILTER_HELMHOLTZ = 1 };
+
 /* Problem description (host struct, copied by topo_create). */
 typedef struct topo_problem {
   int32_t dim;        /* 2 or 3 */
@@ -138,6 +157,7 @@ typedef struct topo_problem {
                          1: the listing's law, see above */
   int32_t warm_start; /* 1: topo_solve starts from the u it is given */
   int32_t gmg_levels; /* 0 = automatic; otherwise the number of levels */
+  int32_t filter;     /* TOPO_FILTER_DISTANCE (0) | TOPO_FILTER_HELMHOLTZ */
 } topo_problem;
 
 /* Length of the per-solve info record written by topo_solve (doubles):

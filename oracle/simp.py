@@ -5,7 +5,9 @@ cell, each iteration (1) solves K(rho) u = f, (2) evaluates the compliance
 and its sensitivity, (3) filters the sensitivity, (4) updates rho by the
 optimality criteria with bisection, and (5) records the change
 max |rho_new - rho|.  Multiple load cases (Section 5.3) are solved one by
-one; compliances and sensitivities are summed over the cases.
+one; compliances and sensitivities are summed over the cases.  Step (3)
+uses the distance-weighted filter, or the Helmholtz PDE filter
+(oracle/helm.py) when the problem's ``filter`` is 1.
 
 The logged objective is the compliance c = sum_r f_r^T u_r; ``c_paper`` is
 sum_e E_e w_e / (2|T_e|), the sum of rho^p psi_e that the listing prints
@@ -19,7 +21,7 @@ from typing import List
 
 import numpy as np
 
-from . import fem, filt, mesh as mesh_mod, oc
+from . import fem, filt, helm, mesh as mesh_mod, oc
 
 
 @dataclasses.dataclass
@@ -31,6 +33,11 @@ class Setup:
     W: object
     R: np.ndarray
     prob: object
+    helm_mats: object = None
+
+
+def _helmholtz(prob) -> bool:
+    return getattr(prob, "filter", 0) == 1
 
 
 def setup(prob, dense_filter: bool = False) -> Setup:
@@ -41,7 +48,15 @@ def setup(prob, dense_filter: bool = False) -> Setup:
     cent = mesh_mod.centroids(m)
     W = filt.weights_dense(cent, prob.rmin) if dense_filter else filt.weights_sparse(cent, prob.rmin)
     R = filt.row_sums(W) if not dense_filter else W.sum(axis=1)
-    return Setup(m, K0, fixed_flat, f, W, R, prob)
+    hm = helm.matrices(m) if _helmholtz(prob) else None
+    return Setup(m, K0, fixed_flat, f, W, R, prob, hm)
+
+
+def filter_sensitivity(S: Setup, rho, s):
+    """Step (3): the configured sensitivity filter."""
+    if _helmholtz(S.prob):
+        return helm.sensitivity_filter(S.mesh, S.prob.rmin, rho, s, S.helm_mats)
+    return filt.apply(S.W, S.R, rho, s)
 
 
 def modulus(S: Setup, rho):
@@ -72,7 +87,7 @@ def iterate(S: Setup, n_iter: int, rho0=None, change_tol: float = 0.0) -> tuple:
     for it in range(n_iter):
         u, c, w, s, E = solve_state(S, rho)
         c_paper = float(np.sum(E * w / (2.0 * vol_cell)))
-        sf = filt.apply(S.W, S.R, rho, s)
+        sf = filter_sensitivity(S, rho, s)
         rho_new, lam, vol, change, passes = oc.update(rho, sf, p.volfrac, p.move, p.eta,
                                                       p.rho_min,
                                                       passive=getattr(p, "passive", None))

@@ -38,6 +38,7 @@ static bool valid_problem(const topo_problem* p) {
   if (p->precond == TOPO_PC_LEARNED && (p->dim != 3 || p->precision != TOPO_FP64)) return false;
   if (p->dim == 2 && p->split2d != TOPO_SPLIT_ALT_ROWS && p->split2d != TOPO_SPLIT_UNIFORM)
     return false;
+  if (p->filter != TOPO_FILTER_DISTANCE && p->filter != TOPO_FILTER_HELMHOLTZ) return false;
   return true;
 }
 
@@ -172,6 +173,7 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.rho_new = take((size_t)g.nc * 8);
   L.rho_tmp = take((size_t)g.nc * 8);
   L.passive = take((size_t)g.nc);
+  L.helm = p->filter == TOPO_FILTER_HELMHOLTZ ? take((size_t)5 * g.nn * 8) : 0;
   L.r32 = L.p32 = L.q32 = L.z32 = L.z32b = L.x32 = 0;
   if (mixed) {
     L.r32 = take(nr * g.nd * 4);
@@ -350,6 +352,15 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->rho_tmp = (double*)(w + L.rho_tmp);
   c->passive = (uint8_t*)(w + L.passive);
   c->has_passive = false;
+  c->hx = c->hr = c->hp = c->hq = c->hinvd = nullptr;
+  if (L.helm) {
+    double* hb = (double*)(w + L.helm);
+    c->hx = hb;
+    c->hr = hb + c->g.nn;
+    c->hp = hb + 2 * c->g.nn;
+    c->hq = hb + 3 * c->g.nn;
+    c->hinvd = hb + 4 * c->g.nn;
+  }
   c->z = L.z ? (double*)(w + L.z) : nullptr;
   c->r32 = L.r32 ? (float*)(w + L.r32) : nullptr;
   c->p32 = L.p32 ? (float*)(w + L.p32) : nullptr;
@@ -453,6 +464,10 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   if (ok) {
     build_filter_taps(c);
     launch_filter_rowsums(c);
+    if (c->hinvd) {
+      build_helm_coef(c);
+      launch_helm_diag(c);
+    }
     ok = hipStreamSynchronize(c->stream) == hipSuccess && hipGetLastError() == hipSuccess;
   }
   if (!ok) {

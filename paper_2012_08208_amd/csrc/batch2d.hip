@@ -687,6 +687,7 @@ struct Carver {
 
 bool valid_batch_problem(const topo_problem& p) {
   if (p.dim != 2 || p.nrhs != 1 || p.precision != TOPO_FP64 || p.precond != TOPO_PC_GMG) return false;
+  if (p.filter != TOPO_FILTER_DISTANCE) return false;
   if (p.paper_mode) return false;
   if (p.nel[0] < 2 || p.nel[1] < 2 || p.nel[0] > (1 << 15) || p.nel[1] > (1 << 15)) return false;
   if (p.split2d != TOPO_SPLIT_ALT_ROWS && p.split2d != TOPO_SPLIT_UNIFORM) return false;

@@ -219,6 +219,10 @@ static void filter_launch(Ctx* c, const double* rho, const double* dc, double* o
 void launch_filter_rowsums(Ctx* c) { filter_launch(c, nullptr, nullptr, c->R, true); }
 
 void launch_filter(Ctx* c, const double* rho, const double* dc, double* dcf) {
+  if (c->prob.filter == TOPO_FILTER_HELMHOLTZ) {
+    launch_filter_helmholtz(c, rho, dc, dcf);
+    return;
+  }
   filter_launch(c, rho, dc, dcf, false);
 }
 

@@ -43,6 +43,23 @@ struct PcgState {
   int iters_sum;    // iterations of the restart passes of one run
 };
 
+// Helmholtz filter solve (Jacobi-preconditioned CG on one scalar field)
+struct HelmState {
+  double rz, rz_old, pq, alpha, beta, rr, bb, tol2;
+  int done, iters, breakdown, pad;
+};
+
+// Constant cell matrices of the Helmholtz operator r^2 K + M: one cube
+// (A[0], corners c = cx + 2 cy + 4 cz), or the two square splits (A[0]
+// diagonal A, A[1] diagonal B, corners c = cx + 2 cy); bit t of
+// cells_of_corner[s][c] is set when cell t of the cube (square, split s)
+// has corner c as a vertex; w_rhs = |T| / (d+1).
+struct HelmCoef {
+  double A[2][8][8];
+  double w_rhs;
+  uint8_t cells_of_corner[2][8];
+};
+
 struct OcState {
   double target;
   double mu, mu_lo, mu_hi;
@@ -71,6 +88,7 @@ struct DevScalars {
   PcgState pcg;
   IrState ir;
   OcState oc;
+  HelmState helm;
   double compliance;
   double c_energy;
   double c_paper;
@@ -157,7 +175,7 @@ struct GmgLevel {
 
 struct WsLayout {
   size_t mask, f, E, E32, E16, invd, invd32, r, p, q, z, wv, partials, scal, R, taps, ttaps,
-      qsoa, dc, dcf, rho_new, rho_tmp, passive, r32, p32, q32, z32, z32b, x32, gmg_scal, pring, qring, total;
+      qsoa, dc, dcf, rho_new, rho_tmp, passive, helm, r32, p32, q32, z32, z32b, x32, gmg_scal, pring, qring, total;
   std::vector<GmgLevel> levels;   // offsets only (pointers filled at creation)
 };
 
@@ -208,6 +226,8 @@ struct Ctx {
   double* qsoa;       // [nc] filter input in class-major order
   double *dc, *dcf, *rho_new, *rho_tmp;  // [nc]
   uint8_t* passive;   // [nc] TOPO_PASSIVE_* per cell
+  double *hx, *hr, *hp, *hq, *hinvd;   // Helmholtz filter: [nn] each (else null)
+  HelmCoef hcoef;
   bool has_passive;   // a passive set is installed (else the OC ignores the array)
   // mixed-precision inner solve buffers [nrhs][dim][nn]
   float *r32, *p32, *q32, *z32, *z32b, *x32;
@@ -273,6 +293,9 @@ int pcg_harvest(Ctx* c, const double* rho, const int* iters, int n, double* r_ou
 void launch_sensitivity(Ctx* c, const double* rho, const double* u, double* dc, double* compliance);
 void launch_filter(Ctx* c, const double* rho, const double* dc, double* dcf);
 void launch_filter_rowsums(Ctx* c);
+void build_helm_coef(Ctx* c);
+void launch_helm_diag(Ctx* c);
+void launch_filter_helmholtz(Ctx* c, const double* rho, const double* dc, double* dcf);
 void build_filter_taps(Ctx* c);
 int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& tab, int* ntaps);
 void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars);

@@ -76,6 +76,7 @@ class Problem:
     rtol: float = 1e-10
     n_iter: int = 50
     passive: object = None   # None, or uint8 [N_c]: 0 free, 1 void, 2 solid
+    filter: int = 0          # 0: distance-weighted filter, 1: Helmholtz PDE filter
 
     @property
     def nrhs(self) -> int:

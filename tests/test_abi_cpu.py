@@ -98,3 +98,31 @@ def test_batch_workspace_and_validation():
     bad = (b.CProblem * 1)(b.make_problem(2, (8, 4), precond=b.TOPO_PC_JACOBI))
     assert lib.topo_batch_workspace_size(bad, 1, ctypes.byref(n)) == -1
     assert lib.topo_batch_workspace_size(arr, 0, ctypes.byref(n)) == -1
+
+
+def test_filter_selector_and_new_modes_validate():
+    """The filter selector sits at the end of topo_problem (the ctypes mirror
+    must match the header's field order); the Helmholtz filter adds five
+    nodal FP64 vectors to the workspace; unknown filters and precisions are
+    rejected; the batch keeps the distance filter only."""
+    b = _lib()
+    lib = b.load_library()
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct topo_problem \{(.*?)\} topo_problem;", txt, re.S).group(1)
+    names = re.findall(r"\b([A-Za-z_][A-Za-z_0-9]*)(?:\[\d\])?\s*[,;]", body)
+    assert names == [f[0] for f in b.CProblem._fields_]
+    n0, n1 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    p = b.make_problem(3, (24, 12, 12), nrhs=1)
+    assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n0)) == 0
+    p = b.make_problem(3, (24, 12, 12), nrhs=1, filter=b.TOPO_FILTER_HELMHOLTZ)
+    assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n1)) == 0
+    assert n1.value >= n0.value + 5 * 25 * 13 * 13 * 8
+    bad = b.make_problem(2, (8, 4), filter=2)
+    assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n0)) == -1
+    bad = b.make_problem(2, (8, 4), precision=4)
+    assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n0)) == -1
+    ok = b.make_problem(2, (8, 4), precision=b.TOPO_MIXED_BF16, precond=b.TOPO_PC_GMG)
+    assert lib.topo_workspace_size(ctypes.byref(ok), ctypes.byref(n0)) == 0
+    bad = (b.CProblem * 1)(b.make_problem(2, (8, 4), precond=b.TOPO_PC_GMG,
+                                          filter=b.TOPO_FILTER_HELMHOLTZ))
+    assert lib.topo_batch_workspace_size(bad, 1, ctypes.byref(n0)) == -1

@@ -141,3 +141,24 @@ def test_cosine_mode_response():
         sel = np.abs(psi) > 0.5
         ratio = F[sel] / psi[sel]
         np.testing.assert_allclose(ratio, want, rtol=1e-2)
+
+
+def test_loop_with_helmholtz_filter_symmetry_and_volume():
+    """The 60 x 30 cantilever loop with the PDE filter: the design stays
+    mirror-symmetric (mesh, loads and filter are), the volume is held, and
+    the compliance falls."""
+    import dataclasses
+    import synth
+    from oracle import simp
+    p = dataclasses.replace(synth.cantilever2d(60, 30), filter=1)
+    S = simp.setup(p)
+    c = M.centroids(S.mesh)
+    key = {tuple(np.round(x * 3).astype(int)): i for i, x in enumerate(c)}
+    mir = c.copy()
+    mir[:, 1] = 30 - mir[:, 1]
+    perm = np.array([key[tuple(np.round(x * 3).astype(int))] for x in mir])
+    rho, log = simp.iterate(S, 12)
+    np.testing.assert_allclose(rho, rho[perm], atol=1e-8)
+    for rec in log:
+        assert abs(rec["vol"] - 0.5) <= 1e-12
+    assert log[-1]["c"] < 0.6 * log[0]["c"]
