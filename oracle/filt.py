@@ -70,3 +70,20 @@ def apply_rows(cent: np.ndarray, rmin: float, rho, s, rows: np.ndarray, tree=Non
         Rout[q] = w.sum()
         out[q] = np.dot(w, rho[nb] * s[nb]) / (rho[a] * Rout[q])
     return out, Rout
+
+
+# ---------------------------------------------------------------------------
+# Density-filter mode (not in the paper, whose filter acts on sensitivities):
+# the physics sees the filtered design x~ = W x / R.  By the chain rule the
+# design gradient of a function f(x~) is W^T (df/dx~ / R), and W is
+# symmetric; the volume sum x~ has gradient W^T (1 / R).
+
+
+def density(W, R, x):
+    """x~ = W x / R."""
+    return (W @ np.asarray(x, dtype=np.float64)) / R
+
+
+def density_grad(W, R, g):
+    """Design gradient W^T (g / R) of a function with gradient g in x~."""
+    return W.T @ (np.asarray(g, dtype=np.float64) / R)

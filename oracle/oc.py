@@ -31,10 +31,11 @@ import numpy as np
 VOID, SOLID = 1, 2
 
 
-def _design(rho, neg_s, lam, move, eta, rho_min, passive=None):
+def _design(rho, neg_s, lam, move, eta, rho_min, passive=None, dv=None):
     lo = np.maximum(rho_min, rho - move)
     hi = np.minimum(1.0, rho + move)
-    out = np.maximum(lo, np.minimum(hi, rho * (neg_s / lam) ** eta))
+    B = neg_s / lam if dv is None else neg_s / (dv * lam)
+    out = np.maximum(lo, np.minimum(hi, rho * B ** eta))
     if passive is not None:
         out[passive == VOID] = rho_min
         out[passive == SOLID] = 1.0
@@ -42,16 +43,22 @@ def _design(rho, neg_s, lam, move, eta, rho_min, passive=None):
 
 
 def update(rho, s_filtered, volfrac, move=0.2, eta=0.5, rho_min=1e-3,
-           l1=0.0, l2=1e5, max_expand=60, passive=None):
+           l1=0.0, l2=1e5, max_expand=60, passive=None, dv=None, phys=None):
     """Returns (rho_new, lam, volume_sum, change, n_passes).  ``passive`` is
-    None or one code per cell: 0 free, 1 void, 2 solid."""
+    None or one code per cell: 0 free, 1 void, 2 solid.
+
+    Density-filter mode: ``dv`` is the volume gradient of the design (the
+    ratio becomes -s / (lambda dv)) and ``phys`` maps a design to the
+    filtered field whose sum is the volume compared with the target, as the
+    filtered design is evaluated at every bisection step."""
+    vol_of = (lambda x: x.sum()) if phys is None else (lambda x: phys(x).sum())
     rho = np.asarray(rho, dtype=np.float64)
     neg_s = np.maximum(0.0, -np.asarray(s_filtered, dtype=np.float64))
     target = volfrac * rho.size
     passes = 0
     for _ in range(max_expand):
         passes += 1
-        if _design(rho, neg_s, l2, move, eta, rho_min, passive).sum() - target > 0:
+        if vol_of(_design(rho, neg_s, l2, move, eta, rho_min, passive, dv)) - target > 0:
             l1, l2 = l2, l2 * 10.0
         else:
             break
@@ -63,12 +70,12 @@ def update(rho, s_filtered, volfrac, move=0.2, eta=0.5, rho_min=1e-3,
             break
         passes += 1
         lam = mid
-        rho_new = _design(rho, neg_s, mid, move, eta, rho_min, passive)
-        if rho_new.sum() - target > 0:
+        rho_new = _design(rho, neg_s, mid, move, eta, rho_min, passive, dv)
+        if vol_of(rho_new) - target > 0:
             l1 = mid
         else:
             l2 = mid
-    vol = float(rho_new.sum())
+    vol = float(vol_of(rho_new))
     change = float(np.max(np.abs(rho_new - rho)))
     return rho_new, lam, vol, change, passes
 

@@ -7,7 +7,9 @@ optimality criteria with bisection, and (5) records the change
 max |rho_new - rho|.  Multiple load cases (Section 5.3) are solved one by
 one; compliances and sensitivities are summed over the cases.  Step (3)
 uses the distance-weighted filter, or the Helmholtz PDE filter
-(oracle/helm.py) when the problem's ``filter`` is 1.
+(oracle/helm.py) when the problem's ``filter`` is 1.  With ``filter`` 2
+(density filter) the physics of steps (1)-(2) sees x~ = W x / R, step (3)
+is the chain rule back to the design x, and the OC volume is that of x~.
 
 The logged objective is the compliance c = sum_r f_r^T u_r; ``c_paper`` is
 sum_e E_e w_e / (2|T_e|), the sum of rho^p psi_e that the listing prints
@@ -84,13 +86,17 @@ def iterate(S: Setup, n_iter: int, rho0=None, change_tol: float = 0.0) -> tuple:
     rho = np.full(S.mesh.n_cells, p.volfrac) if rho0 is None else np.array(rho0, dtype=np.float64)
     log: List[dict] = []
     vol_cell, _ = mesh_mod.geometry(S.mesh)
+    dens = getattr(p, "filter", 0) == 2
+    dv = filt.density_grad(S.W, S.R, np.ones(S.mesh.n_cells)) if dens else None
+    phys = (lambda x: filt.density(S.W, S.R, x)) if dens else None
     for it in range(n_iter):
-        u, c, w, s, E = solve_state(S, rho)
+        u, c, w, s, E = solve_state(S, phys(rho) if dens else rho)
         c_paper = float(np.sum(E * w / (2.0 * vol_cell)))
-        sf = filter_sensitivity(S, rho, s)
+        sf = filt.density_grad(S.W, S.R, s) if dens else filter_sensitivity(S, rho, s)
         rho_new, lam, vol, change, passes = oc.update(rho, sf, p.volfrac, p.move, p.eta,
                                                       p.rho_min,
-                                                      passive=getattr(p, "passive", None))
+                                                      passive=getattr(p, "passive", None),
+                                                      dv=dv, phys=phys)
         log.append(dict(it=it + 1, c=c, c_paper=c_paper, vol=vol / rho.size, change=change,
                         lam=lam, passes=passes))
         rho = rho_new
