@@ -565,8 +565,9 @@ def main():
     ap.add_argument("--workload", default="cantilever3d")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed-ir", "mixed-bf16"])
     ap.add_argument("--precond", default="gmg", choices=["jacobi", "gmg"])
-    ap.add_argument("--filter", default="distance", choices=["distance", "helmholtz"],
-                    help="sensitivity filter: distance-weighted (Sec. 3.2.2) or Helmholtz PDE (Sec. 6.3)")
+    ap.add_argument("--filter", default="distance", choices=["distance", "helmholtz", "density"],
+                    help="filter: distance-weighted sensitivity filter (Sec. 3.2.2), Helmholtz PDE "
+                         "sensitivity filter (Sec. 6.3), or a density filter on the distance weights")
     ap.add_argument("--maxit", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--train-steps", type=int, default=3000,
@@ -595,8 +596,8 @@ def main():
                                       TOPO_MIXED_IR, TOPO_PC_GMG, TOPO_PC_JACOBI, Topo)
 
     p = workload(args.workload)
-    if args.filter == "helmholtz":
-        p = dataclasses.replace(p, filter=1)
+    if args.filter != "distance":
+        p = dataclasses.replace(p, filter={"helmholtz": 1, "density": 2}[args.filter])
     dev = torch.device("cuda:0")
     prec = {"fp64": TOPO_FP64, "mixed": TOPO_MIXED_FP32, "mixed-ir": TOPO_MIXED_IR,
             "mixed-bf16": TOPO_MIXED_BF16}[args.precision]

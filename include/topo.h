@@ -135,8 +135,19 @@ enum { TOPO_PC_JACOBI = 0, TOPO_PC_GMG = 1, TOPO_PC_LEARNED = 2 };
                           relative residual of 1e-12 (the call synchronises
                           with the stream between batches of iterations, as
                           topo_solve does); a solve that stops at its cap of
-                          4000 iterations sets TOPO_S_NOT_CONVERGED. */
-enum { TOPO_FILTER_DISTANCE = 0, TOPO_FILTER_HELMHOLTZ = 1 };
+                          4000 iterations sets TOPO_S_NOT_CONVERGED.
+   TOPO_FILTER_DENSITY:   a density filter on the same weights (not in the
+                          paper, whose filter acts on sensitivities): the
+                          physics sees x~ = W x / R (R_a = sum_b W_ab) and
+                          the design is x.  topo_iterate filters x before the
+                          solve and the sensitivity; topo_filter then returns
+                          the design gradient by the chain rule,
+                          dcf = W (dc / R) (W is symmetric), from dc = dc/dx~;
+                          topo_oc_update uses the volume of the filtered
+                          design, sum x~ = sum_e dv_e x_e with dv = W (1 / R),
+                          and the ratio -dc_e / (lambda dv_e).  topo_solve and
+                          topo_sensitivity take x~ (topo_density_filter). */
+enum { TOPO_FILTER_DISTANCE = 0, TOPO_FILTER_HELMHOLTZ = 1, TOPO_FILTER_DENSITY = 2 };
 
 /* Problem description (host struct, copied by topo_create). */
 typedef struct topo_problem {
@@ -157,7 +168,7 @@ typedef struct topo_problem {
                          1: the listing's law, see above */
   int32_t warm_start; /* 1: topo_solve starts from the u it is given */
   int32_t gmg_levels; /* 0 = automatic; otherwise the number of levels */
-  int32_t filter;     /* TOPO_FILTER_DISTANCE (0) | TOPO_FILTER_HELMHOLTZ */
+  int32_t filter;     /* TOPO_FILTER_DISTANCE (0) | TOPO_FILTER_HELMHOLTZ | TOPO_FILTER_DENSITY */
 } topo_problem;
 
 /* Length of the per-solve info record written by topo_solve (doubles):
@@ -245,6 +256,10 @@ int topo_apply_f32(topo_ctx* ctx, const double* rho, const float* x, float* y);
 /* Jacobi diagonal d = diag(K(rho)) on free DOFs and 1 on fixed DOFs,
    d [dim][N_n]. */
 int topo_diagonal(topo_ctx* ctx, const double* rho, double* d);
+
+/* Density filter x~ = W x / R with the distance weights of Sec. 3.2.2
+   (x, x_phys [N_c], distinct); available in every filter mode. */
+int topo_density_filter(topo_ctx* ctx, const double* x, double* x_phys);
 
 /* Filter row sums R [N_c] computed at creation. */
 int topo_filter_rowsums(topo_ctx* ctx, double* R);

@@ -28,6 +28,7 @@ TOPO_PASSIVE_VOID = 1
 TOPO_PASSIVE_SOLID = 2
 TOPO_FILTER_DISTANCE = 0
 TOPO_FILTER_HELMHOLTZ = 1
+TOPO_FILTER_DENSITY = 2
 TOPO_PC_JACOBI = 0
 TOPO_PC_GMG = 1
 TOPO_PC_LEARNED = 2
@@ -38,7 +39,7 @@ LOG_LEN = 8
 EXPORTED = [
     "topo_workspace_size", "topo_create", "topo_destroy", "topo_set_loads", "topo_solve",
     "topo_sensitivity", "topo_filter", "topo_oc_update", "topo_iterate", "topo_apply",
-    "topo_apply_f32", "topo_set_passive", "topo_diagonal", "topo_filter_rowsums", "topo_timing_enable", "topo_timing_read",
+    "topo_apply_f32", "topo_set_passive", "topo_density_filter", "topo_diagonal", "topo_filter_rowsums", "topo_timing_enable", "topo_timing_read",
     "topo_sync", "topo_status_string",
     "topo_precond_num_params", "topo_precond_workspace_size", "topo_precond_attach",
     "topo_precond_set_weights", "topo_precond_get_weights", "topo_precond_config",
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_diagonal.argtypes = [vp, vp, vp]
     lib.topo_filter_rowsums.argtypes = [vp, vp]
     lib.topo_set_passive.argtypes = [vp, vp]
+    lib.topo_density_filter.argtypes = [vp, vp, vp]
     lib.topo_timing_enable.argtypes = [vp, i32]
     lib.topo_timing_read.argtypes = [vp, P(ctypes.c_int64), P(dbl)]
     lib.topo_timing_read_net.argtypes = [vp, P(ctypes.c_int64), P(dbl)]
@@ -302,6 +304,12 @@ class Topo:
         self._passive = a
         _check(self.lib.topo_set_passive(self.ctx, a.ctypes.data_as(ctypes.c_void_p)),
                "topo_set_passive")
+
+    def density_filter(self, x, x_phys):
+        """x~ = W x / R (distance weights)."""
+        _check(self.lib.topo_density_filter(self.ctx, self._ptr(x, self.n_cells, "x"),
+                                            self._ptr(x_phys, self.n_cells, "x_phys")),
+               "topo_density_filter")
 
     def diagonal(self, rho, d):
         _check(self.lib.topo_diagonal(self.ctx, self._ptr(rho, self.n_cells, "rho"),

@@ -38,7 +38,9 @@ static bool valid_problem(const topo_problem* p) {
   if (p->precond == TOPO_PC_LEARNED && (p->dim != 3 || p->precision != TOPO_FP64)) return false;
   if (p->dim == 2 && p->split2d != TOPO_SPLIT_ALT_ROWS && p->split2d != TOPO_SPLIT_UNIFORM)
     return false;
-  if (p->filter != TOPO_FILTER_DISTANCE && p->filter != TOPO_FILTER_HELMHOLTZ) return false;
+  if (p->filter != TOPO_FILTER_DISTANCE && p->filter != TOPO_FILTER_HELMHOLTZ &&
+      p->filter != TOPO_FILTER_DENSITY)
+    return false;
   return true;
 }
 
@@ -174,6 +176,8 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.rho_tmp = take((size_t)g.nc * 8);
   L.passive = take((size_t)g.nc);
   L.helm = p->filter == TOPO_FILTER_HELMHOLTZ ? take((size_t)5 * g.nn * 8) : 0;
+  L.rho_phys = p->filter == TOPO_FILTER_DENSITY ? take((size_t)g.nc * 8) : 0;
+  L.dv = p->filter == TOPO_FILTER_DENSITY ? take((size_t)g.nc * 8) : 0;
   L.r32 = L.p32 = L.q32 = L.z32 = L.z32b = L.x32 = 0;
   if (mixed) {
     L.r32 = take(nr * g.nd * 4);
@@ -353,6 +357,8 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->passive = (uint8_t*)(w + L.passive);
   c->has_passive = false;
   c->hx = c->hr = c->hp = c->hq = c->hinvd = nullptr;
+  c->rho_phys = L.rho_phys ? (double*)(w + L.rho_phys) : nullptr;
+  c->dv = L.dv ? (double*)(w + L.dv) : nullptr;
   if (L.helm) {
     double* hb = (double*)(w + L.helm);
     c->hx = hb;
@@ -468,6 +474,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
       build_helm_coef(c);
       launch_helm_diag(c);
     }
+    if (c->dv) launch_density_volume_weights(c, c->dv);
     ok = hipStreamSynchronize(c->stream) == hipSuccess && hipGetLastError() == hipSuccess;
   }
   if (!ok) {
@@ -557,11 +564,18 @@ int topo_iterate(topo_ctx* c, double* rho, double* u, int max_iter, double chang
   if (!c || !rho || !u || max_iter < 0) return TOPO_E_INVALID;
   if (!c->loads_set) return TOPO_E_STATE;
   int done = 0;
+  const bool dens = c->prob.filter == TOPO_FILTER_DENSITY;
   for (int it = 0; it < max_iter; ++it) {
     const bool warm = it > 0 || c->prob.warm_start != 0;
-    int rc = solve_impl(c, rho, u, nullptr, warm);
+    // density filter: the physics sees x~ = W x / R, the design is x
+    const double* phys = rho;
+    if (dens) {
+      launch_density_filter(c, rho, c->rho_phys);
+      phys = c->rho_phys;
+    }
+    int rc = solve_impl(c, phys, u, nullptr, warm);
     if (rc != TOPO_OK) return rc;
-    launch_sensitivity(c, rho, u, c->dc, nullptr);
+    launch_sensitivity(c, phys, u, c->dc, nullptr);
     launch_filter(c, rho, c->dc, c->dcf);
     oc_update(c, rho, c->dcf, c->rho_new, nullptr);
     if (log) {
@@ -611,6 +625,12 @@ int topo_diagonal(topo_ctx* c, const double* rho, double* d) {
   if (!c || !rho || !d) return TOPO_E_INVALID;
   launch_simp_modulus(c, rho);
   launch_diagonal(c, d, false);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}
+
+int topo_density_filter(topo_ctx* c, const double* x, double* x_phys) {
+  if (!c || !x || !x_phys || x == x_phys) return TOPO_E_INVALID;
+  launch_density_filter(c, x, x_phys);
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
 

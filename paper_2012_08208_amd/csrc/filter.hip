@@ -125,13 +125,29 @@ void build_filter_taps(Ctx* c) {
   }
 }
 
-// out[e] = sum_taps w q / (rho_e R_e) (rowsum: the plain sum with q = 1)
+// Filter modes (what is summed over the taps, and the divisor):
+//   FM_SENS      q = rho dc, out = sum / (rho_e R_e)   sensitivity filter
+//   FM_ROWSUM    q = 1,      out = sum                  row sums R
+//   FM_DENSITY   q = dc,     out = sum / R_e            density filter x~ = W x / R
+//   FM_TRANSPOSE q = dc / R (1 / R when dc is null), out = sum
+//                                                      its adjoint W (g / R) (W is symmetric)
+enum FilterMode { FM_SENS = 0, FM_ROWSUM = 1, FM_DENSITY = 2, FM_TRANSPOSE = 3 };
+
+__device__ __forceinline__ double filter_input(int mode, long e, const double* rho, const double* dc,
+                                               const double* R) {
+  if (mode == FM_SENS) return rho[e] * dc[e];
+  if (mode == FM_ROWSUM) return 1.0;
+  if (mode == FM_DENSITY) return dc[e];
+  return (dc ? dc[e] : 1.0) / R[e];
+}
+
+// out[e] = sum_taps w q, divided as the mode says
 __global__ __launch_bounds__(256) void filter3d_tiled_kernel(double* out, const double* __restrict__ rho,
                                                              const double* __restrict__ dc,
                                                              const double* __restrict__ R,
                                                              const TiledTap* __restrict__ tt,
                                                              const int* __restrict__ ntaps, int nx,
-                                                             int ny, int nz, int rowsum) {
+                                                             int ny, int nz, int mode) {
   __shared__ double q[kFtV * 6];
   const int tid = threadIdx.x;
   const int gx = (nx + kFtX - 1) / kFtX, gy = (ny + kFtY - 1) / kFtY;
@@ -144,7 +160,7 @@ __global__ __launch_bounds__(256) void filter3d_tiled_kernel(double* out, const 
     double val = 0.0;
     if (gi >= 0 && gi < nx && gj >= 0 && gj < ny && gk >= 0 && gk < nz) {
       const long e = (((long)gk * ny + gj) * nx + gi) * 6 + t;
-      val = rowsum ? 1.0 : rho[e] * dc[e];
+      val = filter_input(mode, e, rho, dc, R);
     }
     q[idx] = val;
   }
@@ -165,19 +181,19 @@ __global__ __launch_bounds__(256) void filter3d_tiled_kernel(double* out, const 
     for (int s = 0; s < nt; ++s) acc += tp[s].w * q[base + tp[s].off];
     if (in) {
       const long e = h * 6 + t;
-      out[e] = rowsum ? acc : acc / (rho[e] * R[e]);
+      out[e] = mode == FM_SENS ? acc / (rho[e] * R[e]) : mode == FM_DENSITY ? acc / R[e] : acc;
     }
   }
 }
 
-// q[t][h] = rho[e] * dc[e] (class-major); with rho == nullptr, q = 1.
-__global__ void filter_gather_kernel(double* q, const double* rho, const double* dc, long ncell,
-                                     int ncls, long nblk) {
+// q[t][h] = the mode's filter input of cell e (class-major)
+__global__ void filter_gather_kernel(double* q, const double* rho, const double* dc,
+                                     const double* R, int mode, long ncell, int ncls, long nblk) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ncell) return;
   const long h = e / ncls;
   const int t = (int)(e % ncls);
-  q[(long)t * nblk + h] = rho ? rho[e] * dc[e] : 1.0;
+  q[(long)t * nblk + h] = filter_input(mode, e, rho, dc, R);
 }
 
 // one thread per (block-cell h, class t = blockIdx.y)
@@ -186,21 +202,21 @@ __global__ __launch_bounds__(256) void filter_kernel(double* out, const double* 
                                                      const double* __restrict__ R,
                                                      const FilterTap* __restrict__ taps,
                                                      const int* __restrict__ ntaps, int dim, int nx,
-                                                     int ny, int nz, int ncls, int alt, int rowsum) {
+                                                     int ny, int nz, int ncls, int alt, int out_mode) {
   const long nblk = (long)nx * ny * nz;
   const long h = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= nblk) return;
-  filter_cell(h, blockIdx.y, out, q, rho, R, taps, ntaps, dim, nx, ny, nz, ncls, alt, rowsum);
+  filter_cell(h, blockIdx.y, out, q, rho, R, taps, ntaps, dim, nx, ny, nz, ncls, alt, out_mode);
 }
 
-static void filter_launch(Ctx* c, const double* rho, const double* dc, double* out, bool rowsum) {
+static void filter_launch(Ctx* c, const double* rho, const double* dc, double* out, int mode) {
   const Grid& g = c->g;
   if (g.dim == 3 && c->filter_tiled) {
     const long tiles = (long)((g.nx + kFtX - 1) / kFtX) * ((g.ny + kFtY - 1) / kFtY) *
                        ((g.nz + kFtZ - 1) / kFtZ);
     filter3d_tiled_kernel<<<(unsigned)tiles, 256, 0, c->stream>>>(
         out, rho, dc, c->R, c->ttaps, (const int*)(c->taps + (size_t)8 * kMaxFilterTaps), g.nx, g.ny,
-        g.nz, rowsum ? 1 : 0);
+        g.nz, mode);
     return;
   }
   const int ncls = g.dim == 2 ? 2 : 6;
@@ -208,22 +224,37 @@ static void filter_launch(Ctx* c, const double* rho, const double* dc, double* o
   const long nblk = (long)g.nx * g.ny * nz;
   const long ncell = nblk * ncls;
   filter_gather_kernel<<<(unsigned)((ncell + 255) / 256), 256, 0, c->stream>>>(
-      c->qsoa, rowsum ? nullptr : rho, dc, ncell, ncls, nblk);
+      c->qsoa, rho, dc, c->R, mode, ncell, ncls, nblk);
   dim3 grid((unsigned)((nblk + 255) / 256), ncls);
   filter_kernel<<<grid, 256, 0, c->stream>>>(out, c->qsoa, rho, c->R, c->taps,
                                              (const int*)(c->taps + (size_t)8 * kMaxFilterTaps),
                                              g.dim, g.nx, g.ny, nz, ncls,
-                                             g.split == TOPO_SPLIT_ALT_ROWS, rowsum ? 1 : 0);
+                                             g.split == TOPO_SPLIT_ALT_ROWS,
+                                             mode == FM_SENS ? 0 : mode == FM_DENSITY ? 2 : 1);
 }
 
-void launch_filter_rowsums(Ctx* c) { filter_launch(c, nullptr, nullptr, c->R, true); }
+void launch_filter_rowsums(Ctx* c) { filter_launch(c, nullptr, nullptr, c->R, FM_ROWSUM); }
+
+void launch_density_filter(Ctx* c, const double* x, double* out) {
+  filter_launch(c, nullptr, x, out, FM_DENSITY);
+}
+
+// volume sensitivity of the density filter: dv = W (1 / R)
+void launch_density_volume_weights(Ctx* c, double* dv) {
+  filter_launch(c, nullptr, nullptr, dv, FM_TRANSPOSE);
+}
 
 void launch_filter(Ctx* c, const double* rho, const double* dc, double* dcf) {
   if (c->prob.filter == TOPO_FILTER_HELMHOLTZ) {
     launch_filter_helmholtz(c, rho, dc, dcf);
     return;
   }
-  filter_launch(c, rho, dc, dcf, false);
+  if (c->prob.filter == TOPO_FILTER_DENSITY) {
+    // chain rule through x~ = W x / R: dc/dx = W (dc/dx~ / R)
+    filter_launch(c, nullptr, dc, dcf, FM_TRANSPOSE);
+    return;
+  }
+  filter_launch(c, rho, dc, dcf, FM_SENS);
 }
 
 }  // namespace topo

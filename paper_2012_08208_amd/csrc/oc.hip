@@ -17,6 +17,13 @@
 // fixed value (rho_min for a void, 1 for solid material) in every
 // evaluation, so the volume at each multiplier counts them; they contribute
 // nothing to the slope, the first multiplier or the bracket.
+//
+// With the density filter (x~ = W x / R) the volume is that of the filtered
+// design, sum_e x~_e = sum_e dv_e x_e with dv = W (1 / R) (the filter is
+// linear), and the OC ratio uses the volume sensitivity:
+// rho_new_e = clamp(rho_e (-dc_e / (lambda dv_e))^eta, lo_e, hi_e).  The
+// kernels take dv as per-cell volume weights (null: all ones), so each
+// evaluation is the same single pass.
 #include <math.h>
 
 #include "common.h"
@@ -43,6 +50,7 @@ __global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__
                                                       long nc, double move, double eta,
                                                       double rho_min,
                                                       const uint8_t* __restrict__ passive,
+                                                      const double* __restrict__ vw,
                                                       double* partials) {
   double acc[3] = {0.0, 0.0, 0.0};
   double mx[1] = {0.0};
@@ -50,11 +58,12 @@ __global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__
     const double r = rho[e];
     double lo, hi;
     oc_bounds(e, r, move, rho_min, passive, lo, hi);
-    const double a = (passive && passive[e]) ? 0.0 : oc_a(r, dcf[e], eta);
+    const double w = vw ? vw[e] : 1.0;
+    const double a = (passive && passive[e]) ? 0.0 : oc_a(r, vw ? dcf[e] / w : dcf[e], eta);
     a_out[e] = a;
-    acc[0] += lo;
-    acc[1] += (a > 0.0) ? hi : lo;  // volume once mu is large
-    acc[2] += a;
+    acc[0] += w * lo;
+    acc[1] += w * ((a > 0.0) ? hi : lo);  // volume once mu is large
+    acc[2] += w * a;
     if (a > 0.0) mx[0] = fmax(mx[0], hi / a);
   }
   block_partials<3, 1>(acc, mx, partials);
@@ -71,6 +80,7 @@ __global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__
                                                       const double* __restrict__ a_in, long nc,
                                                       double move, double rho_min,
                                                       const uint8_t* __restrict__ passive,
+                                                      const double* __restrict__ vw,
                                                       double* partials, const OcState* st) {
   if (st->done) return;
   const double mu = st->mu;
@@ -80,9 +90,10 @@ __global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__
     const double a = a_in[e];
     double lo, hi;
     oc_bounds(e, r, move, rho_min, passive, lo, hi);
+    const double w = vw ? vw[e] : 1.0;
     const double v = a * mu;
-    acc[0] += fmax(lo, fmin(hi, v));
-    acc[1] += (v > lo && v < hi) ? a : 0.0;
+    acc[0] += w * fmax(lo, fmin(hi, v));
+    acc[1] += (v > lo && v < hi) ? w * a : 0.0;
   }
   const double none[1] = {0.0};
   block_partials<2, 0>(acc, none, partials);
@@ -100,6 +111,7 @@ __global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict_
                                                        double* rho_new, long nc, double move,
                                                        double rho_min,
                                                        const uint8_t* __restrict__ passive,
+                                                       const double* __restrict__ vw,
                                                        double* partials, const OcState* st) {
   const double mu = st->mu;
   double acc[1] = {0.0};
@@ -110,7 +122,7 @@ __global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict_
     oc_bounds(e, r, move, rho_min, passive, lo, hi);
     const double v = fmax(lo, fmin(hi, a_in[e] * mu));
     rho_new[e] = v;
-    acc[0] += v;
+    acc[0] += (vw ? vw[e] : 1.0) * v;
     mx[0] = fmax(mx[0], fabs(v - r));
   }
   block_partials<1, 1>(acc, mx, partials);
@@ -130,20 +142,21 @@ void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, do
   OcState* st = &c->scal->oc;
   double* a = c->qsoa;
   const uint8_t* pas = c->has_passive ? c->passive : nullptr;
+  const double* vw = p.filter == TOPO_FILTER_DENSITY ? c->dv : nullptr;
   hipStream_t s = c->stream;
-  oc_init_kernel<<<nb, 256, 0, s>>>(rho, dcf, a, nc, p.move, p.eta, p.rho_min, pas, c->partials);
+  oc_init_kernel<<<nb, 256, 0, s>>>(rho, dcf, a, nc, p.move, p.eta, p.rho_min, pas, vw, c->partials);
   oc_init_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, p.volfrac, st, &c->scal->status);
   const int batch = 6;
   for (int b = 0; b < 40; ++b) {
     for (int k = 0; k < batch; ++k) {
-      oc_pass_kernel<<<nb, 256, 0, s>>>(rho, a, nc, p.move, p.rho_min, pas, c->partials, st);
+      oc_pass_kernel<<<nb, 256, 0, s>>>(rho, a, nc, p.move, p.rho_min, pas, vw, c->partials, st);
       oc_pass_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, st);
     }
     (void)hipMemcpyAsync((void*)&c->pinned[2], &st->done, sizeof(int), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
     if (c->pinned[2]) break;
   }
-  oc_final_kernel<<<nb, 256, 0, s>>>(rho, a, rho_new, nc, p.move, p.rho_min, pas, c->partials, st);
+  oc_final_kernel<<<nb, 256, 0, s>>>(rho, a, rho_new, nc, p.move, p.rho_min, pas, vw, c->partials, st);
   oc_final_fin<<<1, 256, 0, s>>>(c->partials, nb, p.eta, st, scalars);
 }
 

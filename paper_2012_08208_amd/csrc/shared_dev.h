@@ -563,7 +563,7 @@ __device__ inline void sens2d_square(long s, const double* __restrict__ rho, con
 __device__ inline void filter_cell(long h, int t, double* out, const double* __restrict__ q,
                                    const double* __restrict__ rho, const double* __restrict__ R,
                                    const FilterTap* __restrict__ taps, const int* __restrict__ ntaps,
-                                   int dim, int nx, int ny, int nz, int ncls, int alt, int rowsum) {
+                                   int dim, int nx, int ny, int nz, int ncls, int alt, int out_mode) {
   const long nblk = (long)nx * ny * nz;
   const int i = (int)(h % nx);
   const int j = (int)((h / nx) % ny);
@@ -580,7 +580,10 @@ __device__ inline void filter_cell(long h, int t, double* out, const double* __r
     acc += tap.w * q[(long)tap.tb * nblk + hb];
   }
   const long e = h * ncls + t;
-  if (rowsum) out[e] = acc;
+  // out_mode 0: sensitivity filter, divide by rho_e R_e; 1: the plain sum;
+  // 2: divide by R_e (density filter)
+  if (out_mode == 1) out[e] = acc;
+  else if (out_mode == 2) out[e] = acc / R[e];
   else out[e] = acc / (rho[e] * R[e]);
 }
 

@@ -175,7 +175,7 @@ struct GmgLevel {
 
 struct WsLayout {
   size_t mask, f, E, E32, E16, invd, invd32, r, p, q, z, wv, partials, scal, R, taps, ttaps,
-      qsoa, dc, dcf, rho_new, rho_tmp, passive, helm, r32, p32, q32, z32, z32b, x32, gmg_scal, pring, qring, total;
+      qsoa, dc, dcf, rho_new, rho_tmp, passive, helm, rho_phys, dv, r32, p32, q32, z32, z32b, x32, gmg_scal, pring, qring, total;
   std::vector<GmgLevel> levels;   // offsets only (pointers filled at creation)
 };
 
@@ -228,6 +228,7 @@ struct Ctx {
   uint8_t* passive;   // [nc] TOPO_PASSIVE_* per cell
   double *hx, *hr, *hp, *hq, *hinvd;   // Helmholtz filter: [nn] each (else null)
   HelmCoef hcoef;
+  double *rho_phys, *dv;   // density filter: x~ = W x / R and dv = W (1 / R), [nc] (else null)
   bool has_passive;   // a passive set is installed (else the OC ignores the array)
   // mixed-precision inner solve buffers [nrhs][dim][nn]
   float *r32, *p32, *q32, *z32, *z32b, *x32;
@@ -293,6 +294,8 @@ int pcg_harvest(Ctx* c, const double* rho, const int* iters, int n, double* r_ou
 void launch_sensitivity(Ctx* c, const double* rho, const double* u, double* dc, double* compliance);
 void launch_filter(Ctx* c, const double* rho, const double* dc, double* dcf);
 void launch_filter_rowsums(Ctx* c);
+void launch_density_filter(Ctx* c, const double* x, double* out);
+void launch_density_volume_weights(Ctx* c, double* dv);
 void build_helm_coef(Ctx* c);
 void launch_helm_diag(Ctx* c);
 void launch_filter_helmholtz(Ctx* c, const double* rho, const double* dc, double* dcf);

@@ -117,8 +117,14 @@ def test_filter_selector_and_new_modes_validate():
     p = b.make_problem(3, (24, 12, 12), nrhs=1, filter=b.TOPO_FILTER_HELMHOLTZ)
     assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n1)) == 0
     assert n1.value >= n0.value + 5 * 25 * 13 * 13 * 8
-    bad = b.make_problem(2, (8, 4), filter=2)
+    bad = b.make_problem(2, (8, 4), filter=3)
     assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n0)) == -1
+    p = b.make_problem(3, (24, 12, 12), nrhs=1, filter=b.TOPO_FILTER_DENSITY)
+    n2 = ctypes.c_size_t(0)
+    assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n2)) == 0
+    p = b.make_problem(3, (24, 12, 12), nrhs=1)
+    assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n0)) == 0
+    assert n2.value >= n0.value + 2 * 24 * 12 * 12 * 6 * 8   # filtered design and dv
     bad = b.make_problem(2, (8, 4), precision=4)
     assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n0)) == -1
     ok = b.make_problem(2, (8, 4), precision=b.TOPO_MIXED_BF16, precond=b.TOPO_PC_GMG)
