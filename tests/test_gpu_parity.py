@@ -299,6 +299,18 @@ def test_iterate_cantilever_60x30_50_iterations_mixed():
     _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-7)
 
 
+def test_iterate_cantilever_60x30_50_iterations_mixed_bf16():
+    # BF16 moduli in the V-cycle only precondition; the FP64 outer CG meets
+    # the same tolerance, so the mixed bar applies
+    from paper_2012_08208_amd import TOPO_MIXED_BF16, TOPO_PC_GMG
+    p = synth.cantilever2d(60, 30)
+    print("[iterate] cantilever2d 60x30 x50 mixed-bf16", flush=True)
+    S = simp.setup(p)
+    rho_ref, log_ref = simp.iterate(S, 50)
+    t = _topo(p, rtol=1e-10, precond=TOPO_PC_GMG, precision=TOPO_MIXED_BF16)
+    _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-7)
+
+
 def test_iterate_cantilever_60x30_50_iterations_mixed_ir():
     from paper_2012_08208_amd import TOPO_MIXED_IR, TOPO_PC_GMG
     p = synth.cantilever2d(60, 30)
