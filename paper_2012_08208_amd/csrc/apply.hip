@@ -105,6 +105,7 @@ struct ChebEpi {
   const T* b;
   const double* lmax;
   double r_cur, r_prev, low;
+  int kind;   // Chebyshev kind (1 or 4)
 };
 
 template <typename T, typename TE, int EPI>
@@ -133,11 +134,7 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     T* yr = y + (long)rhs * 3 * nn;
     const T* br = EPI == 2 ? ce.b + (long)rhs * 3 * nn : nullptr;
     T it0 = 0;
-    if (EPI == 2) {
-      double theta, delta;
-      cheb_interval(*ce.lmax, ce.low, theta, delta);
-      it0 = T(1.0 / theta);
-    }
+    if (EPI == 2) it0 = T(cheb_first_scale(*ce.lmax, ce.low, ce.kind));
 
     // plane staging: thread handles patch nodes idx = tid and tid + 256
     long poff[2];
@@ -209,10 +206,10 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     T c1 = 0, c2 = 0;
     T* ex_ = nullptr;
     if (EPI == 2) {
-      double theta, delta;
-      cheb_interval(*ce.lmax, ce.low, theta, delta);
-      c1 = T(ce.r_cur * ce.r_prev);
-      c2 = T(2.0 * ce.r_cur / delta);
+      double c1d, c2d;
+      cheb_next_coef(*ce.lmax, ce.low, ChebCoef{ce.r_cur, ce.r_prev, ce.kind, 1}, c1d, c2d);
+      c1 = T(c1d);
+      c2 = T(c2d);
       ex_ = ce.x + (long)rhs * 3 * nn;
     }
 
@@ -426,36 +423,36 @@ static void apply_dispatch(Ctx* c, const OpDesc& d, const TE* E, const T* x, T* 
 // d0 = D^-1 b / theta
 template <typename T, typename TE>
 static void cheb_pre3d(Ctx* c, const OpDesc& d, const TE* E, const T* b, T* x, const T* invd,
-                       const double* lmax, double r_cur, double r_prev, double low, int nrhs,
-                       const int* stop) {
+                       const double* lmax, double r_cur, double r_prev, double low, int kind,
+                       int nrhs, const int* stop) {
   const T lam = T(c->m.lam0 * c->m.vol), mu = T(c->m.mu0 * c->m.vol);
   const TileMap tm = make_tilemap(d, nrhs);
   const unsigned blocks = (unsigned)(8L * tm.per_xcd * nrhs);
-  ChebEpi<T> ce{x, invd, b, lmax, r_cur, r_prev, low};
+  ChebEpi<T> ce{x, invd, b, lmax, r_cur, r_prev, low, kind};
   apply3d_kernel<T, TE, 2><<<blocks, 256, 0, c->stream>>>(nullptr, nullptr, E, d, tm, lam, mu,
                                                           nullptr, stop, ce);
 }
 
 template <typename T>
 void launch_apply_cheb_pre3d(Ctx* c, const OpDesc& d, const T* E, const T* b, T* x, const T* invd,
-                             const double* lmax, double r_cur, double r_prev, double low, int nrhs,
-                             const int* stop) {
-  cheb_pre3d<T, T>(c, d, E, b, x, invd, lmax, r_cur, r_prev, low, nrhs, stop);
+                             const double* lmax, double r_cur, double r_prev, double low, int kind,
+                             int nrhs, const int* stop) {
+  cheb_pre3d<T, T>(c, d, E, b, x, invd, lmax, r_cur, r_prev, low, kind, nrhs, stop);
 }
 
 void launch_apply_cheb_pre3d_bf16(Ctx* c, const OpDesc& d, const uint16_t* E16, const float* b,
                                   float* x, const float* invd, const double* lmax, double r_cur,
-                                  double r_prev, double low, int nrhs, const int* stop) {
+                                  double r_prev, double low, int kind, int nrhs, const int* stop) {
   cheb_pre3d<float, bf16m>(c, d, reinterpret_cast<const bf16m*>(E16), b, x, invd, lmax, r_cur,
-                           r_prev, low, nrhs, stop);
+                           r_prev, low, kind, nrhs, stop);
 }
 
 template void launch_apply_cheb_pre3d<float>(Ctx*, const OpDesc&, const float*, const float*, float*,
                                              const float*, const double*, double, double, double, int,
-                                             const int*);
+                                             int, const int*);
 template void launch_apply_cheb_pre3d<double>(Ctx*, const OpDesc&, const double*, const double*,
                                               double*, const double*, const double*, double, double,
-                                              double, int, const int*);
+                                              double, int, int, const int*);
 
 void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, double* y,
                      int nrhs, bool fuse_dot, bool timed, const int* stop) {

@@ -1031,7 +1031,7 @@ void cheb_smooth(const Q& q, int l, bool from_zero) {
   for (int k = 1; k < kChebDegree; ++k) {
     const double rho = 1.0 / (2.0 * sigma - rho_prev);
     apply_lv(q, l, BV_D, BV_Q, true, nullptr);
-    ChebCoef cf{rho, rho_prev};
+    ChebCoef cf{rho, rho_prev, 1, k};
     b_cheb_next<<<t.n, 256, 0, q.s>>>(jb, b->d_slots, b->d_state, cf, kChebLow);
     rho_prev = rho;
   }

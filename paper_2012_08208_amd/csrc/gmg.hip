@@ -35,6 +35,7 @@ namespace topo {
 // Smoother parameters (defaults; TOPO_CHEB_DEGREE, TOPO_CHEB_POST, TOPO_CHEB_LOW,
 // TOPO_POWER_ITERS and TOPO_POWER_SAFETY override them at context creation)
 struct GmgParams {
+  int cheb_kind = 1;      // 1: first-kind Chebyshev on [low lmax, lmax]; 4: fourth kind
   int cheb_degree = 2;
   int post_degree = -1;   // post-smoothing degree (-1: cheb_degree)
   double cheb_low = 0.09;
@@ -49,6 +50,7 @@ static GmgParams gmg_params() {
   if (const char* e = getenv("TOPO_POWER_ITERS")) p.power_iters = atoi(e) > 0 ? atoi(e) : p.power_iters;
   if (const char* e = getenv("TOPO_POWER_SAFETY")) p.power_safety = atof(e) > 0 ? atof(e) : p.power_safety;
   if (const char* e = getenv("TOPO_CHEB_POST")) p.post_degree = atoi(e);
+  if (const char* e = getenv("TOPO_CHEB_KIND")) p.cheb_kind = atoi(e) == 4 ? 4 : 1;
   if (p.post_degree < 0) p.post_degree = p.cheb_degree;
   return p;
 }
@@ -273,11 +275,9 @@ __global__ void prolong_add_kernel(T* xf, const T* __restrict__ xc, OpDesc fo, O
 template <typename T>
 __global__ void cheb_first_kernel(T* x, T* r, T* d, const T* __restrict__ b, const T* __restrict__ q,
                                   const T* __restrict__ invd, const double* lmax, long nd, int nrhs,
-                                  int mode, double low, const int* stop) {
+                                  int mode, double low, int kind, const int* stop) {
   if (stop && *stop) return;
-  double theta, delta;
-  cheb_interval(*lmax, low, theta, delta);
-  const T it = T(1.0 / theta);
+  const T it = T(cheb_first_scale(*lmax, low, kind));
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
     const T id = invd[i];
     for (int k = 0; k < nrhs; ++k) {
@@ -296,9 +296,9 @@ __global__ void cheb_next_kernel(T* x, T* r, T* d, const T* __restrict__ q, cons
                                  const double* lmax, long nd, int nrhs, ChebCoef cf, double low,
                                  const int* stop) {
   if (stop && *stop) return;
-  double theta, delta;
-  cheb_interval(*lmax, low, theta, delta);
-  const T c1 = T(cf.r_cur * cf.r_prev), c2 = T(2.0 * cf.r_cur / delta);
+  double c1d, c2d;
+  cheb_next_coef(*lmax, low, cf, c1d, c2d);
+  const T c1 = T(c1d), c2 = T(c2d);
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
     const T id = invd[i];
     for (int k = 0; k < nrhs; ++k) {
@@ -471,25 +471,25 @@ static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool fr
     if constexpr (std::is_same<T, float>::value) {
       if (g.E16) {
         launch_apply_cheb_pre3d_bf16(c, g.op, g.E16, b, x, invd, g.lmax, rho, rho_prev,
-                                     gp.cheb_low, nrhs, stop);
+                                     gp.cheb_low, gp.cheb_kind, nrhs, stop);
         return;
       }
     }
     launch_apply_cheb_pre3d<T>(c, g.op, LevelOps<T>::E(g), b, x, invd, g.lmax, rho, rho_prev,
-                               gp.cheb_low, nrhs, stop);
+                               gp.cheb_low, gp.cheb_kind, nrhs, stop);
     return;
   }
   const int degree = from_zero ? gp.cheb_degree : gp.post_degree;
   if (degree == 0) return;
   if (!from_zero) LevelOps<T>::apply(c, g, x, gq, nrhs, stop);
   cheb_first_kernel<T><<<nb, 256, 0, s>>>(x, gr, gd, b, gq, invd, g.lmax, nd, nrhs,
-                                          from_zero ? 0 : 1, gp.cheb_low, stop);
+                                          from_zero ? 0 : 1, gp.cheb_low, gp.cheb_kind, stop);
   const double sigma = (1.0 + gp.cheb_low) / (1.0 - gp.cheb_low);
   double rho_prev = 1.0 / sigma;
   for (int k = 1; k < degree; ++k) {
     const double rho = 1.0 / (2.0 * sigma - rho_prev);
     LevelOps<T>::apply(c, g, gd, gq, nrhs, stop);
-    ChebCoef cf{rho, rho_prev};
+    ChebCoef cf{rho, rho_prev, gp.cheb_kind, k};
     cheb_next_kernel<T><<<nb, 256, 0, s>>>(x, gr, gd, gq, invd, g.lmax, nd, nrhs, cf, gp.cheb_low,
                                            stop);
     rho_prev = rho;

@@ -218,8 +218,15 @@ __device__ inline void prolong_node(long n, T* xf, const T* __restrict__ xc, con
 }
 
 // ------------------------------------------------------- smoother
+// Chebyshev smoothing of D^-1 K, d_0 = s D^-1 r_0, d_i = c1 d_(i-1) + c2 D^-1 r_i.
+// kind 1: first-kind polynomial on [low lmax, lmax] (rho_k, rho_(k-1) of its
+// three-term recurrence); kind 4: the fourth-kind polynomial on (0, lmax]
+// (Lottes 2023), s = 4 / (3 lmax), c1 = (2i-1)/(2i+3), c2 = (8i+4)/((2i+3) lmax),
+// which needs no lower bound of the spectrum.
 struct ChebCoef {
-  double r_cur, r_prev;  // rho_k, rho_(k-1) of the Chebyshev recurrence
+  double r_cur, r_prev;
+  int kind;   // 1 or 4
+  int step;   // i >= 1
 };
 
 __device__ inline void cheb_interval(double lmax, double low, double& theta,
@@ -227,6 +234,27 @@ __device__ inline void cheb_interval(double lmax, double low, double& theta,
   const double hi = lmax, lo = low * lmax;
   theta = 0.5 * (hi + lo);
   delta = 0.5 * (hi - lo);
+}
+
+__device__ inline double cheb_first_scale(double lmax, double low, int kind) {
+  if (kind == 4) return 4.0 / (3.0 * lmax);
+  double theta, delta;
+  cheb_interval(lmax, low, theta, delta);
+  return 1.0 / theta;
+}
+
+__device__ inline void cheb_next_coef(double lmax, double low, const ChebCoef& cf, double& c1,
+                                      double& c2) {
+  if (cf.kind == 4) {
+    const double i = (double)cf.step;
+    c1 = (2.0 * i - 1.0) / (2.0 * i + 3.0);
+    c2 = (8.0 * i + 4.0) / ((2.0 * i + 3.0) * lmax);
+    return;
+  }
+  double theta, delta;
+  cheb_interval(lmax, low, theta, delta);
+  c1 = cf.r_cur * cf.r_prev;
+  c2 = 2.0 * cf.r_cur / delta;
 }
 
 // ---------------------------------------------------- coarsest level

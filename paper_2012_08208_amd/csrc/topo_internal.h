@@ -267,13 +267,13 @@ void launch_apply_op_bf16(Ctx* c, const OpDesc& d, const uint16_t* E16, const fl
                           int nrhs, bool timed, const int* stop);
 void launch_apply_cheb_pre3d_bf16(Ctx* c, const OpDesc& d, const uint16_t* E16, const float* b,
                                   float* x, const float* invd, const double* lmax, double r_cur,
-                                  double r_prev, double low, int nrhs, const int* stop);
+                                  double r_prev, double low, int kind, int nrhs, const int* stop);
 void launch_apply_op_f32_dot(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
                              int nrhs);
 template <typename T>
 void launch_apply_cheb_pre3d(Ctx* c, const OpDesc& d, const T* E, const T* b, T* x, const T* invd,
-                             const double* lmax, double r_cur, double r_prev, double low, int nrhs,
-                             const int* stop);
+                             const double* lmax, double r_cur, double r_prev, double low, int kind,
+                             int nrhs, const int* stop);
 void launch_to_f32(Ctx* c, float* dst, const double* src, int64_t n);
 void launch_to_f64(Ctx* c, double* dst, const float* src, int64_t n);
 int pick_kz(int dim, int nx, int ny, int nz);
