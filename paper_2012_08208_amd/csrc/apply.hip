@@ -26,9 +26,20 @@ constexpr int PATCH2 = PATCH * PATCH;
 
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
-template <typename T>
-__device__ __forceinline__ T shift_down1(T v) {
-  return __shfl_down(v, 1, 16);
+// Value of the next lane in the 16-lane row (tx + 1), by a DPP row shift
+// (row_shl:1) instead of an LDS permute; the last lane of a row keeps its
+// own value (it holds no owned node).
+__device__ __forceinline__ float shift_down1(float v) {
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x101, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ double shift_down1(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int slo = __builtin_amdgcn_update_dpp(lo, lo, 0x101, 0xf, 0xf, false);
+  const int shi = __builtin_amdgcn_update_dpp(hi, hi, 0x101, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)shi << 32) | (unsigned)slo));
 }
 
 // Block -> (tile, load case) map.  Work-groups are handed to the 8 XCDs
@@ -275,7 +286,7 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
             if ((om >> a) & 1) yb = 0;
             if (EPI == 0) {
               yr[a * nn + on] = yb;
-              dot += (double)yb * (double)u[3][a];
+              if (partials) dot += (double)yb * (double)u[3][a];
             } else {
               // u[3][a] = d0 at the owned node; r = b - K d0
               const T rv = pb_[a] - yb;
