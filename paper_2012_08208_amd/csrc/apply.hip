@@ -26,21 +26,6 @@ constexpr int PATCH2 = PATCH * PATCH;
 
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
-// Value of the next lane in the 16-lane row (tx + 1), by a DPP row shift
-// (row_shl:1) instead of an LDS permute; the last lane of a row keeps its
-// own value (it holds no owned node).
-__device__ __forceinline__ float shift_down1(float v) {
-  const int b = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x101, 0xf, 0xf, false));
-}
-
-__device__ __forceinline__ double shift_down1(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = (int)b, hi = (int)(b >> 32);
-  const int slo = __builtin_amdgcn_update_dpp(lo, lo, 0x101, 0xf, 0xf, false);
-  const int shi = __builtin_amdgcn_update_dpp(hi, hi, 0x101, 0xf, 0xf, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)shi << 32) | (unsigned)slo));
-}
 
 // Block -> (tile, load case) map.  Work-groups are handed to the 8 XCDs
 // round-robin by linear id, so id % 8 selects the XCD.  Each XCD gets a
@@ -267,7 +252,7 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
         for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
           for (int a = 0; a < 3; ++a)
-            X[cy][cz][a] = f[1 + 2 * cy + 4 * cz][a] + shift_down1(f[2 * cy + 4 * cz][a]);
+            X[cy][cz][a] = f[1 + 2 * cy + 4 * cz][a] + next_lane<16>(f[2 * cy + 4 * cz][a]);
       const int eb = kh & 1;
 #pragma unroll
       for (int cz = 0; cz < 2; ++cz)

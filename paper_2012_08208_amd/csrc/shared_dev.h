@@ -14,6 +14,31 @@
 
 namespace topo {
 
+// Value held by the next lane of the same tile row (tx + 1).  Rows of 16
+// lanes use the DPP row shift (row_shl:1), rows of 32 or 64 lanes the DPP
+// wave shift (wave_shl:1, which crosses the 16-lane rows), other widths a
+// permute through LDS.  The last lane of a row receives no neighbour value;
+// callers do not use it.
+template <int BX>
+__device__ __forceinline__ int next_lane_b32(int v) {
+  if constexpr (BX == 16) return __builtin_amdgcn_update_dpp(v, v, 0x101, 0xf, 0xf, false);
+  else if constexpr (BX == 32 || BX == 64)
+    return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);
+  else return __shfl_down(v, 1, BX);
+}
+
+template <int BX>
+__device__ __forceinline__ float next_lane(float v) {
+  return __int_as_float(next_lane_b32<BX>(__float_as_int(v)));
+}
+
+template <int BX>
+__device__ __forceinline__ double next_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = next_lane_b32<BX>((int)b), hi = next_lane_b32<BX>((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // One tile of a BX x BY thread block (BX * BY = 256): the block owns
 // (BX-1) x (BY-1) nodes and computes the BX x BY squares touching them.
 // Returns this thread's share of (x, y) over owned nodes.
@@ -70,7 +95,7 @@ __device__ inline double apply2d_tile(bool live, int bx, int by, int rhs,
 #pragma unroll
     for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) X[cy][c] = f[1 + 2 * cy][c] + __shfl_down(f[2 * cy][c], 1, BX);
+      for (int c = 0; c < 2; ++c) X[cy][c] = f[1 + 2 * cy][c] + next_lane<BX>(f[2 * cy][c]);
     ex[0][tid] = X[0][0];
     ex[1][tid] = X[0][1];
     lds_barrier();
