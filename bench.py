@@ -68,7 +68,7 @@ def apply_bytes(p, precision: str) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("apply.hip", "element.h", "common.h"):
+    for f in ("apply.hip", "element.h", "common.h", "shared_dev.h"):
         with open(os.path.join(ROOT, "paper_2012_08208_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
