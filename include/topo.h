@@ -41,10 +41,14 @@
  * Every pointer argument is a DEVICE pointer unless marked "host".  The
  * caller owns all buffers, including the workspace given to topo_create;
  * the library allocates no device memory and keeps no caller pointer
- * after a call returns.  All compute calls are asynchronous on the
- * context's stream (a hipStream_t passed as void*; NULL = default stream).
- * Scalars are written to device memory; topo_sync waits for the stream and
- * returns the sticky device status.  A context is not thread-safe.
+ * after a call returns.  All compute calls are ordered on the context's
+ * stream (a hipStream_t passed as void*; NULL = default stream) and return
+ * without waiting for their kernels, except where an iteration's length is
+ * decided on the device: topo_solve, topo_iterate and topo_oc_update (and
+ * topo_filter with the Helmholtz filter) queue batches of steps and wait on
+ * a pinned converged flag between them.  Scalars are written to device
+ * memory; topo_sync waits for the stream and returns the sticky device
+ * status.  A context is not thread-safe.
  *
  * Return values: 0 = OK; negative = host-detected error (TOPO_E_*), in
  * which case nothing was enqueued.  Device-detected outcomes (not converged,
