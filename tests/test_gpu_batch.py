@@ -111,3 +111,33 @@ def test_graph_replays_equal_direct_launches():
         bx, by, us = b.tile_shape()
         assert (bx, by) == (32, 8) and all(v > 0 for v in us)
     np.testing.assert_array_equal(rhos[0], rhos[1])
+
+
+def test_batch_full_size_64_instances_sampled_against_oracle():
+    """The configured batch (64 instances, nx ~ U{80..640}, ny = nx / 2, about
+    10M triangles) in the bench's launch configuration: one SIMP round at CG
+    rtol 1e-10 (solve, sensitivity, filter, OC of every instance), then the
+    smallest and the largest instance against the oracle's first iteration
+    (design to 1e-6, compliance to 1e-8 relative, change to 1e-6) and every
+    instance's volume fraction to 1e-10."""
+    from paper_2012_08208_amd import BATCH_REC_LEN, Batch
+    probs = synth.batch2d()
+    assert len(probs) == 64
+    print("[batch] full size, cells", sum(p.n_cells for p in probs), flush=True)
+    b = Batch(probs, rtol=1e-10, device=DEV)
+    rho = torch.as_tensor(_batch_rho0(probs), device=DEV)
+    rec = torch.zeros(len(probs) * BATCH_REC_LEN, dtype=torch.float64, device=DEV)
+    assert b.iterate(rho, 1, 0.0, rec) == 1 and b.sync() == 0
+    rho = rho.cpu().numpy()
+    rec = rec.cpu().numpy().reshape(len(probs), BATCH_REC_LEN)
+    assert np.all(rec[:, 0] == 1)
+    assert np.all(np.abs(rec[:, 3] - np.array([p.volfrac for p in probs])) <= 1e-10)
+    sizes = [p.n_cells for p in probs]
+    for i in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        S = simp.setup(probs[i])
+        rho_o, log = simp.iterate(S, 1)
+        err = np.max(np.abs(rho[b.cell_off[i]:b.cell_off[i + 1]] - rho_o))
+        ec = abs(rec[i, 2] - log[-1]["c"]) / log[-1]["c"]
+        print(f"  instance {i} nel={probs[i].nel}: design {err:.2e}, compliance {ec:.2e}", flush=True)
+        assert err <= 1e-6 and ec <= 1e-8
+        assert abs(rec[i, 1] - log[-1]["change"]) <= 1e-6

@@ -100,3 +100,35 @@ def test_iterate_density_filter(case):
     print(f"  max |x - x_oracle| = {err:.3e}", flush=True)
     assert err <= 1e-4
     t.close()
+
+
+def test_density_filter_oc_with_passive_cells():
+    """Density mode and passive cells together: passive cells pinned inside
+    the filtered-volume multiplier search, against the oracle."""
+    from oracle import oc as ocm
+    p = synth.cantilever3d(14, 9, 6, nrhs=1, rmin=2.5, volfrac=0.4)
+    print("[density] OC with passive cells", flush=True)
+    m = M.build(p.dim, p.nel, p.split)
+    W = filt.weights_sparse(M.centroids(m), p.rmin)
+    R = filt.row_sums(W)
+    n = m.cells.shape[0]
+    rng = np.random.default_rng(73)
+    x = rng.uniform(0.05, 0.8, n)
+    g = -rng.lognormal(0.0, 1.5, n)
+    passive = np.zeros(n, np.uint8)
+    passive[rng.choice(n, n // 10, replace=False)] = ocm.VOID
+    passive[rng.choice(np.flatnonzero(passive == 0), n // 30, replace=False)] = ocm.SOLID
+    dv = filt.density_grad(W, R, np.ones(n))
+    ref, lam, vol, change, _ = ocm.update(x, g, p.volfrac, dv=dv, passive=passive,
+                                          phys=lambda z: filt.density(W, R, z))
+    t = _topo(p)
+    t.set_passive(passive)
+    rn = torch.zeros(n, dtype=torch.float64, device=DEV)
+    sc = torch.zeros(3, dtype=torch.float64, device=DEV)
+    t.oc_update(_t(x), _t(g), rn, sc)
+    assert t.sync() == 0
+    got = rn.cpu().numpy()
+    assert np.all(got[passive == ocm.VOID] == p.rho_min) and np.all(got[passive == ocm.SOLID] == 1.0)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(sc.cpu().numpy()[1], vol, rtol=1e-12)
+    t.close()

@@ -294,3 +294,39 @@ def test_training_on_gpu_cuts_fcg_iterations():
     print(f"[gain] FCG iterations trained {its['trained']:.0f} vs without network "
           f"{its['none']:.0f}", flush=True)
     assert its["trained"] <= 0.8 * its["none"]
+
+
+def test_network_full_size_properties():
+    """The 128 x 64 x 64 learned-preconditioner grid (129 x 65 x 65 nodes, the
+    configuration the learned bench times), where the oracle's full forward
+    would take minutes: properties that hold exactly at any size.  The pass
+    is deterministic (two calls agree bit for bit); scaling r by 2 scales z
+    by exactly 2 (the input is r / rms(r), and power-of-two scaling is exact
+    through the sum of squares and the square root); z is exactly zero on
+    fixed DOFs; a zero residual gives a zero output."""
+    p = synth.learned3d()
+    assert p.nel == (128, 64, 64)
+    print("[net] full-size properties 128x64x64", flush=True)
+    m_nodes = p.n_nodes
+    rho = synth.rho_random(21, p.n_cells, 0.05, 1.0)
+    r = synth.vec_random(22, (3, m_nodes), p.fixed)
+    w = net.init_params(23)
+    t = _ctx(p)
+    t.precond_set_weights(_t(w, torch.float32))
+    t.precond_config(1.3, 10, 1)
+    z1 = torch.zeros(p.n_dofs, dtype=torch.float64, device=DEV)
+    z2 = torch.zeros_like(z1)
+    z3 = torch.zeros_like(z1)
+    t.precond_apply(_t(rho), _t(r), z1)
+    t.precond_apply(_t(rho), _t(r), z2)
+    t.precond_apply(_t(rho), _t(2.0 * r), z3)
+    assert t.sync() == 0
+    a, b, c = (v.cpu().numpy() for v in (z1, z2, z3))
+    assert np.array_equal(a, b)
+    assert np.array_equal(c, 2.0 * a)
+    fixed = p.fixed.reshape(-1) != 0
+    assert np.all(a[fixed] == 0.0) and np.count_nonzero(a[~fixed]) > 0.9 * np.count_nonzero(~fixed)
+    t.precond_apply(_t(rho), torch.zeros(p.n_dofs, dtype=torch.float64, device=DEV), z1)
+    assert t.sync() == 0
+    assert torch.count_nonzero(z1).item() == 0
+    t.close()
