@@ -94,6 +94,11 @@ struct PlaneBuf {
 // patch; at each owned node the epilogue forms r = b - K d0,
 // d1 = c1 d0 + c2 D^-1 r and writes x = d0 + d1 (r and the increments are
 // not needed afterwards), so r and d are never stored.
+// EPI = 3 and 4: degree-2 smoothing from a given x in two kernels.  EPI 3
+// takes x as the operator input and writes r = b - K x and d1 = s D^-1 r at
+// owned nodes (x itself is left alone: other blocks still read it as halo).
+// EPI 4 takes d1 as the operator input and, at owned nodes, forms
+// r - K d1, d2 = c1 d1 + c2 D^-1 (r - K d1) and writes x = (x + d1) + d2.
 template <typename T>
 struct ChebEpi {
   T* x;
@@ -102,6 +107,8 @@ struct ChebEpi {
   const double* lmax;
   double r_cur, r_prev, low;
   int kind;   // Chebyshev kind (1 or 4)
+  T* r;       // EPI 3: residual out; EPI 4: residual in
+  T* d;       // EPI 3: first increment out
 };
 
 template <typename T, typename TE, int EPI>
@@ -128,9 +135,11 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     const long plane = (long)(nx + 1) * (ny + 1);
     const T* xr = x + (long)rhs * 3 * nn;
     T* yr = y + (long)rhs * 3 * nn;
-    const T* br = EPI == 2 ? ce.b + (long)rhs * 3 * nn : nullptr;
+    const T* br = (EPI == 2 || EPI == 3) ? ce.b + (long)rhs * 3 * nn : nullptr;
+    T* rr_ = (EPI == 3 || EPI == 4) ? ce.r + (long)rhs * 3 * nn : nullptr;
+    T* dd_ = EPI == 3 ? ce.d + (long)rhs * 3 * nn : nullptr;
     T it0 = 0;
-    if (EPI == 2) it0 = T(cheb_first_scale(*ce.lmax, ce.low, ce.kind));
+    if (EPI == 2 || EPI == 3) it0 = T(cheb_first_scale(*ce.lmax, ce.low, ce.kind));
 
     // plane staging: thread handles patch nodes idx = tid and tid + 256
     long poff[2];
@@ -201,7 +210,7 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     T carry[3] = {0, 0, 0};
     T c1 = 0, c2 = 0;
     T* ex_ = nullptr;
-    if (EPI == 2) {
+    if (EPI == 2 || EPI == 4) {
       double c1d, c2d;
       cheb_next_coef(*ce.lmax, ce.low, ChebCoef{ce.r_cur, ce.r_prev, ce.kind, 1}, c1d, c2d);
       c1 = T(c1d);
@@ -220,13 +229,14 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
       fetch_E(kh, ev);
       // smoothing epilogue: this layer's b and D^-1 at the owned node, issued
       // now so their latency hides behind the layer's arithmetic
-      T pb_[3], pi[3];
-      if (EPI == 2) {
+      T pb_[3], pi[3], px[3];
+      if (EPI >= 2) {
         const long on = (long)min(max(kh, 0), nz) * plane + (owner ? ocol : 0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          pb_[a] = br[a * nn + on];
+          pb_[a] = EPI == 4 ? rr_[a * nn + on] : br[a * nn + on];
           pi[a] = ce.invd[a * nn + on];
+          if (EPI == 4) px[a] = ex_[a * nn + on];
         }
       }
       commit(kh + 1, pb);
@@ -272,10 +282,19 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
             if (EPI == 0) {
               yr[a * nn + on] = yb;
               if (partials) dot += (double)yb * (double)u[3][a];
-            } else {
+            } else if (EPI == 2) {
               // u[3][a] = d0 at the owned node; r = b - K d0
               const T rv = pb_[a] - yb;
               ex_[a * nn + on] = u[3][a] + (c1 * u[3][a] + c2 * pi[a] * rv);
+            } else if (EPI == 3) {
+              const T rv = pb_[a] - yb;
+              rr_[a * nn + on] = rv;
+              dd_[a * nn + on] = it0 * pi[a] * rv;
+            } else {
+              // u[3][a] = d1 at the owned node, pb_ = r, px = x
+              const T rv = pb_[a] - yb;
+              const T dv = c1 * u[3][a] + c2 * pi[a] * rv;
+              ex_[a * nn + on] = (px[a] + u[3][a]) + dv;
             }
           }
         }
@@ -428,6 +447,47 @@ static void cheb_pre3d(Ctx* c, const OpDesc& d, const TE* E, const T* b, T* x, c
   apply3d_kernel<T, TE, 2><<<blocks, 256, 0, c->stream>>>(nullptr, nullptr, E, d, tm, lam, mu,
                                                           nullptr, stop, ce);
 }
+
+// degree-2 smoothing from a given x (3D), two kernels (EPI 3, EPI 4); the
+// coefficients are those of the first and second step of the separate
+// smoothing kernels, so the result is the same arithmetic
+template <typename T, typename TE>
+static void cheb_post3d(Ctx* c, const OpDesc& d, const TE* E, T* x, const T* b, T* r, T* dd,
+                        const T* invd, const double* lmax, double r_cur, double r_prev, double low,
+                        int kind, int nrhs, const int* stop) {
+  const T lam = T(c->m.lam0 * c->m.vol), mu = T(c->m.mu0 * c->m.vol);
+  const TileMap tm = make_tilemap(d, nrhs);
+  const unsigned blocks = (unsigned)(8L * tm.per_xcd * nrhs);
+  ChebEpi<T> ce{x, invd, b, lmax, r_cur, r_prev, low, kind, r, dd};
+  apply3d_kernel<T, TE, 3><<<blocks, 256, 0, c->stream>>>(x, nullptr, E, d, tm, lam, mu, nullptr,
+                                                          stop, ce);
+  apply3d_kernel<T, TE, 4><<<blocks, 256, 0, c->stream>>>(dd, nullptr, E, d, tm, lam, mu, nullptr,
+                                                          stop, ce);
+}
+
+template <typename T>
+void launch_apply_cheb_post3d(Ctx* c, const OpDesc& d, const T* E, const uint16_t* E16, T* x,
+                              const T* b, T* r, T* dd, const T* invd, const double* lmax,
+                              double r_cur, double r_prev, double low, int kind, int nrhs,
+                              const int* stop) {
+  if constexpr (sizeof(T) == 4) {
+    if (E16) {
+      cheb_post3d<T, bf16m>(c, d, reinterpret_cast<const bf16m*>(E16), x, b, r, dd, invd, lmax,
+                            r_cur, r_prev, low, kind, nrhs, stop);
+      return;
+    }
+  }
+  cheb_post3d<T, T>(c, d, E, x, b, r, dd, invd, lmax, r_cur, r_prev, low, kind, nrhs, stop);
+}
+
+template void launch_apply_cheb_post3d<float>(Ctx*, const OpDesc&, const float*, const uint16_t*,
+                                              float*, const float*, float*, float*, const float*,
+                                              const double*, double, double, double, int, int,
+                                              const int*);
+template void launch_apply_cheb_post3d<double>(Ctx*, const OpDesc&, const double*, const uint16_t*,
+                                               double*, const double*, double*, double*,
+                                               const double*, const double*, double, double, double,
+                                               int, int, const int*);
 
 template <typename T>
 void launch_apply_cheb_pre3d(Ctx* c, const OpDesc& d, const T* E, const T* b, T* x, const T* invd,

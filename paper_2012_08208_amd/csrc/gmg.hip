@@ -36,6 +36,7 @@ namespace topo {
 // TOPO_POWER_ITERS and TOPO_POWER_SAFETY override them at context creation)
 struct GmgParams {
   int cheb_kind = 1;      // 1: first-kind Chebyshev on [low lmax, lmax]; 4: fourth kind
+  bool fused_post = true; // 3D degree-2 post-smoothing in two fused apply kernels
   int cheb_degree = 2;
   int post_degree = -1;   // post-smoothing degree (-1: cheb_degree)
   double cheb_low = 0.09;
@@ -51,6 +52,7 @@ static GmgParams gmg_params() {
   if (const char* e = getenv("TOPO_POWER_SAFETY")) p.power_safety = atof(e) > 0 ? atof(e) : p.power_safety;
   if (const char* e = getenv("TOPO_CHEB_POST")) p.post_degree = atoi(e);
   if (const char* e = getenv("TOPO_CHEB_KIND")) p.cheb_kind = atoi(e) == 4 ? 4 : 1;
+  if (const char* e = getenv("TOPO_CHEB_POST_FUSED")) p.fused_post = atoi(e) != 0;
   if (p.post_degree < 0) p.post_degree = p.cheb_degree;
   return p;
 }
@@ -481,6 +483,16 @@ static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool fr
   }
   const int degree = from_zero ? gp.cheb_degree : gp.post_degree;
   if (degree == 0) return;
+  if (!from_zero && g.op.dim == 3 && degree == 2 && gp.fused_post) {
+    // degree-2 smoothing from the given x in two fused kernels
+    const double sigma = (1.0 + gp.cheb_low) / (1.0 - gp.cheb_low);
+    const double rho_prev = 1.0 / sigma, rho = 1.0 / (2.0 * sigma - rho_prev);
+    const uint16_t* e16 = nullptr;
+    if constexpr (std::is_same<T, float>::value) e16 = g.E16;
+    launch_apply_cheb_post3d<T>(c, g.op, LevelOps<T>::E(g), e16, x, b, gr, gd, invd, g.lmax, rho,
+                                rho_prev, gp.cheb_low, gp.cheb_kind, nrhs, stop);
+    return;
+  }
   if (!from_zero) LevelOps<T>::apply(c, g, x, gq, nrhs, stop);
   cheb_first_kernel<T><<<nb, 256, 0, s>>>(x, gr, gd, b, gq, invd, g.lmax, nd, nrhs,
                                           from_zero ? 0 : 1, gp.cheb_low, gp.cheb_kind, stop);

@@ -274,6 +274,11 @@ template <typename T>
 void launch_apply_cheb_pre3d(Ctx* c, const OpDesc& d, const T* E, const T* b, T* x, const T* invd,
                              const double* lmax, double r_cur, double r_prev, double low, int kind,
                              int nrhs, const int* stop);
+template <typename T>
+void launch_apply_cheb_post3d(Ctx* c, const OpDesc& d, const T* E, const uint16_t* E16, T* x,
+                              const T* b, T* r, T* dd, const T* invd, const double* lmax,
+                              double r_cur, double r_prev, double low, int kind, int nrhs,
+                              const int* stop);
 void launch_to_f32(Ctx* c, float* dst, const double* src, int64_t n);
 void launch_to_f64(Ctx* c, double* dst, const float* src, int64_t n);
 int pick_kz(int dim, int nx, int ny, int nz);

@@ -355,3 +355,30 @@ def _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-9):
     print(f"[iterate] max |rho - rho_oracle| = {err:.3e}", flush=True)
     assert err <= 1e-4
     return rho.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "bf16"])
+def test_fused_post_smoothing_equals_separate_kernels(prec, monkeypatch):
+    """The 3D degree-2 post-smoothing fused into two apply epilogues does the
+    arithmetic of the separate Chebyshev kernels, operation for operation:
+    the same CG iteration count and the same solution (1e-13 relative, the
+    bar allows a different fused-multiply-add contraction choice)."""
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_BF16, TOPO_MIXED_FP32, TOPO_PC_GMG
+    code = {"fp64": TOPO_FP64, "mixed": TOPO_MIXED_FP32, "bf16": TOPO_MIXED_BF16}[prec]
+    p = synth.cantilever3d(41, 23, 17, nrhs=3, rmin=1.5, rtol=1e-10)
+    rho = synth.rho_random(31, p.n_cells, 0.05, 1.0)
+    print(f"[fused post] {prec} nel={p.nel}", flush=True)
+    out = {}
+    for fused in ("1", "0"):
+        monkeypatch.setenv("TOPO_CHEB_POST_FUSED", fused)
+        t = _topo(p, rtol=1e-10, precond=TOPO_PC_GMG, precision=code)
+        u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=DEV)
+        info = torch.zeros(6, dtype=torch.float64, device=DEV)
+        t.solve(_t(rho), u, info)
+        assert t.sync() == 0
+        out[fused] = (u.cpu().numpy(), info.cpu().numpy())
+        t.close()
+    (u1, i1), (u0, i0) = out["1"], out["0"]
+    print(f"  iterations {i1[0]:.0f} / {i0[0]:.0f}", flush=True)
+    assert i1[0] == i0[0] and i1[1] == 1.0
+    assert np.max(np.abs(u1 - u0)) <= 1e-13 * np.max(np.abs(u0))
