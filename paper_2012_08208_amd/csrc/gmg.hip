@@ -263,6 +263,7 @@ __global__ void restrict_kernel(T* bc, const T* __restrict__ bf, const T* __rest
   restrict_node<T>(C, bc, bf, qf, fo, co, nrhs);
 }
 
+// x_f += P x_c, one thread per fine node (large grids)
 template <typename T>
 __global__ void prolong_add_kernel(T* xf, const T* __restrict__ xc, OpDesc fo, OpDesc co, int nrhs,
                                    const int* stop) {
@@ -270,6 +271,32 @@ __global__ void prolong_add_kernel(T* xf, const T* __restrict__ xc, OpDesc fo, O
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= fo.nn) return;
   prolong_node<T>(n, xf, xc, fo, co, nrhs);
+}
+
+// x_f += P x_c, one thread per (fine node, load case and component
+// = blockIdx.y): the same interpolation as prolong_node, each value in a
+// thread of its own, for small grids where one thread per node leaves the
+// chip nearly idle
+template <typename T>
+__global__ void prolong_add_split_kernel(T* xf, const T* __restrict__ xc, OpDesc fo, OpDesc co,
+                                   const int* stop) {
+  if (stop && *stop) return;
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= fo.nn) return;
+  const int dim = fo.dim;
+  const int rc = blockIdx.y;   // r * dim + c
+  const int c = rc % dim;
+  if ((fo.mask[n] >> c) & 1) return;
+  const int nxf1 = fo.nx + 1, nyf1 = fo.ny + 1;
+  const int i = (int)(n % nxf1), j = (int)((n / nxf1) % nyf1);
+  const int k = dim == 3 ? (int)(n / ((long)nxf1 * nyf1)) : 0;
+  const int nxc1 = co.nx + 1, nyc1 = co.ny + 1;
+  const long c0 = ((long)(k >> 1) * nyc1 + (j >> 1)) * nxc1 + (i >> 1);
+  const long c1 = ((long)((k + 1) >> 1) * nyc1 + ((j + 1) >> 1)) * nxc1 + ((i + 1) >> 1);
+  const bool even = ((i | j | k) & 1) == 0;
+  const T* xcr = xc + (long)rc * co.nn;
+  const T e = even ? xcr[c0] : T(0.5) * (xcr[c0] + xcr[c1]);
+  xf[(long)rc * fo.nn + n] += e;
 }
 
 // ------------------------------------------------------- smoother
@@ -539,7 +566,11 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
     restrict_kernel<T><<<cdivu(h.op.nn, 256), 256, 0, s>>>(hb, b, gq, g.op, h.op, nrhs, stop);
   }
   vcycle_level<T>(c, l + 1, hb, hx, nrhs);
-  prolong_add_kernel<T><<<cdivu(g.op.nn, 256), 256, 0, s>>>(x, hx, g.op, h.op, nrhs, stop);
+  if (g.op.nn >= 262144)
+    prolong_add_kernel<T><<<cdivu(g.op.nn, 256), 256, 0, s>>>(x, hx, g.op, h.op, nrhs, stop);
+  else
+    prolong_add_split_kernel<T><<<dim3(cdivu(g.op.nn, 256), g.op.dim * nrhs), 256, 0, s>>>(
+        x, hx, g.op, h.op, stop);
   cheb_smooth<T>(c, g, b, x, nrhs, false);
 }
 
