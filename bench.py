@@ -578,7 +578,7 @@ def main():
                     help="batch2d workload: also run every instance to max change < 0.01")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: this implementation runs on one GPU only (got --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design note, not an implemented path",
               file=sys.stderr)
         return 2
