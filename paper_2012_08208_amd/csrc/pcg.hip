@@ -17,6 +17,7 @@
 // solve of mixed-precision iterative refinement: FP32 vectors, FP32
 // operator and V-cycle, FP64 dot products and scalars.  Refinement keeps the
 // solution and the true residual f - K u in FP64 (outer loop below).
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -291,6 +292,11 @@ __global__ void pcg_info_kernel(const PcgState* st, double* info, int nr, int* s
   else if (!st->done && *status == 0) *status = TOPO_S_NOT_CONVERGED;
 }
 
+// The direction update has no reduction, so it takes more blocks than the
+// reductions' fixed count: more loads in flight (103 -> 72 us at 5.4M DOFs x
+// 4 load cases); the update and dot kernels gained nothing from more blocks.
+static unsigned dir_grid(long n) { return (unsigned)std::min<long>(std::max<long>((n + 255) / 256, 1), 8192); }
+
 unsigned red_grid(long n) {
   long b = (n + 255) / 256;
   return (unsigned)(b < kRedBlocks ? (b < 1 ? 1 : b) : kRedBlocks);
@@ -353,6 +359,7 @@ static void mixed_flex_iterate(Ctx* c, double* x, double* r, double* p, double* 
   int* status = &c->scal->status;
   hipStream_t s = c->stream;
   const unsigned gb = red_grid(nd);
+  const unsigned gd = dir_grid(nd);
   const long nb_apply = apply_grid_blocks(fine_op(c), NR);
   float* zb[2] = {c->z32, c->z32b};
   launch_to_f32(c, c->r32, r, (int64_t)NR * nd);
@@ -376,7 +383,7 @@ static void mixed_flex_iterate(Ctx* c, double* x, double* r, double* p, double* 
       gmg_vcycle_f32(c, c->r32, zn, NR);
       pcg_rz2_kernel<NR, float><<<gb, 256, 0, s>>>(r, zn, zo, nd, c->partials, st);
       pcg_rz2_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st);
-      pcg_direction_kernel<NR, false, double, float><<<gb, 256, 0, s>>>(p, zn, r, nullptr, nd, st, 0);
+      pcg_direction_kernel<NR, false, double, float><<<gd, 256, 0, s>>>(p, zn, r, nullptr, nd, st, 0);
       zi ^= 1;
     }
     it += nbt;
@@ -417,7 +424,7 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
     Prec<TV>::vcycle(c, r, z, NR);
     pcg_rz_kernel<NR, TV><<<gb, 256, 0, s>>>(r, z, nd, c->partials, st);
     pcg_rz_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, 1, st);
-    pcg_direction_kernel<NR, false, TV><<<gb, 256, 0, s>>>(p, z, r, invd, nd, st, 1);
+    pcg_direction_kernel<NR, false, TV><<<dir_grid(nd), 256, 0, s>>>(p, z, r, invd, nd, st, 1);
   } else {
     jacobi_kernel<NR, TV><<<gb, 256, 0, s>>>(p, r, invd, nd);
     pcg_rz_kernel<NR, TV><<<gb, 256, 0, s>>>(r, p, nd, c->partials, st);
@@ -455,7 +462,7 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
           pcg_rz2_kernel<NR><<<gb, 256, 0, s>>>(r, zn, zo, nd, c->partials, st);
           pcg_rz2_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st);
         }
-        pcg_direction_kernel<NR, false, TV><<<gb, 256, 0, s>>>(p, zn, r, invd, nd, st, 0);
+        pcg_direction_kernel<NR, false, TV><<<dir_grid(nd), 256, 0, s>>>(p, zn, r, invd, nd, st, 0);
         zi ^= 1;
       } else if (gmg) {
         pcg_update_kernel<NR, false, TV><<<gb, 256, 0, s>>>(x, r, p, q, invd, nd, c->partials, st);
@@ -463,11 +470,11 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
         Prec<TV>::vcycle(c, r, z, NR);
         pcg_rz_kernel<NR, TV><<<gb, 256, 0, s>>>(r, z, nd, c->partials, st);
         pcg_rz_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, 0, st);
-        pcg_direction_kernel<NR, false, TV><<<gb, 256, 0, s>>>(p, z, r, invd, nd, st, 0);
+        pcg_direction_kernel<NR, false, TV><<<dir_grid(nd), 256, 0, s>>>(p, z, r, invd, nd, st, 0);
       } else {
         pcg_update_kernel<NR, true, TV><<<gb, 256, 0, s>>>(x, r, p, q, invd, nd, c->partials, st);
         pcg_update_fin<NR, true><<<1, 256, 0, s>>>(c->partials, gb, st, status);
-        pcg_direction_kernel<NR, true, TV><<<gb, 256, 0, s>>>(p, (const TV*)nullptr, r, invd, nd, st, 0);
+        pcg_direction_kernel<NR, true, TV><<<dir_grid(nd), 256, 0, s>>>(p, (const TV*)nullptr, r, invd, nd, st, 0);
       }
       capture(it + k + 1);
     }
