@@ -263,14 +263,49 @@ __global__ void restrict_kernel(T* bc, const T* __restrict__ bf, const T* __rest
   restrict_node<T>(C, bc, bf, qf, fo, co, nrhs);
 }
 
-// x_f += P x_c, one thread per fine node (large grids)
-template <typename T>
-__global__ void prolong_add_kernel(T* xf, const T* __restrict__ xc, OpDesc fo, OpDesc co, int nrhs,
-                                   const int* stop) {
+// x_f += P x_c, one thread per fine node (large grids): the same
+// interpolation as prolong_node with the load-case and component loops
+// unrolled, so all of a node's loads are in flight together
+template <typename T, int NR, int DIM>
+__global__ void prolong_add_kernel(T* __restrict__ xf, const T* __restrict__ xc, OpDesc fo,
+                                   OpDesc co, const int* stop) {
   if (stop && *stop) return;
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= fo.nn) return;
-  prolong_node<T>(n, xf, xc, fo, co, nrhs);
+  const int nxf1 = fo.nx + 1, nyf1 = fo.ny + 1;
+  const int i = (int)(n % nxf1), j = (int)((n / nxf1) % nyf1);
+  const int k = DIM == 3 ? (int)(n / ((long)nxf1 * nyf1)) : 0;
+  const int nxc1 = co.nx + 1, nyc1 = co.ny + 1;
+  const long c0 = ((long)(k >> 1) * nyc1 + (j >> 1)) * nxc1 + (i >> 1);
+  const long c1 = ((long)((k + 1) >> 1) * nyc1 + ((j + 1) >> 1)) * nxc1 + ((i + 1) >> 1);
+  const bool even = ((i | j | k) & 1) == 0;
+  const int fm = fo.mask[n];
+  T a0[NR * DIM], a1[NR * DIM], xv[NR * DIM];
+#pragma unroll
+  for (int rc = 0; rc < NR * DIM; ++rc) {
+    const T* xcr = xc + (long)rc * co.nn;
+    a0[rc] = xcr[c0];
+    a1[rc] = xcr[c1];
+    xv[rc] = xf[(long)rc * fo.nn + n];
+  }
+#pragma unroll
+  for (int rc = 0; rc < NR * DIM; ++rc) {
+    if ((fm >> (rc % DIM)) & 1) continue;
+    const T e = even ? a0[rc] : T(0.5) * (a0[rc] + a1[rc]);
+    xf[(long)rc * fo.nn + n] = xv[rc] + e;
+  }
+}
+
+template <typename T, int DIM>
+static void prolong_large(hipStream_t s, T* xf, const T* xc, const OpDesc& fo, const OpDesc& co,
+                          int nrhs, const int* stop) {
+  const unsigned nb = cdivu(fo.nn, 256);
+  switch (nrhs) {
+    case 1: prolong_add_kernel<T, 1, DIM><<<nb, 256, 0, s>>>(xf, xc, fo, co, stop); break;
+    case 2: prolong_add_kernel<T, 2, DIM><<<nb, 256, 0, s>>>(xf, xc, fo, co, stop); break;
+    case 3: prolong_add_kernel<T, 3, DIM><<<nb, 256, 0, s>>>(xf, xc, fo, co, stop); break;
+    default: prolong_add_kernel<T, 4, DIM><<<nb, 256, 0, s>>>(xf, xc, fo, co, stop); break;
+  }
 }
 
 // x_f += P x_c, one thread per (fine node, load case and component
@@ -566,9 +601,10 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
     restrict_kernel<T><<<cdivu(h.op.nn, 256), 256, 0, s>>>(hb, b, gq, g.op, h.op, nrhs, stop);
   }
   vcycle_level<T>(c, l + 1, hb, hx, nrhs);
-  if (g.op.nn >= 262144)
-    prolong_add_kernel<T><<<cdivu(g.op.nn, 256), 256, 0, s>>>(x, hx, g.op, h.op, nrhs, stop);
-  else
+  if (g.op.nn >= 262144) {
+    if (g.op.dim == 3) prolong_large<T, 3>(s, x, hx, g.op, h.op, nrhs, stop);
+    else prolong_large<T, 2>(s, x, hx, g.op, h.op, nrhs, stop);
+  } else
     prolong_add_split_kernel<T><<<dim3(cdivu(g.op.nn, 256), g.op.dim * nrhs), 256, 0, s>>>(
         x, hx, g.op, h.op, stop);
   cheb_smooth<T>(c, g, b, x, nrhs, false);
