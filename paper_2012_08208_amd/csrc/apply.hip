@@ -82,11 +82,16 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const T* __restrict__ x, T
 // the plane after it and the next layer's moduli are fetched from memory
 // while the layer is computed, and the cube forces are combined into owned
 // nodes.  Two LDS-only barriers per layer; all loads use clamped (always
-// valid) addresses so they are issued unconditionally.
+// valid) addresses so they are issued unconditionally.  A plane's loads are
+// kept raw until the commit one layer later (validity selects, the D^-1 b
+// product of the pre-smoothing), so no wait for them falls inside the layer
+// that issued them.
 template <typename T>
 struct PlaneBuf {
   T v[2][3];
+  T w[2][3];  // EPI 2: D^-1 at the staged nodes (v holds b)
   int m[2];
+  bool ok[2];
 };
 
 // EPI = 2: the whole degree-2 Chebyshev smoothing from x = 0 in one kernel.
@@ -161,11 +166,17 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const long n = base + poff[q];
-        const int m = d.mask[n];
-        pb.m[q] = (pin[q] && kin) ? m : 7;
+        pb.m[q] = d.mask[n];
+        pb.ok[q] = pin[q] && kin;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          pb.v[q][c] = EPI == 2 ? it0 * ce.invd[c * nn + n] * br[c * nn + n] : xr[c * nn + n];
+        for (int c = 0; c < 3; ++c) {
+          if (EPI == 2) {
+            pb.w[q][c] = ce.invd[c * nn + n];
+            pb.v[q][c] = br[c * nn + n];
+          } else {
+            pb.v[q][c] = xr[c * nn + n];
+          }
+        }
       }
     };
     auto commit = [&](int kk, const PlaneBuf<T>& pb) {
@@ -175,8 +186,9 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
         const int idx = tid + 256 * q;
         if (pidx[q]) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) xs[s][c][idx] = pb.v[q][c];
-          ms[s][idx] = (uint8_t)pb.m[q];
+          for (int c = 0; c < 3; ++c)
+            xs[s][c][idx] = EPI == 2 ? it0 * pb.w[q][c] * pb.v[q][c] : pb.v[q][c];
+          ms[s][idx] = pb.ok[q] ? (uint8_t)pb.m[q] : (uint8_t)7;
         }
       }
     };
@@ -184,8 +196,8 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     const int hi = i0 - 1 + tx, hj = j0 - 1 + ty;
     const bool col_ok = hi >= 0 && hi < nx && hj >= 0 && hj < ny;
     const long hcol = (long)min(max(hj, 0), ny - 1) * nx + min(max(hi, 0), nx - 1);
+    // raw moduli; the validity select is applied where they are used
     auto fetch_E = [&](int kk, T (&en)[6]) {
-      const bool ok = col_ok && kk >= 0 && kk < nz;
       const long h = (long)min(max(kk, 0), nz - 1) * ny * nx + hcol;
       if constexpr (sizeof(TE) == 2) {
         // BF16 moduli: the cube's six are 12 bytes, read as three dwords
@@ -193,15 +205,12 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           const uint32_t v = w[q];
-          en[2 * q] = ok ? T(__uint_as_float(v << 16)) : T(0);
-          en[2 * q + 1] = ok ? T(__uint_as_float(v & 0xffff0000u)) : T(0);
+          en[2 * q] = T(__uint_as_float(v << 16));
+          en[2 * q + 1] = T(__uint_as_float(v & 0xffff0000u));
         }
       } else {
 #pragma unroll
-        for (int t = 0; t < 6; ++t) {
-          const T e = T(E[6 * h + t]);
-          en[t] = ok ? e : T(0);
-        }
+        for (int t = 0; t < 6; ++t) en[t] = T(E[6 * h + t]);
       }
     };
     const int oi = i0 + tx, oj = j0 + ty;
@@ -241,10 +250,16 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
       }
       commit(kh + 1, pb);
       lds_barrier();
-      if (kh + 2 <= k1) fetch(kh + 2, pb);
+      // clamped addresses: past the chunk's end this reads a valid plane that
+      // is never committed
+      fetch(kh + 2, pb);
+      const bool eok = col_ok && kh >= 0 && kh < nz;
       T lam[6], mu[6];
 #pragma unroll
-      for (int t = 0; t < 6; ++t) { lam[t] = lam0 * ev[t]; mu[t] = mu0 * ev[t]; }
+      for (int t = 0; t < 6; ++t) {
+        lam[t] = eok ? lam0 * ev[t] : T(0);
+        mu[t] = eok ? mu0 * ev[t] : T(0);
+      }
       const int sb = kh & 1, stp = (kh + 1) & 1;
       T u[8][3], f[8][3];
 #pragma unroll
