@@ -250,9 +250,9 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
       }
       commit(kh + 1, pb);
       lds_barrier();
-      // clamped addresses: past the chunk's end this reads a valid plane that
-      // is never committed
-      fetch(kh + 2, pb);
+      // unconditional: past the chunk's end this re-reads its last plane
+      // (still in cache), which is never committed
+      fetch(min(kh + 2, k1), pb);
       const bool eok = col_ok && kh >= 0 && kh < nz;
       T lam[6], mu[6];
 #pragma unroll
