@@ -435,6 +435,51 @@ int topo_batch_sync(topo_batch* batch, int* device_status /* host */);
    available and the kernels are launched directly */
 int topo_batch_uses_graphs(topo_batch* batch);
 
+/* ------------------------------------------------------------------------
+ * Distance-weighted filter over arbitrary cell midpoints (unstructured
+ * meshes): Sec. 3.2.2 (eq. filter, eq. filter_cond) and Sec. 4.4
+ * (eq. filter_mat), with the weight matrix built once, outside the
+ * iteration loop, by evaluating the Euclidean distance matrix in chunks
+ * (Sec. 6.2).  The chunks are the cells of a spatial hash of side rmin, so
+ * only blocks of the distance matrix that can hold a positive weight are
+ * evaluated.  These calls need no context.
+ *
+ * mid    device, FP64, SoA [dim][n]: mid[c * n + a] is coordinate c of the
+ *        midpoint of cell a; dim is 2 or 3; every coordinate finite.
+ * rmin   filter radius in the midpoints' length unit, > 0.
+ * W      CSR: rowptr [n + 1] (int64), col [nnz] (int32), w [nnz] (FP64);
+ *        W_ab = rmin - |x_a - x_b| for every pair at distance below rmin
+ *        (the diagonal included), no other entries, no duplicates.  Row a
+ *        lists its columns by hash chunk, then by increasing index; the
+ *        order and every value are the same on every run.
+ * R      device [n]: R_a = sum_b W_ab, summed in row order.
+ * work   device scratch of topo_edm_workspace_size bytes, 256-byte aligned,
+ *        owned by the caller.  topo_edm_count leaves in it the hash order
+ *        that topo_edm_fill reads: pass the same buffer, unchanged, with the
+ *        same mid, dim, n and rmin.
+ *
+ * Sequence: topo_edm_count writes rowptr; the caller reads nnz = rowptr[n]
+ * (after synchronising the stream), allocates col and w, then calls
+ * topo_edm_fill; topo_edm_filter is the per-iteration step.  All calls are
+ * asynchronous on stream (a hipStream_t as void*; NULL = default stream).
+ * Returns TOPO_E_INVALID (dim not 2 or 3, rmin not positive and finite, a
+ * needed pointer NULL), TOPO_E_SHAPE (n < 0 or n > 2^31 - 2, nnz < 0),
+ * TOPO_E_WORKSPACE (work too small or misaligned) or TOPO_E_HIP; n = 0
+ * is valid (rowptr[0] = 0, nothing else is touched).
+ */
+int topo_edm_workspace_size(int64_t n, size_t* bytes /* host */);
+int topo_edm_count(const double* mid, int32_t dim, int64_t n, double rmin, int64_t* rowptr,
+                   void* work, size_t work_bytes, void* stream);
+int topo_edm_fill(const double* mid, int32_t dim, int64_t n, double rmin, const int64_t* rowptr,
+                  int32_t* col, double* w, double* R, void* work, size_t work_bytes,
+                  void* stream);
+/* eq. filter_mat on the CSR weights (all device arrays, [n] unless noted):
+   dcf_a = sum_b W_ab rho_b dc_b / (rho_a R_a).  nnz = rowptr[n] (host value,
+   used to pick the lanes per row).  dcf must not alias rho or dc. */
+int topo_edm_filter(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col,
+                    const double* w, const double* R, const double* rho, const double* dc,
+                    double* dcf, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

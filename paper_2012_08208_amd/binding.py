@@ -48,6 +48,7 @@ EXPORTED = [
     "topo_batch_workspace_size", "topo_batch_create", "topo_batch_destroy", "topo_batch_set_loads",
     "topo_batch_iterate", "topo_batch_solution", "topo_batch_tile_shape", "topo_batch_sync",
     "topo_batch_uses_graphs",
+    "topo_edm_workspace_size", "topo_edm_count", "topo_edm_fill", "topo_edm_filter",
 ]
 BATCH_REC_LEN = 6
 
@@ -121,6 +122,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_batch_tile_shape.argtypes = [vp, P(i32), P(i32), P(dbl)]
     lib.topo_batch_sync.argtypes = [vp, P(i32)]
     lib.topo_batch_uses_graphs.argtypes = [vp]
+    i64, szt = ctypes.c_int64, ctypes.c_size_t
+    lib.topo_edm_workspace_size.argtypes = [i64, P(szt)]
+    lib.topo_edm_count.argtypes = [vp, i32, i64, dbl, vp, vp, szt, vp]
+    lib.topo_edm_fill.argtypes = [vp, i32, i64, dbl, vp, vp, vp, vp, vp, szt, vp]
+    lib.topo_edm_filter.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.topo_status_string.argtypes = [i32]
     lib.topo_status_string.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -515,6 +521,68 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class EdmFilter:
+    """Distance-weighted filter over arbitrary cell midpoints: the CSR
+    weight matrix and its row sums are built on the device once
+    (``topo_edm_count`` then ``topo_edm_fill``); ``filter`` is the
+    per-iteration ``topo_edm_filter``."""
+
+    def __init__(self, mid, rmin: float):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        if not isinstance(mid, torch.Tensor) or mid.device.type != "cuda":
+            raise TopoError("mid must be a CUDA tensor")
+        if mid.dtype != torch.float64 or mid.dim() != 2 or mid.shape[0] not in (2, 3):
+            raise TopoError("mid must be float64 of shape [dim, n], dim 2 or 3")
+        self.mid = mid.contiguous()
+        self.dim, self.n = int(mid.shape[0]), int(mid.shape[1])
+        self.rmin = float(rmin)
+        dev = mid.device
+        self.stream = torch.cuda.current_stream(dev)
+        st = ctypes.c_void_p(self.stream.cuda_stream)
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib.topo_edm_workspace_size(self.n, ctypes.byref(nbytes)),
+               "topo_edm_workspace_size")
+        self.work = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+        wp = self.work.data_ptr() + (-self.work.data_ptr()) % 256
+        self.rowptr = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
+        _check(self.lib.topo_edm_count(ctypes.c_void_p(self.mid.data_ptr()), self.dim, self.n,
+                                       self.rmin, ctypes.c_void_p(self.rowptr.data_ptr()),
+                                       ctypes.c_void_p(wp), int(nbytes.value), st),
+               "topo_edm_count")
+        self.stream.synchronize()
+        self.nnz = int(self.rowptr[-1].item())
+        self.col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        self.w = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=dev)
+        self.R = torch.empty(max(self.n, 1), dtype=torch.float64, device=dev)
+        _check(self.lib.topo_edm_fill(ctypes.c_void_p(self.mid.data_ptr()), self.dim, self.n,
+                                      self.rmin, ctypes.c_void_p(self.rowptr.data_ptr()),
+                                      ctypes.c_void_p(self.col.data_ptr()),
+                                      ctypes.c_void_p(self.w.data_ptr()),
+                                      ctypes.c_void_p(self.R.data_ptr()), ctypes.c_void_p(wp),
+                                      int(nbytes.value), st), "topo_edm_fill")
+        self.work = None   # the hash order is needed only by the fill
+
+    def _vec(self, t, name):
+        torch = self.torch
+        if (not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64
+                or not t.is_contiguous() or t.numel() != self.n):
+            raise TopoError(f"{name} must be a contiguous float64 CUDA tensor of {self.n} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def filter(self, rho, dc, dcf):
+        if dcf.data_ptr() in (rho.data_ptr(), dc.data_ptr()):
+            raise TopoError("dcf must not alias rho or dc")
+        _check(self.lib.topo_edm_filter(self.n, self.nnz, ctypes.c_void_p(self.rowptr.data_ptr()),
+                                        ctypes.c_void_p(self.col.data_ptr()),
+                                        ctypes.c_void_p(self.w.data_ptr()),
+                                        ctypes.c_void_p(self.R.data_ptr()), self._vec(rho, "rho"),
+                                        self._vec(dc, "dc"), self._vec(dcf, "dcf"),
+                                        ctypes.c_void_p(self.stream.cuda_stream)),
+               "topo_edm_filter")
 
 
 def status_string(code: int) -> str:

@@ -132,3 +132,22 @@ def test_filter_selector_and_new_modes_validate():
     bad = (b.CProblem * 1)(b.make_problem(2, (8, 4), precond=b.TOPO_PC_GMG,
                                           filter=b.TOPO_FILTER_HELMHOLTZ))
     assert lib.topo_batch_workspace_size(bad, 1, ctypes.byref(n0)) == -1
+
+
+def test_edm_entry_points_reject_bad_arguments_on_the_host():
+    """Argument checks of topo_edm_* return before any device work."""
+    b = _lib()
+    lib = b.load_library()
+    fake = ctypes.c_void_p(256)           # never dereferenced: each call fails first
+    assert lib.topo_edm_count(fake, 4, 10, 1.0, fake, fake, 1 << 20, None) == -1
+    assert lib.topo_edm_count(fake, 3, 10, 0.0, fake, fake, 1 << 20, None) == -1
+    assert lib.topo_edm_count(fake, 3, 10, float("nan"), fake, fake, 1 << 20, None) == -1
+    assert lib.topo_edm_count(None, 3, 10, 1.0, fake, fake, 1 << 20, None) == -1
+    assert lib.topo_edm_count(fake, 3, -1, 1.0, fake, fake, 1 << 20, None) == -2
+    assert lib.topo_edm_count(fake, 3, 1 << 31, 1.0, fake, fake, 1 << 20, None) == -2
+    assert lib.topo_edm_fill(fake, 2, 10, 1.0, fake, None, fake, fake, fake, 1 << 20, None) == -1
+    assert lib.topo_edm_filter(-1, 0, fake, fake, fake, fake, fake, fake, fake, None) == -2
+    assert lib.topo_edm_filter(10, -5, fake, fake, fake, fake, fake, fake, fake, None) == -2
+    assert lib.topo_edm_filter(10, 5, fake, None, fake, fake, fake, fake, fake, None) == -1
+    assert lib.topo_edm_filter(0, 0, None, None, None, None, None, None, None, None) == 0
+    assert lib.topo_edm_workspace_size(-3, ctypes.byref(ctypes.c_size_t())) == -2
