@@ -66,15 +66,18 @@ def apply_bytes(p, precision: str) -> int:
     return p.nrhs * p.n_dofs * sv * 2 + p.n_cells * se + p.n_nodes
 
 
-def kernel_source_hash() -> str:
+APPLY_SOURCES = ("apply.hip", "element.h", "common.h", "shared_dev.h")
+
+
+def kernel_source_hash(files=APPLY_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in ("apply.hip", "element.h", "common.h", "shared_dev.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2012_08208_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(wl: str, precision: str):
+def load_traffic(wl: str, precision: str, files=APPLY_SOURCES):
     path = os.path.join(ROOT, "profiles", "apply_traffic.json")
     if not os.path.exists(path):
         return None
@@ -84,7 +87,7 @@ def load_traffic(wl: str, precision: str):
         return None
     key = f"{wl}:{precision}"
     rec = d.get(key)
-    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+    if not rec or rec.get("kernel_hash") != kernel_source_hash(files):
         return None
     return rec.get("bytes_per_launch")
 
@@ -304,7 +307,8 @@ def bench_edm(args):
                    "nnz": e.nnz, "build_ms": build_ms, "build_wall_s": build_wall},
         "roofline": {"kernel": "edm_filter_kernel<64>", "bound": "hbm", "achieved": gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": alg},
+                     "traffic": load_traffic("edm3d", "f64", ("edm.hip",)),
+                     "algorithmic_bytes_per_launch": alg},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))

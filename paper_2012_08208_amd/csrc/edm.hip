@@ -208,8 +208,13 @@ __global__ __launch_bounds__(256) void edm_rows_kernel(Cloud c, const int32_t* _
     rowcnt[a] = cnt;
 }
 
-// Step 5: G lanes per row, G in {16, 32, 64}; rows are taken in a
-// grid-stride loop, and a row's lanes always share the loop condition.
+// Step 5: G lanes per row, G in {16, 32, 64}.  Rows are split into 8
+// contiguous ranges, one per XCD (consecutive blocks go to consecutive
+// XCDs), so each XCD's L2 holds the rho and s window of its own range only;
+// within a range, rows are taken in a block-stride loop, and a row's lanes
+// always share the loop condition.  Column indices and weights are read
+// once, with non-temporal loads, so that they do not evict that window.
+// gridDim.x is a multiple of 8.
 template <int G>
 __global__ __launch_bounds__(256) void edm_filter_kernel(int64_t n, const int64_t* __restrict__ rowptr,
                                                          const int32_t* __restrict__ col,
@@ -220,13 +225,28 @@ __global__ __launch_bounds__(256) void edm_filter_kernel(int64_t n, const int64_
                                                          double* __restrict__ dcf) {
   constexpr int kRows = 256 / G;
   const int lane = threadIdx.x & (G - 1);
-  for (int64_t g = (int64_t)blockIdx.x * kRows + threadIdx.x / G; g < n;
-       g += (int64_t)gridDim.x * kRows) {
+  const int64_t xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int64_t per_xcd = gridDim.x >> 3;
+  const int64_t chunk = (n + 7) >> 3;
+  const int64_t r1 = min(n, (xcd + 1) * chunk);
+  for (int64_t g = xcd * chunk + q * kRows + threadIdx.x / G; g < r1; g += per_xcd * kRows) {
     double acc = 0.0;
     const int64_t k1 = rowptr[g + 1];
-    for (int64_t k = rowptr[g] + lane; k < k1; k += G) {
-      const int32_t b = col[k];
-      acc += w[k] * (rho[b] * dc[b]);
+    // four entries per lane in flight: their column and weight loads are
+    // issued together, then the gathers; entries past the row's end read
+    // the row's own cell with a zero weight
+    for (int64_t k = rowptr[g] + lane; k < k1; k += 4 * G) {
+      int32_t b[4];
+      double wv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t kk = k + u * G;
+        const bool ok = kk < k1;
+        b[u] = ok ? __builtin_nontemporal_load(col + kk) : (int32_t)g;
+        wv[u] = ok ? __builtin_nontemporal_load(w + kk) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += wv[u] * (rho[b[u]] * dc[b[u]]);
     }
 #pragma unroll
     for (int m = G / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, G);
@@ -320,9 +340,11 @@ int topo_edm_filter(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t
   if (!rowptr || !R || !rho || !dc || !dcf || (nnz > 0 && (!col || !w))) return TOPO_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
   const double avg = double(nnz) / double(n);
-  // 65536 blocks of 256 threads keep every CU busy; longer inputs loop
+  // up to 65536 blocks of 256 threads (a multiple of 8: one share per XCD);
+  // longer inputs loop
   auto blocks = [&](int rows_per_block) {
-    return (int)std::min<int64_t>((n + rows_per_block - 1) / rows_per_block, 65536);
+    const int64_t b = std::min<int64_t>((n + rows_per_block - 1) / rows_per_block, 65536);
+    return (int)((b + 7) / 8 * 8);
   };
   if (avg >= 48.0)
     edm_filter_kernel<64><<<blocks(4), 256, 0, st>>>(n, rowptr, col, w, R, rho, dc, dcf);
