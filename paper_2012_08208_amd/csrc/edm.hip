@@ -224,6 +224,7 @@ __global__ __launch_bounds__(256) void edm_filter_kernel(int64_t n, const int64_
                                                          const double* __restrict__ dc,
                                                          double* __restrict__ dcf) {
   constexpr int kRows = 256 / G;
+  constexpr int kU = 8;
   const int lane = threadIdx.x & (G - 1);
   const int64_t xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
   const int64_t per_xcd = gridDim.x >> 3;
@@ -232,21 +233,21 @@ __global__ __launch_bounds__(256) void edm_filter_kernel(int64_t n, const int64_
   for (int64_t g = xcd * chunk + q * kRows + threadIdx.x / G; g < r1; g += per_xcd * kRows) {
     double acc = 0.0;
     const int64_t k1 = rowptr[g + 1];
-    // four entries per lane in flight: their column and weight loads are
+    // kU entries per lane in flight: their column and weight loads are
     // issued together, then the gathers; entries past the row's end read
     // the row's own cell with a zero weight
-    for (int64_t k = rowptr[g] + lane; k < k1; k += 4 * G) {
-      int32_t b[4];
-      double wv[4];
+    for (int64_t k = rowptr[g] + lane; k < k1; k += kU * G) {
+      int32_t b[kU];
+      double wv[kU];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kU; ++u) {
         const int64_t kk = k + u * G;
         const bool ok = kk < k1;
         b[u] = ok ? __builtin_nontemporal_load(col + kk) : (int32_t)g;
         wv[u] = ok ? __builtin_nontemporal_load(w + kk) : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc += wv[u] * (rho[b[u]] * dc[b[u]]);
+      for (int u = 0; u < kU; ++u) acc += wv[u] * (rho[b[u]] * dc[b[u]]);
     }
 #pragma unroll
     for (int m = G / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, G);
