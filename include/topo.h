@@ -8,9 +8,9 @@
  *   solve        K(rho) u = f                 (Sec. 3.1, eq. fe_form; Sec. 2, eq. simp)
  *   sensitivity  c = f^T u and dc/drho_e      (Sec. 3.2, sensitivity of f)
  *   filter       s~ = W (rho s) / (rho R)     (Sec. 3.2.2, eq. filter, eq. filter_cond;
- *                                             Sec. 4.4, eq. filter_mat)
+ *                                             Sec. 4.5, eq. filter_mat)
  *   oc_update    rho_new by the OC rule       (Sec. 3.2, eq. kkt, eq. update; Sec. 3.2.1)
- *   iterate      the loop of all four         (Sec. 4.3 and the Appendix code)
+ *   iterate      the loop of all four         (Sec. 4.3-4.5 and the Appendix code)
  *
  * Conventions (shared by every entry point)
  * -----------------------------------------
@@ -79,6 +79,10 @@ enum {
   TOPO_S_LEARNED_FALLBACK = 2, /* the learned-preconditioner CG did not converge
                                   within its cap; multigrid PCG finished the
                                   solve (outputs valid) */
+  TOPO_S_OC_INEXACT = 3,    /* the OC multiplier search ended (pass budget, or
+                               no FP64 point left in its bracket) with the
+                               volume more than 1e-12 N_c from volfrac N_c;
+                               the design is valid, its volume inexact */
   TOPO_S_NUMERIC = -5,      /* NaN/Inf or CG breakdown (p^T K p <= 0) */
   TOPO_S_OC_INFEASIBLE = -6 /* volfrac*N outside [sum lo, sum hi] */
 };
@@ -296,6 +300,17 @@ int topo_timing_read_net(topo_ctx* ctx, int64_t* passes /* host */, double* tota
    cleared. */
 int topo_sync(topo_ctx* ctx, int* device_status /* host */);
 
+/* Host-only: the filter's neighbourhood of an interior cell of each cell
+   class (2D: 2 classes, 4 with TOPO_SPLIT_ALT_ROWS (even/odd rows); 3D:
+   the 6 Kuhn tetrahedra), i.e. the number of cells b with
+   |x_a - x_b| < rmin (Sec. 3.2.2, eq. filter), self included.  These are the
+   tap lists the filter kernels walk; every list is stored whole (the
+   workspace grows with rmin).  ntaps: host [8], zero past *nclasses.
+   Returns TOPO_E_INVALID for dim not 2 or 3, rmin outside (0, 16] or a
+   bad split.  Touches no GPU. */
+int topo_filter_taps(int32_t dim, int32_t split, double rmin, int32_t* ntaps /* host [8] */,
+                     int32_t* nclasses /* host */);
+
 /* Static description of a status or error code. */
 const char* topo_status_string(int code);
 
@@ -384,7 +399,7 @@ int topo_precond_stats(topo_ctx* ctx, int* fcg_iters, int* fallback);
 
 /* ------------------------------------------------------------------------
  * Batched 2D instances: many independent SIMP problems of different sizes
- * advanced together (the loop of Sec. 4.3 and the Appendix for every
+ * advanced together (the loop of Sec. 4.3-4.5 and the Appendix for every
  * instance).  Every instance has its own grid, loads, supports, volume
  * fraction, filter radius and convergence; kernels are batched across
  * instances and one SIMP round for all of them is three captured HIP graphs
@@ -437,7 +452,7 @@ int topo_batch_uses_graphs(topo_batch* batch);
 
 /* ------------------------------------------------------------------------
  * Distance-weighted filter over arbitrary cell midpoints (unstructured
- * meshes): Sec. 3.2.2 (eq. filter, eq. filter_cond) and Sec. 4.4
+ * meshes): Sec. 3.2.2 (eq. filter, eq. filter_cond) and Sec. 4.5
  * (eq. filter_mat), with the weight matrix built once, outside the
  * iteration loop, by evaluating the Euclidean distance matrix in chunks
  * (Sec. 6.2).  The chunks are the cells of a spatial hash of side rmin, so

@@ -5,16 +5,16 @@ iteration of arXiv 2012.08208 ("A 55-line code for large-scale parallel
 topology optimization in 2D and 3D"):
 
 * ``mesh``  -- structured P1 simplex meshes built from explicit coordinates
-  (Section 3.1 and Section 4.2.1; three-dimensional boxes, Section 5.1);
+  (Section 3.1 and Section 4.3.1; three-dimensional boxes, Section 5.1);
 * ``fem``   -- element stiffness from coordinates, SIMP interpolation,
   assembly, Dirichlet elimination, direct solve, compliance and its
   sensitivity (Section 2, eq. str_energy, eq. simp; Section 3.1, eq.
   fe_form; Section 3.2, sensitivity of f);
 * ``filt``  -- the distance-weighted sensitivity filter (Section 3.2.2,
-  eq. filter and eq. filter_cond; Section 4.4, eq. filter_mat);
+  eq. filter and eq. filter_cond; Section 4.5, eq. filter_mat);
 * ``oc``    -- the optimality-criteria update with bisection on the
   Lagrange multiplier (Section 3.2, eq. kkt and eq. update; Section 3.2.1);
-* ``simp``  -- the iteration loop (Section 4.3 and the Appendix code);
+* ``simp``  -- the iteration loop (Section 4.3-4.5 and the Appendix code);
 * ``net``   -- the convolutional preconditioner network of this library
   (not in the paper): forward, backward, loss and Adam, in FP64 with
   optional BF16 rounding at the points where the kernels store.

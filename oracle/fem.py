@@ -3,7 +3,7 @@
 * Material law: isotropic linear elasticity with stress
   sigma = lambda tr(eps) I + 2 mu eps and strain-energy density
   psi = lambda/2 tr(eps)^2 + mu tr(eps^2) (Section 2, eq. str_energy;
-  Section 4.1, eq. stress and eq. energy).  Here it is written in Voigt
+  Section 4.2, eq. stress and eq. energy).  Here it is written in Voigt
   form with engineering shear strains.  Two-dimensional problems use plane
   stress with (E, nu); the "paper mode" uses the listing's Lame constants
   mu = 0.4, lambda = 0.6 directly.
@@ -12,9 +12,9 @@
   itself uses E_e = rho_e^p (paper mode, Emin = 0).
 * Discrete form (Section 3.1, eq. fe_form): P1 Galerkin, so the strain is
   constant per cell and K_e = |T_e| B_e^T D B_e exactly.
-* Dirichlet conditions (Section 4.2.2) are imposed by eliminating the
+* Dirichlet conditions (Section 4.3.2) are imposed by eliminating the
   fixed DOFs; the reduced system is solved with a sparse LU factorisation,
-  the paper's default solver (Section 4.2.4).
+  the paper's default solver (Section 4.3.4).
 * Compliance c = sum_r f_r^T u_r and its exact derivative
   dc/drho_e = -p rho_e^(p-1) (E0 - Emin) sum_r u_{r,e}^T K0_e u_{r,e}
   (Section 3.2: sensitivity of f; the paper's per-cell value is this

@@ -1,6 +1,6 @@
 """Distance-weighted sensitivity filter (test oracle, FP64).
 
-Section 3.2.2 (eq. filter, eq. filter_cond) and Section 4.4 (eq. filter_mat):
+Section 3.2.2 (eq. filter, eq. filter_cond) and Section 4.5 (eq. filter_mat):
 with cell midpoints x_a, weights W_ab = max(0, rmin - |x_a - x_b|_2) and
 row sums R_a = sum_b W_ab, the filtered sensitivity is
 

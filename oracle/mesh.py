@@ -1,7 +1,7 @@
 """Structured P1 simplex meshes with explicit coordinates (test oracle).
 
 Section 3.1 discretises the body with three-noded triangles (2D) or
-four-noded tetrahedra (3D) and one density value per cell; Section 4.2.1
+four-noded tetrahedra (3D) and one density value per cell; Section 4.3.1
 builds the 2D mesh from ``nelx x nely`` unit rectangles, each cut into two
 triangles, and Section 5.1 uses a box mesh for 3D.  The paper leaves the cut
 rule to the mesh generator, so this module fixes it:

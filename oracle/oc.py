@@ -14,7 +14,7 @@ the midpoint is no longer strictly inside the bracket in FP64, so that the
 volume constraint holds to rounding.  If the volume at the upper end still
 exceeds the target, the upper end is multiplied by 10 until it does not.
 The returned design is the one evaluated at the last midpoint, and the
-change is the max-norm of rho_new - rho (Section 4.3 / Appendix loop).
+change is the max-norm of rho_new - rho (Section 4.4 / Appendix loop).
 
 Passive cells (Section 5.4): cells marked void are set to the lower density
 bound (the paper writes 0.001, its rho_min) and cells marked solid to 1.

@@ -1,6 +1,6 @@
 """The SIMP iteration loop (test oracle, FP64).
 
-Section 4.3 and the Appendix code: starting from rho = volfrac in every
+Section 4.3-4.5 and the Appendix code: starting from rho = volfrac in every
 cell, each iteration (1) solves K(rho) u = f, (2) evaluates the compliance
 and its sensitivity, (3) filters the sensitivity, (4) updates rho by the
 optimality criteria with bisection, and (5) records the change

@@ -33,6 +33,7 @@ TOPO_PC_JACOBI = 0
 TOPO_PC_GMG = 1
 TOPO_PC_LEARNED = 2
 TOPO_S_LEARNED_FALLBACK = 2
+TOPO_S_OC_INEXACT = 3
 SOLVE_INFO_LEN = 6
 LOG_LEN = 8
 
@@ -40,7 +41,7 @@ EXPORTED = [
     "topo_workspace_size", "topo_create", "topo_destroy", "topo_set_loads", "topo_solve",
     "topo_sensitivity", "topo_filter", "topo_oc_update", "topo_iterate", "topo_apply",
     "topo_apply_f32", "topo_set_passive", "topo_density_filter", "topo_diagonal", "topo_filter_rowsums", "topo_timing_enable", "topo_timing_read",
-    "topo_sync", "topo_status_string",
+    "topo_sync", "topo_status_string", "topo_filter_taps",
     "topo_precond_num_params", "topo_precond_workspace_size", "topo_precond_attach",
     "topo_precond_set_weights", "topo_precond_get_weights", "topo_precond_config",
     "topo_precond_apply", "topo_precond_backward", "topo_precond_train_step",
@@ -127,6 +128,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_edm_count.argtypes = [vp, i32, i64, dbl, vp, vp, szt, vp]
     lib.topo_edm_fill.argtypes = [vp, i32, i64, dbl, vp, vp, vp, vp, vp, szt, vp]
     lib.topo_edm_filter.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.topo_filter_taps.argtypes = [i32, i32, dbl, P(ctypes.c_int32), P(ctypes.c_int32)]
     lib.topo_status_string.argtypes = [i32]
     lib.topo_status_string.restype = ctypes.c_char_p
     for name in EXPORTED:

@@ -1,5 +1,5 @@
 // C ABI entry points: argument checks, workspace carving and the host-side
-// drivers of the SIMP loop (Sec. 4.3 and the Appendix code: solve ->
+// drivers of the SIMP loop (Sec. 4.3-4.5 and the Appendix code: solve ->
 // sensitivity -> filter -> OC -> change).
 #include <math.h>
 #include <stdlib.h>
@@ -167,8 +167,10 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
   L.partials = take((size_t)nblk * 16 * 8);
   L.scal = take(sizeof(DevScalars));
   L.R = take((size_t)g.nc * 8);
-  L.taps = take((size_t)8 * kMaxFilterTaps * sizeof(FilterTap) + 64);
-  L.ttaps = g.dim == 3 ? take((size_t)6 * kMaxFilterTaps * sizeof(TiledTap)) : 0;
+  // tap lists of every class, as long as the longest (filter_taps_host)
+  const size_t tst = (size_t)filter_tap_stride(g.dim, g.split, p->rmin);
+  L.taps = take((size_t)8 * tst * sizeof(FilterTap) + 64);
+  L.ttaps = g.dim == 3 ? take((size_t)6 * tst * sizeof(TiledTap)) : 0;
   L.qsoa = take((size_t)g.nc * 8);
   L.dc = take((size_t)g.nc * 8);
   L.dcf = take((size_t)g.nc * 8);
@@ -685,6 +687,19 @@ int topo_sync(topo_ctx* c, int* device_status) {
   return TOPO_OK;
 }
 
+int topo_filter_taps(int32_t dim, int32_t split, double rmin, int32_t* ntaps, int32_t* nclasses) {
+  if ((dim != 2 && dim != 3) || !(rmin > 0.0 && rmin <= 16.0) || !ntaps || !nclasses)
+    return TOPO_E_INVALID;
+  if (dim == 2 && split != TOPO_SPLIT_ALT_ROWS && split != TOPO_SPLIT_UNIFORM) return TOPO_E_INVALID;
+  std::vector<FilterTap> tab;
+  int nt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int st = 0;
+  const int ncls = filter_taps_host(dim, dim == 2 ? split : TOPO_SPLIT_UNIFORM, rmin, tab, nt, &st);
+  for (int k = 0; k < 8; ++k) ntaps[k] = k < ncls ? nt[k] : 0;
+  *nclasses = ncls;
+  return TOPO_OK;
+}
+
 const char* topo_status_string(int code) {
   switch (code) {
     case TOPO_OK: return "ok";
@@ -697,6 +712,7 @@ const char* topo_status_string(int code) {
     case TOPO_S_LEARNED_FALLBACK: return "learned-preconditioner CG fell back to multigrid PCG";
     case TOPO_S_NUMERIC: return "non-finite value or CG breakdown";
     case TOPO_S_OC_INFEASIBLE: return "OC volume target infeasible";
+    case TOPO_S_OC_INEXACT: return "OC multiplier search stopped before the volume constraint was met";
     default: return "unknown status";
   }
 }

@@ -1,5 +1,5 @@
 // Batched SIMP loop for many independent 2D problems of different sizes
-// (Sec. 4.3 and the Appendix loop, run for every instance at once).
+// (Sec. 4.3-4.5 and the Appendix loop, run for every instance at once).
 //
 // Every instance keeps its own grid, multigrid hierarchy, CG scalars, filter
 // taps, OC multiplier and convergence flags; the kernels are batched across
@@ -62,6 +62,7 @@ struct BInst {
   int split_uniform, alt, nclasses;
   const FilterTap* taps;
   const int* ntaps;
+  int tap_stride;   // entries per class list
   int jd0, jd1;            // fine DOF jobs
   int jc0, jc1;            // fine cell jobs
   int js0, js1;            // fine square jobs
@@ -456,8 +457,8 @@ __global__ void b_filter(const BJob* jobs, const BInst* I, const BState* st, int
   double* out = rowsum ? in.R : in.dcf;
   for (int t = threadIdx.x; t < j.count; t += blockDim.x)
     for (int cls = 0; cls < 2; ++cls)
-      filter_cell(j.begin + t, cls, out, in.qcls, in.rho, in.R, in.taps, in.ntaps, 2, in.nx, in.ny, 1,
-                  2, in.alt, rowsum);
+      filter_cell(j.begin + t, cls, out, in.qcls, in.rho, in.R, in.taps, in.ntaps, in.tap_stride, 2,
+                  in.nx, in.ny, 1, 2, in.alt, rowsum);
 }
 
 // ------------------------------------------------------------------ OC
@@ -547,7 +548,7 @@ __global__ void b_oc_final_fin(const BInst* I, BState* st, const double* partial
   __shared__ double tot[2];
   reduce_partials_range<1, 1>(partials, I[i].jc0, I[i].jc1, tot);
   if (threadIdx.x == 0) {
-    oc_final_finish(tot, I[i].eta, &st[i].oc, nullptr);
+    oc_final_finish(tot, I[i].eta, I[i].nc, &st[i].oc, nullptr, &st[i].status);
     st[i].change = st[i].oc.change;
     st[i].iters += 1;
     st[i].cg_last = st[i].pcg.iters;
@@ -775,7 +776,8 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
     in.split_uniform = p.split2d == TOPO_SPLIT_UNIFORM;
     in.alt = !in.split_uniform;
     in.nclasses = in.alt ? 4 : 2;
-    in.taps = cv.take<FilterTap>((size_t)4 * kMaxFilterTaps);
+    in.tap_stride = filter_tap_stride(2, in.alt ? TOPO_SPLIT_ALT_ROWS : TOPO_SPLIT_UNIFORM, p.rmin);
+    in.taps = cv.take<FilterTap>((size_t)4 * in.tap_stride);
     in.ntaps = cv.take<int>(8);
     in.slot0 = (int)slots.size();
     const int L = (int)plans[i].size();
@@ -950,8 +952,9 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
     for (int i = 0; i < count; ++i) {
       std::vector<FilterTap> tab;
       int nt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int st = 0;
       filter_taps_host(2, probs[i].split2d == TOPO_SPLIT_UNIFORM ? TOPO_SPLIT_UNIFORM : TOPO_SPLIT_ALT_ROWS,
-                       probs[i].rmin, tab, nt);
+                       probs[i].rmin, tab, nt, &st);
       (void)hipMemcpy((void*)inst[i].taps, tab.data(), tab.size() * sizeof(FilterTap), hipMemcpyHostToDevice);
       (void)hipMemcpy((void*)inst[i].ntaps, nt, sizeof(nt), hipMemcpyHostToDevice);
       const std::vector<std::vector<uint8_t>>& ms = (*masks_in)[i];

@@ -1,5 +1,5 @@
 // Distance-weighted sensitivity filter over arbitrary cell midpoints
-// (Sec. 3.2.2, eq. filter and eq. filter_cond; Sec. 4.4, eq. filter_mat).
+// (Sec. 3.2.2, eq. filter and eq. filter_cond; Sec. 4.5, eq. filter_mat).
 //
 // The paper forms the weights W_ab = max(0, rmin - |x_a - x_b|) from the
 // Euclidean distance matrix of the midpoints, computes W and its row sums

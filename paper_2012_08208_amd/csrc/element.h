@@ -1,5 +1,5 @@
 // Element-level arithmetic of the P1 Galerkin operator (Sec. 3.1, eq. fe_form)
-// for the isotropic law sigma = lambda tr(eps) I + 2 mu eps (Sec. 4.1,
+// for the isotropic law sigma = lambda tr(eps) I + 2 mu eps (Sec. 4.2,
 // eq. stress).  P1 strains are constant per cell, so the element force is
 // f_a = |T| E sigma(u) grad N_a exactly.
 //

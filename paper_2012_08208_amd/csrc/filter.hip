@@ -1,5 +1,5 @@
 // Distance-weighted sensitivity filter in stencil form (Sec. 3.2.2, eq. filter
-// and eq. filter_cond; Sec. 4.4, eq. filter_mat):
+// and eq. filter_cond; Sec. 4.5, eq. filter_mat):
 //   dcf_a = sum_b W_ab rho_b dc_b / (rho_a R_a),
 //   W_ab  = max(0, rmin - |x_a - x_b|),   R_a = sum_b W_ab.
 // On the structured grid W_ab depends only on the two cell classes and the
@@ -23,12 +23,14 @@
 
 namespace topo {
 
-// Host tap table of every cell class: (offset, neighbour class, weight),
-// kMaxFilterTaps entries per class; returns the number of classes.
-int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& tab, int* ntaps) {
+// Host tap table of every cell class: (offset, neighbour class, weight).
+// Every tap with a positive weight is kept; the classes' lists are laid out
+// *stride entries apart, where *stride is the longest list rounded up to a
+// multiple of 16 (at least 16).  Returns the number of classes.
+int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& tab, int* ntaps,
+                     int* stride) {
   const int reach = (int)ceil(rmin) + 1;
-  int nclasses = 0;
-  tab.clear();
+  std::vector<std::vector<FilterTap>> lists;
   if (dim == 3) {
     static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
     double cen[6][3];
@@ -37,9 +39,8 @@ int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& ta
       cen[t][perm[t][1]] = 0.5;
       cen[t][perm[t][2]] = 0.25;
     }
-    nclasses = 6;
-    for (int ta = 0; ta < 6; ++ta) {
-      int n = 0;
+    lists.resize(6);
+    for (int ta = 0; ta < 6; ++ta)
       for (int dk = -reach; dk <= reach; ++dk)
         for (int dj = -reach; dj <= reach; ++dj)
           for (int di = -reach; di <= reach; ++di)
@@ -48,25 +49,18 @@ int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& ta
               const double dy = dj + cen[tb][1] - cen[ta][1];
               const double dz = dk + cen[tb][2] - cen[ta][2];
               const double w = rmin - sqrt(dx * dx + dy * dy + dz * dz);
-              if (w > 0.0 && n < kMaxFilterTaps) {
-                tab.push_back({di, dj, dk, tb, w});
-                ++n;
-              }
+              if (w > 0.0) lists[ta].push_back({di, dj, dk, tb, w});
             }
-      ntaps[ta] = n;
-      tab.resize((size_t)(ta + 1) * kMaxFilterTaps);
-    }
   } else {
     // centroids (relative to the square corner) of the two triangles of
     // diagonal A and diagonal B
     const double cA[2][2] = {{2.0 / 3.0, 1.0 / 3.0}, {1.0 / 3.0, 2.0 / 3.0}};
     const double cB[2][2] = {{1.0 / 3.0, 1.0 / 3.0}, {2.0 / 3.0, 2.0 / 3.0}};
     const bool alt = split == TOPO_SPLIT_ALT_ROWS;
-    nclasses = alt ? 4 : 2;
-    for (int cls = 0; cls < nclasses; ++cls) {
+    lists.resize(alt ? 4 : 2);
+    for (int cls = 0; cls < (int)lists.size(); ++cls) {
       const int ta = cls & 1, par = cls >> 1;  // row parity of the target
       const double* ca = (alt && par) ? cB[ta] : cA[ta];
-      int n = 0;
       for (int dj = -reach; dj <= reach; ++dj)
         for (int di = -reach; di <= reach; ++di)
           for (int tb = 0; tb < 2; ++tb) {
@@ -75,16 +69,27 @@ int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& ta
             const double dx = di + cb[0] - ca[0];
             const double dy = dj + cb[1] - ca[1];
             const double w = rmin - sqrt(dx * dx + dy * dy);
-            if (w > 0.0 && n < kMaxFilterTaps) {
-              tab.push_back({di, dj, 0, tb, w});
-              ++n;
-            }
+            if (w > 0.0) lists[cls].push_back({di, dj, 0, tb, w});
           }
-      ntaps[cls] = n;
-      tab.resize((size_t)(cls + 1) * kMaxFilterTaps);
     }
   }
-  return nclasses;
+  size_t longest = 0;
+  for (const auto& l : lists) longest = std::max(longest, l.size());
+  const int st = (int)std::max<size_t>(16, (longest + 15) / 16 * 16);
+  tab.assign((size_t)lists.size() * st, FilterTap{0, 0, 0, 0, 0.0});
+  for (size_t cls = 0; cls < lists.size(); ++cls) {
+    ntaps[cls] = (int)lists[cls].size();
+    std::copy(lists[cls].begin(), lists[cls].end(), tab.begin() + cls * st);
+  }
+  if (stride) *stride = st;
+  return (int)lists.size();
+}
+
+int filter_tap_stride(int dim, int split, double rmin) {
+  std::vector<FilterTap> tab;
+  int nt[8], st = 0;
+  filter_taps_host(dim, split, rmin, tab, nt, &st);
+  return st;
 }
 
 // The 3D filter on LDS boxes: a block owns kFtX x kFtY x kFtZ cubes (all six
@@ -99,24 +104,26 @@ constexpr int kFtV = kFtIX * kFtIY * kFtIZ;
 
 void build_filter_taps(Ctx* c) {
   std::vector<FilterTap> tab;
-  c->nclasses = filter_taps_host(c->g.dim, c->g.split, c->prob.rmin, tab, c->ntaps);
+  int st = 0;
+  c->nclasses = filter_taps_host(c->g.dim, c->g.split, c->prob.rmin, tab, c->ntaps, &st);
+  // the workspace was sized for exactly this stride (filter_tap_stride)
+  c->tap_stride = st;
   (void)hipMemcpy(c->taps, tab.data(), tab.size() * sizeof(FilterTap), hipMemcpyHostToDevice);
-  (void)hipMemcpy(c->taps + (size_t)8 * kMaxFilterTaps, c->ntaps, sizeof(c->ntaps),
-                  hipMemcpyHostToDevice);
+  (void)hipMemcpy(c->taps + (size_t)8 * st, c->ntaps, sizeof(c->ntaps), hipMemcpyHostToDevice);
   c->filter_tiled = false;
   if (c->g.dim == 3 && c->ttaps) {
     int reach = 0;
     for (int t = 0; t < 6; ++t)
       for (int s = 0; s < c->ntaps[t]; ++s) {
-        const FilterTap& f = tab[(size_t)t * kMaxFilterTaps + s];
+        const FilterTap& f = tab[(size_t)t * st + s];
         reach = std::max(reach, std::max(std::abs(f.di), std::max(std::abs(f.dj), std::abs(f.dk))));
       }
     if (reach <= kFtH) {
-      std::vector<TiledTap> tt((size_t)6 * kMaxFilterTaps, TiledTap{0, 0, 0.0});
+      std::vector<TiledTap> tt((size_t)6 * st, TiledTap{0, 0, 0.0});
       for (int t = 0; t < 6; ++t)
         for (int s = 0; s < c->ntaps[t]; ++s) {
-          const FilterTap& f = tab[(size_t)t * kMaxFilterTaps + s];
-          tt[(size_t)t * kMaxFilterTaps + s] =
+          const FilterTap& f = tab[(size_t)t * st + s];
+          tt[(size_t)t * st + s] =
               TiledTap{((f.dk * kFtIY + f.dj) * kFtIX + f.di) * 6 + f.tb, 0, f.w};
         }
       (void)hipMemcpy(c->ttaps, tt.data(), tt.size() * sizeof(TiledTap), hipMemcpyHostToDevice);
@@ -146,8 +153,9 @@ __global__ __launch_bounds__(256) void filter3d_tiled_kernel(double* out, const 
                                                              const double* __restrict__ dc,
                                                              const double* __restrict__ R,
                                                              const TiledTap* __restrict__ tt,
-                                                             const int* __restrict__ ntaps, int nx,
-                                                             int ny, int nz, int mode) {
+                                                             const int* __restrict__ ntaps,
+                                                             int stride, int nx, int ny, int nz,
+                                                             int mode) {
   __shared__ double q[kFtV * 6];
   const int tid = threadIdx.x;
   const int gx = (nx + kFtX - 1) / kFtX, gy = (ny + kFtY - 1) / kFtY;
@@ -175,7 +183,7 @@ __global__ __launch_bounds__(256) void filter3d_tiled_kernel(double* out, const 
 #pragma unroll 1
   for (int r = 0; r < 3; ++r) {
     const int t = half + 2 * r;   // uniform over the wave
-    const TiledTap* tp = tt + (long)t * kMaxFilterTaps;
+    const TiledTap* tp = tt + (long)t * stride;
     const int nt = ntaps[t];
     double acc = 0.0;
     for (int s = 0; s < nt; ++s) acc += tp[s].w * q[base + tp[s].off];
@@ -201,12 +209,14 @@ __global__ __launch_bounds__(256) void filter_kernel(double* out, const double* 
                                                      const double* __restrict__ rho,
                                                      const double* __restrict__ R,
                                                      const FilterTap* __restrict__ taps,
-                                                     const int* __restrict__ ntaps, int dim, int nx,
-                                                     int ny, int nz, int ncls, int alt, int out_mode) {
+                                                     const int* __restrict__ ntaps, int stride,
+                                                     int dim, int nx, int ny, int nz, int ncls,
+                                                     int alt, int out_mode) {
   const long nblk = (long)nx * ny * nz;
   const long h = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= nblk) return;
-  filter_cell(h, blockIdx.y, out, q, rho, R, taps, ntaps, dim, nx, ny, nz, ncls, alt, out_mode);
+  filter_cell(h, blockIdx.y, out, q, rho, R, taps, ntaps, stride, dim, nx, ny, nz, ncls, alt,
+              out_mode);
 }
 
 static void filter_launch(Ctx* c, const double* rho, const double* dc, double* out, int mode) {
@@ -215,8 +225,8 @@ static void filter_launch(Ctx* c, const double* rho, const double* dc, double* o
     const long tiles = (long)((g.nx + kFtX - 1) / kFtX) * ((g.ny + kFtY - 1) / kFtY) *
                        ((g.nz + kFtZ - 1) / kFtZ);
     filter3d_tiled_kernel<<<(unsigned)tiles, 256, 0, c->stream>>>(
-        out, rho, dc, c->R, c->ttaps, (const int*)(c->taps + (size_t)8 * kMaxFilterTaps), g.nx, g.ny,
-        g.nz, mode);
+        out, rho, dc, c->R, c->ttaps, (const int*)(c->taps + (size_t)8 * c->tap_stride),
+        c->tap_stride, g.nx, g.ny, g.nz, mode);
     return;
   }
   const int ncls = g.dim == 2 ? 2 : 6;
@@ -227,8 +237,8 @@ static void filter_launch(Ctx* c, const double* rho, const double* dc, double* o
       c->qsoa, rho, dc, c->R, mode, ncell, ncls, nblk);
   dim3 grid((unsigned)((nblk + 255) / 256), ncls);
   filter_kernel<<<grid, 256, 0, c->stream>>>(out, c->qsoa, rho, c->R, c->taps,
-                                             (const int*)(c->taps + (size_t)8 * kMaxFilterTaps),
-                                             g.dim, g.nx, g.ny, nz, ncls,
+                                             (const int*)(c->taps + (size_t)8 * c->tap_stride),
+                                             c->tap_stride, g.dim, g.nx, g.ny, nz, ncls,
                                              g.split == TOPO_SPLIT_ALT_ROWS,
                                              mode == FM_SENS ? 0 : mode == FM_DENSITY ? 2 : 1);
 }

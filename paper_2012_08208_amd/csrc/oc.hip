@@ -10,8 +10,9 @@
 // Newton steps on V(mu) - target safeguarded by a bisection bracket: a pass
 // reduces V and its slope S = sum over unclamped cells of a_e; once the
 // clamped set is right, one Newton step lands on the root to rounding.
-// Each pass is one kernel with a fused single-pass reduction; the host
-// polls the done flag between batches of passes.
+// Each pass is one kernel with a fused single-pass reduction.  A fixed
+// budget of passes is queued without any host wait (the call is
+// stream-asynchronous); passes after the root return at once.
 //
 // Passive cells (Sec. 5.4: zones of fixed density) take lo_e = hi_e = their
 // fixed value (rho_min for a void, 1 for solid material) in every
@@ -128,11 +129,11 @@ __global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict_
   block_partials<1, 1>(acc, mx, partials);
 }
 
-__global__ void oc_final_fin(const double* partials, long nb, double eta, OcState* st,
-                             double* scalars) {
+__global__ void oc_final_fin(const double* partials, long nb, long nc, double eta, OcState* st,
+                             double* scalars, int* status) {
   __shared__ double tot[2];
   reduce_partials<1, 1>(partials, nb, tot);
-  if (threadIdx.x == 0) oc_final_finish(tot, eta, st, scalars);
+  if (threadIdx.x == 0) oc_final_finish(tot, eta, nc, st, scalars, status);
 }
 
 void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars) {
@@ -146,18 +147,14 @@ void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, do
   hipStream_t s = c->stream;
   oc_init_kernel<<<nb, 256, 0, s>>>(rho, dcf, a, nc, p.move, p.eta, p.rho_min, pas, vw, c->partials);
   oc_init_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, p.volfrac, st, &c->scal->status);
-  const int batch = 6;
-  for (int b = 0; b < 40; ++b) {
-    for (int k = 0; k < batch; ++k) {
-      oc_pass_kernel<<<nb, 256, 0, s>>>(rho, a, nc, p.move, p.rho_min, pas, vw, c->partials, st);
-      oc_pass_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, st);
-    }
-    (void)hipMemcpyAsync((void*)&c->pinned[2], &st->done, sizeof(int), hipMemcpyDeviceToHost, s);
-    (void)hipStreamSynchronize(s);
-    if (c->pinned[2]) break;
+  // a fixed budget of passes, queued without waiting: the passes after the
+  // root return at once on the device's done flag
+  for (int k = 0; k < kOcPasses; ++k) {
+    oc_pass_kernel<<<nb, 256, 0, s>>>(rho, a, nc, p.move, p.rho_min, pas, vw, c->partials, st);
+    oc_pass_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, st);
   }
   oc_final_kernel<<<nb, 256, 0, s>>>(rho, a, rho_new, nc, p.move, p.rho_min, pas, vw, c->partials, st);
-  oc_final_fin<<<1, 256, 0, s>>>(c->partials, nb, p.eta, st, scalars);
+  oc_final_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, p.eta, st, scalars, &c->scal->status);
 }
 
 }  // namespace topo

@@ -1,6 +1,6 @@
 // Preconditioned conjugate gradients for K(rho) u_r = f_r, one independent
 // CG per load case r with FP64 scalars.  (The paper solves the same system
-// by sparse LU, Sec. 4.2.4; the iteration here is the textbook PCG.)
+// by sparse LU, Sec. 4.3.4; the iteration here is the textbook PCG.)
 //
 // One iteration on the context stream:
 //   apply      q = K p and per-block (p,q)        -> alpha_fin: alpha = (r,z)/(p,q)

@@ -564,9 +564,15 @@ __device__ inline void oc_pass_finish(const double* tot, long nc, OcState* st) {
   st->mu = next;
 }
 
-// volume, change and lambda = mu^(-1/eta) of the new design
-__device__ inline void oc_final_finish(const double* tot, double eta, OcState* st, double* scalars) {
+// volume, change and lambda = mu^(-1/eta) of the new design.  A feasible
+// update whose volume misses volfrac * N by more than 1e-12 N (the pass
+// budget ran out, or the bracket could not be split further) sets the
+// sticky TOPO_S_OC_INEXACT: the design is valid, its volume inexact.
+__device__ inline void oc_final_finish(const double* tot, double eta, long nc, OcState* st,
+                                       double* scalars, int* status) {
   const double mu = st->mu;
+  if (!st->infeasible && !(fabs(tot[0] - st->target) <= 1e-12 * (double)nc) && *status == 0)
+    *status = TOPO_S_OC_INEXACT;
   st->vol = tot[0];
   st->change = tot[1];
   st->lam = (mu > 0.0) ? pow(mu, -1.0 / eta) : INFINITY;
@@ -616,13 +622,13 @@ __device__ inline void sens2d_square(long s, const double* __restrict__ rho, con
 __device__ inline void filter_cell(long h, int t, double* out, const double* __restrict__ q,
                                    const double* __restrict__ rho, const double* __restrict__ R,
                                    const FilterTap* __restrict__ taps, const int* __restrict__ ntaps,
-                                   int dim, int nx, int ny, int nz, int ncls, int alt, int out_mode) {
+                                   int stride, int dim, int nx, int ny, int nz, int ncls, int alt, int out_mode) {
   const long nblk = (long)nx * ny * nz;
   const int i = (int)(h % nx);
   const int j = (int)((h / nx) % ny);
   const int k = (int)(h / ((long)nx * ny));
   const int cls = (dim == 2 && alt) ? t + 2 * (j & 1) : t;
-  const FilterTap* tp = taps + (long)cls * kMaxFilterTaps;
+  const FilterTap* tp = taps + (long)cls * stride;
   const int nt = ntaps[cls];
   double acc = 0.0;
   for (int s = 0; s < nt; ++s) {

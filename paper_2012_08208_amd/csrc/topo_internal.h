@@ -20,8 +20,8 @@ inline bool flex_mixed(const topo_problem& p) {
 
 constexpr int kMaxRhs = 4;
 constexpr int kRedBlocks = 1024;   // fixed block count of grid-stride reductions
-constexpr int kMaxFilterTaps = 2048;
 constexpr int kMaxFilterClasses = 6;
+constexpr int kOcPasses = 32;      // multiplier passes queued per OC update (early exit)
 constexpr int kFcgWindow = 8;                 // directions kept by truncated flexible CG
 constexpr int kFcgRing = kFcgWindow + 1;      // ring slots (window + the new direction)
 
@@ -218,10 +218,11 @@ struct Ctx {
   double* partials;   // [kRedBlocks * 16]
   DevScalars* scal;
   double* R;          // [nc] filter row sums
-  FilterTap* taps;    // [classes][kMaxFilterTaps]
+  FilterTap* taps;    // [8][tap_stride], then ntaps[8]
+  int tap_stride;     // entries per class list (the longest list, rounded up)
   int ntaps[8];
   int nclasses;
-  TiledTap* ttaps;    // 3D: [6][kMaxFilterTaps] offsets into the tiled filter's LDS box
+  TiledTap* ttaps;    // 3D: [6][tap_stride] offsets into the tiled filter's LDS box
   bool filter_tiled;  // 3D and every tap within the box's halo
   double* qsoa;       // [nc] filter input in class-major order
   double *dc, *dcf, *rho_new, *rho_tmp;  // [nc]
@@ -305,7 +306,9 @@ void build_helm_coef(Ctx* c);
 void launch_helm_diag(Ctx* c);
 void launch_filter_helmholtz(Ctx* c, const double* rho, const double* dc, double* dcf);
 void build_filter_taps(Ctx* c);
-int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& tab, int* ntaps);
+int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& tab, int* ntaps,
+                     int* stride);
+int filter_tap_stride(int dim, int split, double rmin);
 void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars);
 void launch_log_record(Ctx* c, double* rec, const double* info);
 int timing_begin(Ctx* c, int chan);

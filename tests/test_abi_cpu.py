@@ -151,3 +151,38 @@ def test_edm_entry_points_reject_bad_arguments_on_the_host():
     assert lib.topo_edm_filter(10, 5, fake, None, fake, fake, fake, fake, fake, None) == -1
     assert lib.topo_edm_filter(0, 0, None, None, None, None, None, None, None, None) == 0
     assert lib.topo_edm_workspace_size(-3, ctypes.byref(ctypes.c_size_t())) == -2
+
+
+@pytest.mark.parametrize("dim,split,rmin", [
+    (2, 0, 1.5), (2, 1, 1.5), (2, 0, 3.0), (3, 1, 1.5), (3, 1, 2.5), (3, 1, 4.4), (3, 1, 5.0),
+])
+def test_filter_tap_lists_are_whole_neighbourhoods(dim, split, rmin):
+    """The tap lists the filter kernels walk hold every cell of an interior
+    neighbourhood (Sec. 3.2.2, eq. filter): their lengths equal the
+    exact-rational lattice counts, including radii whose 3D neighbourhoods
+    (2137 cells at 4.4, 3119 at 5) exceed any fixed table size."""
+    from test_oracle_sens_filter_oc import _lattice_neighbourhood
+    b = _lib()
+    lib = b.load_library()
+    nt = (ctypes.c_int32 * 8)()
+    ncls = ctypes.c_int32(0)
+    assert lib.topo_filter_taps(dim, split, rmin, nt, ctypes.byref(ncls)) == 0
+    lat = _lattice_neighbourhood(dim, split, rmin)
+    want = [n for n, _ in lat]
+    if dim == 2 and split == 0:
+        # alternating rows: odd-row classes mirror the even-row ones
+        assert ncls.value == 4 and sorted(nt[2:4]) == sorted(want)
+    else:
+        assert ncls.value == len(want)
+    assert list(nt[:len(want)]) == want
+    if dim == 3 and rmin == 5.0:
+        assert want == [3119] * 6
+    # the workspace grows with the neighbourhood instead of truncating it
+    small = b.make_problem(3, (14, 9, 6), rmin=2.5)
+    big = b.make_problem(3, (14, 9, 6), rmin=5.0)
+    ns, nb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.topo_workspace_size(ctypes.byref(small), ctypes.byref(ns)) == 0
+    assert lib.topo_workspace_size(ctypes.byref(big), ctypes.byref(nb)) == 0
+    assert nb.value >= ns.value + 8 * (3119 - 405) * 24
+    assert lib.topo_filter_taps(4, 0, 1.5, nt, ctypes.byref(ncls)) == -1
+    assert lib.topo_filter_taps(3, 0, 0.0, nt, ctypes.byref(ncls)) == -1

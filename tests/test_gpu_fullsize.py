@@ -7,7 +7,7 @@ The oracle cannot assemble or factor a mesh of this size inside a test, so
 it computes sampled outputs one at a time, with its own element matrices:
   * rows of y = Z K(rho) Z x at sampled nodes (interior, clamped face,
     loaded edge, grid corners), summed over the node's incident
-    tetrahedra (Sec. 3.1, eq. fe_form; Kuhn split of Sec. 4.2);
+    tetrahedra (Sec. 3.1, eq. fe_form; Kuhn split of the 3D boxes, Sec. 5.1);
   * element energies and sensitivities of sampled cells from the GPU
     displacement (Sec. 2, eq. str_energy; Sec. 3.2);
   * filtered sensitivities of sampled cells by brute force over their
@@ -216,7 +216,8 @@ def test_fullsize_solves_sensitivity_filter_oc(full):
 
     # OC: volume, bounds, and the sampled design at the GPU's multiplier
     lam = sc[0]
-    assert abs(rho_new.sum() - p.volfrac * p.n_cells) <= 1e-9 * p.volfrac * p.n_cells
+    assert abs(rho_new.sum() - p.volfrac * p.n_cells) <= 1e-12 * p.n_cells
+    assert abs(sc[1] - p.volfrac * p.n_cells) <= 1e-12 * p.n_cells
     assert rho_new.min() >= p.rho_min - 1e-15 and rho_new.max() <= 1.0 + 1e-15
     assert np.max(np.abs(rho_new - rho)) <= p.move + 1e-12
     d_ref = oc._design(rho[cells], np.maximum(0.0, -dcf[cells]), lam, p.move, p.eta, p.rho_min)

@@ -81,5 +81,6 @@ def test_mbb2d_fullsize_against_stored_oracle(precision, bar):
         er = np.max(np.abs(rn[cells] - g["oc"]["rho_new"]))
         print(f"  sensitivity {es:.2e}, filter {ef:.2e}, lambda {el:.2e}, design {er:.2e}", flush=True)
         assert es <= 3e-8 and ef <= 3e-8 and el <= 3e-8 and er <= 3e-8
-        assert abs(sc[1] - p.volfrac * p.n_cells) <= 1e-9 * p.volfrac * p.n_cells
+        assert abs(sc[1] - p.volfrac * p.n_cells) <= 1e-12 * p.n_cells
+        assert abs(rn.sum() - p.volfrac * p.n_cells) <= 1e-12 * p.n_cells
     t.close()

@@ -1,5 +1,5 @@
 """The oracle's distance filter on irregular midpoint clouds (unstructured
-stand-ins), pinned to the Euclidean distance matrix of Sec. 4.4 computed by
+stand-ins), pinned to the Euclidean distance matrix of Sec. 4.5 computed by
 scipy's pairwise-distance routine and to closed forms of eq. filter."""
 
 import numpy as np

@@ -15,7 +15,7 @@
 import numpy as np
 import pytest
 
-from oracle import helm, mesh as M
+from oracle import filt, helm, mesh as M
 
 
 def _interior_nodes(m):
@@ -162,3 +162,36 @@ def test_loop_with_helmholtz_filter_symmetry_and_volume():
     for rec in log:
         assert abs(rec["vol"] - 0.5) <= 1e-12
     assert log[-1]["c"] < 0.6 * log[0]["c"]
+
+
+def test_radius_rule_matches_the_distance_filter_second_moment():
+    """The reading r = rmin / (2 sqrt 3) equates the second moment of the
+    PDE filter's kernel with that of the distance filter's hat weights in
+    one dimension (2 r^2 = rmin^2 / 6).  On a one-row strip, the x second
+    moment of the oracle's P1 Helmholtz response to a one-square impulse
+    and that of the distance filter's weights around the same square agree
+    to discretisation error: 0.6% at rmin 12, shrinking about fourfold per
+    doubling of rmin (second order).  A radius off by any constant factor
+    (r = rmin / 2, rmin / sqrt 3, rmin / (4 sqrt 3)) fails by 30% or more."""
+    gaps = []
+    for rmin, L in ((12, 240), (24, 400), (48, 800)):
+        m = M.build(2, (L, 1), M.SPLIT_UNIFORM)
+        cen = M.centroids(m)
+        vol, _ = M.geometry(m)
+        i0 = L // 2
+        psi = ((np.arange(m.n_cells) // 2) == i0).astype(float)
+        x0 = i0 + 0.5
+        F = helm.smooth(m, helm.radius(rmin), psi)
+        m_helm = np.sum(vol * F * (cen[:, 0] - x0) ** 2) / np.sum(vol * F)
+        W = filt.weights_sparse(cen, rmin)
+        w = np.asarray(W.T @ psi).ravel()
+        m_dist = np.sum(w * (cen[:, 0] - x0) ** 2) / np.sum(w)
+        # both near the 1D hat's rmin^2 / 6
+        assert abs(m_dist - rmin ** 2 / 6) <= 0.01 * rmin ** 2 / 6
+        gaps.append(abs(m_helm - m_dist) / m_dist)
+        for wrong in (rmin / 2.0, rmin / np.sqrt(3.0), rmin / (4.0 * np.sqrt(3.0))):
+            Fw = helm.smooth(m, wrong, psi)
+            mw = np.sum(vol * Fw * (cen[:, 0] - x0) ** 2) / np.sum(vol * Fw)
+            assert abs(mw - m_dist) / m_dist > 0.3
+    assert gaps[0] < 0.01
+    assert gaps[1] < 0.35 * gaps[0] and gaps[2] < 0.35 * gaps[1]

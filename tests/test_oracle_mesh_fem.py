@@ -247,3 +247,50 @@ def test_bf16_modulus_rounding():
     # relative error at most half a BF16 ulp (2^-8 of the value)
     y = fem.bf16_modulus(x)
     assert np.all(np.abs(y - x) <= 2.0 ** -8 * np.abs(x))
+
+
+def _affine_gradients(coords, cells, u_nodes):
+    """Per-cell displacement gradient of the P1 field, fitted directly from
+    the vertex coordinates: solve [x_v - x_0] G^T = [u_v - u_0]."""
+    d = coords.shape[1]
+    X = coords[cells]                       # [e, d+1, d]
+    U = u_nodes[cells]                      # [e, d+1, d]
+    dX = X[:, 1:, :] - X[:, :1, :]
+    dU = U[:, 1:, :] - U[:, :1, :]
+    Gt = np.linalg.solve(dX, dU)            # [e, d, d]: row j = d u / d x_j
+    return np.transpose(Gt, (0, 2, 1))      # G[e, a, j] = d u_a / d x_j
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_paper_mode_sensitivity_is_minus_p_rho_pm1_energy_density(dim):
+    """The listing's per-cell sensitivity (Sec. 3.2) is -p rho^(p-1) psi_e with
+    psi the strain-energy density of eq. str_energy at the listing's Lame
+    constants lambda = 0.6, mu = 0.4.  Here psi is formed independently of
+    the oracle's element matrices: the strain comes from an affine fit of
+    the nodal displacements on each cell's vertex coordinates, and
+    psi = lambda/2 tr(eps)^2 + mu eps:eps.  The oracle's paper-mode
+    sensitivity times paper_sensitivity_scale must equal it; a dropped
+    factor 2|T|, the exact-derivative scale or the plane-stress law in
+    place of the listing's fails by 2% (3D, whose nu = 0.3 Lame constants
+    are close to the listing's) to 28% (2D) or more."""
+    m = M.build(dim, (5, 4) if dim == 2 else (3, 3, 2))
+    rng = np.random.default_rng(90 + dim)
+    u = rng.standard_normal((dim, m.n_nodes))
+    rho = rng.uniform(0.05, 1.0, m.n_cells)
+    p = 3.0
+    G = _affine_gradients(m.coords, m.cells, u.T)
+    eps = 0.5 * (G + np.transpose(G, (0, 2, 1)))
+    tr = np.trace(eps, axis1=1, axis2=2)
+    psi = 0.5 * 0.6 * tr ** 2 + 0.4 * np.einsum("eij,eij->e", eps, eps)
+    want = -p * rho ** (p - 1.0) * psi
+    w = fem.element_energy(m, u.reshape(1, -1), 0.3, paper_mode=True)
+    got = fem.sensitivity(rho, w, 1.0, 1e-9, p, paper_mode=True) * fem.paper_sensitivity_scale(m)
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+    # the non-paper law differs: plane stress (2D) / nu = 0.3 Lame (3D)
+    w_ns = fem.element_energy(m, u.reshape(1, -1), 0.3, paper_mode=False)
+    got_ns = fem.sensitivity(rho, w_ns, 1.0, 1e-9, p) * fem.paper_sensitivity_scale(m)
+    assert np.max(np.abs(got_ns - want) / np.abs(want)) > 0.02
+    # without the scale the value is the exact derivative, 2|T| times it
+    vol, _ = M.geometry(m)
+    np.testing.assert_allclose(fem.sensitivity(rho, w, 1.0, 1e-9, p, paper_mode=True),
+                               2.0 * vol * want, rtol=1e-12)

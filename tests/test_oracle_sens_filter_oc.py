@@ -2,7 +2,7 @@
 
 * sensitivities against complex-step and central finite differences of the
   compliance (Section 3.2: sensitivity of f);
-* the filter (Section 3.2.2, eq. filter / eq. filter_cond; Section 4.4,
+* the filter (Section 3.2.2, eq. filter / eq. filter_cond; Section 4.5,
   eq. filter_mat) against brute force, constant fields, conservation,
   the identity limit and an exact-rational lattice enumeration of the
   interior neighbourhoods;
@@ -74,7 +74,8 @@ def _lattice_neighbourhood(dim, split, rmin):
         for t in range(2):
             ca = cls(0, 0)[t]
             n, s = 0, 0.0
-            for i, j in itertools.product(range(-5, 6), repeat=2):
+            reach = int(np.ceil(rmin)) + 1
+            for i, j in itertools.product(range(-reach, reach + 1), repeat=2):
                 for cb in cls(i, j):
                     d2 = (i + cb[0] - ca[0]) ** 2 + (j + cb[1] - ca[1]) ** 2
                     if d2 < r2:
@@ -90,7 +91,8 @@ def _lattice_neighbourhood(dim, split, rmin):
     out = []
     for ca in cents:
         n, s = 0, 0.0
-        for off in itertools.product(range(-4, 5), repeat=3):
+        reach = int(np.ceil(rmin)) + 1
+        for off in itertools.product(range(-reach, reach + 1), repeat=3):
             for cb in cents:
                 d2 = sum((off[a] + cb[a] - ca[a]) ** 2 for a in range(3))
                 if d2 < r2:
