@@ -238,6 +238,32 @@ int topo_filter(topo_ctx* ctx, const double* rho, const double* dc, double* dcf)
 int topo_oc_update(topo_ctx* ctx, const double* rho, const double* dcf, double* rho_new,
                    double* scalars);
 
+/* Allocation-free OC update, for callers that cannot allocate device memory
+   (code under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc).  It needs no context and no workspace: it computes what
+   topo_oc_update computes for a context of n cells with no passive cells and
+   the distance or Helmholtz filter (unit cell volumes), with the same
+   kernels in the same order, so the results are the same bits.
+   n         cells, 1 <= n <= TOPO_OC_NOALLOC_MAX_CELLS, else TOPO_E_SHAPE.
+   rho, dcf  device [n], the design and its filtered sensitivity.
+   rho_new   device [n] output; must alias neither input.
+   volfrac, move, eta, rho_min   as in topo_problem; 0 < volfrac <= 1,
+             move > 0, eta > 0, 0 < rho_min < 1, else TOPO_E_INVALID.
+   out       device [4] output: lambda, sum_e rho_new_e, max_e |rho_new_e -
+             rho_e|, and the update's status (TOPO_OK, TOPO_S_OC_INEXACT or
+             TOPO_S_OC_INFEASIBLE) as a double.
+   stream    hipStream_t as void* (NULL = default stream); the call is
+             asynchronous and waits for nothing.
+   Scratch: one static device array of about 132 KB per GPU (block partial
+   sums, multiplier state, status), held until the process ends.  Every call
+   on a GPU shares that GPU's array and overwrites it, so calls that overlap
+   on one GPU (two streams, two host threads) race; order them on one
+   stream.  Calls no hipMalloc/hipFree. */
+#define TOPO_OC_NOALLOC_MAX_CELLS ((int64_t)2147483647)
+int topo_oc_update_noalloc(int64_t n, const double* rho, const double* dcf, double* rho_new,
+                           double volfrac, double move, double eta, double rho_min, double* out,
+                           void* stream);
+
 /* Runs up to max_iter SIMP iterations in place on rho [N_c] (solve ->
    sensitivity -> filter -> OC).  change_tol <= 0: exactly max_iter
    iterations; otherwise stop after the first iteration whose change is

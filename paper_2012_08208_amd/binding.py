@@ -50,7 +50,9 @@ EXPORTED = [
     "topo_batch_iterate", "topo_batch_solution", "topo_batch_tile_shape", "topo_batch_sync",
     "topo_batch_uses_graphs",
     "topo_edm_workspace_size", "topo_edm_count", "topo_edm_fill", "topo_edm_filter",
+    "topo_oc_update_noalloc",
 ]
+OC_NOALLOC_MAX_CELLS = 2147483647
 BATCH_REC_LEN = 6
 
 
@@ -129,6 +131,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_edm_fill.argtypes = [vp, i32, i64, dbl, vp, vp, vp, vp, vp, szt, vp]
     lib.topo_edm_filter.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.topo_filter_taps.argtypes = [i32, i32, dbl, P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.topo_oc_update_noalloc.argtypes = [i64, vp, vp, vp, dbl, dbl, dbl, dbl, vp, vp]
     lib.topo_status_string.argtypes = [i32]
     lib.topo_status_string.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -585,6 +588,30 @@ class EdmFilter:
                                         self._vec(dc, "dc"), self._vec(dcf, "dcf"),
                                         ctypes.c_void_p(self.stream.cuda_stream)),
                "topo_edm_filter")
+
+
+def oc_update_noalloc(rho, dcf, rho_new, out, volfrac: float, move: float = 0.2,
+                      eta: float = 0.5, rho_min: float = 1e-3) -> None:
+    """topo_oc_update_noalloc on the current torch stream of rho's device:
+    rho, dcf, rho_new float64 [n]; out float64 [4] (lambda, volume, change,
+    status).  Allocates nothing; overlapping calls on one GPU race."""
+    import torch
+    n = int(rho.numel())
+    for t, name, size in ((rho, "rho", n), (dcf, "dcf", n), (rho_new, "rho_new", n),
+                          (out, "out", 4)):
+        if (not isinstance(t, torch.Tensor) or t.device.type != "cuda"
+                or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != size):
+            raise TopoError(f"{name} must be a contiguous float64 CUDA tensor of {size} elements")
+    lib = load_library()
+    st = torch.cuda.current_stream(rho.device)
+    with torch.cuda.device(rho.device):
+        _check(lib.topo_oc_update_noalloc(n, ctypes.c_void_p(rho.data_ptr()),
+                                          ctypes.c_void_p(dcf.data_ptr()),
+                                          ctypes.c_void_p(rho_new.data_ptr()), float(volfrac),
+                                          float(move), float(eta), float(rho_min),
+                                          ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(st.cuda_stream)),
+               "topo_oc_update_noalloc")
 
 
 def status_string(code: int) -> str:

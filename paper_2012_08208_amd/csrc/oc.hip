@@ -27,6 +27,8 @@
 // evaluation is the same single pass.
 #include <math.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "shared_dev.h"
 #include "topo_internal.h"
@@ -46,6 +48,16 @@ __device__ __forceinline__ void oc_bounds(long e, double r, double move, double 
   }
 }
 
+// a_e = rho_e (-dcf_e / dv_e)^eta, zero on passive cells: stored by the
+// first pass, or formed again in every pass when no per-cell array is given
+// (the allocation-free entry point); both give the same bits.
+__device__ __forceinline__ double oc_coef(long e, double r, const double* __restrict__ dcf,
+                                          double eta, const uint8_t* __restrict__ passive,
+                                          const double* __restrict__ vw) {
+  if (passive && passive[e]) return 0.0;
+  return oc_a(r, vw ? dcf[e] / vw[e] : dcf[e], eta);
+}
+
 __global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__ rho,
                                                       const double* __restrict__ dcf, double* a_out,
                                                       long nc, double move, double eta,
@@ -60,8 +72,8 @@ __global__ __launch_bounds__(256) void oc_init_kernel(const double* __restrict__
     double lo, hi;
     oc_bounds(e, r, move, rho_min, passive, lo, hi);
     const double w = vw ? vw[e] : 1.0;
-    const double a = (passive && passive[e]) ? 0.0 : oc_a(r, vw ? dcf[e] / w : dcf[e], eta);
-    a_out[e] = a;
+    const double a = oc_coef(e, r, dcf, eta, passive, vw);
+    if (a_out) a_out[e] = a;
     acc[0] += w * lo;
     acc[1] += w * ((a > 0.0) ? hi : lo);  // volume once mu is large
     acc[2] += w * a;
@@ -78,8 +90,9 @@ __global__ void oc_init_fin(const double* partials, long nb, long nc, double vol
 }
 
 __global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__ rho,
-                                                      const double* __restrict__ a_in, long nc,
-                                                      double move, double rho_min,
+                                                      const double* __restrict__ a_in,
+                                                      const double* __restrict__ dcf, double eta,
+                                                      long nc, double move, double rho_min,
                                                       const uint8_t* __restrict__ passive,
                                                       const double* __restrict__ vw,
                                                       double* partials, const OcState* st) {
@@ -88,7 +101,7 @@ __global__ __launch_bounds__(256) void oc_pass_kernel(const double* __restrict__
   double acc[2] = {0.0, 0.0};
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += (long)gridDim.x * blockDim.x) {
     const double r = rho[e];
-    const double a = a_in[e];
+    const double a = a_in ? a_in[e] : oc_coef(e, r, dcf, eta, passive, vw);
     double lo, hi;
     oc_bounds(e, r, move, rho_min, passive, lo, hi);
     const double w = vw ? vw[e] : 1.0;
@@ -109,6 +122,7 @@ __global__ void oc_pass_fin(const double* partials, long nb, long nc, OcState* s
 
 __global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict__ rho,
                                                        const double* __restrict__ a_in,
+                                                       const double* __restrict__ dcf, double eta,
                                                        double* rho_new, long nc, double move,
                                                        double rho_min,
                                                        const uint8_t* __restrict__ passive,
@@ -121,7 +135,8 @@ __global__ __launch_bounds__(256) void oc_final_kernel(const double* __restrict_
     const double r = rho[e];
     double lo, hi;
     oc_bounds(e, r, move, rho_min, passive, lo, hi);
-    const double v = fmax(lo, fmin(hi, a_in[e] * mu));
+    const double a = a_in ? a_in[e] : oc_coef(e, r, dcf, eta, passive, vw);
+    const double v = fmax(lo, fmin(hi, a * mu));
     rho_new[e] = v;
     acc[0] += (vw ? vw[e] : 1.0) * v;
     mx[0] = fmax(mx[0], fabs(v - r));
@@ -150,11 +165,85 @@ void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, do
   // a fixed budget of passes, queued without waiting: the passes after the
   // root return at once on the device's done flag
   for (int k = 0; k < kOcPasses; ++k) {
-    oc_pass_kernel<<<nb, 256, 0, s>>>(rho, a, nc, p.move, p.rho_min, pas, vw, c->partials, st);
+    oc_pass_kernel<<<nb, 256, 0, s>>>(rho, a, dcf, p.eta, nc, p.move, p.rho_min, pas, vw,
+                                      c->partials, st);
     oc_pass_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, st);
   }
-  oc_final_kernel<<<nb, 256, 0, s>>>(rho, a, rho_new, nc, p.move, p.rho_min, pas, vw, c->partials, st);
+  oc_final_kernel<<<nb, 256, 0, s>>>(rho, a, dcf, p.eta, rho_new, nc, p.move, p.rho_min, pas, vw,
+                                     c->partials, st);
   oc_final_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, p.eta, st, scalars, &c->scal->status);
 }
 
+// ---------------------------------------------- allocation-free OC update
+// The update above for a plain design of n cells (no passive cells, unit
+// cell volumes), for callers that cannot allocate device memory.  Its
+// scratch (the per-block partial sums, the multiplier state and a status
+// word) is one file-scope device array, so each GPU holds one copy for the
+// life of the process; calls that overlap on one GPU share it and race.
+// Host code never passes the array's name to a kernel: its device address
+// is looked up once per device (hipGetSymbolAddress) and kept.
+namespace {
+constexpr size_t kNaPartBytes = (size_t)kRedBlocks * kPartStride * sizeof(double);
+constexpr size_t kNaStateOff = kNaPartBytes;
+constexpr size_t kNaStatusOff = kNaStateOff + ((sizeof(OcState) + 255) / 256) * 256;
+constexpr size_t kNaBytes = kNaStatusOff + 256;
+constexpr int kNaMaxDevices = 64;
+
+std::mutex na_mu;
+char* na_ptr[kNaMaxDevices];
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNaBytes];
+
+__global__ void oc_na_reset(int* status) { *status = 0; }
+
+__global__ void oc_na_status(const int* status, double* out) { out[3] = (double)*status; }
+
+// device address of this GPU's scratch array (looked up on first use)
+static char* na_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(na_mu);
+  if (!na_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    na_ptr[dev] = static_cast<char*>(p);
+  }
+  return na_ptr[dev];
+}
+
 }  // namespace topo
+
+using namespace topo;
+
+extern "C" int topo_oc_update_noalloc(int64_t n, const double* rho, const double* dcf,
+                                      double* rho_new, double volfrac, double move, double eta,
+                                      double rho_min, double* out, void* stream) {
+  if (!rho || !dcf || !rho_new || !out || rho == rho_new || dcf == rho_new) return TOPO_E_INVALID;
+  if (!(volfrac > 0.0 && volfrac <= 1.0) || !(move > 0.0) || !(eta > 0.0) ||
+      !(rho_min > 0.0 && rho_min < 1.0))
+    return TOPO_E_INVALID;
+  if (n < 1 || n > TOPO_OC_NOALLOC_MAX_CELLS) return TOPO_E_SHAPE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNaMaxDevices) return TOPO_E_HIP;
+  char* base = na_scratch(dev);
+  if (!base) return TOPO_E_HIP;
+  double* partials = reinterpret_cast<double*>(base);
+  OcState* st = reinterpret_cast<OcState*>(base + kNaStateOff);
+  int* status = reinterpret_cast<int*>(base + kNaStatusOff);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long nc = (long)n;
+  const unsigned nb = red_grid(nc);
+  oc_na_reset<<<1, 1, 0, s>>>(status);
+  oc_init_kernel<<<nb, 256, 0, s>>>(rho, dcf, nullptr, nc, move, eta, rho_min, nullptr, nullptr,
+                                    partials);
+  oc_init_fin<<<1, 256, 0, s>>>(partials, nb, nc, volfrac, st, status);
+  for (int k = 0; k < kOcPasses; ++k) {
+    oc_pass_kernel<<<nb, 256, 0, s>>>(rho, nullptr, dcf, eta, nc, move, rho_min, nullptr, nullptr,
+                                      partials, st);
+    oc_pass_fin<<<1, 256, 0, s>>>(partials, nb, nc, st);
+  }
+  oc_final_kernel<<<nb, 256, 0, s>>>(rho, nullptr, dcf, eta, rho_new, nc, move, rho_min, nullptr,
+                                     nullptr, partials, st);
+  oc_final_fin<<<1, 256, 0, s>>>(partials, nb, nc, eta, st, out, status);
+  oc_na_status<<<1, 1, 0, s>>>(status, out);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
+}

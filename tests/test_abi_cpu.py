@@ -186,3 +186,32 @@ def test_filter_tap_lists_are_whole_neighbourhoods(dim, split, rmin):
     assert nb.value >= ns.value + 8 * (3119 - 405) * 24
     assert lib.topo_filter_taps(4, 0, 1.5, nt, ctypes.byref(ncls)) == -1
     assert lib.topo_filter_taps(3, 0, 0.0, nt, ctypes.byref(ncls)) == -1
+
+
+def test_noalloc_oc_update_rejects_bad_arguments_on_the_host():
+    """topo_oc_update_noalloc checks its arguments before any HIP call, so a
+    bad call returns an error code here, with no GPU: sizes outside
+    [1, TOPO_OC_NOALLOC_MAX_CELLS] give TOPO_E_SHAPE, null or aliased
+    pointers and out-of-range parameters TOPO_E_INVALID."""
+    b = _lib()
+    lib = b.load_library()
+    f = lib.topo_oc_update_noalloc
+    r, d, o, s = 4096, 8192, 12288, 16384      # never dereferenced
+    ok = dict(volfrac=0.5, move=0.2, eta=0.5, rho_min=1e-3)
+
+    def call(n, rho=r, dcf=d, new=o, out=s, **kw):
+        a = dict(ok, **kw)
+        return f(n, rho, dcf, new, a["volfrac"], a["move"], a["eta"], a["rho_min"], out, None)
+
+    assert call(b.OC_NOALLOC_MAX_CELLS + 1) == -2
+    assert call(0) == -2
+    assert call(-5) == -2
+    assert call(10, rho=None) == -1
+    assert call(10, out=None) == -1
+    assert call(10, new=r) == -1
+    assert call(10, new=d) == -1
+    assert call(10, volfrac=0.0) == -1
+    assert call(10, volfrac=1.5) == -1
+    assert call(10, move=0.0) == -1
+    assert call(10, eta=0.0) == -1
+    assert call(10, rho_min=0.0) == -1
