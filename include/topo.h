@@ -43,12 +43,15 @@
  * the library allocates no device memory and keeps no caller pointer
  * after a call returns.  All compute calls are ordered on the context's
  * stream (a hipStream_t passed as void*; NULL = default stream) and return
- * without waiting for their kernels, except where an iteration's length is
- * decided on the device: topo_solve, topo_iterate and topo_oc_update (and
- * topo_filter with the Helmholtz filter) queue batches of steps and wait on
- * a pinned converged flag between them.  Scalars are written to device
- * memory; topo_sync waits for the stream and returns the sticky device
- * status.  A context is not thread-safe.
+ * without waiting for their kernels, except, in the default
+ * TOPO_SYNC_POLL mode, where a solve's length is decided on the device:
+ * topo_solve and topo_iterate (and topo_filter with the Helmholtz filter)
+ * queue batches of CG iterations and read a pinned converged flag one batch
+ * behind.  With topo_problem.sync_mode = TOPO_SYNC_NONE none of the path
+ * calls waits (graph-capturable, fixed iteration budgets).  The OC update
+ * never waits.  Scalars are written to device memory; topo_sync waits for
+ * the stream and returns the sticky device status.  A context is not
+ * thread-safe.
  *
  * Return values: 0 = OK; negative = host-detected error (TOPO_E_*), in
  * which case nothing was enqueued.  Device-detected outcomes (not converged,
@@ -140,10 +143,11 @@ enum { TOPO_PC_JACOBI = 0, TOPO_PC_GMG = 1, TOPO_PC_LEARNED = 2 };
                           T_ne = |T_e| / (d+1) at the vertices of e; then
                           s~_e = (mean of x over the vertices of e) / rho_e.
                           Solved by Jacobi-preconditioned FP64 CG to a
-                          relative residual of 1e-12 (the call synchronises
-                          with the stream between batches of iterations, as
-                          topo_solve does); a solve that stops at its cap of
-                          4000 iterations sets TOPO_S_NOT_CONVERGED.
+                          relative residual of 1e-12 (in TOPO_SYNC_POLL
+                          mode the call reads the converged flag between
+                          batches of iterations, as topo_solve does); a solve
+                          that stops at its cap of 4000 iterations (256 in
+                          TOPO_SYNC_NONE mode) sets TOPO_S_NOT_CONVERGED.
    TOPO_FILTER_DENSITY:   a density filter on the same weights (not in the
                           paper, whose filter acts on sensitivities): the
                           physics sees x~ = W x / R (R_a = sum_b W_ab) and
@@ -177,7 +181,35 @@ typedef struct topo_problem {
   int32_t warm_start; /* 1: topo_solve starts from the u it is given */
   int32_t gmg_levels; /* 0 = automatic; otherwise the number of levels */
   int32_t filter;     /* TOPO_FILTER_DISTANCE (0) | TOPO_FILTER_HELMHOLTZ | TOPO_FILTER_DENSITY */
+  int32_t sync_mode;  /* TOPO_SYNC_POLL (0) | TOPO_SYNC_NONE, see below */
 } topo_problem;
+
+/* Host waits inside the path calls (topo_problem.sync_mode).
+   TOPO_SYNC_POLL: the length of a CG solve is decided on the device and the
+                   host follows it: topo_solve and topo_iterate copy the
+                   device's converged flag to pinned memory after every batch
+                   of queued iterations and read it one batch behind (the GPU
+                   queue stays one batch deep, so the wait is off the
+                   critical path), and read the true-residual restart flag
+                   once per solve; the Helmholtz filter does the same, and
+                   topo_iterate with change_tol > 0 reads the change once per
+                   iteration.  This is the fastest mode.
+   TOPO_SYNC_NONE: no call among topo_set_loads, topo_solve,
+                   topo_sensitivity, topo_filter, topo_oc_update and
+                   topo_iterate waits for the device or reads device memory
+                   on the host, so they can be captured in a HIP graph and
+                   replayed.  Every solve queues a fixed budget: maxit CG
+                   iterations, then up to three true-residual restarts of
+                   max(16, maxit / 4) iterations each, all gated on device
+                   flags (iterations after convergence, and restarts that are
+                   not needed, return at once; each skipped iteration still
+                   costs its launches).  A solve that is not converged within
+                   the budget sets TOPO_S_NOT_CONVERGED.  The Helmholtz
+                   filter queues 256 gated CG iterations.  Restrictions
+                   (TOPO_E_INVALID): precision TOPO_MIXED_IR, preconditioner
+                   TOPO_PC_LEARNED, and topo_iterate with change_tol > 0 (its
+                   stop needs the host). */
+enum { TOPO_SYNC_POLL = 0, TOPO_SYNC_NONE = 1 };
 
 /* Length of the per-solve info record written by topo_solve (doubles):
    [0] PCG iterations, [1] converged (1/0), [2..5] final relative residual
@@ -215,7 +247,8 @@ int topo_set_loads(topo_ctx* ctx, const double* f, int nrhs);
    in [rho_min, 1]; u [nrhs][dim][N_n] output (also the start vector when
    warm_start is set); info (device, may be NULL) receives
    TOPO_SOLVE_INFO_LEN doubles.  The loop checks convergence on the
-   device; the host polls a pinned flag every few iterations. */
+   device; in TOPO_SYNC_POLL mode the host polls a pinned flag every few
+   iterations, in TOPO_SYNC_NONE mode it queues the fixed budget. */
 int topo_solve(topo_ctx* ctx, const double* rho, double* u, double* info);
 
 /* Compliance c = sum_r f_r^T u_r (written to *compliance, device scalar)
@@ -267,7 +300,8 @@ int topo_oc_update_noalloc(int64_t n, const double* rho, const double* dcf, doub
 /* Runs up to max_iter SIMP iterations in place on rho [N_c] (solve ->
    sensitivity -> filter -> OC).  change_tol <= 0: exactly max_iter
    iterations; otherwise stop after the first iteration whose change is
-   below change_tol (this polls the device once per iteration).  u
+   below change_tol (this polls the device once per iteration, so
+   TOPO_SYNC_NONE contexts return TOPO_E_INVALID for it).  u
    [nrhs][dim][N_n] is the displacement work/output buffer (warm-started
    across iterations).  log (device, may be NULL) receives max_iter records
    of TOPO_LOG_LEN doubles; *n_done (host, may be NULL) the iterations

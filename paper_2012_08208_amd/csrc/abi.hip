@@ -41,6 +41,11 @@ static bool valid_problem(const topo_problem* p) {
   if (p->filter != TOPO_FILTER_DISTANCE && p->filter != TOPO_FILTER_HELMHOLTZ &&
       p->filter != TOPO_FILTER_DENSITY)
     return false;
+  if (p->sync_mode != TOPO_SYNC_POLL && p->sync_mode != TOPO_SYNC_NONE) return false;
+  // the no-wait mode has no host-driven refinement loop and no learned cycle
+  if (p->sync_mode == TOPO_SYNC_NONE &&
+      (p->precision == TOPO_MIXED_IR || p->precond == TOPO_PC_LEARNED))
+    return false;
   return true;
 }
 
@@ -564,6 +569,7 @@ int topo_oc_update(topo_ctx* c, const double* rho, const double* dcf, double* rh
 int topo_iterate(topo_ctx* c, double* rho, double* u, int max_iter, double change_tol,
                  double* log, int* n_done) {
   if (!c || !rho || !u || max_iter < 0) return TOPO_E_INVALID;
+  if (change_tol > 0.0 && c->prob.sync_mode == TOPO_SYNC_NONE) return TOPO_E_INVALID;
   if (!c->loads_set) return TOPO_E_STATE;
   int done = 0;
   const bool dens = c->prob.filter == TOPO_FILTER_DENSITY;

@@ -77,18 +77,21 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const T* __restrict__ x, T
 }
 
 // -------------------------------------------------------------- 3D apply
-// One block: one tile of 15 x 15 node columns, one z-chunk, one load case.
-// Per cube layer: the next node plane is committed from registers to LDS,
-// the plane after it and the next layer's moduli are fetched from memory
-// while the layer is computed, and the cube forces are combined into owned
-// nodes.  Two LDS-only barriers per layer; all loads use clamped (always
-// valid) addresses so they are issued unconditionally.  A plane's loads are
-// kept raw until the commit one layer later (validity selects, the D^-1 b
-// product of the pre-smoothing), so no wait for them falls inside the layer
-// that issued them.
-template <typename T>
+// One block: one tile of 15 x 15 node columns, one z-chunk, and NRB load
+// cases (all of them on the fine level), so each layer's moduli, mask and
+// D^-1 are read once for every load case the block handles.  Per cube
+// layer: the next node plane of every load case is committed from registers
+// to LDS, the plane after it is fetched from memory while the layer is
+// computed, and each load case's cube forces are combined into owned nodes.
+// The load cases pass through the LDS exchange in groups of G (G = NRB in
+// FP32; at most 2 in FP64, to bound LDS), each group behind one LDS-only
+// barrier.  All loads use clamped (always valid) addresses so they are
+// issued unconditionally.  A plane's loads are kept raw until the commit one
+// layer later (validity selects, the D^-1 b product of the pre-smoothing),
+// so no wait for them falls inside the layer that issued them.
+template <typename T, int NRB>
 struct PlaneBuf {
-  T v[2][3];
+  T v[NRB][2][3];
   T w[2][3];  // EPI 2: D^-1 at the staged nodes (v holds b)
   int m[2];
   bool ok[2];
@@ -116,21 +119,25 @@ struct ChebEpi {
   T* d;       // EPI 3: first increment out
 };
 
-template <typename T, typename TE, int EPI>
+template <typename T, typename TE, int EPI, int NRB, int G>
 __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T* __restrict__ y,
                                                       const TE* __restrict__ E, OpDesc d,
                                                       TileMap tm, T lam0, T mu0, double* partials,
                                                       const int* stop, ChebEpi<T> ce) {
-  __shared__ T xs[2][3][PATCH2];
-  __shared__ T ex[2][6][256];
+  static_assert(NRB % G == 0, "load-case groups must tile the block's load cases");
+  __shared__ T xs[2][NRB][3][PATCH2];
+  __shared__ T ex[G][6][256];
   __shared__ uint8_t ms[2][PATCH2];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   if (stop && *stop) return;
-  int bx, by, bz, rhs;
-  const bool live = map_block(tm, bx, by, bz, rhs);
+  int bx, by, bz, rb;
+  const bool live = map_block(tm, bx, by, bz, rb);
   if (!live && !partials) return;
-  double dot = 0.0;
+  const int rhs0 = rb * NRB;
+  double dot[NRB];
+#pragma unroll
+  for (int r = 0; r < NRB; ++r) dot[r] = 0.0;
   if (live) {
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const long nn = d.nn;
@@ -138,11 +145,12 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     const int k0 = bz * d.kz;
     const int k1 = min(k0 + d.kz, nz + 1);
     const long plane = (long)(nx + 1) * (ny + 1);
-    const T* xr = x + (long)rhs * 3 * nn;
-    T* yr = y + (long)rhs * 3 * nn;
-    const T* br = (EPI == 2 || EPI == 3) ? ce.b + (long)rhs * 3 * nn : nullptr;
-    T* rr_ = (EPI == 3 || EPI == 4) ? ce.r + (long)rhs * 3 * nn : nullptr;
-    T* dd_ = EPI == 3 ? ce.d + (long)rhs * 3 * nn : nullptr;
+    const long rs = 3 * nn;   // stride between load cases
+    const T* xr = x + (long)rhs0 * rs;
+    T* yr = y + (long)rhs0 * rs;
+    const T* br = (EPI == 2 || EPI == 3) ? ce.b + (long)rhs0 * rs : nullptr;
+    T* rr_ = (EPI == 3 || EPI == 4) ? ce.r + (long)rhs0 * rs : nullptr;
+    T* dd_ = EPI == 3 ? ce.d + (long)rhs0 * rs : nullptr;
     T it0 = 0;
     if (EPI == 2 || EPI == 3) it0 = T(cheb_first_scale(*ce.lmax, ce.low, ce.kind));
 
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
       const int ci = min(max(gi, 0), nx), cj = min(max(gj, 0), ny);
       poff[q] = (long)cj * (nx + 1) + ci;
     }
-    auto fetch = [&](int kk, PlaneBuf<T>& pb) {
+    auto fetch = [&](int kk, PlaneBuf<T, NRB>& pb) {
       const bool kin = kk >= 0 && kk <= nz;
       const long base = (long)min(max(kk, 0), nz) * plane;
 #pragma unroll
@@ -170,24 +178,26 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
         pb.ok[q] = pin[q] && kin;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          if (EPI == 2) {
-            pb.w[q][c] = ce.invd[c * nn + n];
-            pb.v[q][c] = br[c * nn + n];
-          } else {
-            pb.v[q][c] = xr[c * nn + n];
-          }
+          if (EPI == 2) pb.w[q][c] = ce.invd[c * nn + n];
+#pragma unroll
+          for (int r = 0; r < NRB; ++r)
+            pb.v[r][q][c] = EPI == 2 ? br[r * rs + c * nn + n] : xr[r * rs + c * nn + n];
         }
       }
     };
-    auto commit = [&](int kk, const PlaneBuf<T>& pb) {
+    auto commit = [&](int kk, const PlaneBuf<T, NRB>& pb) {
       const int s = kk & 1;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int idx = tid + 256 * q;
         if (pidx[q]) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            xs[s][c][idx] = EPI == 2 ? it0 * pb.w[q][c] * pb.v[q][c] : pb.v[q][c];
+          for (int c = 0; c < 3; ++c) {
+            const T sc = EPI == 2 ? it0 * pb.w[q][c] : T(0);
+#pragma unroll
+            for (int r = 0; r < NRB; ++r)
+              xs[s][r][c][idx] = EPI == 2 ? sc * pb.v[r][q][c] : pb.v[r][q][c];
+          }
           ms[s][idx] = pb.ok[q] ? (uint8_t)pb.m[q] : (uint8_t)7;
         }
       }
@@ -216,7 +226,12 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
     const int oi = i0 + tx, oj = j0 + ty;
     const bool owner = tx < TILE && ty < TILE && oi <= nx && oj <= ny;
     const long ocol = (long)oj * (nx + 1) + oi;
-    T carry[3] = {0, 0, 0};
+    const int oli = (ty + 1) * PATCH + tx + 1;   // the owned node in the patch (mask)
+    T carry[NRB][3];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) carry[r][a] = 0;
     T c1 = 0, c2 = 0;
     T* ex_ = nullptr;
     if (EPI == 2 || EPI == 4) {
@@ -224,10 +239,10 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
       cheb_next_coef(*ce.lmax, ce.low, ChebCoef{ce.r_cur, ce.r_prev, ce.kind, 1}, c1d, c2d);
       c1 = T(c1d);
       c2 = T(c2d);
-      ex_ = ce.x + (long)rhs * 3 * nn;
+      ex_ = ce.x + (long)rhs0 * rs;
     }
 
-    PlaneBuf<T> pb;
+    PlaneBuf<T, NRB> pb;
     fetch(k0 - 1, pb);
     commit(k0 - 1, pb);
     fetch(k0, pb);
@@ -236,16 +251,19 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
       // plane commit and the barrier
       T ev[6];
       fetch_E(kh, ev);
-      // smoothing epilogue: this layer's b and D^-1 at the owned node, issued
-      // now so their latency hides behind the layer's arithmetic
-      T pb_[3], pi[3], px[3];
+      // smoothing epilogue: this layer's b (or r, x) and D^-1 at the owned
+      // node, issued now so their latency hides behind the layer's arithmetic
+      T pb_[NRB][3], pi[3], px[NRB][3];
       if (EPI >= 2) {
         const long on = (long)min(max(kh, 0), nz) * plane + (owner ? ocol : 0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          pb_[a] = EPI == 4 ? rr_[a * nn + on] : br[a * nn + on];
           pi[a] = ce.invd[a * nn + on];
-          if (EPI == 4) px[a] = ex_[a * nn + on];
+#pragma unroll
+          for (int r = 0; r < NRB; ++r) {
+            pb_[r][a] = EPI == 4 ? rr_[r * rs + a * nn + on] : br[r * rs + a * nn + on];
+            if (EPI == 4) px[r][a] = ex_[r * rs + a * nn + on];
+          }
         }
       }
       commit(kh + 1, pb);
@@ -257,66 +275,92 @@ __global__ __launch_bounds__(256) void apply3d_kernel(const T* __restrict__ x, T
       T lam[6], mu[6];
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
-        lam[t] = eok ? lam0 * ev[t] : T(0);
-        mu[t] = eok ? mu0 * ev[t] : T(0);
+        const T e = eok ? ev[t] : T(0);
+        lam[t] = lam0 * e;
+        mu[t] = mu0 * e;
       }
       const int sb = kh & 1, stp = (kh + 1) & 1;
-      T u[8][3], f[8][3];
+      const int om = owner ? ms[sb][oli] : 0;
+      const bool store = owner && kh >= k0;
+      const long on = (long)kh * plane + ocol;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int li = (ty + ((c >> 1) & 1)) * PATCH + tx + (c & 1);
-        const int s = (c >> 2) ? stp : sb;
+      for (int g0 = 0; g0 < NRB; g0 += G) {
+        T X1[G][2][3], U3[G][3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) u[c][a] = xs[s][a][li];
-      }
-      cube_force<T>(u, lam, mu, f);
-      T X[2][2][3];
+        for (int gr = 0; gr < G; ++gr) {
+          const int r = g0 + gr;
+          T u[8][3], f[8][3];
 #pragma unroll
-      for (int cy = 0; cy < 2; ++cy)
+          for (int c = 0; c < 8; ++c) {
+            const int li = (ty + ((c >> 1) & 1)) * PATCH + tx + (c & 1);
+            const int s = (c >> 2) ? stp : sb;
 #pragma unroll
-        for (int cz = 0; cz < 2; ++cz)
+            for (int a = 0; a < 3; ++a) u[c][a] = xs[s][r][a][li];
+          }
+          cube_force<T>(u, lam, mu, f);
+          // corner 3 of this cube is the owned node (its operator input is
+          // kept here: the next layer's commit overwrites this LDS plane)
 #pragma unroll
-          for (int a = 0; a < 3; ++a)
-            X[cy][cz][a] = f[1 + 2 * cy + 4 * cz][a] + next_lane<16>(f[2 * cy + 4 * cz][a]);
-      const int eb = kh & 1;
+          for (int a = 0; a < 3; ++a) U3[gr][a] = u[3][a];
 #pragma unroll
-      for (int cz = 0; cz < 2; ++cz)
+          for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) ex[eb][cz * 3 + a][tid] = X[0][cz][a];
-      lds_barrier();
-      if (owner) {
-        const int om = ms[sb][(ty + 1) * PATCH + tx + 1];
-        const bool store = kh >= k0;
-        const long on = (long)kh * plane + ocol;
+            for (int a = 0; a < 3; ++a) {
+              ex[gr][cz * 3 + a][tid] = f[1 + 4 * cz][a] + next_lane<16>(f[4 * cz][a]);
+              X1[gr][cz][a] = f[3 + 4 * cz][a] + next_lane<16>(f[2 + 4 * cz][a]);
+            }
+        }
+        lds_barrier();
+        if (owner) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          T yb = carry[a] + X[1][0][a] + ex[eb][a][tid + 16];
-          carry[a] = X[1][1][a] + ex[eb][3 + a][tid + 16];
-          if (store) {
-            if ((om >> a) & 1) yb = 0;
-            if (EPI == 0) {
-              yr[a * nn + on] = yb;
-              if (partials) dot += (double)yb * (double)u[3][a];
-            } else if (EPI == 2) {
-              // u[3][a] = d0 at the owned node; r = b - K d0
-              const T rv = pb_[a] - yb;
-              ex_[a * nn + on] = u[3][a] + (c1 * u[3][a] + c2 * pi[a] * rv);
-            } else if (EPI == 3) {
-              const T rv = pb_[a] - yb;
-              rr_[a * nn + on] = rv;
-              dd_[a * nn + on] = it0 * pi[a] * rv;
-            } else {
-              // u[3][a] = d1 at the owned node, pb_ = r, px = x
-              const T rv = pb_[a] - yb;
-              const T dv = c1 * u[3][a] + c2 * pi[a] * rv;
-              ex_[a * nn + on] = (px[a] + u[3][a]) + dv;
+          for (int gr = 0; gr < G; ++gr) {
+            const int r = g0 + gr;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              T yb = carry[r][a] + X1[gr][0][a] + ex[gr][a][tid + 16];
+              carry[r][a] = X1[gr][1][a] + ex[gr][3 + a][tid + 16];
+              if (store) {
+                if ((om >> a) & 1) yb = 0;
+                const long ia = r * rs + a * nn + on;
+                const T uo = U3[gr][a];   // operator input at the owned node
+                if (EPI == 0) {
+                  yr[ia] = yb;
+                  if (partials) dot[r] += (double)yb * (double)uo;
+                } else if (EPI == 2) {
+                  // uo = d0 at the owned node; r = b - K d0
+                  const T rv = pb_[r][a] - yb;
+                  ex_[ia] = uo + (c1 * uo + c2 * pi[a] * rv);
+                } else if (EPI == 3) {
+                  const T rv = pb_[r][a] - yb;
+                  rr_[ia] = rv;
+                  dd_[ia] = it0 * pi[a] * rv;
+                } else {
+                  // uo = d1 at the owned node, pb_ = r, px = x
+                  const T rv = pb_[r][a] - yb;
+                  const T dv = c1 * uo + c2 * pi[a] * rv;
+                  ex_[ia] = (px[r][a] + uo) + dv;
+                }
+              }
             }
           }
         }
+        // the next group reuses the exchange buffer
+        if (g0 + G < NRB) lds_barrier();
       }
     }
   }
-  if (partials) dot_partials(dot, live ? rhs : 0, partials);
+  if (partials) {
+    double acc[kMaxRhs];
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k)
+#pragma unroll
+      for (int r = 0; r < NRB; ++r)
+        if (rhs0 + r == k) acc[k] = dot[r];
+    const double none[1] = {0.0};
+    block_partials<kMaxRhs, 0>(acc, none, partials);
+  }
 }
 
 // ------------------------------------------------------------- diagonal
@@ -416,9 +460,54 @@ static TileMap make_tilemap(const OpDesc& d, int nrhs) {
   return tm;
 }
 
-long apply_grid_blocks(const OpDesc& d, int nrhs) {
-  TileMap tm = make_tilemap(d, nrhs);
-  return 8L * tm.per_xcd * nrhs;
+// Load cases per block of the 3D apply (a divisor of nrhs).  A block that
+// handles all load cases reads the moduli, mask and D^-1 once for all of them
+// (the byte saving of batched load cases); blocks that split them hold fewer
+// registers and keep more blocks in flight.  Measured at 192 x 96 x 96 with
+// 4 load cases (the kernels are bound by arithmetic and latency, not HBM):
+// FP32, all cases per block 128 us against 125 us for one case per block;
+// FP64, 280 us against 216 us (256 VGPRs, one wave per SIMD).  So FP32 grids
+// with 1024 or more tiles take all load cases per block; FP64 applies and
+// smaller grids take one.  TOPO_APPLY_NRB overrides the choice (it must
+// divide nrhs).
+int apply_rhs_per_block(const OpDesc& d, int nrhs, int elem_bytes) {
+  if (d.dim != 3 || nrhs <= 1) return 1;
+  if (const char* e = getenv("TOPO_APPLY_NRB")) {
+    const int v = atoi(e);
+    if (v >= 1 && v <= nrhs && nrhs % v == 0) return v;
+  }
+  if (elem_bytes != 4) return 1;
+  const TileMap tm = make_tilemap(d, 1);
+  return 8L * tm.per_xcd >= 1024 ? nrhs : 1;
+}
+
+long apply_grid_blocks(const OpDesc& d, int nrhs, int elem_bytes) {
+  const int nrb = apply_rhs_per_block(d, nrhs, elem_bytes);
+  TileMap tm = make_tilemap(d, nrhs / nrb);
+  return 8L * tm.per_xcd * (nrhs / nrb);
+}
+
+// launches apply3d_kernel<T, TE, EPI, NRB> with NRB = the block's load cases
+template <typename T, typename TE, int EPI>
+static void launch_apply3d(Ctx* c, const OpDesc& d, const TE* E, const T* x, T* y, int nrhs,
+                           double* part, const int* stop, const ChebEpi<T>& ce) {
+  const T lam = T(c->m.lam0 * c->m.vol), mu = T(c->m.mu0 * c->m.vol);
+  const int nrb = apply_rhs_per_block(d, nrhs, (int)sizeof(T));
+  const TileMap tm = make_tilemap(d, nrhs / nrb);
+  const unsigned blocks = (unsigned)(8L * tm.per_xcd * (nrhs / nrb));
+  hipStream_t s = c->stream;
+  int g = 1;
+  if (const char* e = getenv("TOPO_APPLY_G")) g = atoi(e);
+#define TOPO_APPLY3D(NRB_, G_) \
+  apply3d_kernel<T, TE, EPI, NRB_, G_><<<blocks, 256, 0, s>>>(x, y, E, d, tm, lam, mu, part, stop, ce)
+  if (nrb == 4 && g == 4) TOPO_APPLY3D(4, 4);
+  else if (nrb == 4 && g == 2) TOPO_APPLY3D(4, 2);
+  else if (nrb == 4) TOPO_APPLY3D(4, 1);
+  else if (nrb == 2 && g >= 2) TOPO_APPLY3D(2, 2);
+  else if (nrb == 2) TOPO_APPLY3D(2, 1);
+  else if (nrb == 3) TOPO_APPLY3D(3, 1);
+  else TOPO_APPLY3D(1, 1);
+#undef TOPO_APPLY3D
 }
 
 OpDesc fine_op(const Ctx* c) {
@@ -445,8 +534,7 @@ static void apply_dispatch(Ctx* c, const OpDesc& d, const TE* E, const T* x, T* 
   if (d.dim == 2)
     apply2d_kernel<T, TE><<<blocks, 256, 0, c->stream>>>(x, y, E, d, tm, lam, mu, part, st);
   else
-    apply3d_kernel<T, TE, 0><<<blocks, 256, 0, c->stream>>>(x, y, E, d, tm, lam, mu, part, st,
-                                                            ChebEpi<T>{});
+    launch_apply3d<T, TE, 0>(c, d, E, x, y, nrhs, part, st, ChebEpi<T>{});
 }
 
 // degree-2 smoothing from x = 0 (3D): x = d0 + c1 d0 + c2 D^-1 (b - K d0),
@@ -455,12 +543,8 @@ template <typename T, typename TE>
 static void cheb_pre3d(Ctx* c, const OpDesc& d, const TE* E, const T* b, T* x, const T* invd,
                        const double* lmax, double r_cur, double r_prev, double low, int kind,
                        int nrhs, const int* stop) {
-  const T lam = T(c->m.lam0 * c->m.vol), mu = T(c->m.mu0 * c->m.vol);
-  const TileMap tm = make_tilemap(d, nrhs);
-  const unsigned blocks = (unsigned)(8L * tm.per_xcd * nrhs);
   ChebEpi<T> ce{x, invd, b, lmax, r_cur, r_prev, low, kind};
-  apply3d_kernel<T, TE, 2><<<blocks, 256, 0, c->stream>>>(nullptr, nullptr, E, d, tm, lam, mu,
-                                                          nullptr, stop, ce);
+  launch_apply3d<T, TE, 2>(c, d, E, nullptr, nullptr, nrhs, nullptr, stop, ce);
 }
 
 // degree-2 smoothing from a given x (3D), two kernels (EPI 3, EPI 4); the
@@ -470,14 +554,9 @@ template <typename T, typename TE>
 static void cheb_post3d(Ctx* c, const OpDesc& d, const TE* E, T* x, const T* b, T* r, T* dd,
                         const T* invd, const double* lmax, double r_cur, double r_prev, double low,
                         int kind, int nrhs, const int* stop) {
-  const T lam = T(c->m.lam0 * c->m.vol), mu = T(c->m.mu0 * c->m.vol);
-  const TileMap tm = make_tilemap(d, nrhs);
-  const unsigned blocks = (unsigned)(8L * tm.per_xcd * nrhs);
   ChebEpi<T> ce{x, invd, b, lmax, r_cur, r_prev, low, kind, r, dd};
-  apply3d_kernel<T, TE, 3><<<blocks, 256, 0, c->stream>>>(x, nullptr, E, d, tm, lam, mu, nullptr,
-                                                          stop, ce);
-  apply3d_kernel<T, TE, 4><<<blocks, 256, 0, c->stream>>>(dd, nullptr, E, d, tm, lam, mu, nullptr,
-                                                          stop, ce);
+  launch_apply3d<T, TE, 3>(c, d, E, x, nullptr, nrhs, nullptr, stop, ce);
+  launch_apply3d<T, TE, 4>(c, d, E, dd, nullptr, nrhs, nullptr, stop, ce);
 }
 
 template <typename T>

@@ -183,19 +183,28 @@ __device__ __forceinline__ void cube_force(const T (&u)[8][3], const T (&lam)[6]
   tet_stress<T, 1, 2, 0>(e02, e26, e67, lam[3], mu[3], S3);  // 0-2-6-7
   tet_stress<T, 2, 0, 1>(e04, e45, e57, lam[4], mu[4], S4);  // 0-4-5-7
   tet_stress<T, 2, 1, 0>(e04, e46, e67, lam[5], mu[5], S5);  // 0-4-6-7
+  // Corner sums share their partial sums: tetrahedra 0,1 / 2,3 / 4,5 leave
+  // corner 0 along x / y / z (column pi0 of their stress), and the pairs
+  // meeting at corners 3, 5, 6 (e_pi0 + e_pi1) enter corner 7 along the
+  // same axis (column pi2).
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    // corner 0: -sum S_t[:, pi0]; corner 7: sum S_t[:, pi2]
-    f[0][k] = -(((S0[k][0] + S1[k][0]) + (S2[k][1] + S3[k][1])) + (S4[k][2] + S5[k][2]));
-    f[7][k] = ((S0[k][2] + S1[k][1]) + (S2[k][2] + S3[k][0])) + (S4[k][1] + S5[k][0]);
+    const T ax = S0[k][0] + S1[k][0];   // column pi0 of the tets leaving along x
+    const T ay = S2[k][1] + S3[k][1];   // ... along y
+    const T az = S4[k][2] + S5[k][2];   // ... along z
+    const T c3 = S0[k][2] + S2[k][2];   // column pi2 of the tets through corner 3
+    const T c5 = S1[k][1] + S4[k][1];   // ... through corner 5
+    const T c6 = S3[k][0] + S5[k][0];   // ... through corner 6
+    f[0][k] = -((ax + ay) + az);
+    f[7][k] = (c3 + c5) + c6;
     // corners e_pi0: S[:, pi0] - S[:, pi1]
-    f[1][k] = (S0[k][0] - S0[k][1]) + (S1[k][0] - S1[k][2]);
-    f[2][k] = (S2[k][1] - S2[k][0]) + (S3[k][1] - S3[k][2]);
-    f[4][k] = (S4[k][2] - S4[k][0]) + (S5[k][2] - S5[k][1]);
+    f[1][k] = ax - (S0[k][1] + S1[k][2]);
+    f[2][k] = ay - (S2[k][0] + S3[k][2]);
+    f[4][k] = az - (S4[k][0] + S5[k][1]);
     // corners e_pi0 + e_pi1: S[:, pi1] - S[:, pi2]
-    f[3][k] = (S0[k][1] - S0[k][2]) + (S2[k][0] - S2[k][2]);
-    f[5][k] = (S1[k][2] - S1[k][1]) + (S4[k][0] - S4[k][1]);
-    f[6][k] = (S3[k][2] - S3[k][0]) + (S5[k][1] - S5[k][0]);
+    f[3][k] = (S0[k][1] + S2[k][0]) - c3;
+    f[5][k] = (S1[k][2] + S4[k][0]) - c5;
+    f[6][k] = (S3[k][2] + S5[k][1]) - c6;
   }
 }
 

@@ -22,6 +22,7 @@ namespace topo {
 
 constexpr double kHelmRtol = 1e-12;   // relative residual of the filter solve
 constexpr int kHelmMaxit = 4000;
+constexpr int kHelmNoWaitIters = 256;   // iterations queued per filter call without host waits
 
 static inline unsigned cdivu(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
@@ -373,10 +374,13 @@ void launch_filter_helmholtz(Ctx* c, const double* rho, const double* dc, double
     helm_init_kernel<2><<<nb, 256, 0, s>>>(rho, dc, x, r, p, invd, g.nx, g.ny, 1, uni, hc, nn,
                                            c->partials);
   helm_init_fin<<<1, 256, 0, s>>>(c->partials, nb, kHelmRtol, st);
+  // no-wait contexts queue a fixed budget of gated iterations
+  const bool nowait = c->prob.sync_mode == TOPO_SYNC_NONE;
+  const int maxit = nowait ? kHelmNoWaitIters : kHelmMaxit;
   const int batch = 8;
   bool stop = false;
   int b = 0;
-  for (int it = 0; it < kHelmMaxit && !stop; it += batch, ++b) {
+  for (int it = 0; it < maxit && !stop; it += batch, ++b) {
     for (int k = 0; k < batch; ++k) {
       if (g.dim == 3)
         helm_apply_kernel<3><<<nb, 256, 0, s>>>(p, q, g.nx, g.ny, g.nz, uni, hc, nn, c->partials, st);
@@ -384,9 +388,10 @@ void launch_filter_helmholtz(Ctx* c, const double* rho, const double* dc, double
         helm_apply_kernel<2><<<nb, 256, 0, s>>>(p, q, g.nx, g.ny, 1, uni, hc, nn, c->partials, st);
       helm_alpha_fin<<<1, 256, 0, s>>>(c->partials, nb, st);
       helm_update_kernel<<<nb, 256, 0, s>>>(x, r, p, q, invd, nn, c->partials, st);
-      helm_beta_fin<<<1, 256, 0, s>>>(c->partials, nb, kHelmMaxit, st, status);
+      helm_beta_fin<<<1, 256, 0, s>>>(c->partials, nb, maxit, st, status);
       helm_dir_kernel<<<nb, 256, 0, s>>>(p, r, invd, nn, st);
     }
+    if (nowait) continue;
     // poll the previous batch's flag while this batch runs
     const int sl = b & 1;
     (void)hipMemcpyAsync((void*)&c->pinned[14 + sl], &st->done, sizeof(int), hipMemcpyDeviceToHost, s);

@@ -32,7 +32,8 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(const double* __restrict_
                                                        const double* __restrict__ Ku, double* u,
                                                        double* r, const uint8_t* __restrict__ mask,
                                                        long nn, int dim, int warm,
-                                                       double* partials) {
+                                                       double* partials, const int* gate) {
+  if (gate && *gate) return;
   const long nd = nn * dim;
   double acc[2 * NR];
 #pragma unroll
@@ -63,7 +64,9 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(const double* __restrict_
 
 // rr and the reference norm ff come from the partials; tol2 = rtol^2 ff
 template <int NR>
-__global__ void pcg_init_fin(const double* partials, long nb, double rtol, PcgState* st) {
+__global__ void pcg_init_fin(const double* partials, long nb, double rtol, PcgState* st,
+                             const int* gate) {
+  if (gate && *gate) return;
   __shared__ double tot[2 * NR];
   reduce_partials<2 * NR, 0>(partials, nb, tot);
   if (threadIdx.x == 0) pcg_init_finish<NR>(tot, rtol, st);
@@ -172,7 +175,8 @@ template <int NR>
 __global__ __launch_bounds__(256) void resid64_kernel(const double* __restrict__ f,
                                                       const double* __restrict__ Ku,
                                                       const uint8_t* __restrict__ mask, long nn,
-                                                      int dim, double* partials) {
+                                                      int dim, double* partials, const int* gate) {
+  if (gate && *gate) return;
   const long nd = nn * dim;
   double acc[NR];
 #pragma unroll
@@ -192,9 +196,12 @@ __global__ __launch_bounds__(256) void resid64_kernel(const double* __restrict__
 }
 
 // flag[0] = 1 when a load case's true residual exceeds rtol ||f||; the
-// recursive norms are replaced by the true ones
+// recursive norms are replaced by the true ones.  skip (no-wait solves) is
+// set to the opposite: the next restart pass runs only when one is due.
 template <int NR>
-__global__ void resid64_fin(const double* partials, long nb, PcgState* st, int* flag) {
+__global__ void resid64_fin(const double* partials, long nb, PcgState* st, int* flag,
+                            int* skip) {
+  if (skip && *skip) return;
   __shared__ double tot[NR];
   reduce_partials<NR, 0>(partials, nb, tot);
   if (threadIdx.x == 0) {
@@ -204,6 +211,7 @@ __global__ void resid64_fin(const double* partials, long nb, PcgState* st, int* 
       if (st->ff[k] > 0.0 && tot[k] > st->tol2[k]) again = 1;
     }
     *flag = again;
+    if (skip) *skip = !again;
   }
 }
 
@@ -352,6 +360,25 @@ struct FlexTrait<double> {
 // Flexible CG with the FP32 multigrid V-cycle: FP64 x, r, p, q and dot
 // products; the V-cycle reads the FP32 residual written by the update
 // kernel and returns the preconditioned residual in FP32.
+// Host side of a queue of CG iterations, called after batch b: in
+// TOPO_SYNC_POLL mode the device's done flag is copied to pinned memory and
+// the previous batch's copy is read, so the queue stays one batch deep; in
+// TOPO_SYNC_NONE mode nothing is read and the caller queues its whole budget
+// (the kernels of a converged solve return at once).
+static bool poll_done(Ctx* c, const int* done, int b) {
+  if (c->prob.sync_mode == TOPO_SYNC_NONE) return false;
+  const int sl = b & 1;
+  (void)hipMemcpyAsync((void*)&c->pinned[sl], done, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  (void)hipEventRecord(c->ev_poll[sl], c->stream);
+  if (b == 0) return false;
+  (void)hipEventSynchronize(c->ev_poll[sl ^ 1]);
+  return c->pinned[sl ^ 1] != 0;
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 template <int NR>
 static void mixed_flex_iterate(Ctx* c, double* x, double* r, double* p, double* q, int maxit) {
   const long nd = c->g.nd;
@@ -360,7 +387,7 @@ static void mixed_flex_iterate(Ctx* c, double* x, double* r, double* p, double* 
   hipStream_t s = c->stream;
   const unsigned gb = red_grid(nd);
   const unsigned gd = dir_grid(nd);
-  const long nb_apply = apply_grid_blocks(fine_op(c), NR);
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR, 8);
   float* zb[2] = {c->z32, c->z32b};
   launch_to_f32(c, c->r32, r, (int64_t)NR * nd);
   gmg_vcycle_f32(c, c->r32, zb[0], NR);
@@ -387,14 +414,7 @@ static void mixed_flex_iterate(Ctx* c, double* x, double* r, double* p, double* 
       zi ^= 1;
     }
     it += nbt;
-    const int sl = b & 1;
-    (void)hipMemcpyAsync((void*)&c->pinned[sl], &st->done, sizeof(int), hipMemcpyDeviceToHost, s);
-    (void)hipEventRecord(c->ev_poll[sl], s);
-    if (b > 0) {
-      (void)hipEventSynchronize(c->ev_poll[sl ^ 1]);
-      if (c->pinned[sl ^ 1]) stop = true;
-    }
-    ++b;
+    stop = poll_done(c, &st->done, b++);
   }
 }
 
@@ -419,7 +439,7 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
   };
   capture(0);
   const unsigned gb = red_grid(nd);
-  const long nb_apply = apply_grid_blocks(fine_op(c), NR);
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR, (int)sizeof(TV));
   if (gmg) {
     Prec<TV>::vcycle(c, r, z, NR);
     pcg_rz_kernel<NR, TV><<<gb, 256, 0, s>>>(r, z, nd, c->partials, st);
@@ -479,15 +499,7 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
       capture(it + k + 1);
     }
     it += nbt;
-    // poll the previous batch's flag while this batch runs
-    const int sl = b & 1;
-    (void)hipMemcpyAsync((void*)&c->pinned[sl], &st->done, sizeof(int), hipMemcpyDeviceToHost, s);
-    (void)hipEventRecord(c->ev_poll[sl], s);
-    if (b > 0) {
-      (void)hipEventSynchronize(c->ev_poll[sl ^ 1]);
-      if (c->pinned[sl ^ 1]) stop = true;
-    }
-    ++b;
+    stop = poll_done(c, &st->done, b++);
   }
 }
 
@@ -609,7 +621,7 @@ static void fcg_iterate(Ctx* c, double* x, double* r, double* z, int maxit) {
   int* status = &c->scal->status;
   hipStream_t s = c->stream;
   const unsigned gb = red_grid(nd);
-  const long nb_apply = apply_grid_blocks(fine_op(c), NR);
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR, 8);
   const int m = kFcgWindow;
   constexpr int per = 16 / NR;   // directions per dot-product launch
   int it = 0, b = 0, k = 0;
@@ -656,8 +668,9 @@ static void fcg_iterate(Ctx* c, double* x, double* r, double* z, int maxit) {
 
 // iteration totals over the restart passes of one run: 0 clear, 1 add the
 // pass just finished, 2 report the total as the run's count
-__global__ void iters_sum_kernel(PcgState* st, int mode) {
+__global__ void iters_sum_kernel(PcgState* st, int mode, const int* gate = nullptr) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (gate && *gate) return;
   if (mode == 0) st->iters_sum = 0;
   else if (mode == 1) st->iters_sum += st->iters;
   else st->iters = st->iters_sum;
@@ -695,19 +708,28 @@ static void pcg_run(Ctx* c, double* u, double* info, bool warm) {
   bool fallback = false;
   if (learned) iters_mark_kernel<<<1, 1, 0, s>>>(st, 0, &c->scal->status);
   iters_sum_kernel<<<1, 1, 0, s>>>(st, 0);
+  // No-wait solves queue every restart pass; a pass runs on the device only
+  // while the previous pass left a true residual above rtol (pass_skip = 0).
+  const bool nowait = c->prob.sync_mode == TOPO_SYNC_NONE;
+  int* skip = nowait ? &c->scal->pass_skip : nullptr;
+  if (nowait) set_int_kernel<<<1, 1, 0, s>>>(skip, 0);
   for (int pass = 0; pass < 4; ++pass) {
     const bool w = warm || pass > 0;
-    if (w) launch_apply(c, u, c->q, NR, false);
+    const int* gate = pass > 0 ? skip : nullptr;
+    const int pass_maxit = (nowait && pass > 0) ? std::max(16, maxit / 4) : maxit;
+    if (w) launch_apply_op(c, fine_op(c), c->E, u, c->q, NR, false, c->prob.precision == TOPO_FP64, gate);
     pcg_init_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, u, c->r, c->mask, c->g.nn, c->g.dim, w,
-                                           c->partials);
-    pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, c->prob.rtol, st);
+                                           c->partials, gate);
+    pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, c->prob.rtol, st, gate);
     if (learned) fcg_iterate<NR>(c, u, c->r, c->z, maxit);
-    else pcg_iterate<NR, double>(c, u, c->r, c->p, c->q, c->z, maxit);
-    iters_sum_kernel<<<1, 1, 0, s>>>(st, 1);
+    else pcg_iterate<NR, double>(c, u, c->r, c->p, c->q, c->z, pass_maxit);
+    iters_sum_kernel<<<1, 1, 0, s>>>(st, 1, gate);
     if (!check) break;
-    launch_apply(c, u, c->q, NR, false);
-    resid64_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, c->mask, c->g.nn, c->g.dim, c->partials);
-    resid64_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st, &c->scal->restart);
+    launch_apply_op(c, fine_op(c), c->E, u, c->q, NR, false, c->prob.precision == TOPO_FP64, gate);
+    resid64_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, c->mask, c->g.nn, c->g.dim, c->partials,
+                                          gate);
+    resid64_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st, &c->scal->restart, skip);
+    if (nowait) continue;
     (void)hipMemcpyAsync((void*)&c->pinned[8], &c->scal->restart, sizeof(int),
                          hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync((void*)&c->pinned[9], &st->done, 3 * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -883,7 +905,7 @@ static void mixed_run(Ctx* c, double* u, double* info, bool warm) {
     }
     // inner FP32 solve of K d = r to kInnerRtol, then u += d
     inner_init_kernel<NR, float><<<gb, 256, 0, s>>>(c->x32, c->r32, nd, c->partials);
-    pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, kInnerRtol, st);
+    pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, kInnerRtol, st, nullptr);
     pcg_iterate<NR, float>(c, c->x32, c->r32, c->p32, c->q32, c->z32, c->prob.maxit);
     ir_accumulate_kernel<NR><<<gb, 256, 0, s>>>(u, c->x32, nd, ir);
     ir_step_done<<<1, 1, 0, s>>>(ir, st);

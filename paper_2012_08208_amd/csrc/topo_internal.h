@@ -95,7 +95,7 @@ struct DevScalars {
   double scratch[8];
   int restart;      // mixed-precision CG: true residual above tolerance
   int status;       // sticky device status
-  int pad;
+  int pass_skip;    // no-wait solves: 1 while no true-residual restart is due
   unsigned counters[16];  // last-block-done counters, one per reduction site
   double fcg_pq[kFcgRing][kMaxRhs];       // (p_j, K p_j) of the ring slots
   double fcg_beta[kFcgWindow][kMaxRhs];   // orthogonalisation coefficients
@@ -259,7 +259,8 @@ void launch_simp_modulus(Ctx* c, const double* rho);
 void launch_apply(Ctx* c, const double* x, double* y, int nrhs, bool fuse_dot);
 void launch_apply_f32(Ctx* c, const float* x, float* y, int nrhs, bool fuse_dot);
 OpDesc fine_op(const Ctx* c);
-long apply_grid_blocks(const OpDesc& d, int nrhs);
+long apply_grid_blocks(const OpDesc& d, int nrhs, int elem_bytes);
+int apply_rhs_per_block(const OpDesc& d, int nrhs, int elem_bytes);
 void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, double* y,
                      int nrhs, bool fuse_dot, bool timed, const int* stop);
 void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,

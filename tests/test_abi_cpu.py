@@ -215,3 +215,27 @@ def test_noalloc_oc_update_rejects_bad_arguments_on_the_host():
     assert call(10, move=0.0) == -1
     assert call(10, eta=0.0) == -1
     assert call(10, rho_min=0.0) == -1
+
+
+def test_no_wait_mode_validates_on_the_host():
+    """TOPO_SYNC_NONE (no host wait inside the path calls) is accepted with
+    the FP64 and mixed FP32/BF16 multigrid or Jacobi solves and every
+    filter; it is refused (TOPO_E_INVALID) with the host-driven refinement
+    loop of TOPO_MIXED_IR and with the learned preconditioner, and an unknown
+    mode is refused."""
+    b = _lib()
+    lib = b.load_library()
+    n = ctypes.c_size_t(0)
+    for prec in (b.TOPO_FP64, b.TOPO_MIXED_FP32, b.TOPO_MIXED_BF16):
+        for pc in (b.TOPO_PC_JACOBI, b.TOPO_PC_GMG):
+            for flt in (b.TOPO_FILTER_DISTANCE, b.TOPO_FILTER_HELMHOLTZ, b.TOPO_FILTER_DENSITY):
+                p = b.make_problem(3, (8, 4, 4), nrhs=2, precision=prec, precond=pc, filter=flt,
+                                   sync_mode=b.TOPO_SYNC_NONE)
+                assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    p = b.make_problem(3, (8, 4, 4), precision=b.TOPO_MIXED_IR, precond=b.TOPO_PC_GMG,
+                       sync_mode=b.TOPO_SYNC_NONE)
+    assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+    p = b.make_problem(3, (8, 4, 4), precond=b.TOPO_PC_LEARNED, sync_mode=b.TOPO_SYNC_NONE)
+    assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+    p = b.make_problem(3, (8, 4, 4), sync_mode=2)
+    assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1

@@ -1,0 +1,102 @@
+"""The path calls without host waits (topo_problem.sync_mode = TOPO_SYNC_NONE),
+through the C ABI.
+
+One SIMP iteration (solve, sensitivity, filter, OC: Sec. 4.3-4.5 and the
+Appendix loop) is captured in a HIP graph with topo_iterate(..., 1) and
+replayed several times, with eager work and synchronisations between the
+replays; every replay must equal, bit for bit, the same iteration run
+eagerly.  The no-wait context must also give the same bits as the polling
+context (the skipped iterations and restarts do nothing), in FP64 and in the
+mixed-precision solve, with the distance and the Helmholtz filter.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _ctx(p, prec, sync, stream, filt):
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_FP32, TOPO_PC_GMG, Topo
+    with torch.cuda.stream(stream):
+        return Topo.from_problem(p, precision=TOPO_FP64 if prec == "fp64" else TOPO_MIXED_FP32,
+                                 precond=TOPO_PC_GMG, rtol=1e-10, maxit=160, warm_start=True,
+                                 device=DEV, sync_mode=sync, filter=filt)
+
+
+def _state(p, stream):
+    from paper_2012_08208_amd import LOG_LEN
+    with torch.cuda.stream(stream):
+        rho = torch.full((p.n_cells,), p.volfrac, dtype=torch.float64, device=DEV)
+        u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=DEV)
+        log = torch.zeros(LOG_LEN, dtype=torch.float64, device=DEV)
+    return rho, u, log
+
+
+@pytest.mark.parametrize("prec,filt", [("fp64", 0), ("mixed", 0), ("mixed", 1)])
+def test_iteration_captured_in_a_graph_replays_bit_equal(prec, filt):
+    from paper_2012_08208_amd import TOPO_SYNC_NONE, TOPO_SYNC_POLL
+    p = synth.cantilever3d(20, 10, 9, nrhs=2, volfrac=0.3, rmin=1.5)
+    print(f"[nowait] {prec} filter {filt} nel={p.nel} nrhs={p.nrhs}", flush=True)
+    s_eager, s_poll, s_graph = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    n_rep = 3
+    # eager, no-wait context: the reference trajectory, one iteration per call
+    te = _ctx(p, prec, TOPO_SYNC_NONE, s_eager, filt)
+    rho_e, u_e, log_e = _state(p, s_eager)
+    ref = []
+    for k in range(n_rep):
+        with torch.cuda.stream(s_eager):
+            assert te.iterate(rho_e, u_e, 1, 0.0, log_e) == 1
+        assert te.sync() == 0
+        ref.append((rho_e.clone(), u_e.clone(), log_e.clone()))
+    te.close()
+    # the polling context gives the same bits
+    tp = _ctx(p, prec, TOPO_SYNC_POLL, s_poll, filt)
+    rho_p, u_p, log_p = _state(p, s_poll)
+    for k in range(n_rep):
+        with torch.cuda.stream(s_poll):
+            tp.iterate(rho_p, u_p, 1, 0.0, log_p)
+        assert tp.sync() == 0
+        assert torch.equal(rho_p, ref[k][0]) and torch.equal(u_p, ref[k][1])
+        assert torch.equal(log_p, ref[k][2])
+    tp.close()
+    # captured once, replayed n_rep times
+    tg = _ctx(p, prec, TOPO_SYNC_NONE, s_graph, filt)
+    rho_g, u_g, log_g = _state(p, s_graph)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s_graph):
+        tg.iterate(rho_g, u_g, 1, 0.0, log_g)
+    torch.cuda.synchronize()
+    # capture launches nothing: the state is still the initial one
+    assert torch.all(rho_g == p.volfrac) and torch.all(u_g == 0)
+    for k in range(n_rep):
+        with torch.cuda.stream(s_graph):
+            g.replay()
+        torch.cuda.synchronize()
+        assert tg.sync() == 0
+        print(f"  replay {k + 1}: compliance {log_g[0].item():.10g} "
+              f"(eager {ref[k][2][0].item():.10g})", flush=True)
+        assert torch.equal(rho_g, ref[k][0]), k
+        assert torch.equal(u_g, ref[k][1]), k
+        assert torch.equal(log_g, ref[k][2]), k
+        # eager work of the program between replays
+        scratch = torch.randn(1 << 16, device=DEV)
+        assert torch.isfinite(scratch.sum()).item()
+    del g
+    tg.close()
+
+
+def test_no_wait_iterate_refuses_a_change_tolerance():
+    from paper_2012_08208_amd import TOPO_SYNC_NONE, TopoError
+    p = synth.cantilever2d(24, 12)
+    t = _ctx(p, "fp64", TOPO_SYNC_NONE, torch.cuda.current_stream(), 0)
+    rho, u, log = _state(p, torch.cuda.current_stream())
+    with pytest.raises(TopoError):
+        t.iterate(rho, u, 1, 0.01, log)
+    t.close()
