@@ -555,6 +555,71 @@ int topo_edm_filter(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t
                     const double* w, const double* R, const double* rho, const double* dc,
                     double* dcf, void* stream);
 
+/* ------------------------------------------------------------------------
+ * The SIMP loop on an arbitrary P1 simplex mesh (Sec. 6.1: the loop runs
+ * unchanged on an imported tetrahedral mesh; its filter takes the actual
+ * cell midpoints, Sec. 3.2.2, built in chunks, Sec. 6.2).  Triangles (2D,
+ * plane stress) or tetrahedra (3D), any node positions and numbering.
+ * The operator is applied element by element in two passes without
+ * atomics (cells write their corner forces to node-sorted slots, nodes sum
+ * their slots in a fixed order), so results are the same on every run.
+ * The solve is Jacobi-preconditioned FP64 CG with the FP64 true-residual
+ * restarts of topo_solve.  On such a mesh the cells differ in volume; the
+ * loop follows the listing: it filters the sensitivity per unit volume,
+ * s_e = (dc/drho_e) / |T_e|, and its OC volume constraint counts cells,
+ * sum_e rho_e = volfrac * N_c.
+ *
+ * prob: the topo_problem fields of the material (E0, Emin, nu), SIMP (penal,
+ *   volfrac, move, eta, rho_min), solver (rtol, maxit, warm_start,
+ *   sync_mode) and nrhs; dim is 2 or 3; nel, split2d, rmin, gmg_levels and
+ *   filter are ignored.  precision must be TOPO_FP64, precond
+ *   TOPO_PC_JACOBI, paper_mode 0 (else TOPO_E_INVALID).
+ * coords: host, FP64 SoA [dim][n_nodes]; cells: host, int32 [n_cells][dim+1]
+ *   node ids; fixed_mask: host uint8 [dim][n_nodes], nonzero = fixed.  All
+ *   three are copied at creation; a degenerate cell (zero or non-finite
+ *   volume) or an out-of-range node id gives TOPO_E_INVALID.
+ * Vectors: FP64 [nrhs][dim][n_nodes]; densities and sensitivities FP64
+ *   [n_cells] in the caller's cell order.  Workspace, streams, sticky
+ *   status and sync_mode behave as for topo_create (the create call
+ *   synchronises once).
+ * ---------------------------------------------------------------------- */
+typedef struct topo_umesh topo_umesh;
+
+/* Workspace bytes; TOPO_E_SHAPE for n_nodes or n_cells below 1, n_nodes
+   above 2^31 - 1 or (dim+1) n_cells above 2^31 - 1. */
+int topo_umesh_workspace_size(int32_t dim, int64_t n_nodes, int64_t n_cells, int32_t nrhs,
+                              size_t* bytes /* host */);
+int topo_umesh_create(const topo_problem* prob, int64_t n_nodes, int64_t n_cells,
+                      const double* coords /* host */, const int32_t* cells /* host */,
+                      const uint8_t* fixed_mask /* host */, void* workspace, size_t ws_bytes,
+                      void* stream, topo_umesh** out /* host */);
+int topo_umesh_destroy(topo_umesh* m);
+/* loads f [nrhs][dim][n_nodes] (device, copied) */
+int topo_umesh_set_loads(topo_umesh* m, const double* f, int nrhs);
+/* cell midpoints (vertex averages), SoA [dim][n_cells]: the input of
+   topo_edm_count / topo_edm_fill for this mesh's filter weights */
+int topo_umesh_midpoints(topo_umesh* m, double* mid);
+/* cell volumes |T_e| [n_cells] */
+int topo_umesh_volumes(topo_umesh* m, double* vol);
+/* y = Z K(rho) Z x for every load case (Sec. 3.1, eq. fe_form) */
+int topo_umesh_apply(topo_umesh* m, const double* rho, const double* x, double* y);
+/* K(rho) u_r = f_r for every load case to rtol; info as topo_solve */
+int topo_umesh_solve(topo_umesh* m, const double* rho, double* u, double* info);
+/* compliance c = sum_r f_r^T u_r (device scalar, may be NULL) and
+   dc_e = -p rho_e^(p-1) (E0 - Emin) sum_r u_{r,e}^T K0_e u_{r,e} */
+int topo_umesh_sensitivity(topo_umesh* m, const double* rho, const double* u, double* dc,
+                           double* compliance);
+/* max_iter SIMP iterations in place on rho: solve, sensitivity per unit
+   volume, the midpoint filter on the CSR weights of topo_edm_fill (rowptr,
+   col, w, R; nnz = rowptr[n_cells]) built from topo_umesh_midpoints, and
+   the OC update by cell count.  u is the displacement work/output buffer
+   (warm-started across iterations); log (device, may be NULL) receives
+   max_iter records of TOPO_LOG_LEN doubles (as topo_iterate). */
+int topo_umesh_iterate(topo_umesh* m, double* rho, double* u, int max_iter, int64_t nnz,
+                       const int64_t* rowptr, const int32_t* col, const double* w,
+                       const double* R, double* log);
+int topo_umesh_sync(topo_umesh* m, int* device_status /* host */);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,8 @@ topology optimization in 2D and 3D"):
 * ``oc``    -- the optimality-criteria update with bisection on the
   Lagrange multiplier (Section 3.2, eq. kkt and eq. update; Section 3.2.1);
 * ``simp``  -- the iteration loop (Section 4.3-4.5 and the Appendix code);
+* ``umesh`` -- the same loop on an arbitrary simplex mesh (Section 6.1),
+  with the midpoint filter of Section 3.2.2 and Section 6.2;
 * ``net``   -- the convolutional preconditioner network of this library
   (not in the paper): forward, backward, loss and Adam, in FP64 with
   optional BF16 rounding at the points where the kernels store.
@@ -24,4 +26,4 @@ the benchmark may import this package.  It shares no code with the HIP
 path and imports nothing from it.
 """
 
-from . import mesh, fem, filt, oc, simp, net  # noqa: F401
+from . import mesh, fem, filt, oc, simp, umesh, net  # noqa: F401

@@ -3,7 +3,7 @@ compliance sensitivity, distance-weighted filter and OC update as HIP
 kernels behind a C ABI (``include/topo.h``), after arXiv 2012.08208."""
 
 from .binding import (  # noqa: F401
-    Topo, Batch, EdmFilter, TopoError, make_problem, load_library, status_string, check_exports,
+    Topo, Batch, EdmFilter, UMesh, TopoError, make_problem, load_library, status_string, check_exports,
     TOPO_SPLIT_ALT_ROWS, TOPO_SPLIT_UNIFORM, TOPO_FP64, TOPO_MIXED_FP32, TOPO_MIXED_IR,
     TOPO_MIXED_BF16, TOPO_PASSIVE_FREE, TOPO_PASSIVE_VOID, TOPO_PASSIVE_SOLID,
     TOPO_FILTER_DISTANCE, TOPO_FILTER_HELMHOLTZ, TOPO_FILTER_DENSITY,

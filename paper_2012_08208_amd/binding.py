@@ -53,6 +53,9 @@ EXPORTED = [
     "topo_batch_uses_graphs",
     "topo_edm_workspace_size", "topo_edm_count", "topo_edm_fill", "topo_edm_filter",
     "topo_oc_update_noalloc",
+    "topo_umesh_workspace_size", "topo_umesh_create", "topo_umesh_destroy",
+    "topo_umesh_set_loads", "topo_umesh_midpoints", "topo_umesh_volumes", "topo_umesh_apply",
+    "topo_umesh_solve", "topo_umesh_sensitivity", "topo_umesh_iterate", "topo_umesh_sync",
 ]
 OC_NOALLOC_MAX_CELLS = 2147483647
 BATCH_REC_LEN = 6
@@ -135,6 +138,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.topo_edm_filter.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.topo_filter_taps.argtypes = [i32, i32, dbl, P(ctypes.c_int32), P(ctypes.c_int32)]
     lib.topo_oc_update_noalloc.argtypes = [i64, vp, vp, vp, dbl, dbl, dbl, dbl, vp, vp]
+    lib.topo_umesh_workspace_size.argtypes = [i32, i64, i64, i32, P(szt)]
+    lib.topo_umesh_create.argtypes = [P(CProblem), i64, i64, vp, vp, vp, vp, szt, vp, P(vp)]
+    lib.topo_umesh_destroy.argtypes = [vp]
+    lib.topo_umesh_set_loads.argtypes = [vp, vp, i32]
+    lib.topo_umesh_midpoints.argtypes = [vp, vp]
+    lib.topo_umesh_volumes.argtypes = [vp, vp]
+    lib.topo_umesh_apply.argtypes = [vp, vp, vp, vp]
+    lib.topo_umesh_solve.argtypes = [vp, vp, vp, vp]
+    lib.topo_umesh_sensitivity.argtypes = [vp, vp, vp, vp, vp]
+    lib.topo_umesh_iterate.argtypes = [vp, vp, vp, i32, i64, vp, vp, vp, vp, vp]
+    lib.topo_umesh_sync.argtypes = [vp, P(i32)]
     lib.topo_status_string.argtypes = [i32]
     lib.topo_status_string.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -593,6 +607,121 @@ class EdmFilter:
                                         self._vec(dc, "dc"), self._vec(dcf, "dcf"),
                                         ctypes.c_void_p(self.stream.cuda_stream)),
                "topo_edm_filter")
+
+
+class UMesh:
+    """The SIMP loop on an arbitrary simplex mesh (topo_umesh_*), on the
+    current torch stream.  ``up`` has dim, coords [N, dim], cells
+    [N_c, dim+1], fixed [dim][N], loads [nrhs][dim][N] and the SIMP
+    parameters (synth.UProblem)."""
+
+    def __init__(self, up, rtol=None, maxit: int = 20000, warm_start: bool = False,
+                 sync_mode: int = TOPO_SYNC_POLL, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.dim, self.nrhs = int(up.dim), int(up.loads.shape[0])
+        self.n_nodes, self.n_cells = int(up.coords.shape[0]), int(up.cells.shape[0])
+        self.device = torch.device(device)
+        cp = make_problem(self.dim, (1,) * self.dim, self.nrhs, TOPO_SPLIT_UNIFORM, up.E0, up.Emin,
+                          up.nu, up.penal, up.volfrac, 1.0, up.move, up.eta, up.rho_min, TOPO_FP64,
+                          TOPO_PC_JACOBI, up.rtol if rtol is None else rtol, maxit, False,
+                          warm_start, sync_mode=sync_mode)
+        self.prob = cp
+        coords = np.ascontiguousarray(np.asarray(up.coords, dtype=np.float64).T)
+        cells = np.ascontiguousarray(np.asarray(up.cells), dtype=np.int32)
+        fixed = np.ascontiguousarray(np.asarray(up.fixed), dtype=np.uint8)
+        if coords.shape != (self.dim, self.n_nodes) or cells.shape != (self.n_cells, self.dim + 1) \
+                or fixed.shape != (self.dim, self.n_nodes):
+            raise TopoError("coords [N, dim], cells [N_c, dim+1] and fixed [dim][N] expected")
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib.topo_umesh_workspace_size(self.dim, self.n_nodes, self.n_cells, self.nrhs,
+                                                  ctypes.byref(nbytes)), "topo_umesh_workspace_size")
+        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        wp = self.ws.data_ptr() + (-self.ws.data_ptr()) % 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.topo_umesh_create(ctypes.byref(cp), self.n_nodes, self.n_cells,
+                                          coords.ctypes.data, cells.ctypes.data, fixed.ctypes.data,
+                                          ctypes.c_void_p(wp), int(nbytes.value),
+                                          ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(h)), "topo_umesh_create")
+        self.h = h
+        self.set_loads(torch.as_tensor(np.ascontiguousarray(up.loads), dtype=torch.float64,
+                                       device=self.device))
+
+    def _ptr(self, t, numel, name):
+        torch = self.torch
+        if t is None:
+            return None
+        if (not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64
+                or not t.is_contiguous() or t.numel() != numel):
+            raise TopoError(f"{name} must be a contiguous float64 CUDA tensor of {numel} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    @property
+    def n_dofs(self):
+        return self.dim * self.n_nodes
+
+    def vec_numel(self):
+        return self.nrhs * self.n_dofs
+
+    def set_loads(self, f):
+        _check(self.lib.topo_umesh_set_loads(self.h, self._ptr(f, self.vec_numel(), "f"), self.nrhs),
+               "topo_umesh_set_loads")
+
+    def midpoints(self, mid):
+        _check(self.lib.topo_umesh_midpoints(self.h, self._ptr(mid, self.dim * self.n_cells, "mid")),
+               "topo_umesh_midpoints")
+
+    def volumes(self, vol):
+        _check(self.lib.topo_umesh_volumes(self.h, self._ptr(vol, self.n_cells, "vol")),
+               "topo_umesh_volumes")
+
+    def apply(self, rho, x, y):
+        _check(self.lib.topo_umesh_apply(self.h, self._ptr(rho, self.n_cells, "rho"),
+                                         self._ptr(x, self.vec_numel(), "x"),
+                                         self._ptr(y, self.vec_numel(), "y")), "topo_umesh_apply")
+
+    def solve(self, rho, u, info=None):
+        _check(self.lib.topo_umesh_solve(self.h, self._ptr(rho, self.n_cells, "rho"),
+                                         self._ptr(u, self.vec_numel(), "u"),
+                                         self._ptr(info, SOLVE_INFO_LEN, "info")), "topo_umesh_solve")
+
+    def sensitivity(self, rho, u, dc, compliance=None):
+        _check(self.lib.topo_umesh_sensitivity(self.h, self._ptr(rho, self.n_cells, "rho"),
+                                               self._ptr(u, self.vec_numel(), "u"),
+                                               self._ptr(dc, self.n_cells, "dc"),
+                                               self._ptr(compliance, 1, "compliance")),
+               "topo_umesh_sensitivity")
+
+    def iterate(self, rho, u, max_iter: int, edm, log=None):
+        """max_iter SIMP iterations; ``edm`` is an EdmFilter built from this
+        mesh's midpoints (its CSR weights and row sums)."""
+        _check(self.lib.topo_umesh_iterate(self.h, self._ptr(rho, self.n_cells, "rho"),
+                                           self._ptr(u, self.vec_numel(), "u"), int(max_iter),
+                                           int(edm.nnz), ctypes.c_void_p(edm.rowptr.data_ptr()),
+                                           ctypes.c_void_p(edm.col.data_ptr()),
+                                           ctypes.c_void_p(edm.w.data_ptr()),
+                                           ctypes.c_void_p(edm.R.data_ptr()),
+                                           self._ptr(log, int(max_iter) * LOG_LEN, "log")),
+               "topo_umesh_iterate")
+
+    def sync(self) -> int:
+        st = ctypes.c_int(0)
+        _check(self.lib.topo_umesh_sync(self.h, ctypes.byref(st)), "topo_umesh_sync")
+        return int(st.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.topo_umesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def oc_update_noalloc(rho, dcf, rho_new, out, volfrac: float, move: float = 0.2,

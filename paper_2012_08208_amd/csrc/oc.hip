@@ -174,6 +174,27 @@ void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, do
   oc_final_fin<<<1, 256, 0, s>>>(c->partials, nb, nc, p.eta, st, scalars, &c->scal->status);
 }
 
+// The update for a plain design: no passive cells, every cell of volume
+// weight 1, a_e formed again in every pass (no per-cell scratch).  Used by
+// the allocation-free entry point and by the unstructured-mesh loop, whose
+// volume constraint counts cells.
+void oc_update_plain(hipStream_t s, long nc, const double* rho, const double* dcf,
+                     double* rho_new, double volfrac, double move, double eta, double rho_min,
+                     double* partials, OcState* st, int* status, double* scalars) {
+  const unsigned nb = red_grid(nc);
+  oc_init_kernel<<<nb, 256, 0, s>>>(rho, dcf, nullptr, nc, move, eta, rho_min, nullptr, nullptr,
+                                    partials);
+  oc_init_fin<<<1, 256, 0, s>>>(partials, nb, nc, volfrac, st, status);
+  for (int k = 0; k < kOcPasses; ++k) {
+    oc_pass_kernel<<<nb, 256, 0, s>>>(rho, nullptr, dcf, eta, nc, move, rho_min, nullptr, nullptr,
+                                      partials, st);
+    oc_pass_fin<<<1, 256, 0, s>>>(partials, nb, nc, st);
+  }
+  oc_final_kernel<<<nb, 256, 0, s>>>(rho, nullptr, dcf, eta, rho_new, nc, move, rho_min, nullptr,
+                                     nullptr, partials, st);
+  oc_final_fin<<<1, 256, 0, s>>>(partials, nb, nc, eta, st, scalars, status);
+}
+
 // ---------------------------------------------- allocation-free OC update
 // The update above for a plain design of n cells (no passive cells, unit
 // cell volumes), for callers that cannot allocate device memory.  Its
@@ -230,20 +251,9 @@ extern "C" int topo_oc_update_noalloc(int64_t n, const double* rho, const double
   OcState* st = reinterpret_cast<OcState*>(base + kNaStateOff);
   int* status = reinterpret_cast<int*>(base + kNaStatusOff);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const long nc = (long)n;
-  const unsigned nb = red_grid(nc);
   oc_na_reset<<<1, 1, 0, s>>>(status);
-  oc_init_kernel<<<nb, 256, 0, s>>>(rho, dcf, nullptr, nc, move, eta, rho_min, nullptr, nullptr,
-                                    partials);
-  oc_init_fin<<<1, 256, 0, s>>>(partials, nb, nc, volfrac, st, status);
-  for (int k = 0; k < kOcPasses; ++k) {
-    oc_pass_kernel<<<nb, 256, 0, s>>>(rho, nullptr, dcf, eta, nc, move, rho_min, nullptr, nullptr,
-                                      partials, st);
-    oc_pass_fin<<<1, 256, 0, s>>>(partials, nb, nc, st);
-  }
-  oc_final_kernel<<<nb, 256, 0, s>>>(rho, nullptr, dcf, eta, rho_new, nc, move, rho_min, nullptr,
-                                     nullptr, partials, st);
-  oc_final_fin<<<1, 256, 0, s>>>(partials, nb, nc, eta, st, out, status);
+  oc_update_plain(s, (long)n, rho, dcf, rho_new, volfrac, move, eta, rho_min, partials, st, status,
+                  out);
   oc_na_status<<<1, 1, 0, s>>>(status, out);
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }

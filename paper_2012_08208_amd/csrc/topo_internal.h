@@ -311,6 +311,9 @@ int filter_taps_host(int dim, int split, double rmin, std::vector<FilterTap>& ta
                      int* stride);
 int filter_tap_stride(int dim, int split, double rmin);
 void oc_update(Ctx* c, const double* rho, const double* dcf, double* rho_new, double* scalars);
+void oc_update_plain(hipStream_t s, long nc, const double* rho, const double* dcf,
+                     double* rho_new, double volfrac, double move, double eta, double rho_min,
+                     double* partials, OcState* st, int* status, double* scalars);
 void launch_log_record(Ctx* c, double* rec, const double* info);
 int timing_begin(Ctx* c, int chan);
 void timing_end(Ctx* c, int chan, int slot);

@@ -33,3 +33,4 @@ from .problems import (  # noqa: F401
     node_id,
 )
 from .fields import rho_uniform, rho_random, rho_smooth, vec_random  # noqa: F401
+from .umesh import UProblem, jittered_cantilever, from_structured  # noqa: F401

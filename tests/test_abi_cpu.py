@@ -239,3 +239,36 @@ def test_no_wait_mode_validates_on_the_host():
     assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
     p = b.make_problem(3, (8, 4, 4), sync_mode=2)
     assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+
+
+def test_umesh_entry_points_validate_on_the_host():
+    """topo_umesh_workspace_size and topo_umesh_create check sizes, the
+    problem and the node ids before any HIP call: errors come back with no
+    GPU."""
+    import numpy as np
+    b = _lib()
+    lib = b.load_library()
+    n = ctypes.c_size_t(0)
+    assert lib.topo_umesh_workspace_size(3, 10, 12, 2, ctypes.byref(n)) == 0 and n.value > 0
+    assert lib.topo_umesh_workspace_size(4, 10, 12, 1, ctypes.byref(n)) == -1
+    assert lib.topo_umesh_workspace_size(3, 10, 12, 5, ctypes.byref(n)) == -1
+    assert lib.topo_umesh_workspace_size(3, 0, 12, 1, ctypes.byref(n)) == -2
+    assert lib.topo_umesh_workspace_size(3, 10, 2 ** 30, 1, ctypes.byref(n)) == -2
+    coords = np.zeros((3, 4))
+    cells = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    fixed = np.zeros((3, 4), np.uint8)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_void_p(1 << 20)      # never touched: validation fails first
+    good = b.make_problem(3, (1, 1, 1), 1)
+    for bad in (b.make_problem(3, (1, 1, 1), 1, precond=b.TOPO_PC_GMG),
+                b.make_problem(3, (1, 1, 1), 1, precision=b.TOPO_MIXED_FP32),
+                b.make_problem(3, (1, 1, 1), 1, paper_mode=True)):
+        assert lib.topo_umesh_create(ctypes.byref(bad), 4, 1, coords.ctypes.data,
+                                     cells.ctypes.data, fixed.ctypes.data, ws, 1 << 30, None,
+                                     ctypes.byref(h)) == -1
+    bad_cells = np.array([[0, 1, 2, 7]], dtype=np.int32)
+    assert lib.topo_umesh_create(ctypes.byref(good), 4, 1, coords.ctypes.data,
+                                 bad_cells.ctypes.data, fixed.ctypes.data, ws, 1 << 30, None,
+                                 ctypes.byref(h)) == -1
+    assert lib.topo_umesh_create(ctypes.byref(good), 4, 1, coords.ctypes.data, cells.ctypes.data,
+                                 fixed.ctypes.data, ws, 16, None, ctypes.byref(h)) == -7
