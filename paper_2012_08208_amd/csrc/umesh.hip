@@ -17,6 +17,12 @@
 // So every y is the same on every run.  The shape gradients g_a and |T| of
 // every cell are formed once from the coordinates (inverse Jacobian).
 //
+// Inside, nodes and cells are renumbered for locality: nodes in the Morton
+// order of their coordinates, cells in the Morton order of their
+// midpoints, so a cell's corners and its neighbours' sit close in memory
+// however the caller numbered them.  Arguments keep the caller's numbering;
+// vectors are permuted at the boundary of each call.
+//
 // On this mesh the cells differ in volume; the loop follows the listing:
 // the filtered sensitivity is the derivative per unit volume,
 // s_e = (dc/drho_e) / |T_e|, and the OC volume constraint counts cells.
@@ -49,12 +55,14 @@ struct UMesh {
   hipStream_t stream;
   double lam0, mu0;
   uint8_t* mask;
+  int32_t* nperm;   // internal node -> caller node
+  int32_t* cperm;   // internal cell -> caller cell
   int32_t* cell;
   int32_t* slot;
   int64_t* iptr;
   double *G, *vol, *mid;
   double* F;
-  double *f, *r, *p, *q, *invd;
+  double *f, *r, *p, *q, *invd, *x;
   double *E, *dc, *s, *sf, *rho_new;
   double* partials;
   UState* st;
@@ -68,8 +76,8 @@ namespace {
 constexpr int kUBatch = 8;   // CG iterations queued between host polls
 
 struct ULayout {
-  size_t mask, cell, slot, iptr, G, vol, mid, F, f, r, p, q, invd, E, dc, s, sf, rho_new,
-      partials, st, total;
+  size_t mask, nperm, cperm, cell, slot, iptr, G, vol, mid, F, f, r, p, q, invd, x, E, dc, s, sf,
+      rho_new, partials, st, total;
 };
 
 ULayout u_layout(int dim, long nn, long nc, int nrhs) {
@@ -82,6 +90,8 @@ ULayout u_layout(int dim, long nn, long nc, int nrhs) {
   };
   const long nv = dim + 1, nd = dim * nn;
   L.mask = take((size_t)nn);
+  L.nperm = take((size_t)nn * 4);
+  L.cperm = take((size_t)nc * 4);
   L.cell = take((size_t)nc * nv * 4);
   L.slot = take((size_t)nc * nv * 4);
   L.iptr = take((size_t)(nn + 1) * 8);
@@ -95,6 +105,7 @@ ULayout u_layout(int dim, long nn, long nc, int nrhs) {
   L.p = take((size_t)nrhs * nd * 8);
   L.q = take((size_t)nrhs * nd * 8);
   L.invd = take((size_t)nd * 8);
+  L.x = take((size_t)nrhs * nd * 8);
   L.E = take((size_t)nc * 8);
   L.dc = take((size_t)nc * 8);
   L.s = take((size_t)nc * 8);
@@ -127,7 +138,8 @@ bool u_valid(const topo_problem* p) {
 // g_0 = -sum), |T| = |det J| / dim! and the vertex average of every cell.
 template <int DIM>
 __global__ void ugeom_kernel(const double* __restrict__ X, const int32_t* __restrict__ cell,
-                             long nn, long nc, double* G, double* vol, double* mid, int* bad) {
+                             const int32_t* __restrict__ cperm, long nn, long nc, double* G,
+                             double* vol, double* mid, int* bad) {
   constexpr int NV = DIM + 1;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nc) return;
@@ -178,15 +190,16 @@ __global__ void ugeom_kernel(const double* __restrict__ X, const int32_t* __rest
   for (int c = 0; c < DIM; ++c) {
     double m = 0.0;
     for (int a = 0; a < NV; ++a) m += x[a][c];
-    mid[c * nc + e] = m / NV;
+    mid[c * nc + cperm[e]] = m / NV;   // caller's cell order
   }
 }
 
-__global__ void umod_kernel(double* E, const double* __restrict__ rho, long nc, double E0,
-                            double Emin, double penal) {
+__global__ void umod_kernel(double* E, const double* __restrict__ rho,
+                            const int32_t* __restrict__ cperm, long nc, double E0, double Emin,
+                            double penal) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nc) return;
-  const double r = rho[e];
+  const double r = rho[cperm[e]];
   const double rp = (penal == 3.0) ? r * r * r : pow(r, penal);
   E[e] = Emin + rp * (E0 - Emin);
 }
@@ -530,7 +543,8 @@ __global__ __launch_bounds__(256) void usens_kernel(const double* __restrict__ u
                                                     const double* __restrict__ rho,
                                                     const double* __restrict__ G,
                                                     const double* __restrict__ vol,
-                                                    const int32_t* __restrict__ cell, double* dc,
+                                                    const int32_t* __restrict__ cell,
+                                                    const int32_t* __restrict__ cperm, double* dc,
                                                     double* s, long nn, long nc, double lam0,
                                                     double mu0, double E0, double Emin,
                                                     double penal, double* partials) {
@@ -565,11 +579,12 @@ __global__ __launch_bounds__(256) void usens_kernel(const double* __restrict__ u
     }
     const double v = vol[e];
     w *= v;
-    const double rv = rho[e];
+    const long ec = cperm[e];   // the caller's cell index
+    const double rv = rho[ec];
     const double rp1 = (penal == 3.0) ? rv * rv : pow(rv, penal - 1.0);
     const double d = -penal * rp1 * (E0 - Emin) * w;
-    dc[e] = d;
-    s[e] = d / v;
+    dc[ec] = d;
+    s[ec] = d / v;
     const double Ee = Emin + rp1 * rv * (E0 - Emin);
     acc[0] += Ee * w;
     acc[1] += Ee * w / (2.0 * v);
@@ -723,8 +738,8 @@ static void u_sens(UMesh* m, const double* rho, const double* u, double* dc, dou
   double* pe = m->partials;
   double* pf = m->partials + (size_t)kRedBlocks / 2 * kPartStride;
   usens_kernel<DIM, NR><<<std::min(ge, (unsigned)(kRedBlocks / 2)), 256, 0, s>>>(
-      u, rho, m->G, m->vol, m->cell, dc, m->s, m->nn, m->nc, m->lam0, m->mu0, p.E0, p.Emin,
-      p.penal, pe);
+      u, rho, m->G, m->vol, m->cell, m->cperm, dc, m->s, m->nn, m->nc, m->lam0, m->mu0, p.E0,
+      p.Emin, p.penal, pe);
   ufu_kernel<NR><<<std::min(gf, (unsigned)(kRedBlocks / 2)), 256, 0, s>>>(m->f, u, nd, pf);
   usens_fin<<<1, 256, 0, s>>>(pe, std::min(ge, (unsigned)(kRedBlocks / 2)), pf,
                               std::min(gf, (unsigned)(kRedBlocks / 2)), m->st, compliance);
@@ -766,14 +781,72 @@ struct OpSens {
   }
 };
 
-template <typename T>
-__global__ void umask_copy_kernel(const T* src, T* dst, const uint8_t* mask, long nn, int dim,
-                                  long total) {
+// caller-ordered nodal vector -> internal order (fixed DOFs zeroed when
+// mask is given)
+__global__ void uperm_in_kernel(double* dst, const double* __restrict__ src,
+                                const int32_t* __restrict__ nperm, const uint8_t* mask, long nn,
+                                int dim, long total) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
-  const long n = i % nn;
-  const int c = (int)((i / nn) % dim);
-  dst[i] = ((mask[n] >> c) & 1) ? T(0) : src[i];
+  const long n = i % nn, rc = i / nn;
+  double v = src[rc * nn + nperm[n]];
+  if (mask && ((mask[n] >> (int)(rc % dim)) & 1)) v = 0.0;
+  dst[i] = v;
+}
+
+__global__ void uperm_out_kernel(double* dst, const double* __restrict__ src,
+                                 const int32_t* __restrict__ nperm, long nn, long total) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long n = i % nn, rc = i / nn;
+  dst[rc * nn + nperm[n]] = src[i];
+}
+
+__global__ void uperm_cells_out_kernel(double* dst, const double* __restrict__ src,
+                                       const int32_t* __restrict__ cperm, long nc) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nc) dst[cperm[e]] = src[e];
+}
+
+static void u_in(UMesh* m, double* dst, const double* src, bool masked) {
+  const long total = (long)m->prob.nrhs * m->dim * m->nn;
+  uperm_in_kernel<<<ublocks(total), 256, 0, m->stream>>>(dst, src, m->nperm,
+                                                        masked ? m->mask : nullptr, m->nn, m->dim,
+                                                        total);
+}
+
+static void u_out(UMesh* m, double* dst, const double* src) {
+  const long total = (long)m->prob.nrhs * m->dim * m->nn;
+  uperm_out_kernel<<<ublocks(total), 256, 0, m->stream>>>(dst, src, m->nperm, m->nn, total);
+}
+
+// Morton (Z-order) keys of points: 21 bits per axis over the bounding box
+static std::vector<int32_t> morton_order(const std::vector<double>& pts, int dim, long n) {
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  for (int c = 0; c < dim; ++c) {
+    lo[c] = hi[c] = n > 0 ? pts[(size_t)c * n] : 0.0;
+    for (long i = 0; i < n; ++i) {
+      lo[c] = std::min(lo[c], pts[(size_t)c * n + i]);
+      hi[c] = std::max(hi[c], pts[(size_t)c * n + i]);
+    }
+  }
+  std::vector<std::pair<uint64_t, int32_t>> key((size_t)n);
+  for (long i = 0; i < n; ++i) {
+    uint64_t k = 0;
+    uint32_t q[3] = {0, 0, 0};
+    for (int c = 0; c < dim; ++c) {
+      const double span = hi[c] > lo[c] ? hi[c] - lo[c] : 1.0;
+      const double t = (pts[(size_t)c * n + i] - lo[c]) / span;
+      q[c] = (uint32_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
+    }
+    for (int b = 20; b >= 0; --b)
+      for (int c = 0; c < dim; ++c) k = (k << 1) | ((q[c] >> b) & 1u);
+    key[(size_t)i] = {k, (int32_t)i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> order((size_t)n);
+  for (long i = 0; i < n; ++i) order[(size_t)i] = key[(size_t)i].second;
+  return order;
 }
 
 }  // namespace topo
@@ -805,23 +878,43 @@ int topo_umesh_create(const topo_problem* prob, int64_t n_nodes, int64_t n_cells
   if (ws_bytes < need || ((uintptr_t)workspace & 255)) return TOPO_E_WORKSPACE;
   const int dim = prob->dim, nv = dim + 1;
   const long nn = (long)n_nodes, nc = (long)n_cells, ninc = nc * nv;
-  // node-sorted incidence list (counting sort of the cell corners)
+  for (long k = 0; k < ninc; ++k)
+    if (cells[k] < 0 || cells[k] >= nn) return TOPO_E_INVALID;
+  // internal numbering: nodes by the Morton order of their coordinates,
+  // cells by the Morton order of their vertex averages
+  std::vector<double> pts(coords, coords + (size_t)dim * nn);
+  const std::vector<int32_t> nperm = morton_order(pts, dim, nn);   // internal -> caller
+  std::vector<int32_t> ninv((size_t)nn);
+  for (long i = 0; i < nn; ++i) ninv[(size_t)nperm[(size_t)i]] = (int32_t)i;
+  std::vector<double> cmid((size_t)dim * nc, 0.0);
+  for (long e = 0; e < nc; ++e)
+    for (int c = 0; c < dim; ++c) {
+      double acc = 0.0;
+      for (int a = 0; a < nv; ++a) acc += pts[(size_t)c * nn + cells[e * nv + a]];
+      cmid[(size_t)c * nc + e] = acc / nv;
+    }
+  const std::vector<int32_t> cperm = morton_order(cmid, dim, nc);  // internal -> caller
+  std::vector<int32_t> icell((size_t)ninc);
+  for (long e = 0; e < nc; ++e)
+    for (int a = 0; a < nv; ++a)
+      icell[(size_t)(e * nv + a)] = ninv[(size_t)cells[(size_t)cperm[(size_t)e] * nv + a]];
+  std::vector<double> icoord((size_t)dim * nn);
+  for (int c = 0; c < dim; ++c)
+    for (long i = 0; i < nn; ++i)
+      icoord[(size_t)c * nn + i] = pts[(size_t)c * nn + nperm[(size_t)i]];
+  // node-sorted incidence list (a counting sort of the cell corners)
   std::vector<int64_t> iptr((size_t)nn + 1, 0);
-  for (long k = 0; k < ninc; ++k) {
-    const int32_t n = cells[k];
-    if (n < 0 || n >= nn) return TOPO_E_INVALID;
-    iptr[(size_t)n + 1] += 1;
-  }
+  for (long k = 0; k < ninc; ++k) iptr[(size_t)icell[(size_t)k] + 1] += 1;
   for (long n = 0; n < nn; ++n) iptr[(size_t)n + 1] += iptr[(size_t)n];
   std::vector<int32_t> slot((size_t)ninc);
   {
     std::vector<int64_t> next(iptr.begin(), iptr.end() - 1);
-    for (long k = 0; k < ninc; ++k) slot[(size_t)k] = (int32_t)next[(size_t)cells[k]]++;
+    for (long k = 0; k < ninc; ++k) slot[(size_t)k] = (int32_t)next[(size_t)icell[(size_t)k]]++;
   }
   std::vector<uint8_t> bits((size_t)nn, 0);
   for (int c = 0; c < dim; ++c)
-    for (long n = 0; n < nn; ++n)
-      if (fixed_mask[(size_t)c * nn + n]) bits[(size_t)n] |= (uint8_t)(1u << c);
+    for (long i = 0; i < nn; ++i)
+      if (fixed_mask[(size_t)c * nn + nperm[(size_t)i]]) bits[(size_t)i] |= (uint8_t)(1u << c);
   topo_umesh* m = new topo_umesh();
   m->prob = *prob;
   m->dim = dim;
@@ -836,6 +929,8 @@ int topo_umesh_create(const topo_problem* prob, int64_t n_nodes, int64_t n_cells
   const ULayout L = u_layout(dim, nn, nc, prob->nrhs);
   char* w = static_cast<char*>(workspace);
   m->mask = (uint8_t*)(w + L.mask);
+  m->nperm = (int32_t*)(w + L.nperm);
+  m->cperm = (int32_t*)(w + L.cperm);
   m->cell = (int32_t*)(w + L.cell);
   m->slot = (int32_t*)(w + L.slot);
   m->iptr = (int64_t*)(w + L.iptr);
@@ -848,6 +943,7 @@ int topo_umesh_create(const topo_problem* prob, int64_t n_nodes, int64_t n_cells
   m->p = (double*)(w + L.p);
   m->q = (double*)(w + L.q);
   m->invd = (double*)(w + L.invd);
+  m->x = (double*)(w + L.x);
   m->E = (double*)(w + L.E);
   m->dc = (double*)(w + L.dc);
   m->s = (double*)(w + L.s);
@@ -862,19 +958,24 @@ int topo_umesh_create(const topo_problem* prob, int64_t n_nodes, int64_t n_cells
        hipEventCreateWithFlags(&m->ev[1], hipEventDisableTiming) == hipSuccess;
   hipStream_t s = m->stream;
   UState zero{};
-  ok = ok && hipMemcpyAsync(m->mask, bits.data(), bits.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-  ok = ok && hipMemcpyAsync(m->cell, cells, (size_t)ninc * 4, hipMemcpyHostToDevice, s) == hipSuccess;
-  ok = ok && hipMemcpyAsync(m->slot, slot.data(), (size_t)ninc * 4, hipMemcpyHostToDevice, s) == hipSuccess;
-  ok = ok && hipMemcpyAsync(m->iptr, iptr.data(), iptr.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess;
-  ok = ok && hipMemcpyAsync(m->F, coords, (size_t)dim * nn * 8, hipMemcpyHostToDevice, s) == hipSuccess;
-  ok = ok && hipMemcpyAsync(m->st, &zero, sizeof(zero), hipMemcpyHostToDevice, s) == hipSuccess;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    ok = ok && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  up(m->mask, bits.data(), bits.size());
+  up(m->nperm, nperm.data(), (size_t)nn * 4);
+  up(m->cperm, cperm.data(), (size_t)nc * 4);
+  up(m->cell, icell.data(), (size_t)ninc * 4);
+  up(m->slot, slot.data(), (size_t)ninc * 4);
+  up(m->iptr, iptr.data(), iptr.size() * 8);
+  up(m->F, icoord.data(), (size_t)dim * nn * 8);
+  up(m->st, &zero, sizeof(zero));
   if (ok) {
     if (dim == 2)
-      ugeom_kernel<2><<<ublocks(nc), 256, 0, s>>>(m->F, m->cell, nn, nc, m->G, m->vol, m->mid,
-                                                  &m->st->bad_cells);
+      ugeom_kernel<2><<<ublocks(nc), 256, 0, s>>>(m->F, m->cell, m->cperm, nn, nc, m->G, m->vol,
+                                                  m->mid, &m->st->bad_cells);
     else
-      ugeom_kernel<3><<<ublocks(nc), 256, 0, s>>>(m->F, m->cell, nn, nc, m->G, m->vol, m->mid,
-                                                  &m->st->bad_cells);
+      ugeom_kernel<3><<<ublocks(nc), 256, 0, s>>>(m->F, m->cell, m->cperm, nn, nc, m->G, m->vol,
+                                                  m->mid, &m->st->bad_cells);
     ok = hipMemcpyAsync((void*)&m->pinned[4], &m->st->bad_cells, sizeof(int), hipMemcpyDeviceToHost,
                         s) == hipSuccess;
     ok = ok && hipStreamSynchronize(s) == hipSuccess && hipGetLastError() == hipSuccess;
@@ -901,8 +1002,7 @@ int topo_umesh_destroy(topo_umesh* m) {
 int topo_umesh_set_loads(topo_umesh* m, const double* f, int nrhs) {
   if (!m || !f) return TOPO_E_INVALID;
   if (nrhs != m->prob.nrhs) return TOPO_E_SHAPE;
-  TOPO_HIP(hipMemcpyAsync(m->f, f, (size_t)nrhs * m->dim * m->nn * 8, hipMemcpyDeviceToDevice,
-                          m->stream));
+  u_in(m, m->f, f, false);
   m->loads_set = true;
   return TOPO_OK;
 }
@@ -916,18 +1016,18 @@ int topo_umesh_midpoints(topo_umesh* m, double* mid) {
 
 int topo_umesh_volumes(topo_umesh* m, double* vol) {
   if (!m || !vol) return TOPO_E_INVALID;
-  TOPO_HIP(hipMemcpyAsync(vol, m->vol, (size_t)m->nc * 8, hipMemcpyDeviceToDevice, m->stream));
-  return TOPO_OK;
+  uperm_cells_out_kernel<<<ublocks(m->nc), 256, 0, m->stream>>>(vol, m->vol, m->cperm, m->nc);
+  return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
 
 int topo_umesh_apply(topo_umesh* m, const double* rho, const double* x, double* y) {
   if (!m || !rho || !x || !y || x == y) return TOPO_E_INVALID;
   const topo_problem& p = m->prob;
-  const long total = (long)p.nrhs * m->dim * m->nn;
-  umod_kernel<<<ublocks(m->nc), 256, 0, m->stream>>>(m->E, rho, m->nc, p.E0, p.Emin, p.penal);
-  umask_copy_kernel<double><<<ublocks(total), 256, 0, m->stream>>>(x, m->q, m->mask, m->nn,
-                                                                  m->dim, total);
-  u_dispatch<OpApply>(m, (const double*)m->q, y);
+  umod_kernel<<<ublocks(m->nc), 256, 0, m->stream>>>(m->E, rho, m->cperm, m->nc, p.E0, p.Emin,
+                                                     p.penal);
+  u_in(m, m->q, x, true);
+  u_dispatch<OpApply>(m, (const double*)m->q, m->r);
+  u_out(m, y, m->r);
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
 
@@ -935,8 +1035,11 @@ int topo_umesh_solve(topo_umesh* m, const double* rho, double* u, double* info) 
   if (!m || !rho || !u) return TOPO_E_INVALID;
   if (!m->loads_set) return TOPO_E_STATE;
   const topo_problem& p = m->prob;
-  umod_kernel<<<ublocks(m->nc), 256, 0, m->stream>>>(m->E, rho, m->nc, p.E0, p.Emin, p.penal);
-  u_dispatch<OpSolve>(m, u, info, p.warm_start != 0);
+  umod_kernel<<<ublocks(m->nc), 256, 0, m->stream>>>(m->E, rho, m->cperm, m->nc, p.E0, p.Emin,
+                                                     p.penal);
+  if (p.warm_start) u_in(m, m->x, u, false);
+  u_dispatch<OpSolve>(m, m->x, info, p.warm_start != 0);
+  u_out(m, u, m->x);
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
 
@@ -944,7 +1047,8 @@ int topo_umesh_sensitivity(topo_umesh* m, const double* rho, const double* u, do
                            double* compliance) {
   if (!m || !rho || !u || !dc) return TOPO_E_INVALID;
   if (!m->loads_set) return TOPO_E_STATE;
-  u_dispatch<OpSens>(m, rho, u, dc, compliance);
+  u_in(m, m->x, u, false);
+  u_dispatch<OpSens>(m, rho, (const double*)m->x, dc, compliance);
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
 
@@ -956,11 +1060,12 @@ int topo_umesh_iterate(topo_umesh* m, double* rho, double* u, int max_iter, int6
   if (!m->loads_set) return TOPO_E_STATE;
   const topo_problem& p = m->prob;
   hipStream_t s = m->stream;
+  if (p.warm_start) u_in(m, m->x, u, false);
   for (int it = 0; it < max_iter; ++it) {
     const bool warm = it > 0 || p.warm_start != 0;
-    umod_kernel<<<ublocks(m->nc), 256, 0, s>>>(m->E, rho, m->nc, p.E0, p.Emin, p.penal);
-    u_dispatch<OpSolve>(m, u, (double*)nullptr, warm);
-    u_dispatch<OpSens>(m, (const double*)rho, (const double*)u, m->dc, (double*)nullptr);
+    umod_kernel<<<ublocks(m->nc), 256, 0, s>>>(m->E, rho, m->cperm, m->nc, p.E0, p.Emin, p.penal);
+    u_dispatch<OpSolve>(m, m->x, (double*)nullptr, warm);
+    u_dispatch<OpSens>(m, (const double*)rho, (const double*)m->x, m->dc, (double*)nullptr);
     // the listing filters the derivative per unit volume
     int rc = topo_edm_filter((int64_t)m->nc, nnz, rowptr, col, w, R, rho, m->s, m->sf, s);
     if (rc != TOPO_OK) return rc;
@@ -969,6 +1074,7 @@ int topo_umesh_iterate(topo_umesh* m, double* rho, double* u, int max_iter, int6
     if (log) ulog_kernel<<<1, 1, 0, s>>>(m->st, log + (size_t)it * TOPO_LOG_LEN, m->nc, p.nrhs);
     TOPO_HIP(hipMemcpyAsync(rho, m->rho_new, (size_t)m->nc * 8, hipMemcpyDeviceToDevice, s));
   }
+  if (max_iter > 0) u_out(m, u, m->x);
   return hipGetLastError() == hipSuccess ? TOPO_OK : TOPO_E_HIP;
 }
 
