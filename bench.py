@@ -315,6 +315,50 @@ def bench_edm(args):
     return 0
 
 
+def time_to_solution(p, rho, t_bench, prec_bench, args):
+    """After the timed steps (outside the timed region): the system K(rho) u = f
+    of the last design, all load cases, solved from u = 0 to the workload's
+    rtol by FP64 multigrid PCG, by the bench's own solver, and by plain FP64
+    Jacobi PCG (capped at 12000 iterations).  Each solve is timed from its
+    call to the stream's end; iterations and the final FP64 relative
+    residual (max over load cases) come from the solve's info record."""
+    import torch
+    from paper_2012_08208_amd import (SOLVE_INFO_LEN, TOPO_FP64, TOPO_PC_GMG, TOPO_PC_JACOBI, Topo)
+    dev = rho.device
+    rho0 = rho.clone()
+    out = {}
+
+    def run(name, t, reps):
+        u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=dev)
+        info = torch.zeros(SOLVE_INFO_LEN, dtype=torch.float64, device=dev)
+        best = None
+        for _ in range(reps):
+            u.zero_()
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            t.solve(rho0, u, info)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - c0)
+            best = ms if best is None else min(best, ms)
+        st = t.sync()
+        i = info.cpu().numpy()
+        out[name] = {"ms": best, "cg_iterations": float(i[0]), "converged": bool(i[1] == 1.0),
+                     "max_rel_residual": float(max(i[2:2 + p.nrhs])), "status": st}
+        print(f"[bench] time to solution, {name}: {best:.1f} ms, {i[0]:.0f} iterations",
+              file=sys.stderr, flush=True)
+
+    run(args.precision + " multigrid PCG (the timed solver)", t_bench, 2)
+    if prec_bench != TOPO_FP64 or args.precond != "gmg":
+        t64 = Topo.from_problem(p, precision=TOPO_FP64, precond=TOPO_PC_GMG, maxit=args.maxit,
+                                device=dev)
+        run("fp64 multigrid PCG", t64, 2)
+        t64.close()
+    tj = Topo.from_problem(p, precision=TOPO_FP64, precond=TOPO_PC_JACOBI, maxit=12000, device=dev)
+    run("fp64 Jacobi PCG (plain, capped at 12000)", tj, 1)
+    tj.close()
+    return {"design": "rho after the last timed step", "rtol": p.rtol, "solves": out}
+
+
 def bench_umesh(args):
     """SIMP loop on an unstructured stand-in (Sec. 6.1): a jittered (+-0.2),
     holed (3 voids), shuffled Kuhn-tetrahedron mesh over 96 x 48 x 48 cubes,
@@ -761,6 +805,8 @@ def main():
                     help="learned3d: skip the 192x96x96 time-to-solution comparison")
     ap.add_argument("--batch-converge", action="store_true",
                     help="batch2d workload: also run every instance to max change < 0.01")
+    ap.add_argument("--no-compare", dest="compare", action="store_false",
+                    help="cantilever3d: skip the time-to-solution comparison after the timed steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this implementation runs on one GPU only (got --gpus {args.gpus}); "
@@ -803,15 +849,22 @@ def main():
         print(f"[bench] warmup step {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     t.timing_enable(True)
     t.timing_read()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev[0].record(t.stream)
     for s in range(args.steps):
         t.iterate(rho, u, 1, 0.0, log[s * LOG_LEN:(s + 1) * LOG_LEN])
+        ev[s + 1].record(t.stream)
         print(f"[bench] timed step {s + 1}/{args.steps} queued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
     n_apply, apply_ms = t.timing_read()
     status = t.sync()
+    tts = None
+    if args.workload == "cantilever3d" and args.compare:
+        tts = time_to_solution(p, rho, t, prec, args)
     lg = log.cpu().numpy().reshape(-1, LOG_LEN)
     dt = t1 - t0
     ms_step = 1e3 * dt / args.steps
@@ -845,6 +898,8 @@ def main():
             "apply_launches": n_apply,
             "apply_ms_mean": (apply_ms / n_apply) if n_apply else None,
             "apply_share_of_step": (apply_ms / (dt * 1e3)) if n_apply else None,
+            "ms_per_step_median": float(np.median(step_ms)) if step_ms else None,
+            "time_to_solution": tts,
         },
         "roofline": {
             "kernel": "apply3d" if p.dim == 3 else "apply2d",
