@@ -112,8 +112,18 @@ enum { TOPO_SPLIT_ALT_ROWS = 0, TOPO_SPLIT_UNIFORM = 1 };
                     and the FP64 outer iteration and true-residual check are
                     unchanged, so the solution meets rtol as in the other
                     modes.  With the Jacobi preconditioner this is the FP64
-                    solve. */
-enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1, TOPO_MIXED_IR = 2, TOPO_MIXED_BF16 = 3 };
+                    solve.
+   TOPO_MIXED_RU:   flexible CG whose vectors are all FP32 (the correction
+                    to u, residual, search direction, FP32 operator apply,
+                    FP32 V-cycle) with FP64 dot products, and reliable
+                    updates in FP64: whenever a load case's residual norm has
+                    fallen 10x since the last update, or below rtol, the
+                    correction is added to the FP64 u and the FP64 true
+                    residual f - K u replaces the FP32 one; a load case stops
+                    only when its true residual meets rtol.  With the Jacobi
+                    preconditioner this is the FP64 solve. */
+enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1, TOPO_MIXED_IR = 2, TOPO_MIXED_BF16 = 3,
+       TOPO_MIXED_RU = 4 };
 /* Preconditioner of the CG solve.
    TOPO_PC_JACOBI:  z = D^-1 r.
    TOPO_PC_GMG:     one multigrid V-cycle (Chebyshev-Jacobi smoothing,
@@ -172,7 +182,8 @@ typedef struct topo_problem {
   double volfrac;             /* k in (0, 1] */
   double rmin;                /* filter radius in cell widths, > 0 */
   double move, eta, rho_min;  /* OC move limit m, damping eta, lower bound */
-  int32_t precision;  /* TOPO_FP64 | TOPO_MIXED_FP32 | TOPO_MIXED_IR | TOPO_MIXED_BF16 */
+  int32_t precision;  /* TOPO_FP64 | TOPO_MIXED_FP32 | TOPO_MIXED_IR | TOPO_MIXED_BF16 |
+                         TOPO_MIXED_RU */
   int32_t precond;    /* TOPO_PC_JACOBI | TOPO_PC_GMG | TOPO_PC_LEARNED */
   double rtol;        /* stop when ||f_r - K u_r|| <= rtol ||f_r|| for each r */
   int32_t maxit;      /* cap on preconditioned CG iterations per solve */

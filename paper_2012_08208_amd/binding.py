@@ -23,6 +23,7 @@ TOPO_FP64 = 0
 TOPO_MIXED_FP32 = 1
 TOPO_MIXED_IR = 2
 TOPO_MIXED_BF16 = 3
+TOPO_MIXED_RU = 4
 TOPO_PASSIVE_FREE = 0
 TOPO_PASSIVE_VOID = 1
 TOPO_PASSIVE_SOLID = 2

@@ -31,7 +31,8 @@ static bool valid_problem(const topo_problem* p) {
   if (!(p->move > 0.0) || !(p->eta > 0.0) || !(p->rho_min > 0.0 && p->rho_min < 1.0)) return false;
   if (!(p->rtol > 0.0) || p->maxit < 1) return false;
   if (p->precision != TOPO_FP64 && p->precision != TOPO_MIXED_FP32 &&
-      p->precision != TOPO_MIXED_IR && p->precision != TOPO_MIXED_BF16)
+      p->precision != TOPO_MIXED_IR && p->precision != TOPO_MIXED_BF16 &&
+      p->precision != TOPO_MIXED_RU)
     return false;
   if (p->precond != TOPO_PC_JACOBI && p->precond != TOPO_PC_GMG && p->precond != TOPO_PC_LEARNED)
     return false;

@@ -131,8 +131,8 @@ __global__ void pcg_rz_fin(const double* partials, long nb, int first, PcgState*
 }
 
 // flexible CG: partial (r, z_new) and (r, z_old) per load case
-template <int NR, typename TZ = double>
-__global__ __launch_bounds__(256) void pcg_rz2_kernel(const double* __restrict__ r,
+template <int NR, typename TZ = double, typename TR = double>
+__global__ __launch_bounds__(256) void pcg_rz2_kernel(const TR* __restrict__ r,
                                                       const TZ* __restrict__ zn,
                                                       const TZ* __restrict__ zo, long nd,
                                                       double* partials, const PcgState* st) {
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void pcg_rz2_kernel(const double* __restrict__
   for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      const double rv = r[(long)k * nd + d];
+      const double rv = (double)r[(long)k * nd + d];
       acc[k] += rv * (double)zn[(long)k * nd + d];
       acc[NR + k] += rv * (double)zo[(long)k * nd + d];
     }
@@ -357,9 +357,6 @@ struct FlexTrait<double> {
   static double* second(Ctx* c, double* z) { return c->wv ? c->wv : z; }
 };
 
-// Flexible CG with the FP32 multigrid V-cycle: FP64 x, r, p, q and dot
-// products; the V-cycle reads the FP32 residual written by the update
-// kernel and returns the preconditioned residual in FP32.
 // Host side of a queue of CG iterations, called after batch b: in
 // TOPO_SYNC_POLL mode the device's done flag is copied to pinned memory and
 // the previous batch's copy is read, so the queue stays one batch deep; in
@@ -379,6 +376,9 @@ __global__ void set_int_kernel(int* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// Flexible CG with the FP32 multigrid V-cycle: FP64 x, r, p, q and dot
+// products; the V-cycle reads the FP32 residual written by the update
+// kernel and returns the preconditioned residual in FP32.
 template <int NR>
 static void mixed_flex_iterate(Ctx* c, double* x, double* r, double* p, double* q, int maxit) {
   const long nd = c->g.nd;
@@ -416,6 +416,165 @@ static void mixed_flex_iterate(Ctx* c, double* x, double* r, double* p, double* 
     it += nbt;
     stop = poll_done(c, &st->done, b++);
   }
+}
+
+// ------------------------------------------- FP32 CG with reliable updates
+// TOPO_MIXED_RU: flexible CG whose vectors are all FP32 (correction x32,
+// residual r32, direction p32, K p32 from the FP32 operator, FP32 V-cycle)
+// with FP64 dot products and scalars, and reliable updates of the solution
+// and residual in FP64 (Sleijpen and van der Vorst, 1996; as mixed-precision
+// lattice solvers do): whenever a load case's recursive residual norm has
+// fallen by kRuDelta since the last update, or below rtol, the correction is
+// folded into the FP64 solution (u += x32, x32 = 0) and the FP64 true
+// residual r = Zf - K u replaces r32.  The iteration continues with its
+// search direction; a load case stops only when its true residual is below
+// rtol.  Only the updates (one FP64 apply each) run in FP64.
+constexpr double kRuDelta2 = 1e-2;   // update when ||r||^2 fell by 100x
+
+// after x32 += alpha p, r32 -= alpha q: recursive norms, and whether an
+// update is due (ru_skip = 0 makes the update kernels run)
+template <int NR>
+__global__ void ru_update_fin(const double* partials, long nb, PcgState* st, int* skip, const double* rr_max,
+                              int* status) {
+  if (st->done) return;
+  __shared__ double tot[2 * NR];
+  reduce_partials<2 * NR, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    int due = 0;
+    for (int k = 0; k < NR; ++k) {
+      if (!st->active[k]) continue;
+      st->rr[k] = tot[k];
+      if (!isfinite(tot[k])) { st->breakdown = 1; st->active[k] = 0; }
+      if (!(tot[k] > st->tol2[k]) || tot[k] < kRuDelta2 * rr_max[k]) due = 1;
+    }
+    st->iters += 1;
+    *skip = !due;
+    if (st->breakdown) { *status = TOPO_S_NUMERIC; st->done = 1; }
+  }
+}
+
+// the update: u += x32, x32 = 0 (all load cases)
+template <int NR>
+__global__ void ru_fold_kernel(double* u, float* x32, long nd, const int* skip) {
+  if (skip && *skip) return;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)NR * nd;
+       i += (long)gridDim.x * blockDim.x) {
+    u[i] += (double)x32[i];
+    x32[i] = 0.0f;
+  }
+}
+
+// r = Zf - K u in FP64, r32 = (float) r, partial (r, r)
+template <int NR>
+__global__ __launch_bounds__(256) void ru_resid_kernel(const double* __restrict__ f,
+                                                       const double* __restrict__ Ku, float* r32,
+                                                       const uint8_t* __restrict__ mask, long nn,
+                                                       int dim, double* partials, const int* skip) {
+  if (*skip) return;
+  const long nd = nn * dim;
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+  for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
+    const bool fixed = (mask[d % nn] >> (d / nn)) & 1;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const double rv = fixed ? 0.0 : f[(long)k * nd + d] - Ku[(long)k * nd + d];
+      r32[(long)k * nd + d] = (float)rv;
+      acc[k] += rv * rv;
+    }
+  }
+  const double none[1] = {0.0};
+  block_partials<NR, 0>(acc, none, partials);
+}
+
+// true norms replace the recursive ones; a load case stays active while
+// its true residual is above rtol
+template <int NR>
+__global__ void ru_resid_fin(const double* partials, long nb, PcgState* st, int* skip,
+                             double* rr_max) {
+  if (*skip) return;
+  __shared__ double tot[NR];
+  reduce_partials<NR, 0>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    int any = 0;
+    for (int k = 0; k < NR; ++k) {
+      st->rr[k] = tot[k];
+      rr_max[k] = tot[k];
+      st->active[k] = st->ff[k] > 0.0 && tot[k] > st->tol2[k];
+      if (!isfinite(tot[k])) { st->breakdown = 1; st->active[k] = 0; }
+      any |= st->active[k];
+    }
+    st->done = !any;
+    *skip = 1;
+  }
+}
+
+template <int NR>
+__global__ void ru_setup_kernel(const PcgState* st, double* rr_max, int* skip) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int k = 0; k < kMaxRhs; ++k) rr_max[k] = k < NR ? st->rr[k] : 0.0;
+  *skip = 1;
+}
+
+__global__ void ru_zero_kernel(float* x, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] = 0.0f;
+}
+
+// from a state whose FP64 residual r = Zf - K u and norms are set
+template <int NR>
+static void mixed_ru_iterate(Ctx* c, double* u, const double* r, int maxit) {
+  const long nd = c->g.nd;
+  PcgState* st = &c->scal->pcg;
+  int* status = &c->scal->status;
+  int* skip = &c->scal->ru_skip;
+  double* rr_max = c->scal->ru_rr_max;
+  hipStream_t s = c->stream;
+  const unsigned gb = red_grid(nd);
+  const unsigned gd = dir_grid(nd);
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR, 4);
+  float* zb[2] = {c->z32, c->z32b};
+  const float* invd = c->invd32;
+  launch_to_f32(c, c->r32, r, (int64_t)NR * nd);
+  ru_zero_kernel<<<gb, 256, 0, s>>>(c->x32, (long)NR * nd);
+  ru_setup_kernel<NR><<<1, 1, 0, s>>>(st, rr_max, skip);
+  gmg_vcycle_f32(c, c->r32, zb[0], NR);
+  pcg_rz_kernel<NR, float, float><<<gb, 256, 0, s>>>(c->r32, zb[0], nd, c->partials, st);
+  pcg_rz_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, 1, st);
+  pcg_direction_kernel<NR, false, float, float><<<gd, 256, 0, s>>>(c->p32, zb[0], c->r32, invd, nd,
+                                                                   st, 1);
+  const int batch = 2;
+  int zi = 0, it = 0, b = 0;
+  bool stop = false;
+  while (it < maxit && !stop) {
+    const int nbt = (maxit - it < batch) ? (maxit - it) : batch;
+    for (int k = 0; k < nbt; ++k) {
+      launch_apply_op_f32_dot(c, fine_op(c), c->E32, c->p32, c->q32, NR);
+      pcg_alpha_fin<<<1, 256, 0, s>>>(c->partials, nb_apply, st);
+      pcg_update_kernel<NR, false, float><<<gb, 256, 0, s>>>(c->x32, c->r32, c->p32, c->q32,
+                                                            nullptr, nd, c->partials, st);
+      ru_update_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st, skip, rr_max, status);
+      // reliable update, gated on the device flag
+      ru_fold_kernel<NR><<<gb, 256, 0, s>>>(u, c->x32, nd, skip);
+      launch_apply_op(c, fine_op(c), c->E, u, c->q, NR, false, false, skip);
+      ru_resid_kernel<NR><<<gb, 256, 0, s>>>(c->f, c->q, c->r32, c->mask, c->g.nn, c->g.dim,
+                                            c->partials, skip);
+      ru_resid_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st, skip, rr_max);
+      float* zo = zb[zi];
+      float* zn = zb[zi ^ 1];
+      gmg_vcycle_f32(c, c->r32, zn, NR);
+      pcg_rz2_kernel<NR, float, float><<<gb, 256, 0, s>>>(c->r32, zn, zo, nd, c->partials, st);
+      pcg_rz2_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st);
+      pcg_direction_kernel<NR, false, float, float><<<gd, 256, 0, s>>>(c->p32, zn, c->r32, invd,
+                                                                       nd, st, 0);
+      zi ^= 1;
+    }
+    it += nbt;
+    stop = poll_done(c, &st->done, b++);
+  }
+  // whatever correction is left
+  ru_fold_kernel<NR><<<gb, 256, 0, s>>>(u, c->x32, nd, nullptr);
 }
 
 // The CG iteration proper, from a state whose rr/ff/tol2/active are set and
@@ -722,6 +881,8 @@ static void pcg_run(Ctx* c, double* u, double* info, bool warm) {
                                            c->partials, gate);
     pcg_init_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, c->prob.rtol, st, gate);
     if (learned) fcg_iterate<NR>(c, u, c->r, c->z, maxit);
+    else if (c->prob.precision == TOPO_MIXED_RU && c->prob.precond == TOPO_PC_GMG)
+      mixed_ru_iterate<NR>(c, u, c->r, pass_maxit);
     else pcg_iterate<NR, double>(c, u, c->r, c->p, c->q, c->z, pass_maxit);
     iters_sum_kernel<<<1, 1, 0, s>>>(st, 1, gate);
     if (!check) break;

@@ -96,6 +96,8 @@ struct DevScalars {
   int restart;      // mixed-precision CG: true residual above tolerance
   int status;       // sticky device status
   int pass_skip;    // no-wait solves: 1 while no true-residual restart is due
+  int ru_skip;      // reliable-update CG: 0 while an FP64 update is due
+  double ru_rr_max[kMaxRhs];   // reliable-update CG: ||r||^2 at the last update
   unsigned counters[16];  // last-block-done counters, one per reduction site
   double fcg_pq[kFcgRing][kMaxRhs];       // (p_j, K p_j) of the ring slots
   double fcg_beta[kFcgWindow][kMaxRhs];   // orthogonalisation coefficients

@@ -70,12 +70,12 @@ def _check_trajectory(lg, rho, log_ref, rho_ref, volfrac, c_rtol):
     np.testing.assert_allclose(lg[:, 3], [r["change"] for r in log_ref], atol=1e-6)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed-ru"])
 def test_iterate_3d_four_load_cases_distance_filter_50(prec):
-    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_FP32, TOPO_PC_GMG
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_FP32, TOPO_MIXED_RU, TOPO_PC_GMG
     p, rho_ref, log_ref = _oracle_3d4(50)
     print(f"[loop3d] {prec} nel={p.nel} nrhs={p.nrhs} rmin={p.rmin} x50", flush=True)
-    code = TOPO_FP64 if prec == "fp64" else TOPO_MIXED_FP32
+    code = {"fp64": TOPO_FP64, "mixed": TOPO_MIXED_FP32, "mixed-ru": TOPO_MIXED_RU}[prec]
     t = _topo(p, rtol=1e-12 if prec == "fp64" else 1e-10, precond=TOPO_PC_GMG, precision=code)
     n, st, rho, lg = _run_loop(t, p, 50)
     t.close()

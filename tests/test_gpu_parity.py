@@ -96,11 +96,12 @@ def test_apply_f32_and_bf16_moduli(name, p, prec):
         assert np.max(np.abs(y64 - y_ref)) / scale > 10 * err
 
 
-@pytest.mark.parametrize("pc", ["jacobi", "gmg", "mixed-gmg", "bf16-gmg", "ir-gmg", "ir-jacobi"])
+@pytest.mark.parametrize("pc", ["jacobi", "gmg", "mixed-gmg", "bf16-gmg", "ir-gmg", "ir-jacobi",
+                                "ru-gmg"])
 @pytest.mark.parametrize("name,p", _problems())
 def test_solve_matches_direct(name, p, pc):
     from paper_2012_08208_amd import (TOPO_FP64, TOPO_MIXED_BF16, TOPO_MIXED_FP32, TOPO_MIXED_IR,
-                                      TOPO_PC_GMG, TOPO_PC_JACOBI)
+                                      TOPO_MIXED_RU, TOPO_PC_GMG, TOPO_PC_JACOBI)
     print(f"[solve] {name} {pc}", flush=True)
     m = M.build(p.dim, p.nel, p.split)
     rho = synth.rho_random(3, m.n_cells, 0.05, 1.0)
@@ -109,8 +110,8 @@ def test_solve_matches_direct(name, p, pc):
     f = p.loads.reshape(p.nrhs, -1)
     u_ref = fem.solve(K, f, p.fixed.ravel())
     t = _topo(p, rtol=1e-12, precond=TOPO_PC_GMG if pc.endswith("gmg") else TOPO_PC_JACOBI,
-              precision={"mixed": TOPO_MIXED_FP32, "ir": TOPO_MIXED_IR,
-                         "bf16": TOPO_MIXED_BF16}.get(pc.split("-")[0], TOPO_FP64))
+              precision={"mixed": TOPO_MIXED_FP32, "ir": TOPO_MIXED_IR, "bf16": TOPO_MIXED_BF16,
+                         "ru": TOPO_MIXED_RU}.get(pc.split("-")[0], TOPO_FP64))
     u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=DEV)
     info = torch.zeros(6, dtype=torch.float64, device=DEV)
     t.solve(_t(rho), u, info)
@@ -318,6 +319,16 @@ def test_iterate_cantilever_60x30_50_iterations_mixed_ir():
     S = simp.setup(p)
     rho_ref, log_ref = simp.iterate(S, 50)
     t = _topo(p, rtol=1e-10, precond=TOPO_PC_GMG, precision=TOPO_MIXED_IR)
+    _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-7)
+
+
+def test_iterate_cantilever_60x30_50_iterations_mixed_ru():
+    from paper_2012_08208_amd import TOPO_MIXED_RU, TOPO_PC_GMG
+    p = synth.cantilever2d(60, 30)
+    print("[iterate] cantilever2d 60x30 x50 mixed-ru", flush=True)
+    S = simp.setup(p)
+    rho_ref, log_ref = simp.iterate(S, 50)
+    t = _topo(p, rtol=1e-10, precond=TOPO_PC_GMG, precision=TOPO_MIXED_RU)
     _run_iterate_check(t, p, rho_ref, log_ref, c_rtol=1e-7)
 
 
