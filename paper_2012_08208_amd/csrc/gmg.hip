@@ -10,7 +10,12 @@
 // transpose, and the Galerkin coarse operator P^T K P is the coarse P1
 // operator with each coarse modulus the mean of its 8 (2D: 4) children's
 // moduli -- fine cells outside an odd-sized grid count as void.  The coarse
-// levels re-use the fine-level apply kernels.  A coarse DOF is fixed when
+// levels re-use the fine-level apply kernels, which assume unit cells.  A P1
+// element matrix scales as (cell volume) x (gradient)^2, i.e. as h^(dim-2):
+// unchanged in 2D, doubled per level in 3D.  So the 3D coarse moduli stored
+// for the unit-cell kernels are twice the children's mean (without the
+// factor every level is half its Galerkin operator, the coarse corrections
+// overshoot by 2 per level and the CG iterations grow with the depth).  A coarse DOF is fixed when
 // any fine DOF of the same component in the support of its basis function
 // is fixed (this keeps every level non-singular).
 //
@@ -42,6 +47,7 @@ struct GmgParams {
   double cheb_low = 0.09;
   int power_iters = 12;
   double power_safety = 1.2;
+  int wlevels = 0;        // levels below this visit their coarse level twice (W-cycle)
 };
 
 static GmgParams gmg_params() {
@@ -53,6 +59,7 @@ static GmgParams gmg_params() {
   if (const char* e = getenv("TOPO_CHEB_POST")) p.post_degree = atoi(e);
   if (const char* e = getenv("TOPO_CHEB_KIND")) p.cheb_kind = atoi(e) == 4 ? 4 : 1;
   if (const char* e = getenv("TOPO_CHEB_POST_FUSED")) p.fused_post = atoi(e) != 0;
+  if (const char* e = getenv("TOPO_GMG_WLEVELS")) p.wlevels = atoi(e) > 0 ? atoi(e) : 0;
   if (p.post_degree < 0) p.post_degree = p.cheb_degree;
   return p;
 }
@@ -93,7 +100,8 @@ __global__ void restrict_E3_kernel(double* Ec, const double* __restrict__ Ef, in
           acc[t] += Ef[6 * hf + s];
         }
       }
-  for (int t = 0; t < 6; ++t) Ec[6 * H + t] = acc[t] * 0.125;
+  // mean of the 8 children (x 1/8), times 2 for the doubled cell size
+  for (int t = 0; t < 6; ++t) Ec[6 * H + t] = acc[t] * 0.25;
 }
 
 __global__ void restrict_E2_kernel(double* Ec, const double* __restrict__ Ef, int nxf, int nyf,
@@ -570,13 +578,17 @@ static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool fr
   }
 }
 
+// One cycle at level l for K x = b, from x = 0 (x_zero) or from the given x.
+// Levels below wlevels visit their coarse level twice (a W-cycle on those
+// levels); the second visit starts from the first one's result.
 template <typename T>
-static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
+static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs, bool x_zero, int wlevels) {
   hipStream_t s = c->stream;
   const int L = (int)c->lv.size();
   GmgLevel& g = c->lv[l];
   const int* stop = stop_flag(c);
   if (l == L - 1) {
+    // the direct coarsest solve does not depend on the start
     const int n = (int)(g.op.nn * g.op.dim);
     coarse_solve_kernel<T><<<1, 512, 0, s>>>(x, b, g.Ainv, n, nrhs, stop);
     return;
@@ -585,7 +597,7 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
   T* hb = reinterpret_cast<T*>(h.b);
   T* hx = reinterpret_cast<T*>(h.x);
   T* gq = reinterpret_cast<T*>(g.q);
-  cheb_smooth<T>(c, g, b, x, nrhs, true);
+  cheb_smooth<T>(c, g, b, x, nrhs, x_zero);
   LevelOps<T>::apply(c, g, x, gq, nrhs, stop);
   if (g.op.dim == 3 && h.op.nn >= 65536) {
     // large coarse grids: the z-sweep (fine planes read once, whole rows)
@@ -600,7 +612,8 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
   } else {
     restrict_kernel<T><<<cdivu(h.op.nn, 256), 256, 0, s>>>(hb, b, gq, g.op, h.op, nrhs, stop);
   }
-  vcycle_level<T>(c, l + 1, hb, hx, nrhs);
+  vcycle_level<T>(c, l + 1, hb, hx, nrhs, true, wlevels);
+  if (l < wlevels && l + 2 < L) vcycle_level<T>(c, l + 1, hb, hx, nrhs, false, wlevels);
   if (g.op.nn >= 262144) {
     if (g.op.dim == 3) prolong_large<T, 3>(s, x, hx, g.op, h.op, nrhs, stop);
     else prolong_large<T, 2>(s, x, hx, g.op, h.op, nrhs, stop);
@@ -611,11 +624,11 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs) {
 }
 
 void gmg_vcycle(Ctx* c, const double* b, double* x, int nrhs) {
-  vcycle_level<double>(c, 0, b, x, nrhs);
+  vcycle_level<double>(c, 0, b, x, nrhs, true, gmg_params().wlevels);
 }
 
 void gmg_vcycle_f32(Ctx* c, const float* b, float* x, int nrhs) {
-  vcycle_level<float>(c, 0, b, x, nrhs);
+  vcycle_level<float>(c, 0, b, x, nrhs, true, gmg_params().wlevels);
 }
 
 // the fine-level Chebyshev-Jacobi smoother on its own (FP64)

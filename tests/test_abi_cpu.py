@@ -125,7 +125,7 @@ def test_filter_selector_and_new_modes_validate():
     p = b.make_problem(3, (24, 12, 12), nrhs=1)
     assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n0)) == 0
     assert n2.value >= n0.value + 2 * 24 * 12 * 12 * 6 * 8   # filtered design and dv
-    bad = b.make_problem(2, (8, 4), precision=4)
+    bad = b.make_problem(2, (8, 4), precision=5)
     assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n0)) == -1
     ok = b.make_problem(2, (8, 4), precision=b.TOPO_MIXED_BF16, precond=b.TOPO_PC_GMG)
     assert lib.topo_workspace_size(ctypes.byref(ok), ctypes.byref(n0)) == 0
