@@ -47,8 +47,16 @@ struct GmgParams {
   double cheb_low = 0.09;
   int power_iters = 12;
   double power_safety = 1.2;
-  int wlevels = 0;        // levels below this visit their coarse level twice (W-cycle)
+  // W-cycle: levels below wlevels visit their coarse level twice; -1 picks
+  // them by size (3D levels whose coarse level has >= kWCoarseNodes nodes)
+  int wlevels = -1;
 };
+
+// A revisit of a coarse level with fewer nodes is bound by launch latency,
+// not bandwidth: on 192x96x96 (7 levels) W on the top 3 levels gave 12.5
+// SIMP it/s (29 CG iterations per solve), the top 4 11.5 (25), all 9.7
+// (24), the V-cycle 9.3 (74).  This threshold selects the top 3 there.
+constexpr long kWCoarseNodes = 4096;
 
 static GmgParams gmg_params() {
   GmgParams p;
@@ -579,8 +587,13 @@ static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool fr
 }
 
 // One cycle at level l for K x = b, from x = 0 (x_zero) or from the given x.
-// Levels below wlevels visit their coarse level twice (a W-cycle on those
-// levels); the second visit starts from the first one's result.
+// Levels below wlevels (wlevels < 0: 3D levels whose coarse level has at
+// least kWCoarseNodes nodes) visit their coarse level twice, a W-cycle on
+// those levels; the second visit starts from the first one's result.  Every
+// level's operator is the Galerkin one, so a cycle's error operator is
+// K-symmetric with spectrum in [0, 1) and the repeated coarse correction
+// stays positive definite.  The coarsest level is solved directly and never
+// revisited.
 template <typename T>
 static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs, bool x_zero, int wlevels) {
   hipStream_t s = c->stream;
@@ -613,7 +626,8 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs, bool x_zero,
     restrict_kernel<T><<<cdivu(h.op.nn, 256), 256, 0, s>>>(hb, b, gq, g.op, h.op, nrhs, stop);
   }
   vcycle_level<T>(c, l + 1, hb, hx, nrhs, true, wlevels);
-  if (l < wlevels && l + 2 < L) vcycle_level<T>(c, l + 1, hb, hx, nrhs, false, wlevels);
+  const bool revisit = wlevels >= 0 ? l < wlevels : (g.op.dim == 3 && h.op.nn >= kWCoarseNodes);
+  if (revisit && l + 2 < L) vcycle_level<T>(c, l + 1, hb, hx, nrhs, false, wlevels);
   if (g.op.nn >= 262144) {
     if (g.op.dim == 3) prolong_large<T, 3>(s, x, hx, g.op, h.op, nrhs, stop);
     else prolong_large<T, 2>(s, x, hx, g.op, h.op, nrhs, stop);

@@ -4,7 +4,8 @@
   their 8 children on the unit-cell kernels) the V-cycle preconditioned CG
   needs about the same number of iterations on 24x12x12 and 48x24x24 (one
   more level): the count does not grow with the depth.
-* The W-cycle on the top levels (TOPO_GMG_WLEVELS) is a symmetric positive
+* The W-cycle on the top levels (TOPO_GMG_WLEVELS; by default the 3D levels
+  whose coarse level has at least 4096 nodes) is a symmetric positive
   definite preconditioner for every depth it is given: CG converges, in no
   more iterations than with the V-cycle, to the same solution.
 """
@@ -35,8 +36,9 @@ def _solve(p, precision, rho_val=0.3):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed-ru"])
-def test_vcycle_iterations_do_not_grow_with_depth(prec):
+def test_vcycle_iterations_do_not_grow_with_depth(prec, monkeypatch):
     from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_RU
+    monkeypatch.setenv("TOPO_GMG_WLEVELS", "0")
     code = TOPO_FP64 if prec == "fp64" else TOPO_MIXED_RU
     its = []
     for nel in ((24, 12, 12), (48, 24, 24)):
@@ -50,7 +52,7 @@ def test_vcycle_iterations_do_not_grow_with_depth(prec):
     assert abs(its[1] - its[0]) <= 3
 
 
-@pytest.mark.parametrize("wlevels", ["1", "2", "9"])
+@pytest.mark.parametrize("wlevels", ["1", "2", "9", "auto"])
 def test_wcycle_converges_to_the_vcycle_solution(wlevels, monkeypatch):
     from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_RU
     p = synth.cantilever3d(48, 24, 24, nrhs=2, volfrac=0.3, rmin=1.5, rtol=1e-10)
@@ -58,7 +60,10 @@ def test_wcycle_converges_to_the_vcycle_solution(wlevels, monkeypatch):
     st, info_v, u_v = _solve(p, TOPO_FP64)
     assert st == 0
     for code in (TOPO_FP64, TOPO_MIXED_RU):
-        monkeypatch.setenv("TOPO_GMG_WLEVELS", wlevels)
+        if wlevels == "auto":
+            monkeypatch.delenv("TOPO_GMG_WLEVELS", raising=False)   # default: by level size
+        else:
+            monkeypatch.setenv("TOPO_GMG_WLEVELS", wlevels)
         print(f"[gmg W] wlevels {wlevels} precision {code}", flush=True)
         st, info, u = _solve(p, code)
         print(f"  CG iterations V {info_v[0]:.0f}  W {info[0]:.0f}", flush=True)
@@ -67,5 +72,5 @@ def test_wcycle_converges_to_the_vcycle_solution(wlevels, monkeypatch):
         for r in range(p.nrhs):
             a, b = u[r * p.n_dofs:(r + 1) * p.n_dofs], u_v[r * p.n_dofs:(r + 1) * p.n_dofs]
             assert np.linalg.norm(a - b) <= 1e-7 * np.linalg.norm(b)
-    monkeypatch.delenv("TOPO_GMG_WLEVELS")
+    monkeypatch.delenv("TOPO_GMG_WLEVELS", raising=False)
     assert "TOPO_GMG_WLEVELS" not in os.environ
