@@ -27,8 +27,10 @@
 // inverted by Gauss-Jordan elimination in one work-group.
 #include <math.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <type_traits>
+#include <vector>
 
 #include "common.h"
 #include "element.h"
@@ -50,13 +52,16 @@ struct GmgParams {
   // W-cycle: levels below wlevels visit their coarse level twice; -1 picks
   // them by size (3D levels whose coarse level has >= kWCoarseNodes nodes)
   int wlevels = -1;
+  bool tail = true;       // FP32 3D cycles: the small coarse levels in one work-group
 };
 
-// A revisit of a coarse level with fewer nodes is bound by launch latency,
-// not bandwidth: on 192x96x96 (7 levels) W on the top 3 levels gave 12.5
-// SIMP it/s (29 CG iterations per solve), the top 4 11.5 (25), all 9.7
-// (24), the V-cycle 9.3 (74).  This threshold selects the top 3 there.
-constexpr long kWCoarseNodes = 4096;
+// A revisit of a smaller coarse level costs more in launches than it saves
+// in iterations: on 192x96x96 x 4 load cases (7 levels, the last three in
+// the one-block tail) W on the top 2 levels gave 12.8 SIMP it/s (38 CG
+// iterations per solve), the top 3 14.0 (29), the top 4 14.2 (25), the
+// top 5 13.4 (24).  This threshold selects the top 4 there (coarse levels
+// of 230k, 31k, 4.2k and 637 nodes).
+constexpr long kWCoarseNodes = 512;
 
 static GmgParams gmg_params() {
   GmgParams p;
@@ -68,6 +73,7 @@ static GmgParams gmg_params() {
   if (const char* e = getenv("TOPO_CHEB_KIND")) p.cheb_kind = atoi(e) == 4 ? 4 : 1;
   if (const char* e = getenv("TOPO_CHEB_POST_FUSED")) p.fused_post = atoi(e) != 0;
   if (const char* e = getenv("TOPO_GMG_WLEVELS")) p.wlevels = atoi(e) > 0 ? atoi(e) : 0;
+  if (const char* e = getenv("TOPO_GMG_TAIL")) p.tail = atoi(e) != 0;
   if (p.post_degree < 0) p.post_degree = p.cheb_degree;
   return p;
 }
@@ -586,6 +592,399 @@ static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool fr
   }
 }
 
+// Whether level l visits its coarse level a second time (W-cycle).
+static bool revisits(const Ctx* c, int l, int wlevels) {
+  const int L = (int)c->lv.size();
+  if (l + 2 >= L) return false;   // the coarsest level is solved directly
+  const GmgLevel& h = c->lv[l + 1];
+  return wlevels >= 0 ? l < wlevels : (h.op.dim == 3 && h.op.nn >= kWCoarseNodes);
+}
+
+// ------------------------------------------------ coarse tail, one work-group
+// From the first 3D coarse level whose vectors fit in LDS down to the
+// coarsest, a level's kernels last a few microseconds each and the gaps
+// between dependent launches cost as much again.  There the FP32 cycle
+// runs in one work-group per load case (the cycle acts on each load case
+// on its own), with every vector, the moduli, D^-1 and the masks of those
+// levels staged in LDS: smoothing, residual and restriction, the direct
+// coarsest solve, prolongation and any W revisits, one phase after another
+// with work-group barriers in between.  The phases compute what the
+// per-level kernels compute, in the same order, except the operator's node
+// sums: a cube pass writes each cube's 8 corner forces (the same
+// cube_force) to LDS, then a node pass adds the forces of a node's cubes in
+// corner order.  Every result is the same on every run.
+constexpr int kTailMaxLevels = 8;
+constexpr int kTailMaxOps = 192;
+constexpr int kTailLdsFloats = 36864;   // 144 KiB, and 8 KiB for the coarsest solve's partial sums
+constexpr int kTailCoarseSplit = 8;     // partial sums per coarsest-level row
+constexpr int kTailThreads = 1024;
+enum TailOpKind : uint8_t { kTailSmooth0, kTailSmoothX, kTailRestrict, kTailCoarse, kTailProlong };
+struct TailOp {
+  uint8_t kind, level;   // level relative to the tail's first level
+};
+
+// one level of one load case, pointers into LDS
+struct TailLevel {
+  int nx, ny, nz, nn;
+  const uint8_t* mask;
+  const float* E;      // [6 * cubes] moduli of the unit-cell kernels
+  const float* invd;   // [3 * nn]
+  float *b, *x, *r, *d, *q;   // [3][nn] (r, d, q unused on the coarsest level)
+};
+
+struct TailLevelSrc {
+  int nx, ny, nz, nn;
+  const uint8_t* mask;   // global
+  const float* E;
+  const float* invd;
+  const double* lmax;
+  // LDS offsets in floats (mask: in bytes)
+  int o_mask, o_E, o_invd, o_b, o_x, o_r, o_d, o_q;
+};
+
+struct TailArgs {
+  TailLevelSrc lv[kTailMaxLevels];
+  int nlev;
+  const float* b0;      // first level's right-hand side, [nrhs][3][nn] (global)
+  float* x0;            // and its solution
+  int x0_zero;          // start from x = 0
+  const double* Ainv;   // coarsest level: dense inverse
+  int o_F;              // LDS corner forces [24][cubes of the first level]
+  float lam, mu;        // lambda0 |T|, mu0 |T| of the unit cell
+  double low;
+  double rc[8], rp[8];  // first-kind recurrence coefficients of steps 1..7
+  int kind, deg0, degx; // Chebyshev kind, degree from zero, degree from x
+  int ncoarse, nops;
+  TailOp ops[kTailMaxOps];
+};
+
+__device__ inline TailLevel tail_view(const TailArgs& A, int l, float* lds) {
+  const TailLevelSrc& s = A.lv[l];
+  TailLevel v;
+  v.nx = s.nx;
+  v.ny = s.ny;
+  v.nz = s.nz;
+  v.nn = s.nn;
+  v.mask = reinterpret_cast<const uint8_t*>(lds) + s.o_mask;
+  v.E = lds + s.o_E;
+  v.invd = lds + s.o_invd;
+  v.b = lds + s.o_b;
+  v.x = lds + s.o_x;
+  v.r = lds + s.o_r;
+  v.d = lds + s.o_d;
+  v.q = lds + s.o_q;
+  return v;
+}
+
+// out = Z K Z v on one level (v is zero on fixed DOFs), the whole block
+__device__ void tail_apply(const TailLevel& L, const float* v, float* out, float* F, float lam0,
+                           float mu0) {
+  const int nx = L.nx, ny = L.ny, nz = L.nz, nn = L.nn;
+  const int ncube = nx * ny * nz, nx1 = nx + 1, pl = (nx + 1) * (ny + 1);
+  for (int h = threadIdx.x; h < ncube; h += blockDim.x) {
+    const int i = h % nx, j = (h / nx) % ny, k = h / (nx * ny);
+    float u[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int node = (k + (c >> 2)) * pl + (j + ((c >> 1) & 1)) * nx1 + i + (c & 1);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) u[c][a] = v[a * nn + node];
+    }
+    float lam[6], mu[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const float e = L.E[6 * h + t];
+      lam[t] = lam0 * e;
+      mu[t] = mu0 * e;
+    }
+    float f[8][3];
+    cube_force<float>(u, lam, mu, f);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[(c * 3 + a) * ncube + h] = f[c][a];
+  }
+  __syncthreads();
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+    const int i = n % nx1, j = (n / nx1) % (ny + 1), k = n / pl;
+    const int m = L.mask[n];
+    float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      // the node is corner c of the cube at (i, j, k) - c
+      const int ci = i - (c & 1), cj = j - ((c >> 1) & 1), ck = k - (c >> 2);
+      if (ci < 0 || cj < 0 || ck < 0 || ci >= nx || cj >= ny || ck >= nz) continue;
+      const int h = (ck * ny + cj) * nx + ci;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc[a] += F[(c * 3 + a) * ncube + h];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a * nn + n] = ((m >> a) & 1) ? 0.f : acc[a];
+  }
+  __syncthreads();
+}
+
+// Chebyshev smoothing of one level from x = 0 or from x (cheb_first_kernel,
+// cheb_next_kernel)
+__device__ void tail_smooth(const TailArgs& A, const TailLevel& L, double lmax, float* F,
+                            bool from_zero) {
+  const int degree = from_zero ? A.deg0 : A.degx;
+  if (degree == 0) return;
+  const int nd = 3 * L.nn;
+  if (!from_zero) tail_apply(L, L.x, L.q, F, A.lam, A.mu);
+  const float it = float(cheb_first_scale(lmax, A.low, A.kind));
+  for (int j = threadIdx.x; j < nd; j += blockDim.x) {
+    const float id = L.invd[j];
+    const float rv = from_zero ? L.b[j] : L.b[j] - L.q[j];
+    const float dv = it * id * rv;
+    L.r[j] = rv;
+    L.d[j] = dv;
+    L.x[j] = from_zero ? dv : L.x[j] + dv;
+  }
+  __syncthreads();
+  for (int k = 1; k < degree; ++k) {
+    tail_apply(L, L.d, L.q, F, A.lam, A.mu);
+    double c1d, c2d;
+    cheb_next_coef(lmax, A.low, ChebCoef{A.rc[k], A.rp[k], A.kind, k}, c1d, c2d);
+    const float c1 = float(c1d), c2 = float(c2d);
+    for (int j = threadIdx.x; j < nd; j += blockDim.x) {
+      const float id = L.invd[j];
+      const float rv = L.r[j] - L.q[j];
+      const float dv = c1 * L.d[j] + c2 * id * rv;
+      L.r[j] = rv;
+      L.d[j] = dv;
+      L.x[j] += dv;
+    }
+    __syncthreads();
+  }
+}
+
+// coarse b = P^T (b - K x) of the fine level (restrict_node's sums)
+__device__ void tail_restrict(const TailArgs& A, const TailLevel& Fl, const TailLevel& Cl, float* F) {
+  tail_apply(Fl, Fl.x, Fl.q, F, A.lam, A.mu);
+  const int nxf1 = Fl.nx + 1, nyf1 = Fl.ny + 1;
+  const int nxc1 = Cl.nx + 1, nyc1 = Cl.ny + 1;
+  for (int idx = threadIdx.x; idx < 3 * Cl.nn; idx += blockDim.x) {
+    const int c = idx / Cl.nn, C = idx - c * Cl.nn;
+    const int I = C % nxc1, J = (C / nxc1) % nyc1, K = C / (nxc1 * nyc1);
+    const float* bf = Fl.b + c * Fl.nn;
+    const float* qf = Fl.q + c * Fl.nn;
+    float acc = 0.f;
+    if (2 * I <= Fl.nx && 2 * J <= Fl.ny && 2 * K <= Fl.nz) {
+      const int n = ((2 * K) * nyf1 + 2 * J) * nxf1 + 2 * I;
+      acc += bf[n] - qf[n];
+    }
+    for (int dd = 1; dd <= 7; ++dd) {
+      const int dx = dd & 1, dy = (dd >> 1) & 1, dz = (dd >> 2) & 1;
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const int fi = 2 * I + sgn * dx, fj = 2 * J + sgn * dy, fk = 2 * K + sgn * dz;
+        if (fi < 0 || fj < 0 || fk < 0 || fi > Fl.nx || fj > Fl.ny || fk > Fl.nz) continue;
+        const int n = (fk * nyf1 + fj) * nxf1 + fi;
+        acc += 0.5f * (bf[n] - qf[n]);
+      }
+    }
+    Cl.b[idx] = ((Cl.mask[C] >> c) & 1) ? 0.f : acc;
+  }
+  __syncthreads();
+}
+
+// fine x += P (coarse x) (prolong_add_split_kernel's interpolation)
+__device__ void tail_prolong(const TailLevel& Fl, const TailLevel& Cl) {
+  const int nxf1 = Fl.nx + 1, nyf1 = Fl.ny + 1;
+  const int nxc1 = Cl.nx + 1, nyc1 = Cl.ny + 1;
+  for (int idx = threadIdx.x; idx < 3 * Fl.nn; idx += blockDim.x) {
+    const int c = idx / Fl.nn, n = idx - c * Fl.nn;
+    if ((Fl.mask[n] >> c) & 1) continue;
+    const int i = n % nxf1, j = (n / nxf1) % nyf1, k = n / (nxf1 * nyf1);
+    const int c0 = ((k >> 1) * nyc1 + (j >> 1)) * nxc1 + (i >> 1);
+    const int c1 = (((k + 1) >> 1) * nyc1 + ((j + 1) >> 1)) * nxc1 + ((i + 1) >> 1);
+    const bool even = ((i | j | k) & 1) == 0;
+    const float* xcr = Cl.x + c * Cl.nn;
+    const float e = even ? xcr[c0] : 0.5f * (xcr[c0] + xcr[c1]);
+    Fl.x[idx] += e;
+  }
+  __syncthreads();
+}
+
+// x = Ainv b on the coarsest level (n <= 128): each row's dot product in
+// kTailCoarseSplit strided partial sums, then their sum in order
+__device__ void tail_coarse(const double* __restrict__ Ainv, int n, float* x, const float* b,
+                            double* red) {
+  for (int t = threadIdx.x; t < n * kTailCoarseSplit; t += blockDim.x) {
+    const int i = t % n, p = t / n;
+    double acc = 0.0;
+    for (int j = p; j < n; j += kTailCoarseSplit) acc += Ainv[(long)j * n + i] * (double)b[j];
+    red[p * n + i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double acc = 0.0;
+    for (int p = 0; p < kTailCoarseSplit; ++p) acc += red[p * n + i];
+    x[i] = float(acc);
+  }
+  __syncthreads();
+}
+
+// one work-group per load case (blockIdx.x)
+__global__ __launch_bounds__(kTailThreads) void gmg_tail_kernel(TailArgs A, const int* stop) {
+  if (stop && *stop) return;
+  __shared__ float lds[kTailLdsFloats];
+  __shared__ double red[kTailCoarseSplit * 128];
+  const int r = blockIdx.x;
+  uint8_t* lmask = reinterpret_cast<uint8_t*>(lds);
+  // stage the levels' moduli, D^-1 and masks, and the first level's b (and x)
+  for (int l = 0; l < A.nlev; ++l) {
+    const TailLevelSrc& s = A.lv[l];
+    const int ncube = s.nx * s.ny * s.nz;
+    for (int n = threadIdx.x; n < s.nn; n += blockDim.x) lmask[s.o_mask + n] = s.mask[n];
+    if (l + 1 < A.nlev) {
+      for (int i = threadIdx.x; i < 6 * ncube; i += blockDim.x) lds[s.o_E + i] = s.E[i];
+      for (int i = threadIdx.x; i < 3 * s.nn; i += blockDim.x) lds[s.o_invd + i] = s.invd[i];
+    }
+  }
+  {
+    const TailLevelSrc& s = A.lv[0];
+    const long off = (long)r * 3 * s.nn;
+    for (int i = threadIdx.x; i < 3 * s.nn; i += blockDim.x) {
+      lds[s.o_b + i] = A.b0[off + i];
+      if (!A.x0_zero) lds[s.o_x + i] = A.x0[off + i];
+    }
+  }
+  __syncthreads();
+  float* F = lds + A.o_F;
+  for (int o = 0; o < A.nops; ++o) {
+    const TailOp op = A.ops[o];
+    const TailLevel L = tail_view(A, op.level, lds);
+    switch (op.kind) {
+      case kTailSmooth0: tail_smooth(A, L, *A.lv[op.level].lmax, F, true); break;
+      case kTailSmoothX: tail_smooth(A, L, *A.lv[op.level].lmax, F, false); break;
+      case kTailRestrict: tail_restrict(A, L, tail_view(A, op.level + 1, lds), F); break;
+      case kTailProlong: tail_prolong(L, tail_view(A, op.level + 1, lds)); break;
+      default: tail_coarse(A.Ainv, A.ncoarse, L.x, L.b, red); break;
+    }
+  }
+  {
+    const TailLevelSrc& s = A.lv[0];
+    const long off = (long)r * 3 * s.nn;
+    for (int i = threadIdx.x; i < 3 * s.nn; i += blockDim.x) A.x0[off + i] = lds[s.o_x + i];
+  }
+}
+
+// LDS layout of the levels from l0 down (floats; false if it does not fit)
+static bool tail_layout(const Ctx* c, int l0, TailArgs& A) {
+  const int L = (int)c->lv.size();
+  if (L - l0 > kTailMaxLevels) return false;
+  int mask_bytes = 0;
+  for (int l = l0; l < L; ++l) mask_bytes += (int)c->lv[l].op.nn;
+  int o = (mask_bytes + 15) / 16 * 4;   // masks first, 16-byte aligned
+  int mb = 0;
+  A.nlev = L - l0;
+  for (int l = l0; l < L; ++l) {
+    const OpDesc& d = c->lv[l].op;
+    TailLevelSrc& s = A.lv[l - l0];
+    const int nn = (int)d.nn, nd = 3 * nn, ncube = d.nx * d.ny * d.nz;
+    const bool last = l + 1 == L;
+    s.o_mask = mb;
+    mb += nn;
+    s.o_b = o;
+    o += nd;
+    s.o_x = o;
+    o += nd;
+    if (!last) {
+      s.o_r = o;
+      o += nd;
+      s.o_d = o;
+      o += nd;
+      s.o_q = o;
+      o += nd;
+      s.o_E = o;
+      o += 6 * ncube;
+      s.o_invd = o;
+      o += nd;
+    }
+  }
+  const OpDesc& d0 = c->lv[l0].op;
+  A.o_F = o;
+  o += 24 * d0.nx * d0.ny * d0.nz;
+  return o <= kTailLdsFloats;
+}
+
+// first level of the one-block tail (FP32 cycles of 3D problems), or -1
+static int tail_level(const Ctx* c) {
+  const int L = (int)c->lv.size();
+  if (L < 2 || c->lv[0].op.dim != 3 || !gmg_params().tail) return -1;
+  static thread_local TailArgs probe;
+  for (int l = 1; l + 1 < L; ++l)
+    if (tail_layout(c, l, probe)) return l;
+  return -1;
+}
+
+// the tail's phases, in the order of vcycle_level's recursion
+static bool tail_program(const Ctx* c, int l, int l0, bool x_zero, int wlevels,
+                         std::vector<TailOp>& ops) {
+  const int L = (int)c->lv.size();
+  const uint8_t rl = (uint8_t)(l - l0);
+  if (l == L - 1) {
+    ops.push_back({kTailCoarse, rl});
+    return true;
+  }
+  ops.push_back({x_zero ? (uint8_t)kTailSmooth0 : (uint8_t)kTailSmoothX, rl});
+  ops.push_back({kTailRestrict, rl});
+  if (!tail_program(c, l + 1, l0, true, wlevels, ops)) return false;
+  if (revisits(c, l, wlevels) && !tail_program(c, l + 1, l0, false, wlevels, ops)) return false;
+  ops.push_back({kTailProlong, rl});
+  ops.push_back({kTailSmoothX, rl});
+  return (int)ops.size() <= kTailMaxOps;
+}
+
+static bool launch_tail(Ctx* c, int l0, const float* b, float* x, int nrhs, bool x_zero,
+                        int wlevels) {
+  std::vector<TailOp> ops;
+  if (!tail_program(c, l0, l0, x_zero, wlevels, ops)) return false;
+  const int L = (int)c->lv.size();
+  const GmgParams gp = gmg_params();
+  if (gp.cheb_degree > 8 || gp.post_degree > 8) return false;
+  TailArgs A;
+  memset(&A, 0, sizeof(A));
+  if (!tail_layout(c, l0, A)) return false;
+  for (int l = l0; l < L; ++l) {
+    const GmgLevel& g = c->lv[l];
+    TailLevelSrc& s = A.lv[l - l0];
+    s.nx = g.op.nx;
+    s.ny = g.op.ny;
+    s.nz = g.op.nz;
+    s.nn = (int)g.op.nn;
+    s.mask = g.op.mask;
+    s.E = g.E32;
+    s.invd = g.invd32;
+    s.lmax = g.lmax;
+  }
+  A.b0 = b;
+  A.x0 = x;
+  A.x0_zero = x_zero ? 1 : 0;
+  A.Ainv = c->lv[L - 1].Ainv;
+  A.lam = float(c->m.lam0 * c->m.vol);
+  A.mu = float(c->m.mu0 * c->m.vol);
+  A.low = gp.cheb_low;
+  const double sigma = (1.0 + gp.cheb_low) / (1.0 - gp.cheb_low);
+  double rho_prev = 1.0 / sigma;
+  for (int k = 1; k < 8; ++k) {
+    const double rho = 1.0 / (2.0 * sigma - rho_prev);
+    A.rc[k] = rho;
+    A.rp[k] = rho_prev;
+    rho_prev = rho;
+  }
+  A.kind = gp.cheb_kind;
+  A.deg0 = gp.cheb_degree;
+  A.degx = gp.post_degree;
+  A.ncoarse = (int)(c->lv[L - 1].op.nn * 3);
+  if (A.ncoarse > 128) return false;
+  A.nops = (int)ops.size();
+  for (size_t i = 0; i < ops.size(); ++i) A.ops[i] = ops[i];
+  gmg_tail_kernel<<<nrhs, kTailThreads, 0, c->stream>>>(A, stop_flag(c));
+  return true;
+}
+
 // One cycle at level l for K x = b, from x = 0 (x_zero) or from the given x.
 // Levels below wlevels (wlevels < 0: 3D levels whose coarse level has at
 // least kWCoarseNodes nodes) visit their coarse level twice, a W-cycle on
@@ -605,6 +1004,9 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs, bool x_zero,
     const int n = (int)(g.op.nn * g.op.dim);
     coarse_solve_kernel<T><<<1, 512, 0, s>>>(x, b, g.Ainv, n, nrhs, stop);
     return;
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    if (l == tail_level(c) && launch_tail(c, l, b, x, nrhs, x_zero, wlevels)) return;
   }
   GmgLevel& h = c->lv[l + 1];
   T* hb = reinterpret_cast<T*>(h.b);
@@ -626,8 +1028,7 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs, bool x_zero,
     restrict_kernel<T><<<cdivu(h.op.nn, 256), 256, 0, s>>>(hb, b, gq, g.op, h.op, nrhs, stop);
   }
   vcycle_level<T>(c, l + 1, hb, hx, nrhs, true, wlevels);
-  const bool revisit = wlevels >= 0 ? l < wlevels : (g.op.dim == 3 && h.op.nn >= kWCoarseNodes);
-  if (revisit && l + 2 < L) vcycle_level<T>(c, l + 1, hb, hx, nrhs, false, wlevels);
+  if (revisits(c, l, wlevels)) vcycle_level<T>(c, l + 1, hb, hx, nrhs, false, wlevels);
   if (g.op.nn >= 262144) {
     if (g.op.dim == 3) prolong_large<T, 3>(s, x, hx, g.op, h.op, nrhs, stop);
     else prolong_large<T, 2>(s, x, hx, g.op, h.op, nrhs, stop);

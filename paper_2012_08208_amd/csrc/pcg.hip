@@ -17,6 +17,8 @@
 // solve of mixed-precision iterative refinement: FP32 vectors, FP32
 // operator and V-cycle, FP64 dot products and scalars.  Refinement keeps the
 // solution and the true residual f - K u in FP64 (outer loop below).
+#include <stdlib.h>
+
 #include <algorithm>
 #include <type_traits>
 
@@ -435,7 +437,7 @@ constexpr double kRuDelta2 = 1e-2;   // update when ||r||^2 fell by 100x
 // update is due (ru_skip = 0 makes the update kernels run)
 template <int NR>
 __global__ void ru_update_fin(const double* partials, long nb, PcgState* st, int* skip, const double* rr_max,
-                              int* status) {
+                              int* status, double delta2) {
   if (st->done) return;
   __shared__ double tot[2 * NR];
   reduce_partials<2 * NR, 0>(partials, nb, tot);
@@ -445,7 +447,7 @@ __global__ void ru_update_fin(const double* partials, long nb, PcgState* st, int
       if (!st->active[k]) continue;
       st->rr[k] = tot[k];
       if (!isfinite(tot[k])) { st->breakdown = 1; st->active[k] = 0; }
-      if (!(tot[k] > st->tol2[k]) || tot[k] < kRuDelta2 * rr_max[k]) due = 1;
+      if (!(tot[k] > st->tol2[k]) || tot[k] < delta2 * rr_max[k]) due = 1;
     }
     st->iters += 1;
     *skip = !due;
@@ -536,6 +538,8 @@ static void mixed_ru_iterate(Ctx* c, double* u, const double* r, int maxit) {
   const long nb_apply = apply_grid_blocks(fine_op(c), NR, 4);
   float* zb[2] = {c->z32, c->z32b};
   const float* invd = c->invd32;
+  double delta2 = kRuDelta2;
+  if (const char* e = getenv("TOPO_RU_DELTA2")) delta2 = atof(e) > 0 ? atof(e) : delta2;
   launch_to_f32(c, c->r32, r, (int64_t)NR * nd);
   ru_zero_kernel<<<gb, 256, 0, s>>>(c->x32, (long)NR * nd);
   ru_setup_kernel<NR><<<1, 1, 0, s>>>(st, rr_max, skip);
@@ -554,7 +558,7 @@ static void mixed_ru_iterate(Ctx* c, double* u, const double* r, int maxit) {
       pcg_alpha_fin<<<1, 256, 0, s>>>(c->partials, nb_apply, st);
       pcg_update_kernel<NR, false, float><<<gb, 256, 0, s>>>(c->x32, c->r32, c->p32, c->q32,
                                                             nullptr, nd, c->partials, st);
-      ru_update_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st, skip, rr_max, status);
+      ru_update_fin<NR><<<1, 256, 0, s>>>(c->partials, gb, st, skip, rr_max, status, delta2);
       // reliable update, gated on the device flag
       ru_fold_kernel<NR><<<gb, 256, 0, s>>>(u, c->x32, nd, skip);
       launch_apply_op(c, fine_op(c), c->E, u, c->q, NR, false, false, skip);

@@ -5,7 +5,7 @@
   needs about the same number of iterations on 24x12x12 and 48x24x24 (one
   more level): the count does not grow with the depth.
 * The W-cycle on the top levels (TOPO_GMG_WLEVELS; by default the 3D levels
-  whose coarse level has at least 4096 nodes) is a symmetric positive
+  whose coarse level has at least 512 nodes) is a symmetric positive
   definite preconditioner for every depth it is given: CG converges, in no
   more iterations than with the V-cycle, to the same solution.
 """
@@ -23,9 +23,9 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-def _solve(p, precision, rho_val=0.3):
+def _solve(p, precision, rho_val=0.3, maxit=2000):
     from paper_2012_08208_amd import Topo, TOPO_PC_GMG, SOLVE_INFO_LEN
-    t = Topo.from_problem(p, precision=precision, precond=TOPO_PC_GMG, maxit=2000, device=DEV)
+    t = Topo.from_problem(p, precision=precision, precond=TOPO_PC_GMG, maxit=maxit, device=DEV)
     rho = torch.full((p.n_cells,), rho_val, dtype=torch.float64, device=DEV)
     u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=DEV)
     info = torch.zeros(SOLVE_INFO_LEN, dtype=torch.float64, device=DEV)
@@ -74,3 +74,38 @@ def test_wcycle_converges_to_the_vcycle_solution(wlevels, monkeypatch):
             assert np.linalg.norm(a - b) <= 1e-7 * np.linalg.norm(b)
     monkeypatch.delenv("TOPO_GMG_WLEVELS", raising=False)
     assert "TOPO_GMG_WLEVELS" not in os.environ
+
+
+@pytest.mark.parametrize("nel", [(24, 12, 12), (40, 20, 20), (33, 17, 9)])
+def test_one_block_coarse_tail_matches_the_per_level_kernels(nel, monkeypatch):
+    """The FP32 cycle's small coarse levels in one work-group per load case
+    (default) against the per-level kernels (TOPO_GMG_TAIL=0): the same
+    preconditioner up to the order of the operator's node sums and FP32
+    rounding.  After two CG iterations (plus the true-residual restart
+    passes of two iterations each) the iterates agree to FP32 rounding,
+    far below what a different cycle would give; whole solves reach the
+    same solution in about the same iterations; two runs give the same
+    bits."""
+    from paper_2012_08208_amd import TOPO_MIXED_RU, TOPO_MIXED_FP32
+    p = synth.cantilever3d(*nel, nrhs=3, volfrac=0.3, rmin=1.5, rtol=1e-9)
+    for code in (TOPO_MIXED_FP32, TOPO_MIXED_RU):
+        short, full = {}, {}
+        for tail in ("0", "1", "1"):
+            monkeypatch.setenv("TOPO_GMG_TAIL", tail)
+            print(f"[gmg tail] {nel} precision {code} tail {tail}", flush=True)
+            _, _, u2 = _solve(p, code, rho_val=0.4, maxit=2)
+            st, info, u = _solve(p, code, rho_val=0.4)
+            assert st == 0 and info[1] == 1.0, (st, info)
+            if tail in full:
+                assert np.array_equal(u, full[tail][1]) and np.array_equal(u2, short[tail])
+            short[tail], full[tail] = u2, (info, u)
+        (i0, u0), (i1, u1) = full["0"], full["1"]
+        d2 = np.linalg.norm(short["1"] - short["0"]) / np.linalg.norm(short["0"])
+        print(f"  after 2 iterations: rel diff {d2:.2e}; CG iterations per-level {i0[0]:.0f}"
+              f"  one-block {i1[0]:.0f}", flush=True)
+        assert d2 <= 1e-5
+        assert abs(i1[0] - i0[0]) <= 3
+        for r in range(p.nrhs):
+            a, b = u1[r * p.n_dofs:(r + 1) * p.n_dofs], u0[r * p.n_dofs:(r + 1) * p.n_dofs]
+            assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b)
+    monkeypatch.delenv("TOPO_GMG_TAIL", raising=False)
