@@ -626,6 +626,7 @@ struct TailOp {
 // one level of one load case, pointers into LDS
 struct TailLevel {
   int nx, ny, nz, nn;
+  float rnx, rnxy, rnx1, rpl;   // 1/nx, 1/(nx ny), 1/(nx+1), 1/((nx+1)(ny+1))
   const uint8_t* mask;
   const float* E;      // [6 * cubes] moduli of the unit-cell kernels
   const float* invd;   // [3 * nn]
@@ -634,6 +635,7 @@ struct TailLevel {
 
 struct TailLevelSrc {
   int nx, ny, nz, nn;
+  float rnx, rnxy, rnx1, rpl;
   const uint8_t* mask;   // global
   const float* E;
   const float* invd;
@@ -665,6 +667,10 @@ __device__ inline TailLevel tail_view(const TailArgs& A, int l, float* lds) {
   v.ny = s.ny;
   v.nz = s.nz;
   v.nn = s.nn;
+  v.rnx = s.rnx;
+  v.rnxy = s.rnxy;
+  v.rnx1 = s.rnx1;
+  v.rpl = s.rpl;
   v.mask = reinterpret_cast<const uint8_t*>(lds) + s.o_mask;
   v.E = lds + s.o_E;
   v.invd = lds + s.o_invd;
@@ -676,13 +682,37 @@ __device__ inline TailLevel tail_view(const TailArgs& A, int l, float* lds) {
   return v;
 }
 
-// out = Z K Z v on one level (v is zero on fixed DOFs), the whole block
-__device__ void tail_apply(const TailLevel& L, const float* v, float* out, float* F, float lam0,
-                           float mu0) {
+// floor(a / b) for 0 <= a < 2^22 from the rounded reciprocal rb = 1/b:
+// a/b + 0.5/b stays at least 0.5/b away from an integer
+__device__ __forceinline__ int tail_div(int a, float rb) {
+  return (int)(((float)a + 0.5f) * rb);
+}
+
+// node (i, j, k) of index n on a level
+__device__ __forceinline__ void tail_node_ijk(const TailLevel& L, int n, int& i, int& j, int& k) {
+  k = tail_div(n, L.rpl);
+  const int rem = n - k * (L.nx + 1) * (L.ny + 1);
+  j = tail_div(rem, L.rnx1);
+  i = rem - j * (L.nx + 1);
+}
+
+// K v on one level (v is zero on fixed DOFs; fixed rows give 0), the whole
+// block.  What the node pass does with K v at its node:
+//   EPI 0: q = K v;
+//   EPI 1 (first Chebyshev step from x, v = x): r = b - K x, d = s D^-1 r, x += d;
+//   EPI 2 (next Chebyshev step, v = d): r -= K d, d = c1 d + c2 D^-1 r, x += d.
+// The node pass writes v only at its own node, after the barrier that ends
+// the cube pass, so the in-place updates are safe.
+template <int EPI>
+__device__ void tail_apply(const TailLevel& L, const float* v, float* F, float lam0, float mu0,
+                           float s1 = 0.f, float s2 = 0.f) {
   const int nx = L.nx, ny = L.ny, nz = L.nz, nn = L.nn;
   const int ncube = nx * ny * nz, nx1 = nx + 1, pl = (nx + 1) * (ny + 1);
   for (int h = threadIdx.x; h < ncube; h += blockDim.x) {
-    const int i = h % nx, j = (h / nx) % ny, k = h / (nx * ny);
+    const int k = tail_div(h, L.rnxy);
+    const int rem = h - k * nx * ny;
+    const int j = tail_div(rem, L.rnx);
+    const int i = rem - j * nx;
     float u[8][3];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -706,7 +736,8 @@ __device__ void tail_apply(const TailLevel& L, const float* v, float* out, float
   }
   __syncthreads();
   for (int n = threadIdx.x; n < nn; n += blockDim.x) {
-    const int i = n % nx1, j = (n / nx1) % (ny + 1), k = n / pl;
+    int i, j, k;
+    tail_node_ijk(L, n, i, j, k);
     const int m = L.mask[n];
     float acc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -719,89 +750,104 @@ __device__ void tail_apply(const TailLevel& L, const float* v, float* out, float
       for (int a = 0; a < 3; ++a) acc[a] += F[(c * 3 + a) * ncube + h];
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) out[a * nn + n] = ((m >> a) & 1) ? 0.f : acc[a];
+    for (int a = 0; a < 3; ++a) {
+      const int e = a * nn + n;
+      const float kv = ((m >> a) & 1) ? 0.f : acc[a];
+      if (EPI == 0) {
+        L.q[e] = kv;
+      } else if (EPI == 1) {
+        const float rv = L.b[e] - kv;
+        const float dv = s1 * L.invd[e] * rv;
+        L.r[e] = rv;
+        L.d[e] = dv;
+        L.x[e] = L.x[e] + dv;
+      } else {
+        const float rv = L.r[e] - kv;
+        const float dv = s1 * L.d[e] + s2 * L.invd[e] * rv;
+        L.r[e] = rv;
+        L.d[e] = dv;
+        L.x[e] += dv;
+      }
+    }
   }
   __syncthreads();
 }
 
-// Chebyshev smoothing of one level from x = 0 or from x (cheb_first_kernel,
-// cheb_next_kernel)
+// Chebyshev smoothing of one level from x = 0 or from x (the steps of
+// cheb_first_kernel and cheb_next_kernel)
 __device__ void tail_smooth(const TailArgs& A, const TailLevel& L, double lmax, float* F,
                             bool from_zero) {
   const int degree = from_zero ? A.deg0 : A.degx;
   if (degree == 0) return;
-  const int nd = 3 * L.nn;
-  if (!from_zero) tail_apply(L, L.x, L.q, F, A.lam, A.mu);
   const float it = float(cheb_first_scale(lmax, A.low, A.kind));
-  for (int j = threadIdx.x; j < nd; j += blockDim.x) {
-    const float id = L.invd[j];
-    const float rv = from_zero ? L.b[j] : L.b[j] - L.q[j];
-    const float dv = it * id * rv;
-    L.r[j] = rv;
-    L.d[j] = dv;
-    L.x[j] = from_zero ? dv : L.x[j] + dv;
-  }
-  __syncthreads();
-  for (int k = 1; k < degree; ++k) {
-    tail_apply(L, L.d, L.q, F, A.lam, A.mu);
-    double c1d, c2d;
-    cheb_next_coef(lmax, A.low, ChebCoef{A.rc[k], A.rp[k], A.kind, k}, c1d, c2d);
-    const float c1 = float(c1d), c2 = float(c2d);
-    for (int j = threadIdx.x; j < nd; j += blockDim.x) {
-      const float id = L.invd[j];
-      const float rv = L.r[j] - L.q[j];
-      const float dv = c1 * L.d[j] + c2 * id * rv;
+  if (from_zero) {
+    for (int j = threadIdx.x; j < 3 * L.nn; j += blockDim.x) {
+      const float rv = L.b[j];
+      const float dv = it * L.invd[j] * rv;
       L.r[j] = rv;
       L.d[j] = dv;
-      L.x[j] += dv;
+      L.x[j] = dv;
     }
     __syncthreads();
+  } else {
+    tail_apply<1>(L, L.x, F, A.lam, A.mu, it);
+  }
+  for (int k = 1; k < degree; ++k) {
+    double c1d, c2d;
+    cheb_next_coef(lmax, A.low, ChebCoef{A.rc[k], A.rp[k], A.kind, k}, c1d, c2d);
+    tail_apply<2>(L, L.d, F, A.lam, A.mu, float(c1d), float(c2d));
   }
 }
 
 // coarse b = P^T (b - K x) of the fine level (restrict_node's sums)
 __device__ void tail_restrict(const TailArgs& A, const TailLevel& Fl, const TailLevel& Cl, float* F) {
-  tail_apply(Fl, Fl.x, Fl.q, F, A.lam, A.mu);
+  tail_apply<0>(Fl, Fl.x, F, A.lam, A.mu);
   const int nxf1 = Fl.nx + 1, nyf1 = Fl.ny + 1;
-  const int nxc1 = Cl.nx + 1, nyc1 = Cl.ny + 1;
-  for (int idx = threadIdx.x; idx < 3 * Cl.nn; idx += blockDim.x) {
-    const int c = idx / Cl.nn, C = idx - c * Cl.nn;
-    const int I = C % nxc1, J = (C / nxc1) % nyc1, K = C / (nxc1 * nyc1);
-    const float* bf = Fl.b + c * Fl.nn;
-    const float* qf = Fl.q + c * Fl.nn;
-    float acc = 0.f;
-    if (2 * I <= Fl.nx && 2 * J <= Fl.ny && 2 * K <= Fl.nz) {
-      const int n = ((2 * K) * nyf1 + 2 * J) * nxf1 + 2 * I;
-      acc += bf[n] - qf[n];
-    }
-    for (int dd = 1; dd <= 7; ++dd) {
-      const int dx = dd & 1, dy = (dd >> 1) & 1, dz = (dd >> 2) & 1;
-      for (int sgn = -1; sgn <= 1; sgn += 2) {
-        const int fi = 2 * I + sgn * dx, fj = 2 * J + sgn * dy, fk = 2 * K + sgn * dz;
-        if (fi < 0 || fj < 0 || fk < 0 || fi > Fl.nx || fj > Fl.ny || fk > Fl.nz) continue;
-        const int n = (fk * nyf1 + fj) * nxf1 + fi;
-        acc += 0.5f * (bf[n] - qf[n]);
+  for (int C = threadIdx.x; C < Cl.nn; C += blockDim.x) {
+    int I, J, K;
+    tail_node_ijk(Cl, C, I, J, K);
+    const int cm = Cl.mask[C];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float* bf = Fl.b + c * Fl.nn;
+      const float* qf = Fl.q + c * Fl.nn;
+      float acc = 0.f;
+      if (2 * I <= Fl.nx && 2 * J <= Fl.ny && 2 * K <= Fl.nz) {
+        const int n = ((2 * K) * nyf1 + 2 * J) * nxf1 + 2 * I;
+        acc += bf[n] - qf[n];
       }
+      for (int dd = 1; dd <= 7; ++dd) {
+        const int dx = dd & 1, dy = (dd >> 1) & 1, dz = (dd >> 2) & 1;
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+          const int fi = 2 * I + sgn * dx, fj = 2 * J + sgn * dy, fk = 2 * K + sgn * dz;
+          if (fi < 0 || fj < 0 || fk < 0 || fi > Fl.nx || fj > Fl.ny || fk > Fl.nz) continue;
+          const int n = (fk * nyf1 + fj) * nxf1 + fi;
+          acc += 0.5f * (bf[n] - qf[n]);
+        }
+      }
+      Cl.b[c * Cl.nn + C] = ((cm >> c) & 1) ? 0.f : acc;
     }
-    Cl.b[idx] = ((Cl.mask[C] >> c) & 1) ? 0.f : acc;
   }
   __syncthreads();
 }
 
 // fine x += P (coarse x) (prolong_add_split_kernel's interpolation)
 __device__ void tail_prolong(const TailLevel& Fl, const TailLevel& Cl) {
-  const int nxf1 = Fl.nx + 1, nyf1 = Fl.ny + 1;
   const int nxc1 = Cl.nx + 1, nyc1 = Cl.ny + 1;
-  for (int idx = threadIdx.x; idx < 3 * Fl.nn; idx += blockDim.x) {
-    const int c = idx / Fl.nn, n = idx - c * Fl.nn;
-    if ((Fl.mask[n] >> c) & 1) continue;
-    const int i = n % nxf1, j = (n / nxf1) % nyf1, k = n / (nxf1 * nyf1);
+  for (int n = threadIdx.x; n < Fl.nn; n += blockDim.x) {
+    int i, j, k;
+    tail_node_ijk(Fl, n, i, j, k);
+    const int m = Fl.mask[n];
     const int c0 = ((k >> 1) * nyc1 + (j >> 1)) * nxc1 + (i >> 1);
     const int c1 = (((k + 1) >> 1) * nyc1 + ((j + 1) >> 1)) * nxc1 + ((i + 1) >> 1);
     const bool even = ((i | j | k) & 1) == 0;
-    const float* xcr = Cl.x + c * Cl.nn;
-    const float e = even ? xcr[c0] : 0.5f * (xcr[c0] + xcr[c1]);
-    Fl.x[idx] += e;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if ((m >> c) & 1) continue;
+      const float* xcr = Cl.x + c * Cl.nn;
+      const float e = even ? xcr[c0] : 0.5f * (xcr[c0] + xcr[c1]);
+      Fl.x[c * Fl.nn + n] += e;
+    }
   }
   __syncthreads();
 }
@@ -937,10 +983,13 @@ static bool tail_program(const Ctx* c, int l, int l0, bool x_zero, int wlevels,
   return (int)ops.size() <= kTailMaxOps;
 }
 
+// the cycle of levels l0.. from x_zero, then (visits = 2) once more from
+// its result, in one launch
 static bool launch_tail(Ctx* c, int l0, const float* b, float* x, int nrhs, bool x_zero,
-                        int wlevels) {
+                        int wlevels, int visits) {
   std::vector<TailOp> ops;
   if (!tail_program(c, l0, l0, x_zero, wlevels, ops)) return false;
+  if (visits == 2 && !tail_program(c, l0, l0, false, wlevels, ops)) return false;
   const int L = (int)c->lv.size();
   const GmgParams gp = gmg_params();
   if (gp.cheb_degree > 8 || gp.post_degree > 8) return false;
@@ -954,6 +1003,10 @@ static bool launch_tail(Ctx* c, int l0, const float* b, float* x, int nrhs, bool
     s.ny = g.op.ny;
     s.nz = g.op.nz;
     s.nn = (int)g.op.nn;
+    s.rnx = float(1.0 / s.nx);
+    s.rnxy = float(1.0 / ((double)s.nx * s.ny));
+    s.rnx1 = float(1.0 / (s.nx + 1));
+    s.rpl = float(1.0 / ((double)(s.nx + 1) * (s.ny + 1)));
     s.mask = g.op.mask;
     s.E = g.E32;
     s.invd = g.invd32;
@@ -1006,7 +1059,7 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs, bool x_zero,
     return;
   }
   if constexpr (std::is_same<T, float>::value) {
-    if (l == tail_level(c) && launch_tail(c, l, b, x, nrhs, x_zero, wlevels)) return;
+    if (l == tail_level(c) && launch_tail(c, l, b, x, nrhs, x_zero, wlevels, 1)) return;
   }
   GmgLevel& h = c->lv[l + 1];
   T* hb = reinterpret_cast<T*>(h.b);
@@ -1027,8 +1080,16 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs, bool x_zero,
   } else {
     restrict_kernel<T><<<cdivu(h.op.nn, 256), 256, 0, s>>>(hb, b, gq, g.op, h.op, nrhs, stop);
   }
-  vcycle_level<T>(c, l + 1, hb, hx, nrhs, true, wlevels);
-  if (revisits(c, l, wlevels)) vcycle_level<T>(c, l + 1, hb, hx, nrhs, false, wlevels);
+  const bool twice = revisits(c, l, wlevels);
+  bool in_tail = false;
+  if constexpr (std::is_same<T, float>::value) {
+    // both visits of a tail level in one launch
+    if (l + 1 == tail_level(c)) in_tail = launch_tail(c, l + 1, hb, hx, nrhs, true, wlevels, twice ? 2 : 1);
+  }
+  if (!in_tail) {
+    vcycle_level<T>(c, l + 1, hb, hx, nrhs, true, wlevels);
+    if (twice) vcycle_level<T>(c, l + 1, hb, hx, nrhs, false, wlevels);
+  }
   if (g.op.nn >= 262144) {
     if (g.op.dim == 3) prolong_large<T, 3>(s, x, hx, g.op, h.op, nrhs, stop);
     else prolong_large<T, 2>(s, x, hx, g.op, h.op, nrhs, stop);
