@@ -9,8 +9,9 @@ residual 1e-8 per load case.  One step is one full SIMP iteration (solve,
 sensitivity, filter, OC update) on device-resident data; the design evolves
 from step to step as in a real run, starting from rho = volfrac, so the
 default 2 warmup + 48 timed steps are iterations 3..50 of a 50-iteration
-run.  Default solve: multigrid-preconditioned CG with the FP32 V-cycle
-inside FP64 flexible CG.
+run.  Default solve: reliable-update FP32 conjugate gradients with the FP32
+geometric multigrid cycle (W-cycle on the top levels), FP64 dot products and
+FP64 reliable updates of the solution and the true residual.
 
 Printed: one JSON line with the throughput, the live roofline of the
 operator-apply kernel (algorithmic bytes per launch / mean launch time from
@@ -457,12 +458,14 @@ def bench_umesh(args):
 
 def bench_learned(args):
     """Learned-preconditioner workload: 128 x 64 x 64 cubes (6 tets each,
-    1,635,075 DOFs), load case 1, rtol 1e-8.  Untimed set-up: pairs
-    harvested from FP64 multigrid PCG along three seeded SIMP histories
-    (the canonical problem and two with volfrac ~ U[0.3, 0.5], rmin ~
-    U[1.5, 3]), then on-GPU training.  Reported: time to solution on a
-    held-out later design for FP64 multigrid PCG, mixed multigrid PCG, the
-    learned flexible CG and the same cycle without the network; timed: SIMP
+    1,635,075 DOFs), load case 1, rtol 1e-8.  Untimed set-up: the output gain
+    and a held-out later design from the canonical history; then about
+    20,000 (residual, error) pairs harvested from FP64 multigrid PCG along
+    seeded random SIMP histories (volfrac ~ U[0.3, 0.5], rmin ~ U[1.5, 3])
+    stream through a 2048-pair replay buffer while the network trains on the
+    GPU (one step per pair by default).  Reported: time to solution on the
+    held-out design for FP64 multigrid PCG, mixed multigrid PCG, the learned
+    flexible CG and the same cycle without the network; timed: SIMP
     iterations with the learned preconditioner."""
     import numpy as np
     import torch
@@ -473,40 +476,39 @@ def bench_learned(args):
     p = synth.learned3d(rtol=1e-8)
     its = [1, 2, 4, 8, 16, 24]
     t = learned.gmg_context(p, rtol=1e-8, device=dev)
-    t0 = time.perf_counter()
-    sets = [learned.harvest_history(t, n_designs=5, simp_steps=4, harvest_iters=its)]
-    rng = np.random.default_rng(20120820)
-    for v in range(2):
-        pv = synth.learned3d(rtol=1e-8, volfrac=float(rng.uniform(0.3, 0.5)),
-                             rmin=float(rng.uniform(1.5, 3.0)))
-        tv = learned.gmg_context(pv, rtol=1e-8, device=dev)
-        sets.append(learned.harvest_history(tv, n_designs=4, simp_steps=5, harvest_iters=its))
-        tv.close()
-    ps = learned.PairSet(
-        rhos=[r for s_ in sets for r in s_.rhos],
-        R=torch.cat([s_.R for s_ in sets]), E=torch.cat([s_.E for s_ in sets]),
-        design=np.concatenate([s_.design + sum(len(x.rhos) for x in sets[:i])
-                               for i, s_ in enumerate(sets)]),
-        iters=[k for s_ in sets for k in s_.iters])
-    torch.cuda.synchronize()
-    t_harvest = time.perf_counter() - t0
-    print(f"[bench] harvested {ps.R.shape[0]} pairs in {t_harvest:.1f} s", file=sys.stderr, flush=True)
-    gamma = learned.choose_gamma(ps)
-    rho_test = sets[0].rhos[-1].clone()
+    # the canonical history: the output gain and a held-out later design
+    ps0 = learned.harvest_history(t, n_designs=3, simp_steps=4, harvest_iters=its)
+    gamma = learned.choose_gamma(ps0)
+    rho_test = ps0.rhos[-1].clone()
     u = torch.zeros(p.n_dofs, dtype=torch.float64, device=dev)
     t.iterate(rho_test, u, 4)            # a later design than any trained on
     w = learned.init_weights(60, dev)
     t.precond_set_weights(w)
     t.precond_config(gamma, 500, 1)
+    # training pairs streamed through a replay buffer from seeded random
+    # SIMP histories (volfrac ~ U[0.3, 0.5], rmin ~ U[1.5, 3]); Adam at 3e-4
+    # with cosine decay to 3e-5 (at 1e-3 the loss spiked by orders of
+    # magnitude after a few hundred steps in some runs)
+    rng = np.random.default_rng(20120820)
+    hist = [(float(rng.uniform(0.3, 0.5)), float(rng.uniform(1.5, 3.0))) for _ in range(4096)]
+
+    def histories(h):
+        return synth.learned3d(rtol=1e-8, volfrac=hist[h][0], rmin=hist[h][1])
+
+    dense = [1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 18, 20, 22, 25, 28]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    # Adam at 3e-4 (cosine to 3e-5): at 1e-3 the loss spiked by orders of
-    # magnitude after a few hundred steps in some runs
-    losses = learned.train(t, ps, steps=args.train_steps, lr=3e-4, seed=61, lr_final=3e-5)
+    tr = learned.stream_train(
+        t, histories, n_pairs=args.learned_pairs, harvest_iters=dense,
+        capacity=args.learned_capacity, steps_per_pair=args.train_steps / args.learned_pairs,
+        lr=3e-4, lr_final=3e-5, seed=61, simp_steps=1, designs_per_history=50,
+        log=lambda m: print(f"[bench] learned stream: {m}", file=sys.stderr, flush=True))
     torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    L = losses.cpu().numpy()
-    print(f"[bench] trained {args.train_steps} steps in {t_train:.1f} s, loss {L[:100].mean():.3f} -> "
+    t_setup = time.perf_counter() - t0
+    L = tr["losses"].cpu().numpy()
+    print(f"[bench] streamed {tr['pairs']} pairs ({tr['designs']} designs, {tr['histories']} "
+          f"histories, buffer {tr['capacity']}), {tr['steps']} training steps, harvest "
+          f"{tr['harvest_s']:.1f} s, train {tr['train_s']:.1f} s, loss {L[:100].mean():.3f} -> "
           f"{L[-100:].mean():.3f}", file=sys.stderr, flush=True)
     t.precond_get_weights(w)
     t.close()
@@ -578,7 +580,7 @@ def bench_learned(args):
         w3 = learned.init_weights(62, dev)
         ttr.precond_set_weights(w3)
         ttr.precond_config(gamma3, 500, 1)
-        L3 = learned.train(ttr, ps3, steps=args.train_steps, lr=3e-4, seed=63,
+        L3 = learned.train(ttr, ps3, steps=args.train_steps_full, lr=3e-4, seed=63,
                            lr_final=3e-5).cpu().numpy()
         ttr.precond_get_weights(w3)
         torch.cuda.synchronize()
@@ -586,7 +588,7 @@ def bench_learned(args):
         for tk in cases:
             tk.close()
         del ps3, R3, E3
-        print(f"[bench] 192x96x96: {len(des3)} pairs, trained {args.train_steps} steps, loss "
+        print(f"[bench] 192x96x96: {len(des3)} pairs, trained {args.train_steps_full} steps, loss "
               f"{L3[:100].mean():.3f} -> {L3[-100:].mean():.3f}, set-up {setup3:.1f} s",
               file=sys.stderr, flush=True)
         for name, prec, pc, reps in (("jacobi_fp64", TOPO_FP64, TOPO_PC_JACOBI, 1),
@@ -603,7 +605,7 @@ def bench_learned(args):
         tl3 = learned.learned_context(p3, w3, gamma3, 8000, 1, rtol=1e-8, device=dev)
         res3["learned_fcg"] = tts(tl3, 1, rho3, n_u3)
         tl3.close()
-        res3["training"] = {"pairs": len(des3), "steps": args.train_steps,
+        res3["training"] = {"pairs": len(des3), "steps": args.train_steps_full,
                             "loss_first100": float(L3[:100].mean()),
                             "loss_last100": float(L3[-100:].mean()), "gamma": gamma3,
                             "setup_s": setup3}
@@ -652,10 +654,13 @@ def bench_learned(args):
             "cg_iters_per_step": lg[:, 5].tolist(),
             "time_to_solution_heldout": res,
             "time_to_solution_192x96x96_4rhs": res3 or None,
-            "training": {"pairs": int(ps.R.shape[0]), "steps": args.train_steps,
-                         "ms_per_step": 1e3 * t_train / max(1, args.train_steps),
+            "training": {"pairs_streamed": tr["pairs"], "designs": tr["designs"],
+                         "histories": tr["histories"], "replay_capacity": tr["capacity"],
+                         "steps": tr["steps"],
+                         "ms_per_step": 1e3 * tr["train_s"] / max(1, tr["steps"]),
                          "loss_first100": float(L[:100].mean()), "loss_last100": float(L[-100:].mean()),
-                         "harvest_s": t_harvest, "gamma": gamma},
+                         "harvest_s": tr["harvest_s"], "setup_s": t_setup, "gamma": gamma,
+                         "harvest_solve_iters_mean": tr["solve_iters_mean"]},
         },
         "roofline": {
             "kernel": "network signal pass (12 MFMA convolutions)",
@@ -803,8 +808,14 @@ def main():
                          "sensitivity filter (Sec. 6.3), or a density filter on the distance weights")
     ap.add_argument("--maxit", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--train-steps", type=int, default=3000,
+    ap.add_argument("--train-steps", type=int, default=20000,
                     help="learned3d workload: on-GPU training steps before the timed run")
+    ap.add_argument("--train-steps-full", type=int, default=3000,
+                    help="learned3d workload: training steps of the 192x96x96 comparison")
+    ap.add_argument("--learned-pairs", type=int, default=20000,
+                    help="learned3d workload: pairs streamed through the replay buffer")
+    ap.add_argument("--learned-capacity", type=int, default=2048,
+                    help="learned3d workload: replay buffer size in pairs")
     ap.add_argument("--no-full", dest="full", action="store_false",
                     help="learned3d: skip the 192x96x96 time-to-solution comparison")
     ap.add_argument("--batch-converge", action="store_true",

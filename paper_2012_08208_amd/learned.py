@@ -6,7 +6,8 @@ harvests the iterates of a PCG solve at the current design
 (``topo_precond_harvest``).  Training steps, the loss, the backward pass and
 Adam all run in the library's kernels (``topo_precond_train_step``).  This
 module only chooses which pair to feed next, keeps the pairs in device
-memory, and records losses.
+memory (a fixed pair set, or a replay buffer that pairs stream through),
+and records losses.
 """
 
 from __future__ import annotations
@@ -98,6 +99,127 @@ def train(t: Topo, ps: PairSet, steps: int, lr: float, seed: int = 0, lr_final: 
             a = lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * s / (steps - 1)))
         t.precond_train_step(ps.rhos[int(ps.design[i])], ps.R[i], ps.E[i], a, losses[s:s + 1])
     return losses
+
+
+class Replay:
+    """Ring buffer of (r, e) pairs in device memory, with a ring of the
+    designs they were harvested at.  New pairs overwrite the oldest; a pair
+    whose design slot has since been reused is never drawn."""
+
+    def __init__(self, t: Topo, capacity: int, design_capacity: int):
+        torch = t.torch
+        self.torch = torch
+        self.R = torch.empty((capacity, t.n_dofs), dtype=torch.float64, device=t.device)
+        self.E = torch.empty_like(self.R)
+        self.rhos = torch.empty((design_capacity, t.n_cells), dtype=torch.float64, device=t.device)
+        self.pair_design = np.full(capacity, -1, dtype=np.int64)   # design serial of each slot
+        self.slot_serial = np.full(design_capacity, -1, dtype=np.int64)
+        self.head = 0
+        self.dhead = 0
+        self.pairs_seen = 0
+        self.designs_seen = 0
+
+    @property
+    def capacity(self) -> int:
+        return self.R.shape[0]
+
+    def add_design(self, rho) -> int:
+        """Stores a design; returns its serial number."""
+        slot = self.dhead
+        self.rhos[slot].copy_(rho)
+        serial = self.designs_seen
+        self.slot_serial[slot] = serial
+        self.dhead = (self.dhead + 1) % self.rhos.shape[0]
+        self.designs_seen += 1
+        return serial
+
+    def add_pairs(self, serial: int, R, E) -> None:
+        for i in range(R.shape[0]):
+            self.R[self.head].copy_(R[i])
+            self.E[self.head].copy_(E[i])
+            self.pair_design[self.head] = serial
+            self.head = (self.head + 1) % self.capacity
+            self.pairs_seen += 1
+
+    def valid(self) -> np.ndarray:
+        """Slots whose design is still held."""
+        ds = self.pair_design
+        ok = ds >= 0
+        slots = ds % self.rhos.shape[0]
+        ok &= self.slot_serial[np.where(ok, slots, 0)] == ds
+        return np.nonzero(ok)[0]
+
+    def design_of(self, i: int):
+        return self.rhos[int(self.pair_design[i] % self.rhos.shape[0])]
+
+
+def stream_train(t: Topo, histories, n_pairs: int, harvest_iters: Sequence[int], capacity: int,
+                 steps_per_pair: float, lr: float, lr_final: float, seed: int,
+                 simp_steps: int = 1, designs_per_history: int = 40, log=None) -> dict:
+    """Streams about ``n_pairs`` harvested pairs through a replay buffer of
+    ``capacity`` pairs while training the network of context ``t``.
+
+    ``histories(h)`` returns the problem of the h-th seeded SIMP history (the
+    same grid and supports as ``t``'s problem).  Each history starts from the
+    uniform design; every ``simp_steps`` SIMP iterations its design is
+    stored and a multigrid PCG solve there is harvested at ``harvest_iters``
+    (pre-smoothed pairs).  After each harvest, ``steps_per_pair`` training
+    steps per new pair draw pairs uniformly from the buffer; the learning
+    rate follows a cosine from ``lr`` to ``lr_final`` over the planned
+    steps.  Returns the device tensor of losses and counts and times."""
+    import time
+    torch = t.torch
+    rng = np.random.default_rng(seed)
+    its = [int(k) for k in harvest_iters]
+    per_design = len(its)
+    design_capacity = capacity // max(1, per_design) + 8
+    buf = Replay(t, capacity, design_capacity)
+    planned = max(1, int(round(n_pairs * steps_per_pair)))
+    losses = torch.zeros(planned, dtype=torch.float64, device=t.device)
+    step = 0
+    credit = 0.0
+    h = 0
+    t_harvest = t_train = 0.0
+    solve_iters = []
+    R = torch.empty(per_design * t.n_dofs, dtype=torch.float64, device=t.device)
+    E = torch.empty_like(R)
+    while buf.pairs_seen < n_pairs:
+        th = gmg_context(histories(h), rtol=t.prob.rtol, device=t.device)
+        rho = torch.full((t.n_cells,), th.prob.volfrac, dtype=torch.float64, device=t.device)
+        u = torch.zeros(th.vec_numel(), dtype=torch.float64, device=t.device)
+        for d in range(designs_per_history):
+            if buf.pairs_seen >= n_pairs:
+                break
+            a = time.perf_counter()
+            th.iterate(rho, u, simp_steps)
+            n, fin = th.precond_harvest(rho, its, R, E, True)
+            keep = [i for i in range(n) if its[i] < fin]
+            serial = buf.add_design(rho)
+            buf.add_pairs(serial, R.view(per_design, t.n_dofs)[keep],
+                          E.view(per_design, t.n_dofs)[keep])
+            solve_iters.append(fin)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            t_harvest += b - a
+            credit += steps_per_pair * len(keep)
+            valid = buf.valid()
+            while credit >= 1.0 and step < planned:
+                i = int(valid[int(rng.integers(len(valid)))])
+                c = 0.5 * (1.0 + np.cos(np.pi * step / max(1, planned - 1)))
+                t.precond_train_step(buf.design_of(i), buf.R[i], buf.E[i],
+                                     lr_final + (lr - lr_final) * c, losses[step:step + 1])
+                step += 1
+                credit -= 1.0
+            torch.cuda.synchronize()
+            t_train += time.perf_counter() - b
+            if log is not None and d == 0:
+                log(f"history {h}: {buf.pairs_seen} pairs, {step} steps, "
+                    f"harvest {t_harvest:.1f} s, train {t_train:.1f} s")
+        th.close()
+        h += 1
+    return {"losses": losses[:step], "pairs": buf.pairs_seen, "designs": buf.designs_seen,
+            "histories": h, "steps": step, "capacity": capacity, "harvest_s": t_harvest,
+            "train_s": t_train, "solve_iters_mean": float(np.mean(solve_iters)) if solve_iters else 0.0}
 
 
 def learned_context(p, weights, gamma: float, fcg_maxit: int = 500, smooth: int = 1, rtol=None,
