@@ -697,60 +697,79 @@ __device__ __forceinline__ void tail_node_ijk(const TailLevel& L, int n, int& i,
 }
 
 // K v on one level (v is zero on fixed DOFs; fixed rows give 0), the whole
-// block.  What the node pass does with K v at its node:
+// block.  3D: cubes of six Kuhn tetrahedra (cube_force, 24 corner values);
+// 2D: squares of two diagonal-A triangles, as on every coarse 2D level
+// (square_force, 8 corner values).  What the node pass does with K v at its
+// node:
 //   EPI 0: q = K v;
 //   EPI 1 (first Chebyshev step from x, v = x): r = b - K x, d = s D^-1 r, x += d;
 //   EPI 2 (next Chebyshev step, v = d): r -= K d, d = c1 d + c2 D^-1 r, x += d.
 // The node pass writes v only at its own node, after the barrier that ends
-// the cube pass, so the in-place updates are safe.
-template <int EPI>
+// the cell pass, so the in-place updates are safe.
+template <int DIM, int EPI>
 __device__ void tail_apply(const TailLevel& L, const float* v, float* F, float lam0, float mu0,
                            float s1 = 0.f, float s2 = 0.f) {
-  const int nx = L.nx, ny = L.ny, nz = L.nz, nn = L.nn;
-  const int ncube = nx * ny * nz, nx1 = nx + 1, pl = (nx + 1) * (ny + 1);
-  for (int h = threadIdx.x; h < ncube; h += blockDim.x) {
-    const int k = tail_div(h, L.rnxy);
-    const int rem = h - k * nx * ny;
-    const int j = tail_div(rem, L.rnx);
-    const int i = rem - j * nx;
-    float u[8][3];
+  constexpr int NC = DIM == 3 ? 8 : 4;   // corners per cell
+  const int nx = L.nx, ny = L.ny, nz = DIM == 3 ? L.nz : 1, nn = L.nn;
+  const int ncell = nx * ny * nz, nx1 = nx + 1, pl = (nx + 1) * (ny + 1);
+  for (int h = threadIdx.x; h < ncell; h += blockDim.x) {
+    int i, j, k;
+    if (DIM == 3) {
+      k = tail_div(h, L.rnxy);
+      const int rem = h - k * nx * ny;
+      j = tail_div(rem, L.rnx);
+      i = rem - j * nx;
+    } else {
+      k = 0;
+      j = tail_div(h, L.rnx);
+      i = h - j * nx;
+    }
+    float u[NC][DIM], f[NC][DIM];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < NC; ++c) {
       const int node = (k + (c >> 2)) * pl + (j + ((c >> 1) & 1)) * nx1 + i + (c & 1);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) u[c][a] = v[a * nn + node];
+      for (int a = 0; a < DIM; ++a) u[c][a] = v[a * nn + node];
     }
-    float lam[6], mu[6];
+    if constexpr (DIM == 3) {
+      float lam[6], mu[6];
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
-      const float e = L.E[6 * h + t];
-      lam[t] = lam0 * e;
-      mu[t] = mu0 * e;
+      for (int t = 0; t < 6; ++t) {
+        const float e = L.E[6 * h + t];
+        lam[t] = lam0 * e;
+        mu[t] = mu0 * e;
+      }
+      cube_force<float>(u, lam, mu, f);
+    } else {
+      const float e0 = L.E[2 * h], e1 = L.E[2 * h + 1];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) f[c][0] = f[c][1] = 0.f;
+      square_force<float>(true, u, lam0 * e0, mu0 * e0, lam0 * e1, mu0 * e1, f);
     }
-    float f[8][3];
-    cube_force<float>(u, lam, mu, f);
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) F[(c * 3 + a) * ncube + h] = f[c][a];
+      for (int a = 0; a < DIM; ++a) F[(c * DIM + a) * ncell + h] = f[c][a];
   }
   __syncthreads();
   for (int n = threadIdx.x; n < nn; n += blockDim.x) {
     int i, j, k;
     tail_node_ijk(L, n, i, j, k);
     const int m = L.mask[n];
-    float acc[3] = {0.f, 0.f, 0.f};
+    float acc[DIM];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      // the node is corner c of the cube at (i, j, k) - c
+    for (int a = 0; a < DIM; ++a) acc[a] = 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      // the node is corner c of the cell at (i, j, k) - c
       const int ci = i - (c & 1), cj = j - ((c >> 1) & 1), ck = k - (c >> 2);
       if (ci < 0 || cj < 0 || ck < 0 || ci >= nx || cj >= ny || ck >= nz) continue;
       const int h = (ck * ny + cj) * nx + ci;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) acc[a] += F[(c * 3 + a) * ncube + h];
+      for (int a = 0; a < DIM; ++a) acc[a] += F[(c * DIM + a) * ncell + h];
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < DIM; ++a) {
       const int e = a * nn + n;
       const float kv = ((m >> a) & 1) ? 0.f : acc[a];
       if (EPI == 0) {
@@ -775,13 +794,14 @@ __device__ void tail_apply(const TailLevel& L, const float* v, float* F, float l
 
 // Chebyshev smoothing of one level from x = 0 or from x (the steps of
 // cheb_first_kernel and cheb_next_kernel)
+template <int DIM>
 __device__ void tail_smooth(const TailArgs& A, const TailLevel& L, double lmax, float* F,
                             bool from_zero) {
   const int degree = from_zero ? A.deg0 : A.degx;
   if (degree == 0) return;
   const float it = float(cheb_first_scale(lmax, A.low, A.kind));
   if (from_zero) {
-    for (int j = threadIdx.x; j < 3 * L.nn; j += blockDim.x) {
+    for (int j = threadIdx.x; j < DIM * L.nn; j += blockDim.x) {
       const float rv = L.b[j];
       const float dv = it * L.invd[j] * rv;
       L.r[j] = rv;
@@ -790,37 +810,40 @@ __device__ void tail_smooth(const TailArgs& A, const TailLevel& L, double lmax, 
     }
     __syncthreads();
   } else {
-    tail_apply<1>(L, L.x, F, A.lam, A.mu, it);
+    tail_apply<DIM, 1>(L, L.x, F, A.lam, A.mu, it);
   }
   for (int k = 1; k < degree; ++k) {
     double c1d, c2d;
     cheb_next_coef(lmax, A.low, ChebCoef{A.rc[k], A.rp[k], A.kind, k}, c1d, c2d);
-    tail_apply<2>(L, L.d, F, A.lam, A.mu, float(c1d), float(c2d));
+    tail_apply<DIM, 2>(L, L.d, F, A.lam, A.mu, float(c1d), float(c2d));
   }
 }
 
-// coarse b = P^T (b - K x) of the fine level (restrict_node's sums)
+// coarse b = P^T (b - K x) of the fine level (restrict_node's sums: the
+// centre, then the lattice directions d in {0,1}^DIM \ 0 at -d and +d)
+template <int DIM>
 __device__ void tail_restrict(const TailArgs& A, const TailLevel& Fl, const TailLevel& Cl, float* F) {
-  tail_apply<0>(Fl, Fl.x, F, A.lam, A.mu);
-  const int nxf1 = Fl.nx + 1, nyf1 = Fl.ny + 1;
+  tail_apply<DIM, 0>(Fl, Fl.x, F, A.lam, A.mu);
+  constexpr int NDIR = DIM == 3 ? 7 : 3;
+  const int nxf1 = Fl.nx + 1, nyf1 = Fl.ny + 1, nzf = DIM == 3 ? Fl.nz : 0;
   for (int C = threadIdx.x; C < Cl.nn; C += blockDim.x) {
     int I, J, K;
     tail_node_ijk(Cl, C, I, J, K);
     const int cm = Cl.mask[C];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < DIM; ++c) {
       const float* bf = Fl.b + c * Fl.nn;
       const float* qf = Fl.q + c * Fl.nn;
       float acc = 0.f;
-      if (2 * I <= Fl.nx && 2 * J <= Fl.ny && 2 * K <= Fl.nz) {
+      if (2 * I <= Fl.nx && 2 * J <= Fl.ny && 2 * K <= nzf) {
         const int n = ((2 * K) * nyf1 + 2 * J) * nxf1 + 2 * I;
         acc += bf[n] - qf[n];
       }
-      for (int dd = 1; dd <= 7; ++dd) {
+      for (int dd = 1; dd <= NDIR; ++dd) {
         const int dx = dd & 1, dy = (dd >> 1) & 1, dz = (dd >> 2) & 1;
         for (int sgn = -1; sgn <= 1; sgn += 2) {
           const int fi = 2 * I + sgn * dx, fj = 2 * J + sgn * dy, fk = 2 * K + sgn * dz;
-          if (fi < 0 || fj < 0 || fk < 0 || fi > Fl.nx || fj > Fl.ny || fk > Fl.nz) continue;
+          if (fi < 0 || fj < 0 || fk < 0 || fi > Fl.nx || fj > Fl.ny || fk > nzf) continue;
           const int n = (fk * nyf1 + fj) * nxf1 + fi;
           acc += 0.5f * (bf[n] - qf[n]);
         }
@@ -832,6 +855,7 @@ __device__ void tail_restrict(const TailArgs& A, const TailLevel& Fl, const Tail
 }
 
 // fine x += P (coarse x) (prolong_add_split_kernel's interpolation)
+template <int DIM>
 __device__ void tail_prolong(const TailLevel& Fl, const TailLevel& Cl) {
   const int nxc1 = Cl.nx + 1, nyc1 = Cl.ny + 1;
   for (int n = threadIdx.x; n < Fl.nn; n += blockDim.x) {
@@ -842,7 +866,7 @@ __device__ void tail_prolong(const TailLevel& Fl, const TailLevel& Cl) {
     const int c1 = (((k + 1) >> 1) * nyc1 + ((j + 1) >> 1)) * nxc1 + ((i + 1) >> 1);
     const bool even = ((i | j | k) & 1) == 0;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < DIM; ++c) {
       if ((m >> c) & 1) continue;
       const float* xcr = Cl.x + c * Cl.nn;
       const float e = even ? xcr[c0] : 0.5f * (xcr[c0] + xcr[c1]);
@@ -872,6 +896,7 @@ __device__ void tail_coarse(const double* __restrict__ Ainv, int n, float* x, co
 }
 
 // one work-group per load case (blockIdx.x)
+template <int DIM>
 __global__ __launch_bounds__(kTailThreads) void gmg_tail_kernel(TailArgs A, const int* stop) {
   if (stop && *stop) return;
   __shared__ float lds[kTailLdsFloats];
@@ -881,17 +906,17 @@ __global__ __launch_bounds__(kTailThreads) void gmg_tail_kernel(TailArgs A, cons
   // stage the levels' moduli, D^-1 and masks, and the first level's b (and x)
   for (int l = 0; l < A.nlev; ++l) {
     const TailLevelSrc& s = A.lv[l];
-    const int ncube = s.nx * s.ny * s.nz;
+    const int nE = DIM == 3 ? 6 * s.nx * s.ny * s.nz : 2 * s.nx * s.ny;
     for (int n = threadIdx.x; n < s.nn; n += blockDim.x) lmask[s.o_mask + n] = s.mask[n];
     if (l + 1 < A.nlev) {
-      for (int i = threadIdx.x; i < 6 * ncube; i += blockDim.x) lds[s.o_E + i] = s.E[i];
-      for (int i = threadIdx.x; i < 3 * s.nn; i += blockDim.x) lds[s.o_invd + i] = s.invd[i];
+      for (int i = threadIdx.x; i < nE; i += blockDim.x) lds[s.o_E + i] = s.E[i];
+      for (int i = threadIdx.x; i < DIM * s.nn; i += blockDim.x) lds[s.o_invd + i] = s.invd[i];
     }
   }
   {
     const TailLevelSrc& s = A.lv[0];
-    const long off = (long)r * 3 * s.nn;
-    for (int i = threadIdx.x; i < 3 * s.nn; i += blockDim.x) {
+    const long off = (long)r * DIM * s.nn;
+    for (int i = threadIdx.x; i < DIM * s.nn; i += blockDim.x) {
       lds[s.o_b + i] = A.b0[off + i];
       if (!A.x0_zero) lds[s.o_x + i] = A.x0[off + i];
     }
@@ -902,17 +927,17 @@ __global__ __launch_bounds__(kTailThreads) void gmg_tail_kernel(TailArgs A, cons
     const TailOp op = A.ops[o];
     const TailLevel L = tail_view(A, op.level, lds);
     switch (op.kind) {
-      case kTailSmooth0: tail_smooth(A, L, *A.lv[op.level].lmax, F, true); break;
-      case kTailSmoothX: tail_smooth(A, L, *A.lv[op.level].lmax, F, false); break;
-      case kTailRestrict: tail_restrict(A, L, tail_view(A, op.level + 1, lds), F); break;
-      case kTailProlong: tail_prolong(L, tail_view(A, op.level + 1, lds)); break;
+      case kTailSmooth0: tail_smooth<DIM>(A, L, *A.lv[op.level].lmax, F, true); break;
+      case kTailSmoothX: tail_smooth<DIM>(A, L, *A.lv[op.level].lmax, F, false); break;
+      case kTailRestrict: tail_restrict<DIM>(A, L, tail_view(A, op.level + 1, lds), F); break;
+      case kTailProlong: tail_prolong<DIM>(L, tail_view(A, op.level + 1, lds)); break;
       default: tail_coarse(A.Ainv, A.ncoarse, L.x, L.b, red); break;
     }
   }
   {
     const TailLevelSrc& s = A.lv[0];
-    const long off = (long)r * 3 * s.nn;
-    for (int i = threadIdx.x; i < 3 * s.nn; i += blockDim.x) A.x0[off + i] = lds[s.o_x + i];
+    const long off = (long)r * DIM * s.nn;
+    for (int i = threadIdx.x; i < DIM * s.nn; i += blockDim.x) A.x0[off + i] = lds[s.o_x + i];
   }
 }
 
@@ -928,7 +953,8 @@ static bool tail_layout(const Ctx* c, int l0, TailArgs& A) {
   for (int l = l0; l < L; ++l) {
     const OpDesc& d = c->lv[l].op;
     TailLevelSrc& s = A.lv[l - l0];
-    const int nn = (int)d.nn, nd = 3 * nn, ncube = d.nx * d.ny * d.nz;
+    const int nn = (int)d.nn, nd = d.dim * nn;
+    const int nE = d.dim == 3 ? 6 * d.nx * d.ny * d.nz : 2 * d.nx * d.ny;
     const bool last = l + 1 == L;
     s.o_mask = mb;
     mb += nn;
@@ -944,21 +970,21 @@ static bool tail_layout(const Ctx* c, int l0, TailArgs& A) {
       s.o_q = o;
       o += nd;
       s.o_E = o;
-      o += 6 * ncube;
+      o += nE;
       s.o_invd = o;
       o += nd;
     }
   }
   const OpDesc& d0 = c->lv[l0].op;
   A.o_F = o;
-  o += 24 * d0.nx * d0.ny * d0.nz;
+  o += d0.dim == 3 ? 24 * d0.nx * d0.ny * d0.nz : 8 * d0.nx * d0.ny;
   return o <= kTailLdsFloats;
 }
 
-// first level of the one-block tail (FP32 cycles of 3D problems), or -1
+// first level of the one-block tail (FP32 cycles), or -1
 static int tail_level(const Ctx* c) {
   const int L = (int)c->lv.size();
-  if (L < 2 || c->lv[0].op.dim != 3 || !gmg_params().tail) return -1;
+  if (L < 2 || !gmg_params().tail) return -1;
   static thread_local TailArgs probe;
   for (int l = 1; l + 1 < L; ++l)
     if (tail_layout(c, l, probe)) return l;
@@ -1030,11 +1056,15 @@ static bool launch_tail(Ctx* c, int l0, const float* b, float* x, int nrhs, bool
   A.kind = gp.cheb_kind;
   A.deg0 = gp.cheb_degree;
   A.degx = gp.post_degree;
-  A.ncoarse = (int)(c->lv[L - 1].op.nn * 3);
+  const int dim = c->lv[l0].op.dim;
+  A.ncoarse = (int)(c->lv[L - 1].op.nn * dim);
   if (A.ncoarse > 128) return false;
   A.nops = (int)ops.size();
   for (size_t i = 0; i < ops.size(); ++i) A.ops[i] = ops[i];
-  gmg_tail_kernel<<<nrhs, kTailThreads, 0, c->stream>>>(A, stop_flag(c));
+  if (dim == 3)
+    gmg_tail_kernel<3><<<nrhs, kTailThreads, 0, c->stream>>>(A, stop_flag(c));
+  else
+    gmg_tail_kernel<2><<<nrhs, kTailThreads, 0, c->stream>>>(A, stop_flag(c));
   return true;
 }
 

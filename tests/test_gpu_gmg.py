@@ -76,10 +76,10 @@ def test_wcycle_converges_to_the_vcycle_solution(wlevels, monkeypatch):
     assert "TOPO_GMG_WLEVELS" not in os.environ
 
 
-@pytest.mark.parametrize("nel", [(24, 12, 12), (40, 20, 20), (33, 17, 9)])
+@pytest.mark.parametrize("nel", [(24, 12, 12), (40, 20, 20), (33, 17, 9), (96, 48), (75, 29)])
 def test_one_block_coarse_tail_matches_the_per_level_kernels(nel, monkeypatch):
     """The FP32 cycle's small coarse levels in one work-group per load case
-    (default) against the per-level kernels (TOPO_GMG_TAIL=0): the same
+    (default; 3D and 2D) against the per-level kernels (TOPO_GMG_TAIL=0): the same
     preconditioner up to the order of the operator's node sums and FP32
     rounding.  After two CG iterations (plus the true-residual restart
     passes of two iterations each) the iterates agree to FP32 rounding,
@@ -87,7 +87,11 @@ def test_one_block_coarse_tail_matches_the_per_level_kernels(nel, monkeypatch):
     same solution in about the same iterations; two runs give the same
     bits."""
     from paper_2012_08208_amd import TOPO_MIXED_RU, TOPO_MIXED_FP32
-    p = synth.cantilever3d(*nel, nrhs=3, volfrac=0.3, rmin=1.5, rtol=1e-9)
+    if len(nel) == 3:
+        p = synth.cantilever3d(*nel, nrhs=3, volfrac=0.3, rmin=1.5, rtol=1e-9)
+    else:
+        # the alternating split on the fine level, diagonal A on the coarse ones
+        p = synth.cantilever2d(*nel, volfrac=0.4, rmin=1.5, rtol=1e-9)
     for code in (TOPO_MIXED_FP32, TOPO_MIXED_RU):
         short, full = {}, {}
         for tail in ("0", "1", "1"):
