@@ -124,11 +124,21 @@ __device__ inline void reduce_partials_range(const double* partials, long b0, lo
 #pragma unroll
       for (int k = 0; k < NT; ++k) acc[k] = (k < NV) ? acc[k] + xv[u][k] : fmax(acc[k], xv[u][k]);
   }
-  for (; b < b1; b += step) {
+  // the thread's last (at most U - 1) blocks: their loads issued together
+  // too, then added in the same order as above
+  if (b < b1) {
+    double xv[U - 1][NT];
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      const double x = partials[b * kPartStride + k];
-      acc[k] = (k < NV) ? acc[k] + x : fmax(acc[k], x);
+    for (int u = 0; u < U - 1; ++u)
+#pragma unroll
+      for (int k = 0; k < NT; ++k)
+        xv[u][k] = b + u * step < b1 ? partials[(b + u * step) * kPartStride + k] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U - 1; ++u) {
+      if (b + u * step < b1) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) acc[k] = (k < NV) ? acc[k] + xv[u][k] : fmax(acc[k], xv[u][k]);
+      }
     }
   }
 #pragma unroll
