@@ -113,3 +113,28 @@ def test_one_block_coarse_tail_matches_the_per_level_kernels(nel, monkeypatch):
             a, b = u1[r * p.n_dofs:(r + 1) * p.n_dofs], u0[r * p.n_dofs:(r + 1) * p.n_dofs]
             assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b)
     monkeypatch.delenv("TOPO_GMG_TAIL", raising=False)
+
+
+@pytest.mark.parametrize("env", [{"TOPO_CHEB_DEGREE": "3", "TOPO_CHEB_POST": "1"},
+                                 {"TOPO_CHEB_KIND": "4"},
+                                 {"TOPO_GMG_WLEVELS": "9"}])
+def test_one_block_tail_follows_the_smoother_and_cycle_switches(env, monkeypatch):
+    """The tail runs the same smoothing degrees, Chebyshev kind and W revisits
+    as the per-level kernels: after two CG iterations the iterates agree to
+    FP32 rounding (a different polynomial or cycle would differ at 1e-2)."""
+    from paper_2012_08208_amd import TOPO_MIXED_FP32
+    p = synth.cantilever3d(24, 12, 12, nrhs=2, volfrac=0.3, rmin=1.5, rtol=1e-9)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    out = {}
+    for tail in ("0", "1"):
+        monkeypatch.setenv("TOPO_GMG_TAIL", tail)
+        _, _, u2 = _solve(p, TOPO_MIXED_FP32, rho_val=0.4, maxit=2)
+        st, info, _ = _solve(p, TOPO_MIXED_FP32, rho_val=0.4)
+        assert st == 0 and info[1] == 1.0, (st, info)
+        out[tail] = (u2, info[0])
+    d2 = np.linalg.norm(out["1"][0] - out["0"][0]) / np.linalg.norm(out["0"][0])
+    print(f"[tail switches] {env}: rel diff {d2:.2e}, CG iterations {out['0'][1]:.0f} / "
+          f"{out['1'][1]:.0f}", flush=True)
+    assert d2 <= 1e-5
+    assert abs(out["1"][1] - out["0"][1]) <= 2
