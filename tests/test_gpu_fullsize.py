@@ -150,13 +150,15 @@ def test_fullsize_apply_f32_matches_fp64(full):
 
 
 def test_fullsize_solves_sensitivity_filter_oc(full):
-    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_BF16, TOPO_MIXED_FP32
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_BF16, TOPO_MIXED_FP32, TOPO_MIXED_RU
     p, mesh, rho = full
-    print("[fullsize] FP64, mixed and mixed-BF16 solves 192x96x96 x4, rtol 1e-10", flush=True)
+    print("[fullsize] FP64, mixed, mixed-BF16 and reliable-update solves 192x96x96 x4, rtol 1e-10",
+          flush=True)
     N = mesh.n_nodes
     f = p.loads.reshape(p.nrhs, 3 * N)
     res = {}
-    for name, prec in (("fp64", TOPO_FP64), ("mixed", TOPO_MIXED_FP32), ("bf16", TOPO_MIXED_BF16)):
+    for name, prec in (("fp64", TOPO_FP64), ("mixed", TOPO_MIXED_FP32), ("bf16", TOPO_MIXED_BF16),
+                       ("ru", TOPO_MIXED_RU)):
         t = _ctx(p, prec, rtol=1e-10)
         u = torch.zeros(p.nrhs * 3 * N, dtype=torch.float64, device=DEV)
         info = torch.zeros(6, dtype=torch.float64, device=DEV)
@@ -173,7 +175,7 @@ def test_fullsize_solves_sensitivity_filter_oc(full):
         assert info[1] == 1.0 and rel.max() <= 1.05e-10
         res[name] = (t, u)
     c64 = [float(f[r] @ res["fp64"][1].cpu().numpy().reshape(p.nrhs, -1)[r]) for r in range(p.nrhs)]
-    for name in ("mixed", "bf16"):
+    for name in ("mixed", "bf16", "ru"):
         cmx = [float(f[r] @ res[name][1].cpu().numpy().reshape(p.nrhs, -1)[r]) for r in range(p.nrhs)]
         for a, b in zip(cmx, c64):
             assert abs(a - b) <= 1e-7 * abs(b), name
