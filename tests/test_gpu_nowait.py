@@ -7,7 +7,8 @@ replayed several times, with eager work and synchronisations between the
 replays; every replay must equal, bit for bit, the same iteration run
 eagerly.  The no-wait context must also give the same bits as the polling
 context (the skipped iterations and restarts do nothing), in FP64 and in the
-mixed-precision solve, with the distance and the Helmholtz filter.
+mixed-precision solves (FP64 flexible CG, reliable-update FP32 CG), with the
+distance and the Helmholtz filter.
 """
 
 import numpy as np
@@ -22,9 +23,10 @@ DEV = "cuda:0"
 
 
 def _ctx(p, prec, sync, stream, filt):
-    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_FP32, TOPO_PC_GMG, Topo
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_FP32, TOPO_MIXED_RU, TOPO_PC_GMG, Topo
+    code = {"fp64": TOPO_FP64, "mixed": TOPO_MIXED_FP32, "mixed-ru": TOPO_MIXED_RU}[prec]
     with torch.cuda.stream(stream):
-        return Topo.from_problem(p, precision=TOPO_FP64 if prec == "fp64" else TOPO_MIXED_FP32,
+        return Topo.from_problem(p, precision=code,
                                  precond=TOPO_PC_GMG, rtol=1e-10, maxit=160, warm_start=True,
                                  device=DEV, sync_mode=sync, filter=filt)
 
@@ -38,7 +40,7 @@ def _state(p, stream):
     return rho, u, log
 
 
-@pytest.mark.parametrize("prec,filt", [("fp64", 0), ("mixed", 0), ("mixed", 1)])
+@pytest.mark.parametrize("prec,filt", [("fp64", 0), ("mixed", 0), ("mixed", 1), ("mixed-ru", 0)])
 def test_iteration_captured_in_a_graph_replays_bit_equal(prec, filt):
     from paper_2012_08208_amd import TOPO_SYNC_NONE, TOPO_SYNC_POLL
     p = synth.cantilever3d(20, 10, 9, nrhs=2, volfrac=0.3, rmin=1.5)
