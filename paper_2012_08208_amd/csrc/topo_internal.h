@@ -262,7 +262,7 @@ void launch_apply(Ctx* c, const double* x, double* y, int nrhs, bool fuse_dot);
 void launch_apply_f32(Ctx* c, const float* x, float* y, int nrhs, bool fuse_dot);
 OpDesc fine_op(const Ctx* c);
 long apply_grid_blocks(const OpDesc& d, int nrhs, int elem_bytes);
-int apply_rhs_per_block(const OpDesc& d, int nrhs, int elem_bytes);
+int apply_rhs_per_block(const OpDesc& d, int nrhs, int elem_bytes, int epi);
 void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, double* y,
                      int nrhs, bool fuse_dot, bool timed, const int* stop);
 void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,
