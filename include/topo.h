@@ -190,7 +190,15 @@ typedef struct topo_problem {
   int32_t paper_mode; /* 0: E = Emin + rho^p (E0-Emin), exact dc/drho;
                          1: the listing's law, see above */
   int32_t warm_start; /* 1: topo_solve starts from the u it is given */
-  int32_t gmg_levels; /* 0 = automatic; otherwise the number of levels */
+  int32_t gmg_dense;  /* multigrid: the largest coarsest level, in DOFs, that
+                         is solved directly (its dense inverse is built per
+                         solve, by Gauss-Jordan elimination: in one
+                         work-group up to 128 DOFs, else block by block);
+                         the hierarchy stops at the first level at or
+                         below it.  0 = automatic: 2048 in 3D (the
+                         environment variable TOPO_GMG_DENSE, read at
+                         creation, overrides it), 128 in 2D; otherwise
+                         128..2048 (else TOPO_E_INVALID) */
   int32_t filter;     /* TOPO_FILTER_DISTANCE (0) | TOPO_FILTER_HELMHOLTZ | TOPO_FILTER_DENSITY */
   int32_t sync_mode;  /* TOPO_SYNC_POLL (0) | TOPO_SYNC_NONE, see below */
 } topo_problem;
@@ -582,7 +590,7 @@ int topo_edm_filter(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t
  *
  * prob: the topo_problem fields of the material (E0, Emin, nu), SIMP (penal,
  *   volfrac, move, eta, rho_min), solver (rtol, maxit, warm_start,
- *   sync_mode) and nrhs; dim is 2 or 3; nel, split2d, rmin, gmg_levels and
+ *   sync_mode) and nrhs; dim is 2 or 3; nel, split2d, rmin, gmg_dense and
  *   filter are ignored.  precision must be TOPO_FP64, precond
  *   TOPO_PC_JACOBI, paper_mode 0 (else TOPO_E_INVALID).
  * coords: host, FP64 SoA [dim][n_nodes]; cells: host, int32 [n_cells][dim+1]

@@ -74,7 +74,7 @@ class CProblem(ctypes.Structure):
         ("rmin", ctypes.c_double), ("move", ctypes.c_double), ("eta", ctypes.c_double),
         ("rho_min", ctypes.c_double), ("precision", ctypes.c_int32), ("precond", ctypes.c_int32),
         ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("paper_mode", ctypes.c_int32),
-        ("warm_start", ctypes.c_int32), ("gmg_levels", ctypes.c_int32), ("filter", ctypes.c_int32),
+        ("warm_start", ctypes.c_int32), ("gmg_dense", ctypes.c_int32), ("filter", ctypes.c_int32),
         ("sync_mode", ctypes.c_int32),
     ]
 
@@ -170,7 +170,7 @@ def make_problem(dim: int, nel: Sequence[int], nrhs: int = 1, split: int = TOPO_
                  volfrac: float = 0.5, rmin: float = 1.5, move: float = 0.2, eta: float = 0.5,
                  rho_min: float = 1e-3, precision: int = TOPO_FP64, precond: int = TOPO_PC_JACOBI,
                  rtol: float = 1e-10, maxit: int = 20000, paper_mode: bool = False,
-                 warm_start: bool = False, gmg_levels: int = 0,
+                 warm_start: bool = False, gmg_dense: int = 0,
                  filter: int = 0, sync_mode: int = TOPO_SYNC_POLL) -> CProblem:
     p = CProblem()
     p.dim = int(dim)
@@ -184,7 +184,7 @@ def make_problem(dim: int, nel: Sequence[int], nrhs: int = 1, split: int = TOPO_
                                                    float(eta), float(rho_min))
     p.precision, p.precond = int(precision), int(precond)
     p.rtol, p.maxit = float(rtol), int(maxit)
-    p.paper_mode, p.warm_start, p.gmg_levels = int(bool(paper_mode)), int(bool(warm_start)), int(gmg_levels)
+    p.paper_mode, p.warm_start, p.gmg_dense = int(bool(paper_mode)), int(bool(warm_start)), int(gmg_dense)
     p.filter = int(filter)
     p.sync_mode = int(sync_mode)
     return p
@@ -226,13 +226,15 @@ class Topo:
 
     @classmethod
     def from_problem(cls, p, precision=TOPO_FP64, precond=TOPO_PC_JACOBI, rtol=None, maxit=20000,
-                     warm_start=False, device="cuda", filter=None, sync_mode=TOPO_SYNC_POLL):
+                     warm_start=False, device="cuda", filter=None, sync_mode=TOPO_SYNC_POLL,
+                     gmg_dense=0):
         """Builds a context from any object with the problem attributes
         (dim, nel, split, loads, fixed, E0, Emin, nu, penal, volfrac, rmin,
         move, eta, rho_min, paper_mode, rtol)."""
         cp = make_problem(p.dim, p.nel, p.loads.shape[0], p.split, p.E0, p.Emin, p.nu, p.penal,
                           p.volfrac, p.rmin, p.move, p.eta, p.rho_min, precision, precond,
                           p.rtol if rtol is None else rtol, maxit, p.paper_mode, warm_start,
+                          gmg_dense=gmg_dense,
                           filter=getattr(p, "filter", 0) if filter is None else filter,
                           sync_mode=sync_mode)
         t = cls(cp, p.fixed, device)

@@ -43,6 +43,7 @@ static bool valid_problem(const topo_problem* p) {
       p->filter != TOPO_FILTER_DENSITY)
     return false;
   if (p->sync_mode != TOPO_SYNC_POLL && p->sync_mode != TOPO_SYNC_NONE) return false;
+  if (p->gmg_dense != 0 && (p->gmg_dense < 128 || p->gmg_dense > kDense3)) return false;
   // the no-wait mode has no host-driven refinement loop and no learned cycle
   if (p->sync_mode == TOPO_SYNC_NONE &&
       (p->precision == TOPO_MIXED_IR || p->precond == TOPO_PC_LEARNED))
@@ -96,13 +97,21 @@ static int pick_kz_coarse(int dim, int nx, int ny, int nz) {
 
 // Multigrid levels: halve (rounding up) every axis until the level has at
 // most 128 DOFs, the size the dense coarsest solve handles.
-std::vector<LevelDims> gmg_plan_dims(int dim, int nx, int ny, int nz) {
+int gmg_dense_max(const topo_problem* p) {
+  if (p->gmg_dense > 0) return p->gmg_dense;
+  if (p->dim != 3) return 128;
+  int v = kDense3;
+  if (const char* e = getenv("TOPO_GMG_DENSE")) v = atoi(e);
+  return v < 128 ? 128 : (v > kDense3 ? kDense3 : v);
+}
+
+std::vector<LevelDims> gmg_plan_dims(int dim, int nx, int ny, int nz, int dense_max) {
   std::vector<LevelDims> out;
   LevelDims d{nx, ny, dim == 3 ? nz : 1};
   out.push_back(d);
   for (int l = 0; l < 24; ++l) {
     const long nn = (long)(d.nx + 1) * (d.ny + 1) * (dim == 3 ? (d.nz + 1) : 1);
-    if (nn * dim <= 128) break;
+    if (nn * dim <= dense_max) break;
     LevelDims e{(d.nx + 1) / 2, (d.ny + 1) / 2, dim == 3 ? (d.nz + 1) / 2 : 1};
     if (e.nx == d.nx && e.ny == d.ny && e.nz == d.nz) break;
     d = e;
@@ -111,7 +120,9 @@ std::vector<LevelDims> gmg_plan_dims(int dim, int nx, int ny, int nz) {
   return out;
 }
 
-static std::vector<LevelDims> gmg_plan(const Grid& g) { return gmg_plan_dims(g.dim, g.nx, g.ny, g.nz); }
+static std::vector<LevelDims> gmg_plan(const topo_problem* p, const Grid& g) {
+  return gmg_plan_dims(g.dim, g.nx, g.ny, g.nz, gmg_dense_max(p));
+}
 
 // Coarse node mask: a component is fixed when any fine node of the support
 // of the coarse basis function has it fixed.
@@ -206,7 +217,7 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
     L.z = take(nr * g.nd * 8);
     const bool flex = flex_mixed(*p) || p->precond == TOPO_PC_LEARNED;
     L.wv = flex ? take(nr * g.nd * 8) : 0;
-    const std::vector<LevelDims> plan = gmg_plan(g);
+    const std::vector<LevelDims> plan = gmg_plan(p, g);
     L.gmg_scal = take(8 * 2 * (plan.size() + 1));
     for (size_t l = 0; l < plan.size(); ++l) {
       GmgLevel lv;
@@ -233,8 +244,16 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
         lv.off_q = take(nr * nd * 8);
         lv.off_pv = take((size_t)nd * 8);
         lv.off_pw = take((size_t)nd * 8);
-      } else {
+      } else if (nd <= 128) {
         lv.off_A = take((size_t)nd * nd * 8);
+      } else {
+        // blocked elimination: the matrix padded to whole blocks (identity
+        // rows and columns), its FP32 copy, the pivot block and column panel
+        const size_t np = (size_t)((nd + kGjBlock - 1) / kGjBlock * kGjBlock);
+        lv.np = (int)np;
+        lv.off_A = take(np * np * 8);
+        lv.off_A32 = mixed ? take(np * np * 4) : 0;
+        lv.off_gj = take(((size_t)kGjBlock * kGjBlock + np * kGjBlock) * 8);
       }
       L.levels.push_back(lv);
     }
@@ -331,6 +350,11 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   c->prob = *prob;
   c->g = make_grid(prob);
   c->apply_kz = pick_kz(c->g);
+  c->gp = gmg_params_env();
+  c->env_nrb = 0;
+  c->env_g = 1;
+  if (const char* e = getenv("TOPO_APPLY_NRB")) c->env_nrb = atoi(e);
+  if (const char* e = getenv("TOPO_APPLY_G")) c->env_g = atoi(e);
   c->L = make_layout(prob, c->g, c->apply_kz);
   if (ws_bytes < c->L.total) {
     delete c;
@@ -410,7 +434,7 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
   bool mask_ok = true;
   std::vector<std::vector<uint8_t>> lmasks;
   if (prob->precond != TOPO_PC_JACOBI) {
-    const std::vector<LevelDims> plan = gmg_plan(c->g);
+    const std::vector<LevelDims> plan = gmg_plan(&c->prob, c->g);
     lmasks.push_back(bits);
     for (size_t l = 0; l < plan.size(); ++l) {
       GmgLevel lv = L.levels[l];
@@ -455,6 +479,8 @@ int topo_create(const topo_problem* prob, const uint8_t* fixed_mask, void* works
       lv.pv = lv.off_pv ? (double*)(w + lv.off_pv) : nullptr;
       lv.pw = lv.off_pw ? (double*)(w + lv.off_pw) : nullptr;
       lv.Ainv = lv.off_A ? (double*)(w + lv.off_A) : nullptr;
+      lv.Ainv32 = lv.off_A32 ? (float*)(w + lv.off_A32) : nullptr;
+      lv.gj = lv.off_gj ? (double*)(w + lv.off_gj) : nullptr;
       c->lv.push_back(lv);
     }
   }

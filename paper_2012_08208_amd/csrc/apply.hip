@@ -468,14 +468,11 @@ static TileMap make_tilemap(const OpDesc& d, int nrhs) {
 // FP32, all cases per block 128 us against 125 us for one case per block;
 // FP64, 280 us against 216 us (256 VGPRs, one wave per SIMD).  So FP32 grids
 // with 1024 or more tiles take all load cases per block; FP64 applies and
-// smaller grids take one.  TOPO_APPLY_NRB overrides the choice (it must
-// divide nrhs).
-int apply_rhs_per_block(const OpDesc& d, int nrhs, int elem_bytes, int epi) {
+// smaller grids take one.  env_nrb (TOPO_APPLY_NRB at context creation)
+// overrides the choice when it divides nrhs.
+int apply_rhs_per_block(const OpDesc& d, int nrhs, int elem_bytes, int epi, int env_nrb) {
   if (d.dim != 3 || nrhs <= 1) return 1;
-  if (const char* e = getenv("TOPO_APPLY_NRB")) {
-    const int v = atoi(e);
-    if (v >= 1 && v <= nrhs && nrhs % v == 0) return v;
-  }
+  if (env_nrb >= 1 && env_nrb <= nrhs && nrhs % env_nrb == 0) return env_nrb;
   if (elem_bytes != 4) return 1;
   const TileMap tm = make_tilemap(d, 1);
   if (8L * tm.per_xcd < 1024) return 1;
@@ -485,8 +482,8 @@ int apply_rhs_per_block(const OpDesc& d, int nrhs, int elem_bytes, int epi) {
   return (epi == 0 && nrhs == 4) ? 2 : nrhs;
 }
 
-long apply_grid_blocks(const OpDesc& d, int nrhs, int elem_bytes) {
-  const int nrb = apply_rhs_per_block(d, nrhs, elem_bytes, 0);
+long apply_grid_blocks(const OpDesc& d, int nrhs, int elem_bytes, int env_nrb) {
+  const int nrb = apply_rhs_per_block(d, nrhs, elem_bytes, 0, env_nrb);
   TileMap tm = make_tilemap(d, nrhs / nrb);
   return 8L * tm.per_xcd * (nrhs / nrb);
 }
@@ -496,12 +493,11 @@ template <typename T, typename TE, int EPI>
 static void launch_apply3d(Ctx* c, const OpDesc& d, const TE* E, const T* x, T* y, int nrhs,
                            double* part, const int* stop, const ChebEpi<T>& ce) {
   const T lam = T(c->m.lam0 * c->m.vol), mu = T(c->m.mu0 * c->m.vol);
-  const int nrb = apply_rhs_per_block(d, nrhs, (int)sizeof(T), EPI);
+  const int nrb = apply_rhs_per_block(d, nrhs, (int)sizeof(T), EPI, c->env_nrb);
   const TileMap tm = make_tilemap(d, nrhs / nrb);
   const unsigned blocks = (unsigned)(8L * tm.per_xcd * (nrhs / nrb));
   hipStream_t s = c->stream;
-  int g = 1;
-  if (const char* e = getenv("TOPO_APPLY_G")) g = atoi(e);
+  const int g = c->env_g;
 #define TOPO_APPLY3D(NRB_, G_) \
   apply3d_kernel<T, TE, EPI, NRB_, G_><<<blocks, 256, 0, s>>>(x, y, E, d, tm, lam, mu, part, stop, ce)
   if (nrb == 4 && g == 4) TOPO_APPLY3D(4, 4);

@@ -23,8 +23,9 @@
 // [0.09 lmax, lmax], lmax from a Rayleigh-quotient power iteration with a
 // safety factor; the same polynomial is used before and after the coarse
 // correction, so the V-cycle is a symmetric positive definite operator.
-// Coarsest level (<= 128 DOFs): dense matrix assembled per solve and
-// inverted by Gauss-Jordan elimination in one work-group.
+// Coarsest level (<= 128 DOFs, 3D: <= 2048): dense matrix assembled per
+// solve and inverted by Gauss-Jordan elimination, in one work-group up to
+// 128 DOFs, else block by block over the whole GPU.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -39,26 +40,6 @@
 
 namespace topo {
 
-// Smoother parameters (defaults; TOPO_CHEB_DEGREE, TOPO_CHEB_POST, TOPO_CHEB_LOW,
-// TOPO_POWER_ITERS and TOPO_POWER_SAFETY override them at context creation)
-struct GmgParams {
-  int cheb_kind = 1;      // 1: first-kind Chebyshev on [low lmax, lmax]; 4: fourth kind
-  bool fused_post = true; // 3D degree-2 post-smoothing in two fused apply kernels
-  int cheb_degree = 2;
-  int post_degree = -1;   // post-smoothing degree (-1: cheb_degree)
-  double cheb_low = 0.09;
-  // 6 Rayleigh-quotient steps: on 192x96x96 x 4 load cases 12 / 8 / 6 / 4
-  // steps gave 569 / 568 / 567 / 564 CG iterations over 24 SIMP steps and
-  // 14.63 / 14.79 / 14.87 / 15.03 SIMP it/s; 6 keeps a margin on the
-  // estimate for other problems
-  int power_iters = 6;
-  double power_safety = 1.2;
-  // W-cycle: levels below wlevels visit their coarse level twice; -1 picks
-  // them by size (3D levels whose coarse level has >= kWCoarseNodes nodes)
-  int wlevels = -1;
-  bool tail = true;       // FP32 3D cycles: the small coarse levels in one work-group
-};
-
 // A revisit of a smaller coarse level costs more in launches than it saves
 // in iterations: on 192x96x96 x 4 load cases (7 levels, the last three in
 // the one-block tail) W on the top 2 levels gave 12.8 SIMP it/s (38 CG
@@ -67,7 +48,7 @@ struct GmgParams {
 // of 230k, 31k, 4.2k and 637 nodes).
 constexpr long kWCoarseNodes = 512;
 
-static GmgParams gmg_params() {
+GmgParams gmg_params_env() {
   GmgParams p;
   if (const char* e = getenv("TOPO_CHEB_DEGREE")) p.cheb_degree = atoi(e) > 0 ? atoi(e) : p.cheb_degree;
   if (const char* e = getenv("TOPO_CHEB_LOW")) p.cheb_low = atof(e) > 0 ? atof(e) : p.cheb_low;
@@ -466,6 +447,234 @@ __global__ __launch_bounds__(512) void coarse_solve_kernel(T* x, const T* __rest
   coarse_solve_block<T>(x, b, Ainv, n, nrhs);
 }
 
+// ------------------------------------- larger coarsest level (3D, > 128 DOFs)
+// The coarsest 3D level of a deep hierarchy (12 x 6 x 6 cells, 1911 DOFs, on
+// 192 x 96 x 96) is solved directly too: its matrix, padded to np = a whole
+// number of 64-blocks with identity rows and columns, is assembled and
+// inverted in FP64 by block Gauss-Jordan elimination without pivoting (the
+// matrix is SPD, so every pivot block is SPD), and each visit is one dense
+// matrix-vector product over the whole GPU.  Per block step k, with
+// P = A_kk^-1 and C the column panel A_ik saved before the step:
+//   A_kj <- P A_kj (j != k),  A_ij <- A_ij - C_i A_kj (i, j != k),
+//   A_ik <- -C_i P (i != k),  A_kk <- P.
+// A revisit of a level solved exactly would change nothing, so the level
+// above it never revisits (W) and the tail kernel is not used with it.
+__global__ void dense_fill_kernel(double* A, int n, int np) {
+  const long tot = (long)np * np;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(t / np), j = (int)(t - (long)i * np);
+    A[t] = (i == j && i >= n) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void coarse_assemble_ld_kernel(double* A, const double* __restrict__ E, OpDesc o,
+                                          double lam0, double mu0, double vol, int np) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= (int)(o.nn * o.dim)) return;
+  coarse_assemble_row(row, A, E, o, lam0, mu0, vol, np, false);
+}
+
+constexpr int kGjB = kGjBlock;
+constexpr int kGjPad = kGjB + 1;   // LDS row pitch (doubles)
+
+// P = inverse of the diagonal block k by in-place Gauss-Jordan elimination.
+// The block stays in registers: thread (j, i0) of 1024 holds column j, rows
+// i0 + 16m (m < 4).  Per pivot p the owners publish row p and column p to
+// LDS (double-buffered by the parity of p, so one barrier per step) and
+// every thread updates its 4 entries.
+constexpr int kGjPivThreads = 1024;
+__global__ __launch_bounds__(kGjPivThreads) void gj_pivot_kernel(const double* __restrict__ A,
+                                                                  int np, int k, double* P) {
+  __shared__ double rowb[2][kGjB], colb[2][kGjB];
+  const int j = threadIdx.x & 63, i0 = threadIdx.x >> 6;
+  const long base = ((long)k * np + k) * kGjB;
+  double v[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) v[m] = A[base + (long)(i0 + 16 * m) * np + j];
+  for (int p = 0; p < kGjB; ++p) {
+    const int buf = p & 1;
+    if (i0 == (p & 15)) {
+      const int mp = p >> 4;
+      rowb[buf][j] = mp == 0 ? v[0] : mp == 1 ? v[1] : mp == 2 ? v[2] : v[3];
+    }
+    if (j == p) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) colb[buf][i0 + 16 * m] = v[m];
+    }
+    __syncthreads();
+    const double piv = rowb[buf][p];
+    const double rj = (j == p ? 1.0 : rowb[buf][j]) / piv;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = i0 + 16 * m;
+      v[m] = (i == p) ? rj : ((j == p) ? 0.0 : v[m]) - colb[buf][i] * rj;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) P[(i0 + 16 * m) * kGjB + j] = v[m];
+}
+
+// acc = X Y for 64 x 64 blocks staged in LDS; thread (tx, ty) owns rows
+// ty + 16a and columns tx + 16b (a, b < 4)
+__device__ inline void gj_block_product(const double* Xs, const double* Ys, double acc[4][4]) {
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int q = 0; q < kGjB; ++q) {
+    double xv[4], yv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) xv[a] = Xs[(ty + 16 * a) * kGjPad + q];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) yv[b] = Ys[q * kGjPad + tx + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], yv[b], acc[a][b]);
+  }
+}
+
+// stage the 64 x 64 block at src (leading dimension ld) into LDS
+__device__ inline void gj_stage(double* dst, const double* __restrict__ src, long ld) {
+  for (int t = threadIdx.x; t < kGjB * kGjB; t += blockDim.x) {
+    const int i = t / kGjB, j = t % kGjB;
+    dst[i * kGjPad + j] = src[(long)i * ld + j];
+  }
+}
+
+// blocks [0, nb): row panel A_kj <- P A_kj (j != k); blocks [nb, 2 nb): save
+// the column panel block C_i = A_ik
+__global__ __launch_bounds__(256) void gj_panel_kernel(double* A, int np, int k,
+                                                        const double* __restrict__ P, double* C) {
+  __shared__ double Xs[kGjB * kGjPad], Ys[kGjB * kGjPad];
+  const int nb = np / kGjB;
+  const int blk = blockIdx.x;
+  if (blk >= nb) {
+    const int i = blk - nb;
+    const double* src = A + ((long)i * np + k) * kGjB;
+    double* dst = C + (long)i * kGjB * kGjB;
+    for (int t = threadIdx.x; t < kGjB * kGjB; t += blockDim.x)
+      dst[t] = src[(long)(t / kGjB) * np + t % kGjB];
+    return;
+  }
+  const int j = blk;
+  if (j == k) return;
+  double* Akj = A + ((long)k * np + j) * kGjB;
+  gj_stage(Xs, P, kGjB);
+  gj_stage(Ys, Akj, np);
+  __syncthreads();
+  double acc[4][4];
+  gj_block_product(Xs, Ys, acc);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Akj[(long)(ty + 16 * a) * np + tx + 16 * b] = acc[a][b];
+}
+
+// every block (i, j) outside row block k: A_ij -= C_i A_kj (j != k) or
+// A_ik = -C_i P; block (k, k) takes P
+__global__ __launch_bounds__(256) void gj_update_kernel(double* A, int np, int k,
+                                                         const double* __restrict__ P,
+                                                         const double* __restrict__ C) {
+  __shared__ double Xs[kGjB * kGjPad], Ys[kGjB * kGjPad];
+  const int i = blockIdx.y, j = blockIdx.x;
+  double* Aij = A + ((long)i * np + j) * kGjB;
+  if (i == k) {
+    if (j == k)
+      for (int t = threadIdx.x; t < kGjB * kGjB; t += blockDim.x)
+        Aij[(long)(t / kGjB) * np + t % kGjB] = P[t];
+    return;
+  }
+  gj_stage(Xs, C + (long)i * kGjB * kGjB, kGjB);
+  if (j == k) gj_stage(Ys, P, kGjB);
+  else gj_stage(Ys, A + ((long)k * np + j) * kGjB, np);
+  __syncthreads();
+  double acc[4][4];
+  gj_block_product(Xs, Ys, acc);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double& y = Aij[(long)(ty + 16 * a) * np + tx + 16 * b];
+      y = (j == k) ? -acc[a][b] : y - acc[a][b];
+    }
+}
+
+// x = Ainv b for every load case: one wave per row, 8 waves per work-group
+// with b staged in LDS (zero-padded to np), each lane streaming 16-byte
+// pieces of its row, 8 loads in flight; FP64 sums reduced in a fixed order.
+// Rows are np entries long and np is a multiple of 64, so every piece is
+// aligned and the padded columns (zero) need no bounds test.
+constexpr int kDenseWaves = 8;
+template <typename T, typename TA>
+__global__ __launch_bounds__(64 * kDenseWaves) void dense_solve_kernel(
+    T* x, const T* __restrict__ b, const TA* __restrict__ Ainv, int n, int np, int nrhs,
+    const int* stop) {
+  if (stop && *stop) return;
+  extern __shared__ double dsm[];
+  T* bs = reinterpret_cast<T*>(dsm);   // [nrhs][np]
+  constexpr int V = 16 / (int)sizeof(TA);
+  using VA = typename std::conditional<sizeof(TA) == 4, float4, double2>::type;
+  using VB = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * kDenseWaves + (threadIdx.x >> 6);
+  const int nv = np / V;
+  // the row's first pieces are requested before b is staged (rows past n
+  // read row 0, in bounds, and are not used)
+  const VA* Ar = reinterpret_cast<const VA*>(Ainv + (long)(row < n ? row : 0) * np);
+  VA a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = lane + 64 * u;
+    if (q < nv) a[u] = Ar[q];
+  }
+  for (int t = threadIdx.x; t < nrhs * np; t += blockDim.x) {
+    const int r = t / np, j = t - r * np;
+    bs[t] = j < n ? b[(long)r * n + j] : T(0);
+  }
+  __syncthreads();
+  if (row >= n) return;
+  double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+  for (int q0 = lane; q0 < nv; q0 += 64 * 8) {
+    if (q0 != lane) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + 64 * u;
+        if (q < nv) a[u] = Ar[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + 64 * u;
+      if (q >= nv) break;
+      const TA* av = reinterpret_cast<const TA*>(&a[u]);
+#pragma unroll
+      for (int r = 0; r < kMaxRhs; ++r) {
+        if (r >= nrhs) break;
+        const T* br = bs + (long)r * np + q * V;
+        T bv[V];
+#pragma unroll
+        for (int e = 0; e < V; e += 16 / (int)sizeof(T)) {
+          const VB w = *reinterpret_cast<const VB*>(br + e);
+          const T* wv = reinterpret_cast<const T*>(&w);
+#pragma unroll
+          for (int f = 0; f < 16 / (int)sizeof(T); ++f) bv[e + f] = wv[f];
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[r] = fma((double)av[e], (double)bv[e], acc[r]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kMaxRhs; ++r) {
+    const double v = wave_sum(acc[r]);
+    if (lane == 0 && r < nrhs) x[(long)r * n + row] = T(v);
+  }
+}
+
 __global__ void to_f32_kernel(float* dst, const double* __restrict__ src, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     dst[i] = (float)src[i];
@@ -494,7 +703,7 @@ void gmg_setup(Ctx* c) {
     const unsigned nb = red_grid(nd);
     power_init_kernel<<<cdivu(nd, 256), 256, 0, s>>>(g.pv, g.op.mask, g.op.nn, g.op.dim);
     set_scalar_kernel<<<1, 1, 0, s>>>(g.pscale, 1.0);
-    const GmgParams gp = gmg_params();
+    const GmgParams& gp = c->gp;
     for (int it = 0; it < gp.power_iters; ++it) {
       launch_apply_op(c, g.op, g.E, g.pv, g.pw, 1, false, false, nullptr);
       power_step_kernel<<<nb, 256, 0, s>>>(g.pv, g.pw, g.invd, nd, g.pscale, c->partials);
@@ -512,9 +721,24 @@ void gmg_setup(Ctx* c) {
   }
   GmgLevel& cl = c->lv[L - 1];
   const int n = (int)(cl.op.nn * cl.op.dim);
-  coarse_assemble_kernel<<<cdivu(n, 128), 128, 0, s>>>(cl.Ainv, cl.E, cl.op, c->m.lam0, c->m.mu0,
-                                                      c->m.vol);
-  gauss_jordan_kernel<<<1, 1024, 0, s>>>(cl.Ainv, n);
+  if (cl.np == 0) {
+    coarse_assemble_kernel<<<cdivu(n, 128), 128, 0, s>>>(cl.Ainv, cl.E, cl.op, c->m.lam0, c->m.mu0,
+                                                        c->m.vol);
+    gauss_jordan_kernel<<<1, 1024, 0, s>>>(cl.Ainv, n);
+    return;
+  }
+  const int np = cl.np, nb = np / kGjB;
+  double* P = cl.gj;
+  double* C = cl.gj + kGjB * kGjB;
+  dense_fill_kernel<<<red_grid((long)np * np), 256, 0, s>>>(cl.Ainv, n, np);
+  coarse_assemble_ld_kernel<<<cdivu(n, 64), 64, 0, s>>>(cl.Ainv, cl.E, cl.op, c->m.lam0, c->m.mu0,
+                                                       c->m.vol, np);
+  for (int k = 0; k < nb; ++k) {
+    gj_pivot_kernel<<<1, kGjPivThreads, 0, s>>>(cl.Ainv, np, k, P);
+    gj_panel_kernel<<<2 * nb, 256, 0, s>>>(cl.Ainv, np, k, P, C);
+    gj_update_kernel<<<dim3(nb, nb), 256, 0, s>>>(cl.Ainv, np, k, P, C);
+  }
+  if (cl.Ainv32) to_f32_kernel<<<red_grid((long)np * np), 256, 0, s>>>(cl.Ainv32, cl.Ainv, (long)np * np);
 }
 
 // per-precision views of a level's operator data
@@ -553,7 +777,7 @@ static void cheb_smooth(Ctx* c, GmgLevel& g, const T* b, T* x, int nrhs, bool fr
   T* gd = reinterpret_cast<T*>(g.d);
   T* gq = reinterpret_cast<T*>(g.q);
   const T* invd = LevelOps<T>::invd(g);
-  const GmgParams gp = gmg_params();
+  const GmgParams& gp = c->gp;
   if (from_zero && g.op.dim == 3 && gp.cheb_degree == 2) {
     // the whole degree-2 smoothing from zero in one kernel
     const double sigma = (1.0 + gp.cheb_low) / (1.0 - gp.cheb_low);
@@ -988,7 +1212,7 @@ static bool tail_layout(const Ctx* c, int l0, TailArgs& A) {
 // first level of the one-block tail (FP32 cycles), or -1
 static int tail_level(const Ctx* c) {
   const int L = (int)c->lv.size();
-  if (L < 2 || !gmg_params().tail) return -1;
+  if (L < 2 || !c->gp.tail || c->lv[L - 1].np > 0) return -1;
   static thread_local TailArgs probe;
   for (int l = 1; l + 1 < L; ++l)
     if (tail_layout(c, l, probe)) return l;
@@ -1021,7 +1245,7 @@ static bool launch_tail(Ctx* c, int l0, const float* b, float* x, int nrhs, bool
   if (!tail_program(c, l0, l0, x_zero, wlevels, ops)) return false;
   if (visits == 2 && !tail_program(c, l0, l0, false, wlevels, ops)) return false;
   const int L = (int)c->lv.size();
-  const GmgParams gp = gmg_params();
+  const GmgParams& gp = c->gp;
   if (gp.cheb_degree > 8 || gp.post_degree > 8) return false;
   TailArgs A;
   memset(&A, 0, sizeof(A));
@@ -1089,7 +1313,17 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs, bool x_zero,
   if (l == L - 1) {
     // the direct coarsest solve does not depend on the start
     const int n = (int)(g.op.nn * g.op.dim);
-    coarse_solve_kernel<T><<<1, 512, 0, s>>>(x, b, g.Ainv, n, nrhs, stop);
+    if (g.np == 0) {
+      coarse_solve_kernel<T><<<1, 512, 0, s>>>(x, b, g.Ainv, n, nrhs, stop);
+    } else if constexpr (std::is_same<T, float>::value) {
+      dense_solve_kernel<float, float><<<cdivu(n, kDenseWaves), 64 * kDenseWaves,
+                                         (size_t)nrhs * g.np * sizeof(float), s>>>(
+          x, b, g.Ainv32, n, g.np, nrhs, stop);
+    } else {
+      dense_solve_kernel<double, double><<<cdivu(n, kDenseWaves), 64 * kDenseWaves,
+                                           (size_t)nrhs * g.np * sizeof(double), s>>>(
+          x, b, g.Ainv, n, g.np, nrhs, stop);
+    }
     return;
   }
   if constexpr (std::is_same<T, float>::value) {
@@ -1134,11 +1368,11 @@ static void vcycle_level(Ctx* c, int l, const T* b, T* x, int nrhs, bool x_zero,
 }
 
 void gmg_vcycle(Ctx* c, const double* b, double* x, int nrhs) {
-  vcycle_level<double>(c, 0, b, x, nrhs, true, gmg_params().wlevels);
+  vcycle_level<double>(c, 0, b, x, nrhs, true, c->gp.wlevels);
 }
 
 void gmg_vcycle_f32(Ctx* c, const float* b, float* x, int nrhs) {
-  vcycle_level<float>(c, 0, b, x, nrhs, true, gmg_params().wlevels);
+  vcycle_level<float>(c, 0, b, x, nrhs, true, c->gp.wlevels);
 }
 
 // the fine-level Chebyshev-Jacobi smoother on its own (FP64)

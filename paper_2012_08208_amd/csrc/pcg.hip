@@ -389,7 +389,7 @@ static void mixed_flex_iterate(Ctx* c, double* x, double* r, double* p, double* 
   hipStream_t s = c->stream;
   const unsigned gb = red_grid(nd);
   const unsigned gd = dir_grid(nd);
-  const long nb_apply = apply_grid_blocks(fine_op(c), NR, 8);
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR, 8, c->env_nrb);
   float* zb[2] = {c->z32, c->z32b};
   launch_to_f32(c, c->r32, r, (int64_t)NR * nd);
   gmg_vcycle_f32(c, c->r32, zb[0], NR);
@@ -538,7 +538,7 @@ static void mixed_ru_iterate(Ctx* c, double* u, const double* r, int maxit) {
   hipStream_t s = c->stream;
   const unsigned gb = red_grid(nd);
   const unsigned gd = dir_grid(nd);
-  const long nb_apply = apply_grid_blocks(fine_op(c), NR, 4);
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR, 4, c->env_nrb);
   float* zb[2] = {c->z32, c->z32b};
   const float* invd = c->invd32;
   double delta2 = kRuDelta2;
@@ -605,7 +605,7 @@ static void pcg_iterate(Ctx* c, TV* x, TV* r, TV* p, TV* q, TV* z, int maxit) {
   };
   capture(0);
   const unsigned gb = red_grid(nd);
-  const long nb_apply = apply_grid_blocks(fine_op(c), NR, (int)sizeof(TV));
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR, (int)sizeof(TV), c->env_nrb);
   if (gmg) {
     Prec<TV>::vcycle(c, r, z, NR);
     pcg_rz_kernel<NR, TV><<<gb, 256, 0, s>>>(r, z, nd, c->partials, st);
@@ -787,7 +787,7 @@ static void fcg_iterate(Ctx* c, double* x, double* r, double* z, int maxit) {
   int* status = &c->scal->status;
   hipStream_t s = c->stream;
   const unsigned gb = red_grid(nd);
-  const long nb_apply = apply_grid_blocks(fine_op(c), NR, 8);
+  const long nb_apply = apply_grid_blocks(fine_op(c), NR, 8, c->env_nrb);
   const int m = kFcgWindow;
   constexpr int per = 16 / NR;   // directions per dot-product launch
   int it = 0, b = 0, k = 0;

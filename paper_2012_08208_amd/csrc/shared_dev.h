@@ -283,16 +283,20 @@ __device__ inline void cheb_next_coef(double lmax, double low, const ChebCoef& c
 }
 
 // ---------------------------------------------------- coarsest level
-// Dense A (row-major, n = dim * nn): row i = c * nn + node, built by the
-// thread that owns the row from the element matrices
-// K_e[(a,i),(b,j)] = |T| E (lambda g_a,i g_b,j + mu (g_a,j g_b,i + delta_ij g_a.g_b)).
+// Dense A (row-major with leading dimension ld, n = dim * nn): row i =
+// c * nn + node, built by the thread that owns the row from the element
+// matrices K_e[(a,i),(b,j)] = |T| E (lambda g_a,i g_b,j + mu (g_a,j g_b,i +
+// delta_ij g_a.g_b)).  ld = 0 means ld = n; with zero = false the row must
+// already hold zeros.
 __device__ inline void coarse_assemble_row(int row, double* A, const double* __restrict__ E,
-                                    const OpDesc& o, double lam0, double mu0, double vol) {
+                                    const OpDesc& o, double lam0, double mu0, double vol,
+                                    long ld = 0, bool zero = true) {
   const int n = (int)(o.nn * o.dim);
   const int dim = o.dim;
   const int node = row % (int)o.nn, ci = row / (int)o.nn;
-  double* Ar = A + (long)row * n;
-  for (int j = 0; j < n; ++j) Ar[j] = 0.0;
+  double* Ar = A + (long)row * (ld > 0 ? ld : n);
+  if (zero)
+    for (int j = 0; j < n; ++j) Ar[j] = 0.0;
   const int nx1 = o.nx + 1, ny1 = o.ny + 1;
   const int i = node % nx1, jj = (node / nx1) % ny1, k = dim == 3 ? node / (nx1 * ny1) : 0;
   if ((o.mask[node] >> ci) & 1) {

@@ -169,10 +169,13 @@ struct GmgLevel {
   double *pv, *pw;             // [dim*nn] power-iteration vectors
   double* lmax;                // device scalar: lambda_max(D^-1 K) estimate
   double* pscale;              // device scalar: power-iteration scale
-  double* Ainv;                // coarsest level: dense inverse [n*n]
+  double* Ainv;                // coarsest level: dense inverse [n*n], or [np*np] when np > 0
+  float* Ainv32;               // coarsest level with np > 0, mixed precision: FP32 copy [np*np]
+  double* gj;                  // coarsest level with np > 0: elimination scratch [64*64 + np*64]
+  int np;                      // coarsest level above 128 DOFs: n rounded up to kGjBlock, else 0
   uint8_t* mask;               // [nn]
   size_t off_E, off_invd, off_b, off_x, off_r, off_d, off_q, off_pv, off_pw, off_mask, off_A,
-      off_E32, off_invd32;
+      off_E32, off_invd32, off_A32, off_gj;
 };
 
 struct WsLayout {
@@ -196,9 +199,39 @@ struct Capture {
 struct LevelDims {
   int nx, ny, nz;
 };
-std::vector<LevelDims> gmg_plan_dims(int dim, int nx, int ny, int nz);
+// Largest coarsest level (DOFs) that the multigrid hierarchy solves
+// directly: topo_problem.gmg_dense, else 128 (one work-group's
+// Gauss-Jordan) in 2D and kDense3 in 3D (blocked Gauss-Jordan over the
+// whole GPU; TOPO_GMG_DENSE overrides it).  At most kDense3: the dense solve
+// stages 4 FP64 right-hand sides of that length in 64 KiB of LDS.
+constexpr int kDense3 = 2048;
+constexpr int kGjBlock = 64;
+int gmg_dense_max(const topo_problem* p);
+std::vector<LevelDims> gmg_plan_dims(int dim, int nx, int ny, int nz, int dense_max = 128);
 std::vector<uint8_t> coarse_mask_host(const std::vector<uint8_t>& fm, const LevelDims& f,
                                       const LevelDims& d, int dim);
+
+// Smoother parameters (defaults; TOPO_CHEB_DEGREE, TOPO_CHEB_POST, TOPO_CHEB_LOW,
+// TOPO_POWER_ITERS and TOPO_POWER_SAFETY override them; read once at context creation)
+struct GmgParams {
+  int cheb_kind = 1;      // 1: first-kind Chebyshev on [low lmax, lmax]; 4: fourth kind
+  bool fused_post = true; // 3D degree-2 post-smoothing in two fused apply kernels
+  int cheb_degree = 2;
+  int post_degree = -1;   // post-smoothing degree (-1: cheb_degree)
+  double cheb_low = 0.09;
+  // 6 Rayleigh-quotient steps: on 192x96x96 x 4 load cases 12 / 8 / 6 / 4
+  // steps gave 569 / 568 / 567 / 564 CG iterations over 24 SIMP steps and
+  // 14.63 / 14.79 / 14.87 / 15.03 SIMP it/s (an earlier hierarchy); 6 keeps
+  // a margin on the estimate for other problems
+  int power_iters = 6;
+  double power_safety = 1.2;
+  // W-cycle: levels below wlevels visit their coarse level twice; -1 picks
+  // them by size (3D levels whose coarse level has >= kWCoarseNodes nodes)
+  int wlevels = -1;
+  bool tail = true;       // FP32 3D cycles: the small coarse levels in one work-group
+};
+
+GmgParams gmg_params_env();
 
 struct Ctx {
   topo_problem prob;
@@ -248,6 +281,9 @@ struct Ctx {
   int64_t t_launches;
   double t_ms;
   int apply_kz;       // z-chunk (node planes) of the 3D apply
+  GmgParams gp;       // multigrid switches (environment, read at creation)
+  int env_nrb;        // TOPO_APPLY_NRB at creation (0: the built-in policy)
+  int env_g;          // TOPO_APPLY_G at creation
   std::vector<GmgLevel> lv;   // multigrid hierarchy (empty for Jacobi)
   NetState* net;              // learned preconditioner (attached on request)
   const int* net_stop;        // device flag that makes network kernels return
@@ -261,8 +297,8 @@ void launch_simp_modulus(Ctx* c, const double* rho);
 void launch_apply(Ctx* c, const double* x, double* y, int nrhs, bool fuse_dot);
 void launch_apply_f32(Ctx* c, const float* x, float* y, int nrhs, bool fuse_dot);
 OpDesc fine_op(const Ctx* c);
-long apply_grid_blocks(const OpDesc& d, int nrhs, int elem_bytes);
-int apply_rhs_per_block(const OpDesc& d, int nrhs, int elem_bytes, int epi);
+long apply_grid_blocks(const OpDesc& d, int nrhs, int elem_bytes, int env_nrb);
+int apply_rhs_per_block(const OpDesc& d, int nrhs, int elem_bytes, int epi, int env_nrb);
 void launch_apply_op(Ctx* c, const OpDesc& d, const double* E, const double* x, double* y,
                      int nrhs, bool fuse_dot, bool timed, const int* stop);
 void launch_apply_op_f32(Ctx* c, const OpDesc& d, const float* E, const float* x, float* y,

@@ -57,6 +57,28 @@ def test_workspace_size_and_validation():
     assert lib.topo_status_string(-7) == b"workspace too small"
 
 
+def test_directly_solved_coarsest_level_size():
+    """topo_problem.gmg_dense: 0 (automatic) or 128..2048 DOFs.  The 3D
+    default stops the 192 x 96 x 96 hierarchy at 12 x 6 x 6 (1911 DOFs) and
+    holds its padded 1920 x 1920 inverse (FP64 and, mixed, FP32); 128 goes
+    on down to 3 x 2 x 2 with a 108 x 108 inverse."""
+    b = _lib()
+    lib = b.load_library()
+    n = ctypes.c_size_t(0)
+    sizes = {}
+    for dense in (0, 128, 2048):
+        p = b.make_problem(3, (192, 96, 96), nrhs=4, volfrac=0.3, rmin=2.5,
+                           precision=b.TOPO_MIXED_RU, precond=b.TOPO_PC_GMG, gmg_dense=dense)
+        assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+        sizes[dense] = n.value
+    assert sizes[0] == sizes[2048]
+    # the 1920 x 1920 FP64 + FP32 inverse against the levels below 12 x 6 x 6
+    assert sizes[2048] - sizes[128] > 1920 * 1920 * 12 - 8 * 1024 ** 2
+    for dense in (-1, 1, 127, 2049, 4096):
+        bad = b.make_problem(3, (16, 8, 8), precond=b.TOPO_PC_GMG, gmg_dense=dense)
+        assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == -1, dense
+
+
 def test_network_parameter_count_and_workspace():
     from oracle import net
     b = _lib()

@@ -8,6 +8,11 @@
   whose coarse level has at least 512 nodes) is a symmetric positive
   definite preconditioner for every depth it is given: CG converges, in no
   more iterations than with the V-cycle, to the same solution.
+* The 3D hierarchy stops at the first level of at most 2048 DOFs
+  (TOPO_GMG_DENSE; 128 gives the hierarchy that goes down to 128 DOFs) and
+  solves it with its exact inverse, built by block Gauss-Jordan
+  elimination: on a grid that small the preconditioner is the inverse of
+  K itself.
 """
 
 import os
@@ -23,10 +28,14 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-def _solve(p, precision, rho_val=0.3, maxit=2000):
+def _solve(p, precision, rho_val=0.3, maxit=2000, gmg_dense=0):
     from paper_2012_08208_amd import Topo, TOPO_PC_GMG, SOLVE_INFO_LEN
-    t = Topo.from_problem(p, precision=precision, precond=TOPO_PC_GMG, maxit=maxit, device=DEV)
-    rho = torch.full((p.n_cells,), rho_val, dtype=torch.float64, device=DEV)
+    t = Topo.from_problem(p, precision=precision, precond=TOPO_PC_GMG, maxit=maxit, device=DEV,
+                          gmg_dense=gmg_dense)
+    if np.isscalar(rho_val):
+        rho = torch.full((p.n_cells,), rho_val, dtype=torch.float64, device=DEV)
+    else:
+        rho = torch.as_tensor(rho_val, dtype=torch.float64, device=DEV)
     u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=DEV)
     info = torch.zeros(SOLVE_INFO_LEN, dtype=torch.float64, device=DEV)
     t.solve(rho, u, info)
@@ -39,6 +48,7 @@ def _solve(p, precision, rho_val=0.3, maxit=2000):
 def test_vcycle_iterations_do_not_grow_with_depth(prec, monkeypatch):
     from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_RU
     monkeypatch.setenv("TOPO_GMG_WLEVELS", "0")
+    monkeypatch.setenv("TOPO_GMG_DENSE", "128")   # 3 and 4 levels down to 3 x 2 x 2
     code = TOPO_FP64 if prec == "fp64" else TOPO_MIXED_RU
     its = []
     for nel in ((24, 12, 12), (48, 24, 24)):
@@ -87,6 +97,8 @@ def test_one_block_coarse_tail_matches_the_per_level_kernels(nel, monkeypatch):
     same solution in about the same iterations; two runs give the same
     bits."""
     from paper_2012_08208_amd import TOPO_MIXED_RU, TOPO_MIXED_FP32
+    # the tail serves hierarchies that go down to 128 DOFs
+    monkeypatch.setenv("TOPO_GMG_DENSE", "128")
     if len(nel) == 3:
         p = synth.cantilever3d(*nel, nrhs=3, volfrac=0.3, rmin=1.5, rtol=1e-9)
     else:
@@ -124,6 +136,7 @@ def test_one_block_tail_follows_the_smoother_and_cycle_switches(env, monkeypatch
     FP32 rounding (a different polynomial or cycle would differ at 1e-2)."""
     from paper_2012_08208_amd import TOPO_MIXED_FP32
     p = synth.cantilever3d(24, 12, 12, nrhs=2, volfrac=0.3, rmin=1.5, rtol=1e-9)
+    monkeypatch.setenv("TOPO_GMG_DENSE", "128")
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     out = {}
@@ -138,3 +151,60 @@ def test_one_block_tail_follows_the_smoother_and_cycle_switches(env, monkeypatch
           f"{out['1'][1]:.0f}", flush=True)
     assert d2 <= 1e-5
     assert abs(out["1"][1] - out["0"][1]) <= 2
+
+
+@pytest.mark.parametrize("nel", [(10, 6, 5), (7, 7, 7)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed-ru"])
+def test_direct_level_above_128_dofs_is_the_exact_inverse(nel, prec):
+    """A 3D grid of 128 < DOFs <= 2048 is its own coarsest level (1386 DOFs,
+    padded to 1408 = 22 blocks of 64; 1536 = 24 blocks, no padding), so the
+    preconditioner is K^-1 from the blocked elimination: FP64 CG stops after
+    one iteration (two at most), the reliable-update CG with the FP32 copy of the inverse
+    after a few, both at the direct solution (SIMP contrast 1e-9, fixed DOFs
+    as identity rows)."""
+    from oracle import fem, mesh as M
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_RU
+    p = synth.cantilever3d(*nel, nrhs=2, volfrac=0.3, rmin=1.5, rtol=1e-10)
+    m = M.build(p.dim, p.nel, p.split)
+    rho = synth.rho_random(5, m.n_cells, 1e-3, 1.0)
+    K = fem.assemble(m, fem.simp_modulus(rho, p.E0, p.Emin, p.penal), p.nu)
+    f = p.loads.reshape(p.nrhs, -1)
+    u_ref = fem.solve(K, f, p.fixed.ravel())
+    code = TOPO_FP64 if prec == "fp64" else TOPO_MIXED_RU
+    print(f"[dense direct] {nel} {prec}", flush=True)
+    st, info, u = _solve(p, code, rho_val=rho)
+    print(f"  CG iterations {info[0]:.0f}", flush=True)
+    assert st == 0 and info[1] == 1.0, (st, info)
+    assert info[0] <= (2 if prec == "fp64" else 6)
+    u = u.reshape(p.nrhs, -1)
+    for r in range(p.nrhs):
+        err = np.linalg.norm(u[r] - u_ref[r]) / np.linalg.norm(u_ref[r])
+        assert err <= 1e-8, (r, err)
+
+
+@pytest.mark.parametrize("nel", [(48, 24, 24), (33, 17, 9)])
+def test_direct_2048_dof_level_against_the_128_dof_hierarchy(nel, monkeypatch):
+    """The hierarchy that stops at 12 x 6 x 6 (1911 DOFs; 9 x 5 x 3, 720 DOFs,
+    on the odd grid) and solves it exactly, against the one that goes on down
+    to 128 DOFs: the same solution, in no more CG iterations (an exact coarse
+    solve is at least as good as a cycle over the levels below it).  The
+    size comes from topo_problem.gmg_dense, or from TOPO_GMG_DENSE when that
+    field is 0 (automatic)."""
+    from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_RU
+    p = synth.cantilever3d(*nel, nrhs=2, volfrac=0.3, rmin=1.5, rtol=1e-10)
+    for code in (TOPO_FP64, TOPO_MIXED_RU):
+        out = {}
+        for dense in ("128", "2048"):
+            field = 128 if (dense == "128" and code == TOPO_FP64) else 0
+            monkeypatch.setenv("TOPO_GMG_DENSE", "2048" if field else dense)
+            print(f"[dense level] {nel} precision {code} dense {dense} (field {field})", flush=True)
+            st, info, u = _solve(p, code, gmg_dense=field)
+            assert st == 0 and info[1] == 1.0, (st, info)
+            out[dense] = (info[0], u)
+        print(f"  CG iterations 128: {out['128'][0]:.0f}  2048: {out['2048'][0]:.0f}", flush=True)
+        assert out["2048"][0] <= out["128"][0] + 1
+        for r in range(p.nrhs):
+            sl = slice(r * p.n_dofs, (r + 1) * p.n_dofs)
+            a, b = out["2048"][1][sl], out["128"][1][sl]
+            assert np.linalg.norm(a - b) <= 1e-7 * np.linalg.norm(b)
+    monkeypatch.delenv("TOPO_GMG_DENSE", raising=False)
