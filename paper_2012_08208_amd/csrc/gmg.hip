@@ -502,8 +502,13 @@ __global__ __launch_bounds__(kGjPivThreads) void gj_pivot_kernel(const double* _
       for (int m = 0; m < 4; ++m) colb[buf][i0 + 16 * m] = v[m];
     }
     __syncthreads();
+    // 1 / pivot: the hardware reciprocal and one Newton step (error about
+    // the square of the reciprocal's, i.e. FP64 rounding), shorter than a
+    // division on the serial path of the 64 steps
     const double piv = rowb[buf][p];
-    const double rj = (j == p ? 1.0 : rowb[buf][j]) / piv;
+    double rp = __builtin_amdgcn_rcp(piv);
+    rp = fma(rp, fma(-piv, rp, 1.0), rp);
+    const double rj = (j == p ? 1.0 : rowb[buf][j]) * rp;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int i = i0 + 16 * m;
@@ -609,6 +614,7 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double* A, int np, int k
 // Rows are np entries long and np is a multiple of 64, so every piece is
 // aligned and the padded columns (zero) need no bounds test.
 constexpr int kDenseWaves = 8;
+static_assert(kDense3 <= 4 * 64 * kDenseWaves, "the b staging covers np <= 4 * blockDim");
 template <typename T, typename TA>
 __global__ __launch_bounds__(64 * kDenseWaves) void dense_solve_kernel(
     T* x, const T* __restrict__ b, const TA* __restrict__ Ainv, int n, int np, int nrhs,
@@ -631,9 +637,23 @@ __global__ __launch_bounds__(64 * kDenseWaves) void dense_solve_kernel(
     const int q = lane + 64 * u;
     if (q < nv) a[u] = Ar[q];
   }
-  for (int t = threadIdx.x; t < nrhs * np; t += blockDim.x) {
-    const int r = t / np, j = t - r * np;
-    bs[t] = j < n ? b[(long)r * n + j] : T(0);
+  // b staged with every load issued before the stores (np <= 4 * blockDim)
+  {
+    T v[kMaxRhs][4];
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = threadIdx.x + u * (int)blockDim.x;
+        v[r][u] = (r < nrhs && j < n) ? b[(long)r * n + j] : T(0);
+      }
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = threadIdx.x + u * (int)blockDim.x;
+        if (r < nrhs && j < np) bs[(long)r * np + j] = v[r][u];
+      }
   }
   __syncthreads();
   if (row >= n) return;
