@@ -477,46 +477,102 @@ __global__ void coarse_assemble_ld_kernel(double* A, const double* __restrict__ 
 constexpr int kGjB = kGjBlock;
 constexpr int kGjPad = kGjB + 1;   // LDS row pitch (doubles)
 
-// P = inverse of the diagonal block k by in-place Gauss-Jordan elimination.
-// The block stays in registers: thread (j, i0) of 1024 holds column j, rows
-// i0 + 16m (m < 4).  Per pivot p the owners publish row p and column p to
-// LDS (double-buffered by the parity of p, so one barrier per step) and
-// every thread updates its 4 entries.
-constexpr int kGjPivThreads = 1024;
+// P = inverse of the diagonal block k by in-place Gauss-Jordan elimination,
+// itself blocked by 16: for each 16 x 16 diagonal sub-block one wave
+// inverts it in registers (lane l holds column l & 15, rows (l >> 4) + 4m;
+// the pivot row and column come from lane shuffles, so its 16 steps need no
+// barrier), then the work-group forms the sub-block row panel and updates
+// the other 48 rows, as the blocked elimination over the whole matrix
+// does.  Four sub-blocks, three barriers each, instead of 64 barrier-
+// separated steps.
+constexpr int kGjPivThreads = 256;
+constexpr int kGjSub = 16;
 __global__ __launch_bounds__(kGjPivThreads) void gj_pivot_kernel(const double* __restrict__ A,
                                                                   int np, int k, double* P) {
-  __shared__ double rowb[2][kGjB], colb[2][kGjB];
-  const int j = threadIdx.x & 63, i0 = threadIdx.x >> 6;
+  __shared__ double S[kGjB * kGjPad];
+  __shared__ double Cb[(kGjB - kGjSub) * (kGjSub + 1)];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const long base = ((long)k * np + k) * kGjB;
-  double v[4];
+  for (int e = t; e < kGjB * kGjB; e += kGjPivThreads)
+    S[(e / kGjB) * kGjPad + e % kGjB] = A[base + (long)(e / kGjB) * np + e % kGjB];
+  __syncthreads();
+  for (int kb = 0; kb < kGjB / kGjSub; ++kb) {
+    const int o = kb * kGjSub;
+    if (wave == 0) {
+      const int j = lane & 15, g = lane >> 4;
+      double v[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) v[m] = A[base + (long)(i0 + 16 * m) * np + j];
-  for (int p = 0; p < kGjB; ++p) {
-    const int buf = p & 1;
-    if (i0 == (p & 15)) {
-      const int mp = p >> 4;
-      rowb[buf][j] = mp == 0 ? v[0] : mp == 1 ? v[1] : mp == 2 ? v[2] : v[3];
-    }
-    if (j == p) {
+      for (int m = 0; m < 4; ++m) v[m] = S[(o + g + 4 * m) * kGjPad + o + j];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) colb[buf][i0 + 16 * m] = v[m];
+      for (int p = 0; p < kGjSub; ++p) {
+        const int rp = p >> 2, lp = (p & 3) << 4;
+        const double piv = __shfl(v[rp], lp | p);
+        const double rowv = __shfl(v[rp], lp | j);
+        double colv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) colv[m] = __shfl(v[m], (lane & 0x30) | p);
+        double r = __builtin_amdgcn_rcp(piv);
+        r = fma(r, fma(-piv, r, 1.0), r);
+        const double rj = (j == p ? 1.0 : rowv) * r;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int i = g + 4 * m;
+          v[m] = (i == p) ? rj : ((j == p) ? 0.0 : v[m]) - colv[m] * rj;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) S[(o + g + 4 * m) * kGjPad + o + j] = v[m];
     }
     __syncthreads();
-    // 1 / pivot: the hardware reciprocal and one Newton step (error about
-    // the square of the reciprocal's, i.e. FP64 rounding), shorter than a
-    // division on the serial path of the 64 steps
-    const double piv = rowb[buf][p];
-    double rp = __builtin_amdgcn_rcp(piv);
-    rp = fma(rp, fma(-piv, rp, 1.0), rp);
-    const double rj = (j == p ? 1.0 : rowb[buf][j]) * rp;
+    // row panel (16 rows x 48 columns) from the sub-block inverse; the
+    // other rows' sub-block columns saved for the update
+    double col[kGjSub];
+    const int cc = t % 48, r0 = t / 48;
+    const int c = cc < o ? cc : cc + kGjSub;
+    if (t < 192) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int i = i0 + 16 * m;
-      v[m] = (i == p) ? rj : ((j == p) ? 0.0 : v[m]) - colb[buf][i] * rj;
+      for (int q = 0; q < kGjSub; ++q) col[q] = S[(o + q) * kGjPad + c];
     }
-  }
+    for (int e = t; e < (kGjB - kGjSub) * kGjSub; e += kGjPivThreads) {
+      const int ri = e / kGjSub, q = e % kGjSub;
+      const int i = ri < o ? ri : ri + kGjSub;
+      Cb[ri * (kGjSub + 1) + q] = S[i * kGjPad + o + q];
+    }
+    __syncthreads();
+    if (t < 192) {
 #pragma unroll
-  for (int m = 0; m < 4; ++m) P[(i0 + 16 * m) * kGjB + j] = v[m];
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + 4 * u;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kGjSub; ++q) acc = fma(S[(o + r) * kGjPad + o + q], col[q], acc);
+        S[(o + r) * kGjPad + c] = acc;
+      }
+    }
+    __syncthreads();
+    // every other row: A_ic -= C_i (row panel)_c, and the sub-block columns
+    // become -C_i P16 (the same product: those columns of the sub-block rows
+    // hold P16)
+    {
+      const int c2 = t & 63, g2 = t >> 6;
+      double rc[kGjSub];
+#pragma unroll
+      for (int q = 0; q < kGjSub; ++q) rc[q] = S[(o + q) * kGjPad + c2];
+      const bool diag = c2 >= o && c2 < o + kGjSub;
+#pragma unroll
+      for (int u = 0; u < 12; ++u) {
+        const int ri = g2 + 4 * u;
+        const int i = ri < o ? ri : ri + kGjSub;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kGjSub; ++q) acc = fma(Cb[ri * (kGjSub + 1) + q], rc[q], acc);
+        double& y = S[i * kGjPad + c2];
+        y = diag ? -acc : y - acc;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < kGjB * kGjB; e += kGjPivThreads) P[e] = S[(e / kGjB) * kGjPad + e % kGjB];
 }
 
 // acc = X Y for 64 x 64 blocks staged in LDS; thread (tx, ty) owns rows
