@@ -354,7 +354,7 @@ def time_to_solution(p, rho, t_bench, prec_bench, args):
     run(args.precision + " multigrid PCG (the timed solver)", t_bench, 2)
     if prec_bench != TOPO_FP64 or args.precond != "gmg":
         t64 = Topo.from_problem(p, precision=TOPO_FP64, precond=TOPO_PC_GMG, maxit=args.maxit,
-                                device=dev)
+                                device=dev, gmg_dense=args.gmg_dense)
         run("fp64 multigrid PCG", t64, 2)
         t64.close()
     tj = Topo.from_problem(p, precision=TOPO_FP64, precond=TOPO_PC_JACOBI, maxit=12000, device=dev)
@@ -810,6 +810,9 @@ def main():
                     help="filter: distance-weighted sensitivity filter (Sec. 3.2.2), Helmholtz PDE "
                          "sensitivity filter (Sec. 6.3), or a density filter on the distance weights")
     ap.add_argument("--maxit", type=int, default=40000)
+    ap.add_argument("--gmg-dense", type=int, default=0,
+                    help="largest multigrid coarsest level solved directly, in DOFs (128..2048; "
+                         "0: 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20000,
                     help="learned3d workload: on-GPU training steps before the timed run")
@@ -861,7 +864,8 @@ def main():
     prec = {"fp64": TOPO_FP64, "mixed": TOPO_MIXED_FP32, "mixed-ir": TOPO_MIXED_IR,
             "mixed-bf16": TOPO_MIXED_BF16, "mixed-ru": TOPO_MIXED_RU}[args.precision]
     pc = TOPO_PC_JACOBI if args.precond == "jacobi" else TOPO_PC_GMG
-    t = Topo.from_problem(p, precision=prec, precond=pc, maxit=args.maxit, device=dev)
+    t = Topo.from_problem(p, precision=prec, precond=pc, maxit=args.maxit, device=dev,
+                          gmg_dense=args.gmg_dense)
     rho = torch.full((p.n_cells,), p.volfrac, dtype=torch.float64, device=dev)
     u = torch.zeros(p.nrhs * p.n_dofs, dtype=torch.float64, device=dev)
     log = torch.zeros(max(1, args.steps) * LOG_LEN, dtype=torch.float64, device=dev)

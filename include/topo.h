@@ -195,10 +195,10 @@ typedef struct topo_problem {
                          solve, by Gauss-Jordan elimination: in one
                          work-group up to 128 DOFs, else block by block);
                          the hierarchy stops at the first level at or
-                         below it.  0 = automatic: 2048 in 3D (the
-                         environment variable TOPO_GMG_DENSE, read at
-                         creation, overrides it), 128 in 2D; otherwise
-                         128..2048 (else TOPO_E_INVALID) */
+                         below it.  0 = automatic: 2048 (the environment
+                         variable TOPO_GMG_DENSE, read at creation,
+                         overrides it); otherwise 128..2048 (else
+                         TOPO_E_INVALID) */
   int32_t filter;     /* TOPO_FILTER_DISTANCE (0) | TOPO_FILTER_HELMHOLTZ | TOPO_FILTER_DENSITY */
   int32_t sync_mode;  /* TOPO_SYNC_POLL (0) | TOPO_SYNC_NONE, see below */
 } topo_problem;

@@ -99,7 +99,6 @@ static int pick_kz_coarse(int dim, int nx, int ny, int nz) {
 // most 128 DOFs, the size the dense coarsest solve handles.
 int gmg_dense_max(const topo_problem* p) {
   if (p->gmg_dense > 0) return p->gmg_dense;
-  if (p->dim != 3) return 128;
   int v = kDense3;
   if (const char* e = getenv("TOPO_GMG_DENSE")) v = atoi(e);
   return v < 128 ? 128 : (v > kDense3 ? kDense3 : v);

@@ -200,10 +200,11 @@ struct LevelDims {
   int nx, ny, nz;
 };
 // Largest coarsest level (DOFs) that the multigrid hierarchy solves
-// directly: topo_problem.gmg_dense, else 128 (one work-group's
-// Gauss-Jordan) in 2D and kDense3 in 3D (blocked Gauss-Jordan over the
-// whole GPU; TOPO_GMG_DENSE overrides it).  At most kDense3: the dense solve
-// stages 4 FP64 right-hand sides of that length in 64 KiB of LDS.
+// directly: topo_problem.gmg_dense, else kDense3 (TOPO_GMG_DENSE overrides
+// it).  Up to 128 DOFs the inverse comes from one work-group's Gauss-Jordan
+// elimination, above from the blocked one over the whole GPU.  At most
+// kDense3: the dense solve stages 4 FP64 right-hand sides of that length in
+// 64 KiB of LDS.
 constexpr int kDense3 = 2048;
 constexpr int kGjBlock = 64;
 int gmg_dense_max(const topo_problem* p);

@@ -74,6 +74,15 @@ def test_directly_solved_coarsest_level_size():
     assert sizes[0] == sizes[2048]
     # the 1920 x 1920 FP64 + FP32 inverse against the levels below 12 x 6 x 6
     assert sizes[2048] - sizes[128] > 1920 * 1920 * 12 - 8 * 1024 ** 2
+    # 2D: the MBB beam stops at 38 x 13 (1092 DOFs, padded to 1152) instead
+    # of going on to 5 x 2
+    s2 = {}
+    for dense in (0, 128):
+        p = b.make_problem(2, (1200, 400), nrhs=1, volfrac=0.4, rmin=3.0,
+                           precision=b.TOPO_MIXED_FP32, precond=b.TOPO_PC_GMG, gmg_dense=dense)
+        assert lib.topo_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+        s2[dense] = n.value
+    assert s2[0] - s2[128] > 1152 * 1152 * 12 - 4 * 1024 ** 2
     for dense in (-1, 1, 127, 2049, 4096):
         bad = b.make_problem(3, (16, 8, 8), precond=b.TOPO_PC_GMG, gmg_dense=dense)
         assert lib.topo_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == -1, dense

@@ -8,11 +8,11 @@
   whose coarse level has at least 512 nodes) is a symmetric positive
   definite preconditioner for every depth it is given: CG converges, in no
   more iterations than with the V-cycle, to the same solution.
-* The 3D hierarchy stops at the first level of at most 2048 DOFs
-  (TOPO_GMG_DENSE; 128 gives the hierarchy that goes down to 128 DOFs) and
-  solves it with its exact inverse, built by block Gauss-Jordan
-  elimination: on a grid that small the preconditioner is the inverse of
-  K itself.
+* The hierarchy stops at the first level of at most 2048 DOFs
+  (TOPO_GMG_DENSE or topo_problem.gmg_dense; 128 gives the hierarchy that
+  goes down to 128 DOFs) and solves it with its exact inverse, built by
+  block Gauss-Jordan elimination: on a grid that small the preconditioner
+  is the inverse of K itself.
 """
 
 import os
