@@ -153,18 +153,22 @@ def test_one_block_tail_follows_the_smoother_and_cycle_switches(env, monkeypatch
     assert abs(out["1"][1] - out["0"][1]) <= 2
 
 
-@pytest.mark.parametrize("nel", [(10, 6, 5), (7, 7, 7)])
+@pytest.mark.parametrize("nel", [(10, 6, 5), (7, 7, 7), (30, 15), (31, 16)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed-ru"])
 def test_direct_level_above_128_dofs_is_the_exact_inverse(nel, prec):
-    """A 3D grid of 128 < DOFs <= 2048 is its own coarsest level (1386 DOFs,
-    padded to 1408 = 22 blocks of 64; 1536 = 24 blocks, no padding), so the
+    """A grid of 128 < DOFs <= 2048 is its own coarsest level (3D: 1386 DOFs,
+    padded to 1408 = 22 blocks of 64, and 1536 = 24 blocks, no padding; 2D:
+    992 DOFs padded to 1024, and 1088 = 17 blocks), so the
     preconditioner is K^-1 from the blocked elimination: FP64 CG stops after
     one iteration (two at most), the reliable-update CG with the FP32 copy of the inverse
     after a few, both at the direct solution (SIMP contrast 1e-9, fixed DOFs
     as identity rows)."""
     from oracle import fem, mesh as M
     from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_RU
-    p = synth.cantilever3d(*nel, nrhs=2, volfrac=0.3, rmin=1.5, rtol=1e-10)
+    if len(nel) == 3:
+        p = synth.cantilever3d(*nel, nrhs=2, volfrac=0.3, rmin=1.5, rtol=1e-10)
+    else:
+        p = synth.cantilever2d(*nel, volfrac=0.4, rmin=1.5, rtol=1e-10)
     m = M.build(p.dim, p.nel, p.split)
     rho = synth.rho_random(5, m.n_cells, 1e-3, 1.0)
     K = fem.assemble(m, fem.simp_modulus(rho, p.E0, p.Emin, p.penal), p.nu)
@@ -182,16 +186,20 @@ def test_direct_level_above_128_dofs_is_the_exact_inverse(nel, prec):
         assert err <= 1e-8, (r, err)
 
 
-@pytest.mark.parametrize("nel", [(48, 24, 24), (33, 17, 9)])
+@pytest.mark.parametrize("nel", [(48, 24, 24), (33, 17, 9), (192, 64), (149, 57)])
 def test_direct_2048_dof_level_against_the_128_dof_hierarchy(nel, monkeypatch):
     """The hierarchy that stops at 12 x 6 x 6 (1911 DOFs; 9 x 5 x 3, 720 DOFs,
-    on the odd grid) and solves it exactly, against the one that goes on down
-    to 128 DOFs: the same solution, in no more CG iterations (an exact coarse
-    solve is at least as good as a cycle over the levels below it).  The
-    size comes from topo_problem.gmg_dense, or from TOPO_GMG_DENSE when that
-    field is 0 (automatic)."""
+    on the odd grid; 2D: 48 x 16, 1666 DOFs, and 38 x 15, 1248 DOFs) and solves
+    it exactly, against the one that goes on down to 128 DOFs (with the
+    one-block tail in the FP32 2D cycle): the same solution, in no more CG
+    iterations (an exact coarse solve is at least as good as a cycle over
+    the levels below it).  The size comes from topo_problem.gmg_dense, or
+    from TOPO_GMG_DENSE when that field is 0 (automatic)."""
     from paper_2012_08208_amd import TOPO_FP64, TOPO_MIXED_RU
-    p = synth.cantilever3d(*nel, nrhs=2, volfrac=0.3, rmin=1.5, rtol=1e-10)
+    if len(nel) == 3:
+        p = synth.cantilever3d(*nel, nrhs=2, volfrac=0.3, rmin=1.5, rtol=1e-10)
+    else:
+        p = synth.mbb2d(*nel, volfrac=0.4, rmin=1.5, rtol=1e-10)
     for code in (TOPO_FP64, TOPO_MIXED_RU):
         out = {}
         for dense in ("128", "2048"):
