@@ -493,8 +493,20 @@ __global__ __launch_bounds__(kGjPivThreads) void gj_pivot_kernel(const double* _
   __shared__ double Cb[(kGjB - kGjSub) * (kGjSub + 1)];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const long base = ((long)k * np + k) * kGjB;
-  for (int e = t; e < kGjB * kGjB; e += kGjPivThreads)
-    S[(e / kGjB) * kGjPad + e % kGjB] = A[base + (long)(e / kGjB) * np + e % kGjB];
+  {
+    constexpr int PER = kGjB * kGjB / kGjPivThreads;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * kGjPivThreads;
+      v[u] = A[base + (long)(e / kGjB) * np + e % kGjB];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * kGjPivThreads;
+      S[(e / kGjB) * kGjPad + e % kGjB] = v[u];
+    }
+  }
   __syncthreads();
   for (int kb = 0; kb < kGjB / kGjSub; ++kb) {
     const int o = kb * kGjSub;
@@ -596,18 +608,32 @@ __device__ inline void gj_block_product(const double* Xs, const double* Ys, doub
   }
 }
 
-// stage the 64 x 64 block at src (leading dimension ld) into LDS
-__device__ inline void gj_stage(double* dst, const double* __restrict__ src, long ld) {
-  for (int t = threadIdx.x; t < kGjB * kGjB; t += blockDim.x) {
-    const int i = t / kGjB, j = t % kGjB;
-    dst[i * kGjPad + j] = src[(long)i * ld + j];
+// stage two 64 x 64 blocks (leading dimensions lx, ly) into LDS, every
+// load of the 256 threads issued before the first store
+constexpr int kGjThreads = 256;
+__device__ inline void gj_stage2(double* dx, const double* __restrict__ sx, long lx, double* dy,
+                                 const double* __restrict__ sy, long ly) {
+  constexpr int PER = kGjB * kGjB / kGjThreads;
+  double vx[PER], vy[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    vx[u] = sx[(long)(t / kGjB) * lx + t % kGjB];
+    vy[u] = sy[(long)(t / kGjB) * ly + t % kGjB];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    dx[(t / kGjB) * kGjPad + t % kGjB] = vx[u];
+    dy[(t / kGjB) * kGjPad + t % kGjB] = vy[u];
   }
 }
 
 // blocks [0, nb): row panel A_kj <- P A_kj (j != k); blocks [nb, 2 nb): save
 // the column panel block C_i = A_ik
-__global__ __launch_bounds__(256) void gj_panel_kernel(double* A, int np, int k,
-                                                        const double* __restrict__ P, double* C) {
+__global__ __launch_bounds__(kGjThreads) void gj_panel_kernel(double* A, int np, int k,
+                                                               const double* __restrict__ P,
+                                                               double* C) {
   __shared__ double Xs[kGjB * kGjPad], Ys[kGjB * kGjPad];
   const int nb = np / kGjB;
   const int blk = blockIdx.x;
@@ -615,15 +641,21 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(double* A, int np, int k,
     const int i = blk - nb;
     const double* src = A + ((long)i * np + k) * kGjB;
     double* dst = C + (long)i * kGjB * kGjB;
-    for (int t = threadIdx.x; t < kGjB * kGjB; t += blockDim.x)
-      dst[t] = src[(long)(t / kGjB) * np + t % kGjB];
+    constexpr int PER = kGjB * kGjB / kGjThreads;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = threadIdx.x + u * kGjThreads;
+      v[u] = src[(long)(t / kGjB) * np + t % kGjB];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) dst[threadIdx.x + u * kGjThreads] = v[u];
     return;
   }
   const int j = blk;
   if (j == k) return;
   double* Akj = A + ((long)k * np + j) * kGjB;
-  gj_stage(Xs, P, kGjB);
-  gj_stage(Ys, Akj, np);
+  gj_stage2(Xs, P, kGjB, Ys, Akj, np);
   __syncthreads();
   double acc[4][4];
   gj_block_product(Xs, Ys, acc);
@@ -636,32 +668,46 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(double* A, int np, int k,
 
 // every block (i, j) outside row block k: A_ij -= C_i A_kj (j != k) or
 // A_ik = -C_i P; block (k, k) takes P
-__global__ __launch_bounds__(256) void gj_update_kernel(double* A, int np, int k,
+__global__ __launch_bounds__(kGjThreads) void gj_update_kernel(double* A, int np, int k,
                                                          const double* __restrict__ P,
                                                          const double* __restrict__ C) {
   __shared__ double Xs[kGjB * kGjPad], Ys[kGjB * kGjPad];
   const int i = blockIdx.y, j = blockIdx.x;
   double* Aij = A + ((long)i * np + j) * kGjB;
   if (i == k) {
-    if (j == k)
-      for (int t = threadIdx.x; t < kGjB * kGjB; t += blockDim.x)
-        Aij[(long)(t / kGjB) * np + t % kGjB] = P[t];
+    if (j == k) {
+      constexpr int PER = kGjB * kGjB / kGjThreads;
+      double v[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) v[u] = P[threadIdx.x + u * kGjThreads];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int t = threadIdx.x + u * kGjThreads;
+        Aij[(long)(t / kGjB) * np + t % kGjB] = v[u];
+      }
+    }
     return;
   }
-  gj_stage(Xs, C + (long)i * kGjB * kGjB, kGjB);
-  if (j == k) gj_stage(Ys, P, kGjB);
-  else gj_stage(Ys, A + ((long)k * np + j) * kGjB, np);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  // the block's own entries are requested first: their latency hides
+  // behind the staging and the product
+  double yv[4][4];
+  if (j != k) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) yv[a][b] = Aij[(long)(ty + 16 * a) * np + tx + 16 * b];
+  }
+  if (j == k) gj_stage2(Xs, C + (long)i * kGjB * kGjB, kGjB, Ys, P, kGjB);
+  else gj_stage2(Xs, C + (long)i * kGjB * kGjB, kGjB, Ys, A + ((long)k * np + j) * kGjB, np);
   __syncthreads();
   double acc[4][4];
   gj_block_product(Xs, Ys, acc);
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      double& y = Aij[(long)(ty + 16 * a) * np + tx + 16 * b];
-      y = (j == k) ? -acc[a][b] : y - acc[a][b];
-    }
+    for (int b = 0; b < 4; ++b)
+      Aij[(long)(ty + 16 * a) * np + tx + 16 * b] = (j == k) ? -acc[a][b] : yv[a][b] - acc[a][b];
 }
 
 // x = Ainv b for every load case: one wave per row, 8 waves per work-group
@@ -811,8 +857,8 @@ void gmg_setup(Ctx* c) {
                                                        c->m.vol, np);
   for (int k = 0; k < nb; ++k) {
     gj_pivot_kernel<<<1, kGjPivThreads, 0, s>>>(cl.Ainv, np, k, P);
-    gj_panel_kernel<<<2 * nb, 256, 0, s>>>(cl.Ainv, np, k, P, C);
-    gj_update_kernel<<<dim3(nb, nb), 256, 0, s>>>(cl.Ainv, np, k, P, C);
+    gj_panel_kernel<<<2 * nb, kGjThreads, 0, s>>>(cl.Ainv, np, k, P, C);
+    gj_update_kernel<<<dim3(nb, nb), kGjThreads, 0, s>>>(cl.Ainv, np, k, P, C);
   }
   if (cl.Ainv32) to_f32_kernel<<<red_grid((long)np * np), 256, 0, s>>>(cl.Ainv32, cl.Ainv, (long)np * np);
 }
