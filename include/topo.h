@@ -126,9 +126,11 @@ enum { TOPO_FP64 = 0, TOPO_MIXED_FP32 = 1, TOPO_MIXED_IR = 2, TOPO_MIXED_BF16 = 
        TOPO_MIXED_RU = 4 };
 /* Preconditioner of the CG solve.
    TOPO_PC_JACOBI:  z = D^-1 r.
-   TOPO_PC_GMG:     one multigrid V-cycle (Chebyshev-Jacobi smoothing,
-                    nested P1 transfers, Galerkin-exact coarse moduli, dense
-                    coarsest solve).
+   TOPO_PC_GMG:     one multigrid cycle (Chebyshev-Jacobi smoothing,
+                    nested P1 transfers, Galerkin-exact coarse moduli; a
+                    W-cycle on the 3D levels whose coarse level has at least
+                    512 nodes, else V; the coarsest level, of at most
+                    gmg_dense DOFs, solved with its dense inverse).
    TOPO_PC_LEARNED: 3D, TOPO_FP64 only.  Flexible CG (Polak-Ribiere beta)
                     preconditioned by a two-level cycle whose coarse
                     correction is the convolutional network of

@@ -23,9 +23,10 @@
 // [0.09 lmax, lmax], lmax from a Rayleigh-quotient power iteration with a
 // safety factor; the same polynomial is used before and after the coarse
 // correction, so the V-cycle is a symmetric positive definite operator.
-// Coarsest level (<= 128 DOFs, 3D: <= 2048): dense matrix assembled per
-// solve and inverted by Gauss-Jordan elimination, in one work-group up to
-// 128 DOFs, else block by block over the whole GPU.
+// Coarsest level (the first of at most 2048 DOFs, or the size the problem
+// asks for): dense matrix assembled per solve and inverted by Gauss-Jordan
+// elimination, in one work-group up to 128 DOFs, else block by block over
+// the whole GPU.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -447,8 +448,8 @@ __global__ __launch_bounds__(512) void coarse_solve_kernel(T* x, const T* __rest
   coarse_solve_block<T>(x, b, Ainv, n, nrhs);
 }
 
-// ------------------------------------- larger coarsest level (3D, > 128 DOFs)
-// The coarsest 3D level of a deep hierarchy (12 x 6 x 6 cells, 1911 DOFs, on
+// ------------------------------------------ larger coarsest level (> 128 DOFs)
+// The coarsest level of a deep hierarchy (12 x 6 x 6 cells, 1911 DOFs, on
 // 192 x 96 x 96) is solved directly too: its matrix, padded to np = a whole
 // number of 64-blocks with identity rows and columns, is assembled and
 // inverted in FP64 by block Gauss-Jordan elimination without pivoting (the

@@ -229,7 +229,7 @@ struct GmgParams {
   // W-cycle: levels below wlevels visit their coarse level twice; -1 picks
   // them by size (3D levels whose coarse level has >= kWCoarseNodes nodes)
   int wlevels = -1;
-  bool tail = true;       // FP32 3D cycles: the small coarse levels in one work-group
+  bool tail = true;       // FP32 cycles down to <= 128 DOFs: the small levels in one work-group
 };
 
 GmgParams gmg_params_env();
