@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "common.h"
+#include "dense_dev.h"
 #include "element.h"
 #include "shared_dev.h"
 #include "topo_internal.h"
@@ -47,7 +48,10 @@ struct BSlot {
   double* E;
   double* invd;
   double* v[BV_N];
-  double* Ainv;
+  double* Ainv;                // last level: dense inverse [nd*nd], or [np*np] when np > 0
+  int np;                      // last level above 128 DOFs: nd rounded up to kGjBlock, else 0
+  double* gjP;                 // np > 0: the pivot block's inverse [64*64]
+  double* gjC;                 // np > 0: the saved column panel [np*64]
   double* lmax;
   double* pscale;
   int j0, j1;  // this slot's jobs in its level's DOF-job table
@@ -183,7 +187,7 @@ __global__ void b_power_fin(const int* list, const BSlot* slots, const BState* s
 
 __global__ void b_coarse_assemble(const int* list, const BSlot* slots, const BState* st) {
   const BSlot& s = slots[list[blockIdx.x]];
-  if (!st[s.inst].active) return;
+  if (!st[s.inst].active || s.np > 0) return;
   const int n = (int)(s.op.nn * 2);
   for (int row = threadIdx.x; row < n; row += blockDim.x)
     coarse_assemble_row(row, s.Ainv, s.E, s.op, s.lam0, s.mu0, s.vol);
@@ -192,8 +196,49 @@ __global__ void b_coarse_assemble(const int* list, const BSlot* slots, const BSt
 __global__ __launch_bounds__(1024) void b_gauss_jordan(const int* list, const BSlot* slots,
                                                        const BState* st) {
   const BSlot& s = slots[list[blockIdx.x]];
-  if (!st[s.inst].active) return;
+  if (!st[s.inst].active || s.np > 0) return;
   gauss_jordan_block(s.Ainv, (int)(s.op.nn * 2));
+}
+
+// last levels above 128 DOFs (np > 0): the blocked Gauss-Jordan inverse of
+// dense_dev.h, one launch per block step for all instances (the list gives
+// the slots, blockIdx.y / z the instance; a slot with fewer blocks returns)
+__global__ void b_dense_fill(const int* list, const BSlot* slots, const BState* st) {
+  const BSlot& s = slots[list[blockIdx.y]];
+  if (!st[s.inst].active || s.np == 0) return;
+  dense_fill_range(s.Ainv, (int)s.nd, s.np, (long)blockIdx.x * blockDim.x + threadIdx.x,
+                   (long)gridDim.x * blockDim.x);
+}
+
+__global__ void b_coarse_assemble_ld(const int* list, const BSlot* slots, const BState* st) {
+  const BSlot& s = slots[list[blockIdx.y]];
+  if (!st[s.inst].active || s.np == 0) return;
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= (int)s.nd) return;
+  coarse_assemble_row(row, s.Ainv, s.E, s.op, s.lam0, s.mu0, s.vol, s.np, false);
+}
+
+__global__ __launch_bounds__(kGjPivThreads) void b_gj_pivot(const int* list, const BSlot* slots,
+                                                             const BState* st, int k) {
+  const BSlot& s = slots[list[blockIdx.x]];
+  if (!st[s.inst].active || k >= s.np / kGjB) return;
+  gj_pivot_block(s.Ainv, s.np, k, s.gjP);
+}
+
+__global__ __launch_bounds__(kGjThreads) void b_gj_panel(const int* list, const BSlot* slots,
+                                                          const BState* st, int k) {
+  const BSlot& s = slots[list[blockIdx.y]];
+  const int nb = s.np / kGjB;
+  if (!st[s.inst].active || k >= nb || (int)blockIdx.x >= 2 * nb) return;
+  gj_panel_block(s.Ainv, s.np, k, s.gjP, s.gjC, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kGjThreads) void b_gj_update(const int* list, const BSlot* slots,
+                                                           const BState* st, int k) {
+  const BSlot& s = slots[list[blockIdx.z]];
+  const int nb = s.np / kGjB;
+  if (!st[s.inst].active || k >= nb || (int)blockIdx.x >= nb || (int)blockIdx.y >= nb) return;
+  gj_update_block(s.Ainv, s.np, k, s.gjP, s.gjC, blockIdx.y, blockIdx.x);
 }
 
 // ------------------------------------------------------------- operator
@@ -279,8 +324,19 @@ __global__ void b_prolong(const BJob* jobs, const BSlot* slots, const BState* st
 
 __global__ void b_coarse_solve(const int* list, const BSlot* slots, const BState* st) {
   const BSlot& s = slots[list[blockIdx.x]];
-  if (!b_live(st, s.inst, true)) return;
+  if (s.np > 0 || !b_live(st, s.inst, true)) return;
   coarse_solve_block<double>(s.v[BV_X], s.v[BV_B], s.Ainv, (int)(s.op.nn * 2), 1);
+}
+
+// x = Ainv b on the last levels above 128 DOFs (blockIdx.y: the slot)
+__global__ __launch_bounds__(64 * kDenseWaves) void b_dense_solve(const int* list,
+                                                                  const BSlot* slots,
+                                                                  const BState* st) {
+  const BSlot& s = slots[list[blockIdx.y]];
+  if (s.np == 0 || !b_live(st, s.inst, true)) return;
+  const int n = (int)s.nd;
+  if ((int)blockIdx.x * kDenseWaves >= n) return;
+  dense_solve_rows<double, double>(s.v[BV_X], s.v[BV_B], s.Ainv, n, s.np, 1, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ CG
@@ -662,6 +718,10 @@ struct BatchCtx {
   std::vector<DevTable> lv_dof, lv_node, lv_child_node, lv_child_sq, lv_tiles, lv_listA, lv_listC;
   std::vector<std::vector<int>> A, C;
   DevTable all_last;
+  // last levels above 128 DOFs: the most 64-blocks of any, the most rows,
+  // and per level the most rows and the largest padded size
+  int gj_nb_max = 0, dense_n_max = 0;
+  std::vector<int> lv_dense_rows, lv_dense_np;
   int shape = 0;
   double shape_us[kBShapes] = {0, 0, 0};
   hipGraphExec_t g_setup = nullptr, g_cg = nullptr, g_post = nullptr;
@@ -705,6 +765,15 @@ bool valid_batch_problem(const topo_problem& p) {
 const int kShapeBX[kBShapes] = {16, 32, 64};
 const int kShapeBY[kBShapes] = {16, 8, 4};
 
+// An instance's levels: down to the first level of at most gmg_dense DOFs
+// (2048 by default), solved directly; an instance whose fine level is
+// already that small keeps the hierarchy down to 128 DOFs.
+static std::vector<LevelDims> batch_plan(const topo_problem& p) {
+  int cap = gmg_dense_max(&p);
+  if (2L * (p.nel[0] + 1) * (p.nel[1] + 1) <= cap) cap = 128;
+  return gmg_plan_dims(2, p.nel[0], p.nel[1], 1, cap);
+}
+
 // Plan (and with base != nullptr, carve) the batch; returns total bytes.
 size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
                   std::vector<std::vector<LevelDims>>* plans_out,
@@ -714,7 +783,7 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
   std::vector<std::vector<LevelDims>> plans(count);
   long cells = 0, dofs = 0;
   for (int i = 0; i < count; ++i) {
-    plans[i] = gmg_plan_dims(2, probs[i].nel[0], probs[i].nel[1], 1);
+    plans[i] = batch_plan(probs[i]);
     cells += 2L * probs[i].nel[0] * probs[i].nel[1];
     dofs += 2L * (probs[i].nel[0] + 1) * (probs[i].nel[1] + 1);
   }
@@ -828,8 +897,13 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
         s.v[BV_Q] = cv.take<double>(s.nd);
         s.v[BV_PV] = cv.take<double>(s.nd);
         s.v[BV_PW] = cv.take<double>(s.nd);
-      } else {
+      } else if (s.nd <= 128) {
         s.Ainv = cv.take<double>((size_t)s.nd * s.nd);
+      } else {
+        s.np = (int)((s.nd + kGjBlock - 1) / kGjBlock * kGjBlock);
+        s.Ainv = cv.take<double>((size_t)s.np * s.np);
+        s.gjP = cv.take<double>((size_t)kGjBlock * kGjBlock);
+        s.gjC = cv.take<double>((size_t)s.np * kGjBlock);
       }
       slots.push_back(s);
     }
@@ -987,6 +1061,19 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
     b->A = A;
     b->C = C;
     b->all_last = t_last;
+    b->gj_nb_max = 0;
+    b->dense_n_max = 0;
+    b->lv_dense_rows.assign(Lmax, 0);
+    b->lv_dense_np.assign(Lmax, 0);
+    for (int sid : all_last) {
+      const BSlot& s = slots[sid];
+      if (s.np == 0) continue;
+      const int nb = s.np / kGjBlock, n = (int)s.nd;
+      if (nb > b->gj_nb_max) b->gj_nb_max = nb;
+      if (n > b->dense_n_max) b->dense_n_max = n;
+      if (n > b->lv_dense_rows[s.level]) b->lv_dense_rows[s.level] = n;
+      if (s.np > b->lv_dense_np[s.level]) b->lv_dense_np[s.level] = s.np;
+    }
   }
   if (plans_out) *plans_out = plans;
   return cv.off;
@@ -1043,9 +1130,14 @@ void cheb_smooth(const Q& q, int l, bool from_zero) {
 void vcycle(const Q& q, int l) {
   BatchCtx* b = q.b;
   if (l >= b->Lmax) return;
-  if (b->lv_listC[l].n > 0)
+  if (b->lv_listC[l].n > 0) {
     b_coarse_solve<<<b->lv_listC[l].n, 128, 0, q.s>>>((const int*)b->lv_listC[l].p, b->d_slots,
                                                       b->d_state);
+    if (b->lv_dense_rows[l] > 0)
+      b_dense_solve<<<dim3((b->lv_dense_rows[l] + kDenseWaves - 1) / kDenseWaves, b->lv_listC[l].n),
+                      64 * kDenseWaves, (size_t)b->lv_dense_np[l] * sizeof(double), q.s>>>(
+          (const int*)b->lv_listC[l].p, b->d_slots, b->d_state);
+  }
   if (b->lv_listA[l].n == 0) return;
   cheb_smooth(q, l, true);
   apply_lv(q, l, BV_X, BV_Q, true, nullptr);
@@ -1084,6 +1176,19 @@ void enqueue_setup(const Q& q) {
   if (b->all_last.n > 0) {
     b_coarse_assemble<<<b->all_last.n, 128, 0, q.s>>>((const int*)b->all_last.p, b->d_slots, b->d_state);
     b_gauss_jordan<<<b->all_last.n, 1024, 0, q.s>>>((const int*)b->all_last.p, b->d_slots, b->d_state);
+    if (b->gj_nb_max > 0) {
+      const int nl = b->all_last.n;
+      const int* lst = (const int*)b->all_last.p;
+      b_dense_fill<<<dim3(256, nl), 256, 0, q.s>>>(lst, b->d_slots, b->d_state);
+      b_coarse_assemble_ld<<<dim3((b->dense_n_max + 63) / 64, nl), 64, 0, q.s>>>(lst, b->d_slots,
+                                                                                 b->d_state);
+      for (int k = 0; k < b->gj_nb_max; ++k) {
+        b_gj_pivot<<<nl, kGjPivThreads, 0, q.s>>>(lst, b->d_slots, b->d_state, k);
+        b_gj_panel<<<dim3(2 * b->gj_nb_max, nl), kGjThreads, 0, q.s>>>(lst, b->d_slots, b->d_state, k);
+        b_gj_update<<<dim3(b->gj_nb_max, b->gj_nb_max, nl), kGjThreads, 0, q.s>>>(lst, b->d_slots,
+                                                                                 b->d_state, k);
+      }
+    }
   }
   // CG start from the previous round's u
   apply_lv(q, 0, BV_U, BV_CQ, false, nullptr);
@@ -1236,7 +1341,7 @@ int topo_batch_create(const topo_problem* probs, int count, const uint8_t* fixed
   std::vector<std::vector<std::vector<uint8_t>>> masks(count);
   const uint8_t* fm = fixed_masks;
   for (int i = 0; i < count; ++i) {
-    const std::vector<LevelDims> plan = gmg_plan_dims(2, probs[i].nel[0], probs[i].nel[1], 1);
+    const std::vector<LevelDims> plan = batch_plan(probs[i]);
     const long nn = (long)(probs[i].nel[0] + 1) * (probs[i].nel[1] + 1);
     std::vector<uint8_t> bits((size_t)nn, 0);
     for (int c = 0; c < 2; ++c)

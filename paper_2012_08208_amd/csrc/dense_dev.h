@@ -1,0 +1,353 @@
+// Dense direct solve of a multigrid coarsest level above 128 DOFs: the
+// blocked Gauss-Jordan inverse and the dense matrix-vector product, as
+// device functions shared by the single-context solver and the batch.
+//
+// The matrix, padded to np = a whole number of 64-blocks with identity rows
+// and columns, is inverted in FP64 by block Gauss-Jordan elimination
+// without pivoting (the matrix is SPD, so every pivot block is SPD).  Per
+// block step k, with P = A_kk^-1 and C the column panel A_ik saved before
+// the step:
+//   A_kj <- P A_kj (j != k),  A_ij <- A_ij - C_i A_kj (i, j != k),
+//   A_ik <- -C_i P (i != k),  A_kk <- P.
+// The work-group of every function below has kGjThreads (256) threads,
+// except dense_solve_rows (64 * kDenseWaves); each returns, if it returns
+// early, for the whole work-group.
+#pragma once
+
+#include <type_traits>
+
+#include "common.h"
+#include "topo_internal.h"
+
+namespace topo {
+
+// A: zeros, with identity rows and columns past n (the padding), by the
+// threads t0, t0 + dt, ... of a grid
+__device__ inline void dense_fill_range(double* A, int n, int np, long t0, long dt) {
+  const long tot = (long)np * np;
+  for (long t = t0; t < tot; t += dt) {
+    const int i = (int)(t / np), j = (int)(t - (long)i * np);
+    A[t] = (i == j && i >= n) ? 1.0 : 0.0;
+  }
+}
+
+constexpr int kGjB = kGjBlock;
+constexpr int kGjPad = kGjB + 1;   // LDS row pitch (doubles)
+
+// P = inverse of the diagonal block k by in-place Gauss-Jordan elimination,
+// itself blocked by 16: for each 16 x 16 diagonal sub-block one wave
+// inverts it in registers (lane l holds column l & 15, rows (l >> 4) + 4m;
+// the pivot row and column come from lane shuffles, so its 16 steps need no
+// barrier), then the work-group forms the sub-block row panel and updates
+// the other 48 rows, as the blocked elimination over the whole matrix
+// does.  Four sub-blocks, three barriers each, instead of 64 barrier-
+// separated steps.
+constexpr int kGjPivThreads = 256;
+constexpr int kGjSub = 16;
+__device__ inline void gj_pivot_block(const double* __restrict__ A, int np, int k, double* P) {
+  __shared__ double S[kGjB * kGjPad];
+  __shared__ double Cb[(kGjB - kGjSub) * (kGjSub + 1)];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const long base = ((long)k * np + k) * kGjB;
+  {
+    constexpr int PER = kGjB * kGjB / kGjPivThreads;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * kGjPivThreads;
+      v[u] = A[base + (long)(e / kGjB) * np + e % kGjB];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * kGjPivThreads;
+      S[(e / kGjB) * kGjPad + e % kGjB] = v[u];
+    }
+  }
+  __syncthreads();
+  for (int kb = 0; kb < kGjB / kGjSub; ++kb) {
+    const int o = kb * kGjSub;
+    if (wave == 0) {
+      const int j = lane & 15, g = lane >> 4;
+      double v[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) v[m] = S[(o + g + 4 * m) * kGjPad + o + j];
+#pragma unroll
+      for (int p = 0; p < kGjSub; ++p) {
+        const int rp = p >> 2, lp = (p & 3) << 4;
+        const double piv = __shfl(v[rp], lp | p);
+        const double rowv = __shfl(v[rp], lp | j);
+        double colv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) colv[m] = __shfl(v[m], (lane & 0x30) | p);
+        double r = __builtin_amdgcn_rcp(piv);
+        r = fma(r, fma(-piv, r, 1.0), r);
+        const double rj = (j == p ? 1.0 : rowv) * r;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int i = g + 4 * m;
+          v[m] = (i == p) ? rj : ((j == p) ? 0.0 : v[m]) - colv[m] * rj;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) S[(o + g + 4 * m) * kGjPad + o + j] = v[m];
+    }
+    __syncthreads();
+    // row panel (16 rows x 48 columns) from the sub-block inverse; the
+    // other rows' sub-block columns saved for the update
+    double col[kGjSub];
+    const int cc = t % 48, r0 = t / 48;
+    const int c = cc < o ? cc : cc + kGjSub;
+    if (t < 192) {
+#pragma unroll
+      for (int q = 0; q < kGjSub; ++q) col[q] = S[(o + q) * kGjPad + c];
+    }
+    for (int e = t; e < (kGjB - kGjSub) * kGjSub; e += kGjPivThreads) {
+      const int ri = e / kGjSub, q = e % kGjSub;
+      const int i = ri < o ? ri : ri + kGjSub;
+      Cb[ri * (kGjSub + 1) + q] = S[i * kGjPad + o + q];
+    }
+    __syncthreads();
+    if (t < 192) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + 4 * u;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kGjSub; ++q) acc = fma(S[(o + r) * kGjPad + o + q], col[q], acc);
+        S[(o + r) * kGjPad + c] = acc;
+      }
+    }
+    __syncthreads();
+    // every other row: A_ic -= C_i (row panel)_c, and the sub-block columns
+    // become -C_i P16 (the same product: those columns of the sub-block rows
+    // hold P16)
+    {
+      const int c2 = t & 63, g2 = t >> 6;
+      double rc[kGjSub];
+#pragma unroll
+      for (int q = 0; q < kGjSub; ++q) rc[q] = S[(o + q) * kGjPad + c2];
+      const bool diag = c2 >= o && c2 < o + kGjSub;
+#pragma unroll
+      for (int u = 0; u < 12; ++u) {
+        const int ri = g2 + 4 * u;
+        const int i = ri < o ? ri : ri + kGjSub;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kGjSub; ++q) acc = fma(Cb[ri * (kGjSub + 1) + q], rc[q], acc);
+        double& y = S[i * kGjPad + c2];
+        y = diag ? -acc : y - acc;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < kGjB * kGjB; e += kGjPivThreads) P[e] = S[(e / kGjB) * kGjPad + e % kGjB];
+}
+
+// acc = X Y for 64 x 64 blocks staged in LDS; thread (tx, ty) owns rows
+// ty + 16a and columns tx + 16b (a, b < 4)
+__device__ inline void gj_block_product(const double* Xs, const double* Ys, double acc[4][4]) {
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int q = 0; q < kGjB; ++q) {
+    double xv[4], yv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) xv[a] = Xs[(ty + 16 * a) * kGjPad + q];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) yv[b] = Ys[q * kGjPad + tx + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], yv[b], acc[a][b]);
+  }
+}
+
+// stage two 64 x 64 blocks (leading dimensions lx, ly) into LDS, every
+// load of the 256 threads issued before the first store
+constexpr int kGjThreads = 256;
+__device__ inline void gj_stage2(double* dx, const double* __restrict__ sx, long lx, double* dy,
+                                 const double* __restrict__ sy, long ly) {
+  constexpr int PER = kGjB * kGjB / kGjThreads;
+  double vx[PER], vy[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    vx[u] = sx[(long)(t / kGjB) * lx + t % kGjB];
+    vy[u] = sy[(long)(t / kGjB) * ly + t % kGjB];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    dx[(t / kGjB) * kGjPad + t % kGjB] = vx[u];
+    dy[(t / kGjB) * kGjPad + t % kGjB] = vy[u];
+  }
+}
+
+// work-group blk < nb: row panel A_kj <- P A_kj (j = blk != k); blk in
+// [nb, 2 nb): save the column panel block C_i = A_ik (i = blk - nb)
+__device__ inline void gj_panel_block(double* A, int np, int k, const double* __restrict__ P,
+                                      double* C, int blk) {
+  __shared__ double Xs[kGjB * kGjPad], Ys[kGjB * kGjPad];
+  const int nb = np / kGjB;
+  if (blk >= nb) {
+    const int i = blk - nb;
+    const double* src = A + ((long)i * np + k) * kGjB;
+    double* dst = C + (long)i * kGjB * kGjB;
+    constexpr int PER = kGjB * kGjB / kGjThreads;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = threadIdx.x + u * kGjThreads;
+      v[u] = src[(long)(t / kGjB) * np + t % kGjB];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) dst[threadIdx.x + u * kGjThreads] = v[u];
+    return;
+  }
+  const int j = blk;
+  if (j == k) return;
+  double* Akj = A + ((long)k * np + j) * kGjB;
+  gj_stage2(Xs, P, kGjB, Ys, Akj, np);
+  __syncthreads();
+  double acc[4][4];
+  gj_block_product(Xs, Ys, acc);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Akj[(long)(ty + 16 * a) * np + tx + 16 * b] = acc[a][b];
+}
+
+// block (i, j) outside row block k: A_ij -= C_i A_kj (j != k) or
+// A_ik = -C_i P; block (k, k) takes P
+__device__ inline void gj_update_block(double* A, int np, int k, const double* __restrict__ P,
+                                       const double* __restrict__ C, int i, int j) {
+  __shared__ double Xs[kGjB * kGjPad], Ys[kGjB * kGjPad];
+  double* Aij = A + ((long)i * np + j) * kGjB;
+  if (i == k) {
+    if (j == k) {
+      constexpr int PER = kGjB * kGjB / kGjThreads;
+      double v[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) v[u] = P[threadIdx.x + u * kGjThreads];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int t = threadIdx.x + u * kGjThreads;
+        Aij[(long)(t / kGjB) * np + t % kGjB] = v[u];
+      }
+    }
+    return;
+  }
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  // the block's own entries are requested first: their latency hides
+  // behind the staging and the product
+  double yv[4][4];
+  if (j != k) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) yv[a][b] = Aij[(long)(ty + 16 * a) * np + tx + 16 * b];
+  }
+  if (j == k) gj_stage2(Xs, C + (long)i * kGjB * kGjB, kGjB, Ys, P, kGjB);
+  else gj_stage2(Xs, C + (long)i * kGjB * kGjB, kGjB, Ys, A + ((long)k * np + j) * kGjB, np);
+  __syncthreads();
+  double acc[4][4];
+  gj_block_product(Xs, Ys, acc);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      Aij[(long)(ty + 16 * a) * np + tx + 16 * b] = (j == k) ? -acc[a][b] : yv[a][b] - acc[a][b];
+}
+
+// x = Ainv b for every load case: one wave per row, 8 waves per work-group
+// with b staged in LDS (zero-padded to np), each lane streaming 16-byte
+// pieces of its row, 8 loads in flight; FP64 sums reduced in a fixed order.
+// Rows are np entries long and np is a multiple of 64, so every piece is
+// aligned and the padded columns (zero) need no bounds test.
+constexpr int kDenseWaves = 8;
+static_assert(kDense3 <= 4 * 64 * kDenseWaves, "the b staging covers np <= 4 * blockDim");
+// (work-group rb: rows rb * kDenseWaves ...; nrhs * np * sizeof(T) bytes of
+// dynamic LDS)
+template <typename T, typename TA>
+__device__ inline void dense_solve_rows(T* x, const T* __restrict__ b, const TA* __restrict__ Ainv,
+                                        int n, int np, int nrhs, int rb) {
+  extern __shared__ double dsm[];
+  T* bs = reinterpret_cast<T*>(dsm);   // [nrhs][np]
+  constexpr int V = 16 / (int)sizeof(TA);
+  using VA = typename std::conditional<sizeof(TA) == 4, float4, double2>::type;
+  using VB = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  const int lane = threadIdx.x & 63;
+  const int row = rb * kDenseWaves + (threadIdx.x >> 6);
+  const int nv = np / V;
+  // the row's first pieces are requested before b is staged (rows past n
+  // read row 0, in bounds, and are not used)
+  const VA* Ar = reinterpret_cast<const VA*>(Ainv + (long)(row < n ? row : 0) * np);
+  VA a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = lane + 64 * u;
+    if (q < nv) a[u] = Ar[q];
+  }
+  // b staged with every load issued before the stores (np <= 4 * blockDim)
+  {
+    T v[kMaxRhs][4];
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = threadIdx.x + u * (int)blockDim.x;
+        v[r][u] = (r < nrhs && j < n) ? b[(long)r * n + j] : T(0);
+      }
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = threadIdx.x + u * (int)blockDim.x;
+        if (r < nrhs && j < np) bs[(long)r * np + j] = v[r][u];
+      }
+  }
+  __syncthreads();
+  if (row >= n) return;
+  double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+  for (int q0 = lane; q0 < nv; q0 += 64 * 8) {
+    if (q0 != lane) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + 64 * u;
+        if (q < nv) a[u] = Ar[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + 64 * u;
+      if (q >= nv) break;
+      const TA* av = reinterpret_cast<const TA*>(&a[u]);
+#pragma unroll
+      for (int r = 0; r < kMaxRhs; ++r) {
+        if (r >= nrhs) break;
+        const T* br = bs + (long)r * np + q * V;
+        T bv[V];
+#pragma unroll
+        for (int e = 0; e < V; e += 16 / (int)sizeof(T)) {
+          const VB w = *reinterpret_cast<const VB*>(br + e);
+          const T* wv = reinterpret_cast<const T*>(&w);
+#pragma unroll
+          for (int f = 0; f < 16 / (int)sizeof(T); ++f) bv[e + f] = wv[f];
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[r] = fma((double)av[e], (double)bv[e], acc[r]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kMaxRhs; ++r) {
+    const double v = wave_sum(acc[r]);
+    if (lane == 0 && r < nrhs) x[(long)r * n + row] = T(v);
+  }
+}
+
+
+}  // namespace topo

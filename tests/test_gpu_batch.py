@@ -8,7 +8,10 @@ batch of instances must reproduce independent single-instance runs up to
 reduction order and CG stopping: bars are L-inf 1e-7 on the densities at
 CG rtol 1e-10, the oracle's design to 1e-6 after the same iterations, the
 per-instance stopping iteration exactly, and graph replays bit-identical to
-direct launches.
+direct launches.  Instances whose fine level has at most 2048 DOFs keep the
+hierarchy down to 128 DOFs (a single context is given gmg_dense = 128 to
+match); larger ones stop at a level of at most 2048 DOFs, solved with its
+blocked Gauss-Jordan inverse, as a single context does by default.
 """
 
 import os
@@ -31,7 +34,10 @@ def _problems(count=5, seed=7, lo=10, hi=40):
 
 def _single(p, rho0, iters, change_tol=0.0, rtol=1e-10):
     from paper_2012_08208_amd import TOPO_FP64, TOPO_PC_GMG, Topo
-    t = Topo.from_problem(p, precision=TOPO_FP64, precond=TOPO_PC_GMG, rtol=rtol, device=DEV)
+    # the batch's hierarchy: instances of at most 2048 DOFs go down to 128
+    dense = 128 if p.n_dofs <= 2048 else 0
+    t = Topo.from_problem(p, precision=TOPO_FP64, precond=TOPO_PC_GMG, rtol=rtol, device=DEV,
+                          gmg_dense=dense)
     rho = torch.as_tensor(rho0, dtype=torch.float64, device=DEV).clone()
     u = torch.zeros(p.n_dofs, dtype=torch.float64, device=DEV)
     n = t.iterate(rho, u, iters, change_tol)
@@ -43,9 +49,10 @@ def _batch_rho0(probs):
     return np.concatenate([np.full(p.n_cells, p.volfrac) for p in probs])
 
 
-def test_batch_matches_single_instances_and_oracle():
+@pytest.mark.parametrize("lo,hi", [(10, 40), (60, 90)])
+def test_batch_matches_single_instances_and_oracle(lo, hi):
     from paper_2012_08208_amd import BATCH_REC_LEN, Batch
-    probs = _problems()
+    probs = _problems(lo=lo, hi=hi)
     print("[batch] sizes", [p.nel for p in probs], flush=True)
     b = Batch(probs, rtol=1e-10, device=DEV)
     rho = torch.as_tensor(_batch_rho0(probs), device=DEV)
@@ -71,9 +78,10 @@ def test_batch_matches_single_instances_and_oracle():
     assert err <= 1e-6
 
 
-def test_batch_instances_stop_individually():
+@pytest.mark.parametrize("lo,hi", [(12, 36), (56, 84)])
+def test_batch_instances_stop_individually(lo, hi):
     from paper_2012_08208_amd import BATCH_REC_LEN, Batch
-    probs = _problems(count=4, seed=11, lo=12, hi=36)
+    probs = _problems(count=4, seed=11, lo=lo, hi=hi)
     b = Batch(probs, rtol=1e-10, device=DEV)
     rho = torch.as_tensor(_batch_rho0(probs), device=DEV)
     rec = torch.zeros(len(probs) * BATCH_REC_LEN, dtype=torch.float64, device=DEV)
@@ -91,9 +99,10 @@ def test_batch_instances_stop_individually():
         assert np.max(np.abs(rho[b.cell_off[i]:b.cell_off[i + 1]] - r_s)) <= 1e-7
 
 
-def test_graph_replays_equal_direct_launches():
+@pytest.mark.parametrize("lo,hi", [(10, 30), (60, 80)])
+def test_graph_replays_equal_direct_launches(lo, hi):
     from paper_2012_08208_amd import Batch
-    probs = _problems(count=3, seed=5, lo=10, hi=30)
+    probs = _problems(count=3, seed=5, lo=lo, hi=hi)
     rhos = []
     for eager in ("0", "1"):
         os.environ["TOPO_BATCH_EAGER"] = eager
