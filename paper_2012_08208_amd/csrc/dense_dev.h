@@ -143,25 +143,41 @@ __device__ inline void gj_pivot_block(const double* __restrict__ A, int np, int 
   for (int e = t; e < kGjB * kGjB; e += kGjPivThreads) P[e] = S[(e / kGjB) * kGjPad + e % kGjB];
 }
 
-// acc = X Y for 64 x 64 blocks staged in LDS; thread (tx, ty) owns rows
-// ty + 16a and columns tx + 16b (a, b < 4)
-__device__ inline void gj_block_product(const double* Xs, const double* Ys, double acc[4][4]) {
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+// acc = X Y for 64 x 64 blocks staged in LDS, on the FP64 matrix cores:
+// wave w owns the 32 x 32 quadrant (32 (w / 2), 32 (w % 2)) as 2 x 2 tiles
+// of v_mfma_f64_16x16x4_f64.  Lane layout of that instruction (checked on
+// gfx950): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], and
+// register r of its result holds D[l / 16 + 4 r][l % 16].
+typedef double gj_d4 __attribute__((ext_vector_type(4)));
+__device__ inline void gj_block_product(const double* Xs, const double* Ys, gj_d4 acc[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int q = 0; q < kGjB; ++q) {
-    double xv[4], yv[4];
+    for (int b = 0; b < 2; ++b) acc[a][b] = gj_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < kGjB; k0 += 4) {
+    double xa[2], yb[2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) xv[a] = Xs[(ty + 16 * a) * kGjPad + q];
+    for (int a = 0; a < 2; ++a) xa[a] = Xs[(r0 + 16 * a + li) * kGjPad + k0 + lk];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) yv[b] = Ys[q * kGjPad + tx + 16 * b];
+    for (int b = 0; b < 2; ++b) yb[b] = Ys[(k0 + lk) * kGjPad + c0 + 16 * b + li];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], yv[b], acc[a][b]);
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], yb[b], acc[a][b], 0, 0, 0);
   }
+}
+
+// the entry (row, column) of the block that register r of acc[a][b] holds
+__device__ inline int gj_acc_row(int a, int r) {
+  return 32 * ((threadIdx.x >> 6) >> 1) + 16 * a + ((threadIdx.x & 63) >> 4) + 4 * r;
+}
+__device__ inline int gj_acc_col(int b) {
+  return 32 * ((threadIdx.x >> 6) & 1) + 16 * b + (threadIdx.x & 15);
 }
 
 // stage two 64 x 64 blocks (leading dimensions lx, ly) into LDS, every
@@ -211,13 +227,14 @@ __device__ inline void gj_panel_block(double* A, int np, int k, const double* __
   double* Akj = A + ((long)k * np + j) * kGjB;
   gj_stage2(Xs, P, kGjB, Ys, Akj, np);
   __syncthreads();
-  double acc[4][4];
+  gj_d4 acc[2][2];
   gj_block_product(Xs, Ys, acc);
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) Akj[(long)(ty + 16 * a) * np + tx + 16 * b] = acc[a][b];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Akj[(long)gj_acc_row(a, r) * np + gj_acc_col(b)] = acc[a][b][r];
 }
 
 // block (i, j) outside row block k: A_ij -= C_i A_kj (j != k) or
@@ -240,26 +257,30 @@ __device__ inline void gj_update_block(double* A, int np, int k, const double* _
     }
     return;
   }
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   // the block's own entries are requested first: their latency hides
   // behind the staging and the product
-  double yv[4][4];
+  double yv[2][2][4];
   if (j != k) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) yv[a][b] = Aij[(long)(ty + 16 * a) * np + tx + 16 * b];
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yv[a][b][r] = Aij[(long)gj_acc_row(a, r) * np + gj_acc_col(b)];
   }
   if (j == k) gj_stage2(Xs, C + (long)i * kGjB * kGjB, kGjB, Ys, P, kGjB);
   else gj_stage2(Xs, C + (long)i * kGjB * kGjB, kGjB, Ys, A + ((long)k * np + j) * kGjB, np);
   __syncthreads();
-  double acc[4][4];
+  gj_d4 acc[2][2];
   gj_block_product(Xs, Ys, acc);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-      Aij[(long)(ty + 16 * a) * np + tx + 16 * b] = (j == k) ? -acc[a][b] : yv[a][b] - acc[a][b];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Aij[(long)gj_acc_row(a, r) * np + gj_acc_col(b)] =
+            (j == k) ? -acc[a][b][r] : yv[a][b][r] - acc[a][b][r];
 }
 
 // x = Ainv b for every load case: one wave per row, 8 waves per work-group
