@@ -346,11 +346,15 @@ __global__ void prolong_add_split_kernel(T* xf, const T* __restrict__ xc, OpDesc
 // ------------------------------------------------------- smoother
 // mode 0: x = 0 on entry (r = b);  mode 1: r = b - q with q = K x
 template <typename T>
-__global__ void cheb_first_kernel(T* x, T* r, T* d, const T* __restrict__ b, const T* __restrict__ q,
+__global__ void cheb_first_kernel(T* __restrict__ x, T* __restrict__ r, T* __restrict__ d,
+                                  const T* __restrict__ b, const T* __restrict__ q,
                                   const T* __restrict__ invd, const double* lmax, long nd, int nrhs,
                                   int mode, double low, int kind, const int* stop) {
   if (stop && *stop) return;
   const T it = T(cheb_first_scale(*lmax, low, kind));
+  // distinct vectors (restrict): the next element's loads may pass this
+  // one's stores
+#pragma unroll 2
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
     const T id = invd[i];
     for (int k = 0; k < nrhs; ++k) {
@@ -365,13 +369,15 @@ __global__ void cheb_first_kernel(T* x, T* r, T* d, const T* __restrict__ b, con
 }
 
 template <typename T>
-__global__ void cheb_next_kernel(T* x, T* r, T* d, const T* __restrict__ q, const T* __restrict__ invd,
+__global__ void cheb_next_kernel(T* __restrict__ x, T* __restrict__ r, T* __restrict__ d,
+                                 const T* __restrict__ q, const T* __restrict__ invd,
                                  const double* lmax, long nd, int nrhs, ChebCoef cf, double low,
                                  const int* stop) {
   if (stop && *stop) return;
   double c1d, c2d;
   cheb_next_coef(*lmax, low, cf, c1d, c2d);
   const T c1 = T(c1d), c2 = T(c2d);
+#pragma unroll 2
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (long)gridDim.x * blockDim.x) {
     const T id = invd[i];
     for (int k = 0; k < nrhs; ++k) {

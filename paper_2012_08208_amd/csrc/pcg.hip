@@ -227,11 +227,12 @@ __global__ void pcg_alpha_fin(const double* partials, long nb, PcgState* st) {
 // x += alpha p, r -= alpha q; partial (r,r) and, for Jacobi, (r, D^-1 r)
 // r32 (optional): FP32 copy of the updated residual for the FP32 V-cycle
 template <int NR, bool JAC, typename TV>
-__global__ __launch_bounds__(256) void pcg_update_kernel(TV* x, TV* r, const TV* __restrict__ p,
+__global__ __launch_bounds__(256) void pcg_update_kernel(TV* __restrict__ x, TV* __restrict__ r,
+                                                         const TV* __restrict__ p,
                                                          const TV* __restrict__ q,
                                                          const TV* __restrict__ invd, long nd,
                                                          double* partials, const PcgState* st,
-                                                         float* r32 = nullptr) {
+                                                         float* __restrict__ r32 = nullptr) {
   if (st->done) return;
   TV al[NR];
   bool act[NR];
@@ -240,6 +241,9 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(TV* x, TV* r, const TV*
   double acc[2 * NR];
 #pragma unroll
   for (int k = 0; k < 2 * NR; ++k) acc[k] = 0.0;
+  // distinct vectors (restrict), so the next element's loads may be issued
+  // before this one's stores
+#pragma unroll 2
   for (long d = (long)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (long)gridDim.x * blockDim.x) {
     const TV id = JAC ? invd[d] : TV(0);
 #pragma unroll
