@@ -183,7 +183,8 @@ __global__ __launch_bounds__(256) void helm_init_kernel(const double* __restrict
 
 // q = (r^2 K + M) p, partial (p, q)
 template <int DIM>
-__global__ __launch_bounds__(256) void helm_apply_kernel(const double* __restrict__ p, double* q,
+__global__ __launch_bounds__(256) void helm_apply_kernel(const double* __restrict__ p,
+                                                         double* __restrict__ q,
                                                          int nx, int ny, int nz, int uniform,
                                                          HelmCoef hc, long nn, double* partials,
                                                          const HelmState* st) {
@@ -267,7 +268,8 @@ __global__ void helm_alpha_fin(const double* partials, long nb, HelmState* st) {
 }
 
 // x += alpha p, r -= alpha q, partials (r, D^-1 r), (r, r)
-__global__ __launch_bounds__(256) void helm_update_kernel(double* x, double* r,
+__global__ __launch_bounds__(256) void helm_update_kernel(double* __restrict__ x,
+                                                          double* __restrict__ r,
                                                           const double* __restrict__ p,
                                                           const double* __restrict__ q,
                                                           const double* __restrict__ invd, long nn,
@@ -275,6 +277,9 @@ __global__ __launch_bounds__(256) void helm_update_kernel(double* x, double* r,
   if (st->done) return;
   const double alpha = st->alpha;
   double acc[2] = {0.0, 0.0};
+  // distinct vectors (restrict): the next node's loads may pass this one's
+  // stores
+#pragma unroll 2
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (long)gridDim.x * blockDim.x) {
     x[n] += alpha * p[n];
     const double rv = r[n] - alpha * q[n];
