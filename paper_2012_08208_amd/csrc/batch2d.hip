@@ -52,6 +52,7 @@ struct BSlot {
   int np;                      // last level above 128 DOFs: nd rounded up to kGjBlock, else 0
   double* gjP;                 // np > 0: the pivot block's inverse [64*64]
   double* gjC;                 // np > 0: the saved column panel [np*64]
+  double* gjR;                 // np > 0: the row panel times the pivot inverse [np*64]
   double* lmax;
   double* pscale;
   int j0, j1;  // this slot's jobs in its level's DOF-job table
@@ -230,15 +231,28 @@ __global__ __launch_bounds__(kGjThreads) void b_gj_panel(const int* list, const 
   const BSlot& s = slots[list[blockIdx.y]];
   const int nb = s.np / kGjB;
   if (!st[s.inst].active || k >= nb || (int)blockIdx.x >= 2 * nb) return;
-  gj_panel_block(s.Ainv, s.np, k, s.gjP, s.gjC, blockIdx.x);
+  sw_panel_block(s.Ainv, s.np, k, s.gjP, s.gjC, s.gjR, blockIdx.x);
 }
 
+// blockIdx.x numbers the blocks on and above the diagonal
 __global__ __launch_bounds__(kGjThreads) void b_gj_update(const int* list, const BSlot* slots,
                                                            const BState* st, int k) {
-  const BSlot& s = slots[list[blockIdx.z]];
+  const BSlot& s = slots[list[blockIdx.y]];
   const int nb = s.np / kGjB;
-  if (!st[s.inst].active || k >= nb || (int)blockIdx.x >= nb || (int)blockIdx.y >= nb) return;
-  gj_update_block(s.Ainv, s.np, k, s.gjP, s.gjC, blockIdx.y, blockIdx.x);
+  if (!st[s.inst].active || k >= nb || (int)blockIdx.x >= nb * (nb + 1) / 2) return;
+  int i, j;
+  sw_tri_index(blockIdx.x, i, j);
+  sw_update_block(s.Ainv, s.np, k, s.gjP, s.gjC, s.gjR, i, j);
+}
+
+__global__ __launch_bounds__(kGjThreads) void b_gj_mirror(const int* list, const BSlot* slots,
+                                                           const BState* st) {
+  const BSlot& s = slots[list[blockIdx.y]];
+  const int nb = s.np / kGjB;
+  if (!st[s.inst].active || s.np == 0 || (int)blockIdx.x >= nb * (nb + 1) / 2) return;
+  int i, j;
+  sw_tri_index(blockIdx.x, i, j);
+  sw_mirror_block(s.Ainv, s.np, i, j);
 }
 
 // ------------------------------------------------------------- operator
@@ -904,6 +918,7 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
         s.Ainv = cv.take<double>((size_t)s.np * s.np);
         s.gjP = cv.take<double>((size_t)kGjBlock * kGjBlock);
         s.gjC = cv.take<double>((size_t)s.np * kGjBlock);
+        s.gjR = cv.take<double>((size_t)s.np * kGjBlock);
       }
       slots.push_back(s);
     }
@@ -1179,15 +1194,16 @@ void enqueue_setup(const Q& q) {
     if (b->gj_nb_max > 0) {
       const int nl = b->all_last.n;
       const int* lst = (const int*)b->all_last.p;
+      const int ntri = b->gj_nb_max * (b->gj_nb_max + 1) / 2;
       b_dense_fill<<<dim3(256, nl), 256, 0, q.s>>>(lst, b->d_slots, b->d_state);
       b_coarse_assemble_ld<<<dim3((b->dense_n_max + 63) / 64, nl), 64, 0, q.s>>>(lst, b->d_slots,
                                                                                  b->d_state);
       for (int k = 0; k < b->gj_nb_max; ++k) {
         b_gj_pivot<<<nl, kGjPivThreads, 0, q.s>>>(lst, b->d_slots, b->d_state, k);
         b_gj_panel<<<dim3(2 * b->gj_nb_max, nl), kGjThreads, 0, q.s>>>(lst, b->d_slots, b->d_state, k);
-        b_gj_update<<<dim3(b->gj_nb_max, b->gj_nb_max, nl), kGjThreads, 0, q.s>>>(lst, b->d_slots,
-                                                                                 b->d_state, k);
+        b_gj_update<<<dim3(ntri, nl), kGjThreads, 0, q.s>>>(lst, b->d_slots, b->d_state, k);
       }
+      b_gj_mirror<<<dim3(ntri, nl), kGjThreads, 0, q.s>>>(lst, b->d_slots, b->d_state);
     }
   }
   // CG start from the previous round's u

@@ -3,12 +3,14 @@
 // device functions shared by the single-context solver and the batch.
 //
 // The matrix, padded to np = a whole number of 64-blocks with identity rows
-// and columns, is inverted in FP64 by block Gauss-Jordan elimination
-// without pivoting (the matrix is SPD, so every pivot block is SPD).  Per
-// block step k, with P = A_kk^-1 and C the column panel A_ik saved before
-// the step:
-//   A_kj <- P A_kj (j != k),  A_ij <- A_ij - C_i A_kj (i, j != k),
-//   A_ik <- -C_i P (i != k),  A_kk <- P.
+// and columns, is inverted in FP64 by block elimination without pivoting
+// (the matrix is SPD, so every pivot block is SPD), in the symmetric form
+// of the sweep operator: per block step k, with P = A_kk^-1,
+//   A_ij <- A_ij - A_ik P A_kj,  A_ik <- A_ik P,  A_kj <- P A_kj  (i, j != k),
+//   A_kk <- -P,
+// which keeps the matrix symmetric and ends at -A^-1.  Only the blocks on
+// and above the diagonal are updated (half the work of the unsymmetric
+// Gauss-Jordan form); a last pass negates and mirrors them.
 // The work-group of every function below has kGjThreads (256) threads,
 // except dense_solve_rows (64 * kDenseWaves); each returns, if it returns
 // early, for the whole work-group.
@@ -201,66 +203,123 @@ __device__ inline void gj_stage2(double* dx, const double* __restrict__ sx, long
   }
 }
 
-// work-group blk < nb: row panel A_kj <- P A_kj (j = blk != k); blk in
-// [nb, 2 nb): save the column panel block C_i = A_ik (i = blk - nb)
-__device__ inline void gj_panel_block(double* A, int np, int k, const double* __restrict__ P,
-                                      double* C, int blk) {
+// The elimination keeps the matrix symmetric (the block sweep operator):
+// per block step k, with P = A_kk^-1,
+//   A_ij -= A_ik P A_kj,  A_ik <- A_ik P,  A_kj <- P A_kj  (i, j != k),
+//   A_kk <- -P,
+// and after the last step the matrix is -A^-1.  Only the blocks (i, j) with
+// i <= j are kept; a block below the diagonal is the transpose of its
+// mirror.  Per step the panel saves the old column, C_i = A_ik, and the row
+// panel R_j = P A_kj (both as 64 x 64 blocks of scratch, leading dimension
+// 64), the update rewrites the upper blocks, and a last pass mirrors the
+// upper blocks and negates.
+
+// the 64 x 64 block (bi, bj) of the symmetric matrix held in its upper
+// blocks, into LDS (row pitch kGjPad): coalesced loads from the stored block,
+// transposed on the LDS store when the block lies below the diagonal
+__device__ inline void sw_stage_block(double* Ls, const double* A, int np, int bi, int bj) {
+  constexpr int PER = kGjB * kGjB / kGjThreads;
+  const bool tr = bi > bj;
+  const double* src = tr ? A + ((long)bj * np + bi) * kGjB : A + ((long)bi * np + bj) * kGjB;
+  double v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    v[u] = src[(long)(t / kGjB) * np + t % kGjB];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    const int r = t / kGjB, c = t % kGjB;
+    Ls[tr ? c * kGjPad + r : r * kGjPad + c] = v[u];
+  }
+}
+
+// a contiguous 64 x 64 block into LDS (row pitch kGjPad)
+__device__ inline void sw_stage_dense(double* Ls, const double* __restrict__ src) {
+  constexpr int PER = kGjB * kGjB / kGjThreads;
+  double v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) v[u] = src[threadIdx.x + u * kGjThreads];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    Ls[(t / kGjB) * kGjPad + t % kGjB] = v[u];
+  }
+}
+
+// work-group blk < nb: R_j = P A_kj (j = blk != k) into R; blk in [nb, 2 nb):
+// C_i = A_ik (i = blk - nb != k) into C
+__device__ inline void sw_panel_block(const double* A, int np, int k,
+                                      const double* __restrict__ P, double* C, double* R,
+                                      int blk) {
   __shared__ double Xs[kGjB * kGjPad], Ys[kGjB * kGjPad];
+  constexpr int PER = kGjB * kGjB / kGjThreads;
   const int nb = np / kGjB;
   if (blk >= nb) {
     const int i = blk - nb;
-    const double* src = A + ((long)i * np + k) * kGjB;
+    if (i == k) return;
+    sw_stage_block(Xs, A, np, i, k);
+    __syncthreads();
     double* dst = C + (long)i * kGjB * kGjB;
-    constexpr int PER = kGjB * kGjB / kGjThreads;
-    double v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int t = threadIdx.x + u * kGjThreads;
-      v[u] = src[(long)(t / kGjB) * np + t % kGjB];
+      dst[t] = Xs[(t / kGjB) * kGjPad + t % kGjB];
     }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) dst[threadIdx.x + u * kGjThreads] = v[u];
     return;
   }
   const int j = blk;
   if (j == k) return;
-  double* Akj = A + ((long)k * np + j) * kGjB;
-  gj_stage2(Xs, P, kGjB, Ys, Akj, np);
+  sw_stage_dense(Xs, P);
+  sw_stage_block(Ys, A, np, k, j);
   __syncthreads();
   gj_d4 acc[2][2];
   gj_block_product(Xs, Ys, acc);
+  double* dst = R + (long)j * kGjB * kGjB;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Akj[(long)gj_acc_row(a, r) * np + gj_acc_col(b)] = acc[a][b][r];
+      for (int r = 0; r < 4; ++r) dst[gj_acc_row(a, r) * kGjB + gj_acc_col(b)] = acc[a][b][r];
 }
 
-// block (i, j) outside row block k: A_ij -= C_i A_kj (j != k) or
-// A_ik = -C_i P; block (k, k) takes P
-__device__ inline void gj_update_block(double* A, int np, int k, const double* __restrict__ P,
-                                       const double* __restrict__ C, int i, int j) {
+// the upper block (i, j), i <= j, numbered tri = j (j + 1) / 2 + i
+__device__ inline void sw_tri_index(int tri, int& i, int& j) {
+  j = (int)((sqrtf(8.0f * (float)tri + 1.0f) - 1.0f) * 0.5f);
+  while (j * (j + 1) / 2 > tri) --j;
+  while ((j + 1) * (j + 2) / 2 <= tri) ++j;
+  i = tri - j * (j + 1) / 2;
+}
+
+// upper block (i, j), i <= j: A_ij -= C_i R_j; A_ik = C_i P; A_kj = R_j;
+// A_kk = -P
+__device__ inline void sw_update_block(double* A, int np, int k, const double* __restrict__ P,
+                                       const double* __restrict__ C, const double* __restrict__ R,
+                                       int i, int j) {
   __shared__ double Xs[kGjB * kGjPad], Ys[kGjB * kGjPad];
+  constexpr int PER = kGjB * kGjB / kGjThreads;
   double* Aij = A + ((long)i * np + j) * kGjB;
   if (i == k) {
-    if (j == k) {
-      constexpr int PER = kGjB * kGjB / kGjThreads;
-      double v[PER];
+    // row block k: A_kk = -P, A_kj = R_j
+    const double* src = j == k ? P : R + (long)j * kGjB * kGjB;
+    const double sg = j == k ? -1.0 : 1.0;
+    double v[PER];
 #pragma unroll
-      for (int u = 0; u < PER; ++u) v[u] = P[threadIdx.x + u * kGjThreads];
+    for (int u = 0; u < PER; ++u) v[u] = src[threadIdx.x + u * kGjThreads];
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int t = threadIdx.x + u * kGjThreads;
-        Aij[(long)(t / kGjB) * np + t % kGjB] = v[u];
-      }
+    for (int u = 0; u < PER; ++u) {
+      const int t = threadIdx.x + u * kGjThreads;
+      Aij[(long)(t / kGjB) * np + t % kGjB] = sg * v[u];
     }
     return;
   }
   // the block's own entries are requested first: their latency hides
   // behind the staging and the product
+  const bool upd = j != k;
   double yv[2][2][4];
-  if (j != k) {
+  if (upd) {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -268,8 +327,7 @@ __device__ inline void gj_update_block(double* A, int np, int k, const double* _
 #pragma unroll
         for (int r = 0; r < 4; ++r) yv[a][b][r] = Aij[(long)gj_acc_row(a, r) * np + gj_acc_col(b)];
   }
-  if (j == k) gj_stage2(Xs, C + (long)i * kGjB * kGjB, kGjB, Ys, P, kGjB);
-  else gj_stage2(Xs, C + (long)i * kGjB * kGjB, kGjB, Ys, A + ((long)k * np + j) * kGjB, np);
+  gj_stage2(Xs, C + (long)i * kGjB * kGjB, kGjB, Ys, upd ? R + (long)j * kGjB * kGjB : P, kGjB);
   __syncthreads();
   gj_d4 acc[2][2];
   gj_block_product(Xs, Ys, acc);
@@ -280,7 +338,38 @@ __device__ inline void gj_update_block(double* A, int np, int k, const double* _
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         Aij[(long)gj_acc_row(a, r) * np + gj_acc_col(b)] =
-            (j == k) ? -acc[a][b][r] : yv[a][b][r] - acc[a][b][r];
+            upd ? yv[a][b][r] - acc[a][b][r] : acc[a][b][r];
+}
+
+// after the last step: A^-1 = -(the upper blocks and their mirrors); upper
+// block (i, j) by one work-group, its mirror written through LDS so that
+// both stores are coalesced
+__device__ inline void sw_mirror_block(double* A, int np, int i, int j) {
+  __shared__ double Xs[kGjB * kGjPad];
+  constexpr int PER = kGjB * kGjB / kGjThreads;
+  double* Aij = A + ((long)i * np + j) * kGjB;
+  double* Aji = A + ((long)j * np + i) * kGjB;
+  double v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    v[u] = Aij[(long)(t / kGjB) * np + t % kGjB];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    const int r = t / kGjB, c = t % kGjB;
+    Aij[(long)r * np + c] = -v[u];
+    Xs[c * kGjPad + r] = -v[u];
+  }
+  if (i == j) return;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * kGjThreads;
+    const int r = t / kGjB, c = t % kGjB;
+    Aji[(long)r * np + c] = Xs[r * kGjPad + c];
+  }
 }
 
 // x = Ainv b for every load case: one wave per row, 8 waves per work-group

@@ -480,16 +480,26 @@ __global__ __launch_bounds__(kGjPivThreads) void gj_pivot_kernel(const double* _
   gj_pivot_block(A, np, k, P);
 }
 
-__global__ __launch_bounds__(kGjThreads) void gj_panel_kernel(double* A, int np, int k,
+__global__ __launch_bounds__(kGjThreads) void sw_panel_kernel(const double* A, int np, int k,
                                                                const double* __restrict__ P,
-                                                               double* C) {
-  gj_panel_block(A, np, k, P, C, blockIdx.x);
+                                                               double* C, double* R) {
+  sw_panel_block(A, np, k, P, C, R, blockIdx.x);
 }
 
-__global__ __launch_bounds__(kGjThreads) void gj_update_kernel(double* A, int np, int k,
+// one work-group per block on or above the diagonal
+__global__ __launch_bounds__(kGjThreads) void sw_update_kernel(double* A, int np, int k,
                                                                 const double* __restrict__ P,
-                                                                const double* __restrict__ C) {
-  gj_update_block(A, np, k, P, C, blockIdx.y, blockIdx.x);
+                                                                const double* __restrict__ C,
+                                                                const double* __restrict__ R) {
+  int i, j;
+  sw_tri_index(blockIdx.x, i, j);
+  sw_update_block(A, np, k, P, C, R, i, j);
+}
+
+__global__ __launch_bounds__(kGjThreads) void sw_mirror_kernel(double* A, int np) {
+  int i, j;
+  sw_tri_index(blockIdx.x, i, j);
+  sw_mirror_block(A, np, i, j);
 }
 
 template <typename T, typename TA>
@@ -555,14 +565,16 @@ void gmg_setup(Ctx* c) {
   const int np = cl.np, nb = np / kGjB;
   double* P = cl.gj;
   double* C = cl.gj + kGjB * kGjB;
+  double* R = C + (long)np * kGjB;
   dense_fill_kernel<<<red_grid((long)np * np), 256, 0, s>>>(cl.Ainv, n, np);
   coarse_assemble_ld_kernel<<<cdivu(n, 64), 64, 0, s>>>(cl.Ainv, cl.E, cl.op, c->m.lam0, c->m.mu0,
                                                        c->m.vol, np);
   for (int k = 0; k < nb; ++k) {
     gj_pivot_kernel<<<1, kGjPivThreads, 0, s>>>(cl.Ainv, np, k, P);
-    gj_panel_kernel<<<2 * nb, kGjThreads, 0, s>>>(cl.Ainv, np, k, P, C);
-    gj_update_kernel<<<dim3(nb, nb), kGjThreads, 0, s>>>(cl.Ainv, np, k, P, C);
+    sw_panel_kernel<<<2 * nb, kGjThreads, 0, s>>>(cl.Ainv, np, k, P, C, R);
+    sw_update_kernel<<<nb * (nb + 1) / 2, kGjThreads, 0, s>>>(cl.Ainv, np, k, P, C, R);
   }
+  sw_mirror_kernel<<<nb * (nb + 1) / 2, kGjThreads, 0, s>>>(cl.Ainv, np);
   if (cl.Ainv32) to_f32_kernel<<<red_grid((long)np * np), 256, 0, s>>>(cl.Ainv32, cl.Ainv, (long)np * np);
 }
 
