@@ -194,8 +194,9 @@ typedef struct topo_problem {
   int32_t warm_start; /* 1: topo_solve starts from the u it is given */
   int32_t gmg_dense;  /* multigrid: the largest coarsest level, in DOFs, that
                          is solved directly (its dense inverse is built per
-                         solve, by Gauss-Jordan elimination: in one
-                         work-group up to 128 DOFs, else block by block);
+                         solve: by Gauss-Jordan elimination in one
+                         work-group up to 128 DOFs, else by the symmetric
+                         block sweep, block by block);
                          the hierarchy stops at the first level at or
                          below it.  0 = automatic: 2048 (the environment
                          variable TOPO_GMG_DENSE, read at creation,

@@ -201,9 +201,9 @@ __global__ __launch_bounds__(1024) void b_gauss_jordan(const int* list, const BS
   gauss_jordan_block(s.Ainv, (int)(s.op.nn * 2));
 }
 
-// last levels above 128 DOFs (np > 0): the blocked Gauss-Jordan inverse of
+// last levels above 128 DOFs (np > 0): the block sweep inverse of
 // dense_dev.h, one launch per block step for all instances (the list gives
-// the slots, blockIdx.y / z the instance; a slot with fewer blocks returns)
+// the slots, blockIdx.y the instance; a slot with fewer blocks returns)
 __global__ void b_dense_fill(const int* list, const BSlot* slots, const BState* st) {
   const BSlot& s = slots[list[blockIdx.y]];
   if (!st[s.inst].active || s.np == 0) return;

@@ -1,5 +1,5 @@
 // Dense direct solve of a multigrid coarsest level above 128 DOFs: the
-// blocked Gauss-Jordan inverse and the dense matrix-vector product, as
+// block sweep inverse and the dense matrix-vector product, as
 // device functions shared by the single-context solver and the batch.
 //
 // The matrix, padded to np = a whole number of 64-blocks with identity rows

@@ -24,9 +24,9 @@
 // safety factor; the same polynomial is used before and after the coarse
 // correction, so the V-cycle is a symmetric positive definite operator.
 // Coarsest level (the first of at most 2048 DOFs, or the size the problem
-// asks for): dense matrix assembled per solve and inverted by Gauss-Jordan
-// elimination, in one work-group up to 128 DOFs, else block by block over
-// the whole GPU.
+// asks for): dense matrix assembled per solve and inverted, by Gauss-Jordan
+// elimination in one work-group up to 128 DOFs, else by the symmetric block
+// sweep over the whole GPU.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -458,9 +458,8 @@ __global__ __launch_bounds__(512) void coarse_solve_kernel(T* x, const T* __rest
 // ------------------------------------------ larger coarsest level (> 128 DOFs)
 // The coarsest level of a deep hierarchy (12 x 6 x 6 cells, 1911 DOFs, on
 // 192 x 96 x 96) is solved directly too: its padded matrix is assembled and
-// inverted per solve by the blocked Gauss-Jordan elimination of
-// dense_dev.h, and each visit is one dense matrix-vector product over the
-// whole GPU.  A revisit of a level solved exactly would change nothing, so
+// inverted per solve by the symmetric block sweep of dense_dev.h, and each
+// visit is one dense matrix-vector product over the whole GPU.  A revisit of a level solved exactly would change nothing, so
 // the level above it never revisits (W) and the tail kernel is not used
 // with it.
 __global__ void dense_fill_kernel(double* A, int n, int np) {

@@ -202,7 +202,7 @@ struct LevelDims {
 // Largest coarsest level (DOFs) that the multigrid hierarchy solves
 // directly: topo_problem.gmg_dense, else kDense3 (TOPO_GMG_DENSE overrides
 // it).  Up to 128 DOFs the inverse comes from one work-group's Gauss-Jordan
-// elimination, above from the blocked one over the whole GPU.  At most
+// elimination, above from the symmetric block sweep over the whole GPU.  At most
 // kDense3: the dense solve stages 4 FP64 right-hand sides of that length in
 // 64 KiB of LDS.
 constexpr int kDense3 = 2048;
