@@ -252,7 +252,7 @@ static WsLayout make_layout(const topo_problem* p, const Grid& g, int kz) {
         lv.np = (int)np;
         lv.off_A = take(np * np * 8);
         lv.off_A32 = mixed ? take(np * np * 4) : 0;
-        lv.off_gj = take(((size_t)kGjBlock * kGjBlock + 2 * np * kGjBlock) * 8);
+        lv.off_gj = take((2 * (size_t)kGjBlock * kGjBlock + 2 * np * kGjBlock) * 8);
       }
       L.levels.push_back(lv);
     }

@@ -50,7 +50,7 @@ struct BSlot {
   double* v[BV_N];
   double* Ainv;                // last level: dense inverse [nd*nd], or [np*np] when np > 0
   int np;                      // last level above 128 DOFs: nd rounded up to kGjBlock, else 0
-  double* gjP;                 // np > 0: the pivot block's inverse [64*64]
+  double* gjP;                 // np > 0: the pivot blocks' inverses of two steps [2*64*64]
   double* gjC;                 // np > 0: the saved column panel [np*64]
   double* gjR;                 // np > 0: the row panel times the pivot inverse [np*64]
   double* lmax;
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kGjPivThreads) void b_gj_pivot(const int* list, con
                                                              const BState* st, int k) {
   const BSlot& s = slots[list[blockIdx.x]];
   if (!st[s.inst].active || k >= s.np / kGjB) return;
-  gj_pivot_block(s.Ainv, s.np, k, s.gjP);
+  gj_pivot_block(s.Ainv, s.np, k, s.gjP + (k & 1) * kGjB * kGjB);
 }
 
 __global__ __launch_bounds__(kGjThreads) void b_gj_panel(const int* list, const BSlot* slots,
@@ -231,18 +231,21 @@ __global__ __launch_bounds__(kGjThreads) void b_gj_panel(const int* list, const 
   const BSlot& s = slots[list[blockIdx.y]];
   const int nb = s.np / kGjB;
   if (!st[s.inst].active || k >= nb || (int)blockIdx.x >= 2 * nb) return;
-  sw_panel_block(s.Ainv, s.np, k, s.gjP, s.gjC, s.gjR, blockIdx.x);
+  sw_panel_block(s.Ainv, s.np, k, s.gjP + (k & 1) * kGjB * kGjB, s.gjC, s.gjR, blockIdx.x);
 }
 
-// blockIdx.x numbers the blocks on and above the diagonal
+// blockIdx.x numbers the blocks on and above the diagonal (the next
+// diagonal block first), blockIdx.y the instance: an instance's blocks are
+// dispatched together and share its panels in the caches
 __global__ __launch_bounds__(kGjThreads) void b_gj_update(const int* list, const BSlot* slots,
                                                            const BState* st, int k) {
   const BSlot& s = slots[list[blockIdx.y]];
   const int nb = s.np / kGjB;
   if (!st[s.inst].active || k >= nb || (int)blockIdx.x >= nb * (nb + 1) / 2) return;
   int i, j;
-  sw_tri_index(blockIdx.x, i, j);
-  sw_update_block(s.Ainv, s.np, k, s.gjP, s.gjC, s.gjR, i, j);
+  sw_update_index(blockIdx.x, nb, k, i, j);
+  sw_update_block(s.Ainv, s.np, k, s.gjP + (k & 1) * kGjB * kGjB, s.gjC, s.gjR, i, j,
+                  k + 1 < nb ? s.gjP + ((k + 1) & 1) * kGjB * kGjB : nullptr);
 }
 
 __global__ __launch_bounds__(kGjThreads) void b_gj_mirror(const int* list, const BSlot* slots,
@@ -916,7 +919,7 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
       } else {
         s.np = (int)((s.nd + kGjBlock - 1) / kGjBlock * kGjBlock);
         s.Ainv = cv.take<double>((size_t)s.np * s.np);
-        s.gjP = cv.take<double>((size_t)kGjBlock * kGjBlock);
+        s.gjP = cv.take<double>(2 * (size_t)kGjBlock * kGjBlock);
         s.gjC = cv.take<double>((size_t)s.np * kGjBlock);
         s.gjR = cv.take<double>((size_t)s.np * kGjBlock);
       }
@@ -1198,8 +1201,8 @@ void enqueue_setup(const Q& q) {
       b_dense_fill<<<dim3(256, nl), 256, 0, q.s>>>(lst, b->d_slots, b->d_state);
       b_coarse_assemble_ld<<<dim3((b->dense_n_max + 63) / 64, nl), 64, 0, q.s>>>(lst, b->d_slots,
                                                                                  b->d_state);
+      b_gj_pivot<<<nl, kGjPivThreads, 0, q.s>>>(lst, b->d_slots, b->d_state, 0);
       for (int k = 0; k < b->gj_nb_max; ++k) {
-        b_gj_pivot<<<nl, kGjPivThreads, 0, q.s>>>(lst, b->d_slots, b->d_state, k);
         b_gj_panel<<<dim3(2 * b->gj_nb_max, nl), kGjThreads, 0, q.s>>>(lst, b->d_slots, b->d_state, k);
         b_gj_update<<<dim3(ntri, nl), kGjThreads, 0, q.s>>>(lst, b->d_slots, b->d_state, k);
       }

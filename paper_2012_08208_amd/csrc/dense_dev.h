@@ -46,26 +46,11 @@ constexpr int kGjPad = kGjB + 1;   // LDS row pitch (doubles)
 // separated steps.
 constexpr int kGjPivThreads = 256;
 constexpr int kGjSub = 16;
-__device__ inline void gj_pivot_block(const double* __restrict__ A, int np, int k, double* P) {
-  __shared__ double S[kGjB * kGjPad];
+// S: the block in LDS (row pitch kGjPad), overwritten; every thread of the
+// work-group has stored its part of S and passed a barrier before the call
+__device__ __forceinline__ void gj_pivot_lds(double* S, double* P) {
   __shared__ double Cb[(kGjB - kGjSub) * (kGjSub + 1)];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const long base = ((long)k * np + k) * kGjB;
-  {
-    constexpr int PER = kGjB * kGjB / kGjPivThreads;
-    double v[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = t + u * kGjPivThreads;
-      v[u] = A[base + (long)(e / kGjB) * np + e % kGjB];
-    }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = t + u * kGjPivThreads;
-      S[(e / kGjB) * kGjPad + e % kGjB] = v[u];
-    }
-  }
-  __syncthreads();
   for (int kb = 0; kb < kGjB / kGjSub; ++kb) {
     const int o = kb * kGjSub;
     if (wave == 0) {
@@ -145,6 +130,26 @@ __device__ inline void gj_pivot_block(const double* __restrict__ A, int np, int 
   for (int e = t; e < kGjB * kGjB; e += kGjPivThreads) P[e] = S[(e / kGjB) * kGjPad + e % kGjB];
 }
 
+__device__ inline void gj_pivot_block(const double* __restrict__ A, int np, int k, double* P) {
+  __shared__ double S[kGjB * kGjPad];
+  const int t = threadIdx.x;
+  const long base = ((long)k * np + k) * kGjB;
+  constexpr int PER = kGjB * kGjB / kGjPivThreads;
+  double v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = t + u * kGjPivThreads;
+    v[u] = A[base + (long)(e / kGjB) * np + e % kGjB];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = t + u * kGjPivThreads;
+    S[(e / kGjB) * kGjPad + e % kGjB] = v[u];
+  }
+  __syncthreads();
+  gj_pivot_lds(S, P);
+}
+
 // acc = X Y for 64 x 64 blocks staged in LDS, on the FP64 matrix cores:
 // wave w owns the 32 x 32 quadrant (32 (w / 2), 32 (w % 2)) as 2 x 2 tiles
 // of v_mfma_f64_16x16x4_f64.  Lane layout of that instruction (checked on
@@ -185,6 +190,7 @@ __device__ inline int gj_acc_col(int b) {
 // stage two 64 x 64 blocks (leading dimensions lx, ly) into LDS, every
 // load of the 256 threads issued before the first store
 constexpr int kGjThreads = 256;
+static_assert(kGjThreads == kGjPivThreads, "the update work-group also inverts the next pivot");
 __device__ inline void gj_stage2(double* dx, const double* __restrict__ sx, long lx, double* dy,
                                  const double* __restrict__ sy, long ly) {
   constexpr int PER = kGjB * kGjB / kGjThreads;
@@ -293,11 +299,24 @@ __device__ inline void sw_tri_index(int tri, int& i, int& j) {
   i = tri - j * (j + 1) / 2;
 }
 
+// the upper block of work-group blk (< nb (nb + 1) / 2) in a step-k update:
+// the numbering starts at the next diagonal block, the one whose
+// work-group also inverts it, so that it is dispatched first
+__device__ inline void sw_update_index(int blk, int nb, int k, int& i, int& j) {
+  const int ntri = nb * (nb + 1) / 2;
+  int t = blk + (k + 1 < nb ? (k + 1) * (k + 2) / 2 + k + 1 : 0);
+  if (t >= ntri) t -= ntri;
+  sw_tri_index(t, i, j);
+}
+
 // upper block (i, j), i <= j: A_ij -= C_i R_j; A_ik = C_i P; A_kj = R_j;
-// A_kk = -P
+// A_kk = -P.  Pnext (if not null): the work-group of the next diagonal
+// block, which this step completes, goes on to invert it for the next
+// step (so no pivot launch stands between two steps); Pnext must not be P,
+// which the other work-groups are still reading.
 __device__ inline void sw_update_block(double* A, int np, int k, const double* __restrict__ P,
                                        const double* __restrict__ C, const double* __restrict__ R,
-                                       int i, int j) {
+                                       int i, int j, double* Pnext) {
   __shared__ double Xs[kGjB * kGjPad], Ys[kGjB * kGjPad];
   constexpr int PER = kGjB * kGjB / kGjThreads;
   double* Aij = A + ((long)i * np + j) * kGjB;
@@ -336,9 +355,21 @@ __device__ inline void sw_update_block(double* A, int np, int k, const double* _
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        Aij[(long)gj_acc_row(a, r) * np + gj_acc_col(b)] =
-            upd ? yv[a][b][r] - acc[a][b][r] : acc[a][b][r];
+      for (int r = 0; r < 4; ++r) {
+        yv[a][b][r] = upd ? yv[a][b][r] - acc[a][b][r] : acc[a][b][r];
+        Aij[(long)gj_acc_row(a, r) * np + gj_acc_col(b)] = yv[a][b][r];
+      }
+  if (Pnext && i == k + 1 && j == k + 1) {
+    __syncthreads();   // every wave is done reading Xs
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xs[gj_acc_row(a, r) * kGjPad + gj_acc_col(b)] = yv[a][b][r];
+    __syncthreads();
+    gj_pivot_lds(Xs, Pnext);
+  }
 }
 
 // after the last step: A^-1 = -(the upper blocks and their mirrors); upper

@@ -489,10 +489,11 @@ __global__ __launch_bounds__(kGjThreads) void sw_panel_kernel(const double* A, i
 __global__ __launch_bounds__(kGjThreads) void sw_update_kernel(double* A, int np, int k,
                                                                 const double* __restrict__ P,
                                                                 const double* __restrict__ C,
-                                                                const double* __restrict__ R) {
+                                                                const double* __restrict__ R,
+                                                                double* Pnext) {
   int i, j;
-  sw_tri_index(blockIdx.x, i, j);
-  sw_update_block(A, np, k, P, C, R, i, j);
+  sw_update_index(blockIdx.x, np / kGjB, k, i, j);
+  sw_update_block(A, np, k, P, C, R, i, j, Pnext);
 }
 
 __global__ __launch_bounds__(kGjThreads) void sw_mirror_kernel(double* A, int np) {
@@ -562,16 +563,19 @@ void gmg_setup(Ctx* c) {
     return;
   }
   const int np = cl.np, nb = np / kGjB;
-  double* P = cl.gj;
-  double* C = cl.gj + kGjB * kGjB;
+  // two pivot inverses (step k reads one while its update writes the next)
+  double* P2 = cl.gj;
+  double* C = cl.gj + 2 * kGjB * kGjB;
   double* R = C + (long)np * kGjB;
   dense_fill_kernel<<<red_grid((long)np * np), 256, 0, s>>>(cl.Ainv, n, np);
   coarse_assemble_ld_kernel<<<cdivu(n, 64), 64, 0, s>>>(cl.Ainv, cl.E, cl.op, c->m.lam0, c->m.mu0,
                                                        c->m.vol, np);
+  gj_pivot_kernel<<<1, kGjPivThreads, 0, s>>>(cl.Ainv, np, 0, P2);
   for (int k = 0; k < nb; ++k) {
-    gj_pivot_kernel<<<1, kGjPivThreads, 0, s>>>(cl.Ainv, np, k, P);
+    double* P = P2 + (k & 1) * kGjB * kGjB;
+    double* Pn = k + 1 < nb ? P2 + ((k + 1) & 1) * kGjB * kGjB : nullptr;
     sw_panel_kernel<<<2 * nb, kGjThreads, 0, s>>>(cl.Ainv, np, k, P, C, R);
-    sw_update_kernel<<<nb * (nb + 1) / 2, kGjThreads, 0, s>>>(cl.Ainv, np, k, P, C, R);
+    sw_update_kernel<<<nb * (nb + 1) / 2, kGjThreads, 0, s>>>(cl.Ainv, np, k, P, C, R, Pn);
   }
   sw_mirror_kernel<<<nb * (nb + 1) / 2, kGjThreads, 0, s>>>(cl.Ainv, np);
   if (cl.Ainv32) to_f32_kernel<<<red_grid((long)np * np), 256, 0, s>>>(cl.Ainv32, cl.Ainv, (long)np * np);
