@@ -34,6 +34,9 @@
 namespace topo {
 
 constexpr int kBChunk = 2048;      // elements per job
+constexpr int kBChunkNode = 256;   // nodes per job of the restriction, prolongation and
+                                   // diagonal tables: their gathers, one node per thread,
+                                   // are not serialised over a strided loop
 constexpr int kBCgPerGraph = 4;    // CG iterations per continuation replay
 constexpr int kBOcPasses = 40;     // OC root passes per round (early exit per instance)
 constexpr int kBShapes = 3;        // fine-level apply tile shapes: 16x16, 32x8, 64x4
@@ -929,13 +932,13 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
     dof += in.nd;
   }
   // job tables
-  auto chunks = [](std::vector<BJob>& out, int slot, int inst_id, long n) {
-    for (long b0 = 0; b0 < n; b0 += kBChunk) {
+  auto chunks = [](std::vector<BJob>& out, int slot, int inst_id, long n, int cap = kBChunk) {
+    for (long b0 = 0; b0 < n; b0 += cap) {
       BJob j;
       j.slot = slot;
       j.inst = inst_id;
       j.begin = b0;
-      j.count = (int)((n - b0) < kBChunk ? (n - b0) : kBChunk);
+      j.count = (int)((n - b0) < cap ? (n - b0) : cap);
       j.pad = 0;
       out.push_back(j);
     }
@@ -980,9 +983,9 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
       s.j0 = (int)ldof[l].size();
       chunks(ldof[l], sid, i, s.nd);
       s.j1 = (int)ldof[l].size();
-      chunks(lnode[l], sid, i, s.op.nn);
+      chunks(lnode[l], sid, i, s.op.nn, kBChunkNode);
       const BSlot& cs = slots[s.child];
-      chunks(lcnode[l], s.child, i, cs.op.nn);
+      chunks(lcnode[l], s.child, i, cs.op.nn, kBChunkNode);
       chunks(lcsq[l], s.child, i, (long)cs.op.nx * cs.op.ny);
       if (l > 0) tiles(ltiles[l], sid, i, s.op, 16, 16);
     }
