@@ -5,7 +5,8 @@
 // The matrix, padded to np = a whole number of 64-blocks with identity rows
 // and columns, is inverted in FP64 by block elimination without pivoting
 // (the matrix is SPD, so every pivot block is SPD), in the symmetric form
-// of the sweep operator: per block step k, with P = A_kk^-1,
+// of the sweep operator (Goodnight, The American Statistician 33(3), 1979)
+// applied block by block: per block step k, with P = A_kk^-1,
 //   A_ij <- A_ij - A_ik P A_kj,  A_ik <- A_ik P,  A_kj <- P A_kj  (i, j != k),
 //   A_kk <- -P,
 // which keeps the matrix symmetric and ends at -A^-1.  Only the blocks on
