@@ -987,7 +987,9 @@ size_t plan_batch(const topo_problem* probs, int count, BatchCtx* b, char* base,
       const BSlot& cs = slots[s.child];
       chunks(lcnode[l], s.child, i, cs.op.nn, kBChunkNode);
       chunks(lcsq[l], s.child, i, (long)cs.op.nx * cs.op.ny);
-      if (l > 0) tiles(ltiles[l], sid, i, s.op, 16, 16);
+      // level 1 (a quarter of the fine grid) in 32 x 8 tiles, fewer halo
+      // nodes per tile; the smaller levels in 16 x 16
+      if (l > 0) tiles(ltiles[l], sid, i, s.op, l == 1 ? 32 : 16, l == 1 ? 8 : 16);
     }
   }
   for (int i = 0; i < count; ++i) {
@@ -1121,7 +1123,10 @@ void apply_lv(const Q& q, int l, int src, int dst, bool cg, double* partials) {
   } else {
     const DevTable& t = b->lv_tiles[l];
     if (t.n == 0) return;
-    b_apply<16, 16><<<t.n, 256, 0, q.s>>>((const BTile*)t.p, b->d_slots, st, src, dst, cg, partials);
+    if (l == 1)
+      b_apply<32, 8><<<t.n, 256, 0, q.s>>>((const BTile*)t.p, b->d_slots, st, src, dst, cg, partials);
+    else
+      b_apply<16, 16><<<t.n, 256, 0, q.s>>>((const BTile*)t.p, b->d_slots, st, src, dst, cg, partials);
   }
 }
 
